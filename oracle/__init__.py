@@ -1,0 +1,266 @@
+"""Plain CPU oracle for LVQ encoding and LVQ similarities (arXiv 2402.02044).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, by the package smoke
+check and by the benchmark's CPU-baseline leg, never by the library.  It shares
+no code with the HIP library.
+
+The arithmetic lives in ``lvq_oracle.c`` (plain scalar C, binary32 encoder with
+one rounding per operation, binary64 similarities); this module is ctypes and
+numpy marshalling around it, plus the list/top-k bookkeeping of Sec. 2.1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lvq_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liblvqoracle.so")
+
+L2, IP = 0, 1
+SEQUENTIAL, TURBO = 0, 1
+PRIMARY, FULL = 1, 2
+HEADER_BYTES = 32
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(_SRC),
+                                              os.path.getmtime(os.path.join(_HERE, "lvq_oracle.h"))):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Fmt(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("dim", "bits1", "bits2", "layout", "align", "npos", "code_bytes",
+                 "row_bytes", "resid_bytes")]
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        lib.orc_format_init.argtypes = [ctypes.POINTER(_Fmt), i32, i32, i32, i32, i32]
+        lib.orc_pos_to_dim.argtypes = [ctypes.POINTER(_Fmt), i32]
+        lib.orc_assign.argtypes = [P, i32, P, i32]
+        lib.orc_encode_codes.argtypes = [P, i32, P, i32, i32, P, P, P, P, P]
+        lib.orc_encode_rows.argtypes = [ctypes.POINTER(_Fmt), P, i64, P, i32, P, P]
+        lib.orc_encode_rows.restype = i64
+        lib.orc_unpack.argtypes = [ctypes.POINTER(_Fmt), P, P, P, P, P, P, P, P]
+        lib.orc_reconstruct.argtypes = [ctypes.POINTER(_Fmt), P, P, P, i32, P]
+        lib.orc_distances.argtypes = [ctypes.POINTER(_Fmt), i32, i32, P, i64, P, P, P, P, P, P]
+        lib.orc_select_topk.argtypes = [i32, P, P, P, i64, i32, P, P]
+        lib.orc_eps1.argtypes = [ctypes.POINTER(_Fmt), P, i64, P, P]
+        lib.orc_eps1.restype = ctypes.c_double
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass(frozen=True)
+class Format:
+    """Row format: see ``lvq_oracle.h``."""
+    dim: int
+    bits1: int
+    bits2: int = 0
+    layout: int = SEQUENTIAL
+    align: int = 32
+
+    def _c(self) -> _Fmt:
+        f = _Fmt()
+        rc = _L().orc_format_init(ctypes.byref(f), self.dim, self.bits1, self.bits2,
+                                  self.layout, self.align)
+        if rc != 0:
+            raise ValueError("unsupported LVQ format %r" % (self,))
+        return f
+
+    @property
+    def npos(self) -> int:
+        return self._c().npos
+
+    @property
+    def code_bytes(self) -> int:
+        return self._c().code_bytes
+
+    @property
+    def row_bytes(self) -> int:
+        return self._c().row_bytes
+
+    @property
+    def resid_bytes(self) -> int:
+        return self._c().resid_bytes
+
+
+def pos_to_dim(fmt: Format) -> np.ndarray:
+    f = fmt._c()
+    return np.array([_L().orc_pos_to_dim(ctypes.byref(f), p) for p in range(f.npos)], np.int32)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def assign(x, means) -> int:
+    x, means = _f32(x), _f32(means)
+    return _L().orc_assign(_p(x), x.shape[-1], _p(means), means.shape[0])
+
+
+def encode_codes(x, mean, bits1, bits2=0):
+    """Codes of one vector: returns (rc, l, delta, delta2, c1, c2)."""
+    x, mean = _f32(x), _f32(mean)
+    d = x.shape[-1]
+    out = np.zeros(3, np.float32)
+    c1 = np.zeros(d, np.uint8)
+    c2 = np.zeros(d, np.uint8)
+    rc = _L().orc_encode_codes(_p(x), d, _p(mean), bits1, bits2, _p(out[0:1]), _p(out[1:2]),
+                               _p(out[2:3]), _p(c1), _p(c2) if bits2 else None)
+    return rc, float(out[0]), float(out[1]), float(out[2]), c1, c2
+
+
+def encode_rows(fmt: Format, X, means):
+    """Encode vectors into (rows, resid, n_rejected)."""
+    X, means = _f32(X), _f32(means)
+    n = X.shape[0]
+    f = fmt._c()
+    rows = np.zeros((n, f.row_bytes), np.uint8)
+    resid = np.zeros((n, f.resid_bytes), np.uint8) if fmt.bits2 else None
+    rej = _L().orc_encode_rows(ctypes.byref(f), _p(X), n, _p(means), means.shape[0],
+                               _p(rows), _p(resid))
+    return rows, resid, int(rej)
+
+
+def unpack(fmt: Format, rows, resid=None):
+    """Header fields and codes (logical dim order) of every row."""
+    f = fmt._c()
+    rows = np.ascontiguousarray(rows, np.uint8).reshape(-1, f.row_bytes)
+    n = rows.shape[0]
+    hdr = np.zeros((n, 3), np.float32)
+    mid = np.zeros(n, np.int32)
+    c1 = np.zeros((n, fmt.dim), np.uint8)
+    c2 = np.zeros((n, fmt.dim), np.uint8)
+    m = np.zeros(1, np.int32)
+    for i in range(n):
+        res = None if resid is None else np.ascontiguousarray(resid[i], np.uint8)
+        _L().orc_unpack(ctypes.byref(f), _p(rows[i]), _p(res), _p(hdr[i, 0:1]), _p(hdr[i, 1:2]),
+                        _p(hdr[i, 2:3]), _p(m), _p(c1[i]), _p(c2[i]))
+        mid[i] = m[0]
+    return hdr[:, 0], hdr[:, 1], hdr[:, 2], mid, c1, c2
+
+
+def reconstruct(fmt: Format, rows, resid, means, level=PRIMARY) -> np.ndarray:
+    f = fmt._c()
+    rows = np.ascontiguousarray(rows, np.uint8).reshape(-1, f.row_bytes)
+    means = _f32(means)
+    out = np.zeros((rows.shape[0], fmt.dim), np.float64)
+    for i in range(rows.shape[0]):
+        res = None if resid is None else np.ascontiguousarray(resid[i], np.uint8)
+        _L().orc_reconstruct(ctypes.byref(f), _p(rows[i]), _p(res), _p(means), level,
+                             _p(out[i]))
+    return out
+
+
+def distances(fmt: Format, metric, level, Q, rows, resid, means, offsets, ids) -> np.ndarray:
+    """binary64 similarity of every (query, listed slot) pair."""
+    f = fmt._c()
+    Q, means = _f32(Q), _f32(means)
+    rows = np.ascontiguousarray(rows, np.uint8)
+    resid = None if resid is None else np.ascontiguousarray(resid, np.uint8)
+    offsets = np.ascontiguousarray(offsets, np.int64)
+    ids = np.ascontiguousarray(ids, np.int32)
+    out = np.zeros(ids.shape[0], np.float64)
+    _L().orc_distances(ctypes.byref(f), metric, level, _p(Q), Q.shape[0], _p(rows), _p(resid),
+                       _p(means), _p(offsets), _p(ids), _p(out))
+    return out
+
+
+def select_topk(metric, score, slot, k, keep=None):
+    score = np.ascontiguousarray(score, np.float64)
+    slot = np.ascontiguousarray(slot, np.int32)
+    keep = None if keep is None else np.ascontiguousarray(keep, np.uint8)
+    ts = np.zeros(k, np.int32)
+    tv = np.zeros(k, np.float64)
+    _L().orc_select_topk(metric, _p(score), _p(slot), _p(keep), score.shape[0], k, _p(ts), _p(tv))
+    return ts, tv
+
+
+def topk_lists(metric, dist, offsets, ids, k, keep_slot=None):
+    """Best k of every candidate list; keep_slot masks slots (lazy deletes)."""
+    nq = len(offsets) - 1
+    out_s = np.zeros((nq, k), np.int32)
+    out_v = np.zeros((nq, k), np.float64)
+    for i in range(nq):
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        keep = None if keep_slot is None else keep_slot[ids[a:b]]
+        out_s[i], out_v[i] = select_topk(metric, dist[a:b], ids[a:b], k, keep)
+    return out_s, out_v
+
+
+def topk_exhaustive(fmt: Format, metric, level, Q, rows, resid, means, k, live=None):
+    """Best k over every live slot for every query (brute-force scan)."""
+    nq = Q.shape[0]
+    n = rows.shape[0]
+    slots = np.arange(n, dtype=np.int32) if live is None else np.flatnonzero(live).astype(np.int32)
+    out_s = np.zeros((nq, k), np.int32)
+    out_v = np.zeros((nq, k), np.float64)
+    for i in range(nq):
+        offs = np.array([0, slots.shape[0]], np.int64)
+        d = distances(fmt, metric, level, Q[i:i + 1], rows, resid, means, offs, slots)
+        out_s[i], out_v[i] = select_topk(metric, d, slots, k)
+    return out_s, out_v
+
+
+def eps1(fmt: Format, X, rows, means) -> float:
+    """Eq. 4 first-level quantisation error (sum over vectors)."""
+    f = fmt._c()
+    X = _f32(X)
+    rows = np.ascontiguousarray(rows, np.uint8)
+    return float(_L().orc_eps1(ctypes.byref(f), _p(X), X.shape[0], _p(rows), _p(_f32(means))))
+
+
+def recall(found, truth) -> float:
+    """k-recall@k = |S intersect G| / k averaged over queries (Sec. 2.1)."""
+    found = np.asarray(found)
+    truth = np.asarray(truth)
+    k = truth.shape[1]
+    hits = sum(len(set(found[i].tolist()) & set(truth[i].tolist())) for i in range(truth.shape[0]))
+    return hits / float(k * truth.shape[0])
+
+
+def float_groundtruth(metric, Q, X, k, live=None, chunk=4096):
+    """binary64 brute-force top-k over the original float vectors (the ground
+    truth G_t of Sec. 2.1), ties to the lower slot."""
+    Q = np.asarray(Q, np.float64)
+    slots = np.arange(X.shape[0]) if live is None else np.flatnonzero(live)
+    best_s = np.zeros((Q.shape[0], 0), np.int64)
+    best_v = np.zeros((Q.shape[0], 0), np.float64)
+    for a in range(0, slots.shape[0], chunk):
+        sl = slots[a:a + chunk]
+        Xs = np.asarray(X[sl], np.float64)
+        if metric == IP:
+            v = -(Q @ Xs.T)                       # rank by descending similarity
+        else:
+            v = (Q * Q).sum(1)[:, None] - 2.0 * (Q @ Xs.T) + (Xs * Xs).sum(1)[None, :]
+        cv = np.concatenate([best_v, v], 1)
+        cs = np.concatenate([best_s, np.broadcast_to(sl, v.shape)], 1)
+        order = np.lexsort((cs, cv), axis=1)[:, :k]
+        best_v = np.take_along_axis(cv, order, 1)
+        best_s = np.take_along_axis(cs, order, 1)
+    return best_s.astype(np.int32)

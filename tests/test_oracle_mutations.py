@@ -1,0 +1,51 @@
+"""Sensitivity of the oracle's pins: each plausible mistake planted in a copy
+of the oracle (on the CPU) must make at least one pin fail."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PINS = ["tests/test_oracle_encode.py", "tests/test_oracle_distance.py"]
+
+MUTATIONS = {
+    "round_half_even": ("float c = b + 0.5f;\n    float v = floorf(c);",
+                        "float c = b;\n    float v = rintf(c);"),
+    "no_clamp_top": ("if (v > (float)top) return top;", ""),
+    "residual_step_pow2": ("delta2 = delta / (float)top2;", "delta2 = delta / (float)(top2 + 1u);"),
+    "residual_wrong_offset": ("c2[j] = (uint8_t)quantize_one(r, -half, inv2, top2);",
+                              "c2[j] = (uint8_t)quantize_one(r, 0.0f, inv2, top2);"),
+    "turbo_transposed": ("dim = b * blk + 16 * k + w;", "dim = b * blk + per_word * w + k;"),
+    "upper_bound_as_min": ("if (j == 0 || t[j] > u) u = t[j];", "if (j == 0 || t[j] < u) u = t[j];"),
+    "full_level_sign": ("v += -0.5 * (double)delta", "v += 0.5 * (double)delta"),
+    "mean_dropped": ("double v = (double)mu[j] + (double)l", "double v = (double)l"),
+    "ties_to_highest_mean": ("if (m == 0 || s < best_s) {", "if (m == 0 || s <= best_s) {"),
+    "topk_ties_reversed": ("return ia < ib;", "return ia > ib;"),
+    "nibble_order": ("return (codes[p / 2] >> (4 * (p % 2))) & 0xFu;",
+                     "return (codes[p / 2] >> (4 * (1 - p % 2))) & 0xFu;"),
+    "step_off_by_one": ("delta = (u - l) / (float)top1;", "delta = (u - l) / (float)(top1 + 1u);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    old, new = MUTATIONS[name]
+    work = tmp_path / "repo"
+    (work / "tests").mkdir(parents=True)
+    shutil.copytree(os.path.join(ROOT, "oracle"), work / "oracle",
+                    ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    shutil.copytree(os.path.join(ROOT, "synth"), work / "synth",
+                    ignore=shutil.ignore_patterns("__pycache__"))
+    shutil.copytree(os.path.join(ROOT, "tests", "golden"), work / "tests" / "golden")
+    for f in PINS + ["tests/conftest.py"]:
+        shutil.copy(os.path.join(ROOT, f), work / f)
+    src = work / "oracle" / "lvq_oracle.c"
+    text = src.read_text()
+    assert text.count(old) == 1, "mutation anchor not found: " + name
+    src.write_text(text.replace(old, new))
+    env = dict(os.environ, PYTHONPATH=str(work), PYTHONDONTWRITEBYTECODE="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"] + PINS,
+                       cwd=work, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, "pins did not catch mutation %s:\n%s" % (name, r.stdout[-2000:])
