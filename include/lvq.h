@@ -1,0 +1,195 @@
+/*
+ * lvq.h -- C ABI of the MI355X (gfx950) LVQ library.
+ *
+ * Locally-adaptive Vector Quantization after "Locally-Adaptive Quantization
+ * for Streaming Vector Search" (arXiv 2402.02044): per-vector LVQ encoding
+ * (Sec. 2.3, Eq. 1-3), the two-level residual variant LVQ-B1xB2 (Sec. 2.3),
+ * multi-means LVQ (Sec. 3.2, Def. 1), the Turbo code layout (Sec. 3.1,
+ * App. B), and similarities between float queries and stored codes
+ * (Sec. 3.2) over candidate lists and as an exhaustive top-k (Sec. 2.1).
+ *
+ * Conventions for every entry point
+ *  - Pointers named *_dev are device pointers (HBM of the current device); the
+ *    caller owns them and keeps them alive until the stream has passed the
+ *    call.  Pointers named *_host are host pointers read before return.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    asynchronously on it; argument checks are synchronous.
+ *  - Return value: LVQ_OK (0) or a negative LVQ_ERR_* code; no C++ exception
+ *    crosses the ABI.  Errors found inside kernels (an out-of-range slot, a
+ *    non-finite input vector) set a sticky per-index error word, write NaN to
+ *    the affected outputs, and are reported (and cleared) by lvq_sync.
+ *  - The library owns the store (rows, residual rows, means, free-slot list)
+ *    and its workspace, all in device memory it allocates itself, counted
+ *    against lvq_config.mem_budget_bytes.
+ *  - Matrices are row-major and dense: x_dev is n x dim float32, q_dev is
+ *    nq x dim (float32, or bfloat16 / float16 for lvq_topk's MFMA forms).
+ *  - Similarity: LVQ_L2 returns the squared Euclidean distance to the
+ *    reconstruction (smaller is better); LVQ_IP returns the inner product with
+ *    it (larger is better).  Ties rank the lower slot first; NaN ranks last.
+ */
+#ifndef LVQ_H
+#define LVQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lvq_index lvq_index;            /* opaque, owned by the library */
+
+typedef enum { LVQ_L2 = 0, LVQ_IP = 1 } lvq_metric;
+typedef enum { LVQ_SEQUENTIAL = 0, LVQ_TURBO = 1 } lvq_layout;
+typedef enum { LVQ_PRIMARY = 1, LVQ_FULL = 2 } lvq_level;
+typedef enum { LVQ_FP32 = 0, LVQ_BF16 = 1, LVQ_FP16 = 2 } lvq_precision;
+
+enum {
+    LVQ_OK = 0,
+    LVQ_ERR_INVALID_ARG = -1,
+    LVQ_ERR_UNSUPPORTED = -2,
+    LVQ_ERR_OOM = -3,          /* device allocation failed or memory budget exceeded */
+    LVQ_ERR_CAPACITY = -4,     /* not enough free slots */
+    LVQ_ERR_DEVICE = -5,       /* HIP runtime error */
+    LVQ_ERR_NONFINITE = -6,    /* an input vector had a non-finite component */
+    LVQ_ERR_BAD_SLOT = -7      /* a slot id out of range (or not live for lvq_delete) */
+};
+
+/* Index configuration.
+ *  dim       vector dimensionality d (1..8192)
+ *  bits1     first-level bits B1: 4 or 8 (Eq. 3)
+ *  bits2     residual bits B2: 0 (one level), 4 or 8 (Sec. 2.3, LVQ-B1xB2)
+ *  metric    LVQ_L2 or LVQ_IP
+ *  layout    LVQ_SEQUENTIAL (dimension j at code position j) or LVQ_TURBO
+ *            (Sec. 3.1: per 64-byte block of sixteen 32-bit words, dimension
+ *            16k + w of the block in field k of word w; 128 dims per block
+ *            at 4 bits, 64 dims at 8 bits; zero padded)
+ *  align     row stride alignment in bytes: 32 (the paper's padding, App. D),
+ *            64 or 128
+ *  capacity  number of slots of the store (may be 0 for encode-only use)
+ *  mem_budget_bytes  cap on device memory owned by the index (0 = none)   */
+typedef struct {
+    int32_t dim, bits1, bits2;
+    int32_t metric, layout, align;
+    int64_t capacity;
+    int64_t mem_budget_bytes;
+} lvq_config;
+
+/* Row format.  Each slot holds one row of row_bytes: a 32-byte header
+ *   [0]  float l        per-vector lower bound (Eq. 1)
+ *   [4]  float delta    first-level step (Eq. 2); 0 when u == l
+ *   [8]  float delta2   residual step delta / (2^B2 - 1); 0 without residual
+ *   [12] uint8 mean id  index of the mean the vector was encoded against (Def. 1)
+ *   [13] uint8 flags    bit 0: slot holds a stored vector
+ *   [16] uint32 insert epoch, [20] uint32 delete epoch (0xFFFFFFFF = live)
+ *   [24] uint64 external id
+ * then the first-level codes (little-endian fields of B1 bits by code
+ * position), zero padded to a multiple of align.  The residual codes of the
+ * same slot occupy resid_bytes in a separate array, by the same code
+ * positions.  lvq_encode writes zero store fields.  A vector rejected as
+ * non-finite is written as all-zero except l = NaN.                        */
+int lvq_row_format(const lvq_config *cfg, int32_t *row_bytes, int32_t *resid_bytes,
+                   int32_t *code_positions);
+
+/* Create an index on the current device.  means_host: n_means x dim float32,
+ * the centres of Def. 1 (n_means = 1 is plain LVQ with the global mean);
+ * 1 <= n_means <= 256, values finite.                                      */
+int lvq_create(const lvq_config *cfg, const float *means_host, int32_t n_means,
+               lvq_index **out);
+int lvq_destroy(lvq_index *index);
+
+/* Append means (M-LVQ re-estimation, Sec. 3.2); existing rows keep their
+ * mean ids.  *first_id_out receives the id of the first appended mean.
+ * Synchronises the device.                                                 */
+int lvq_set_means(lvq_index *index, const float *means_host, int32_t n_means,
+                  int32_t *first_id_out);
+
+/* Encode n vectors (Eq. 1-3, residual level, Def. 1) into caller buffers:
+ * rows_dev n x row_bytes, resid_dev n x resid_bytes (NULL when bits2 == 0).
+ * Rows are bit-identical to a binary32 evaluation with one rounding per
+ * operation.  Pure: the store is not touched.                              */
+int lvq_encode(lvq_index *index, const float *x_dev, int64_t n, uint8_t *rows_dev,
+               uint8_t *resid_dev, void *stream);
+
+/* Encode n vectors into free slots (a new insert epoch).  Slots are taken
+ * from the top of the free-slot stack: vector i receives the i-th slot
+ * popped; slots_out_dev (n int32) receives them.  ext_ids_dev (n uint64) may
+ * be NULL (external id = slot).  LVQ_ERR_CAPACITY if fewer than n slots are
+ * free (checked synchronously; nothing is written).                        */
+int lvq_insert(lvq_index *index, const float *x_dev, int64_t n, const uint64_t *ext_ids_dev,
+               int32_t *slots_out_dev, void *stream);
+
+/* Lazy delete (Sec. 2.2 / App. A, delete consolidation): tombstone n slots at
+ * a new epoch.  A slot that is out of range or not live sets LVQ_ERR_BAD_SLOT
+ * (sticky) and is skipped.                                                 */
+int lvq_delete(lvq_index *index, const int32_t *slots_dev, int64_t n, void *stream);
+
+/* Batched consolidation: every tombstoned slot whose delete epoch no
+ * in-flight query (lvq_distances / lvq_topk not yet complete) can still see
+ * is cleared and pushed on the free-slot stack, in descending slot order (so
+ * later inserts pop them in ascending order).  Synchronises `stream`;
+ * *n_freed_out (may be NULL) receives the number of slots freed.           */
+int lvq_consolidate(lvq_index *index, void *stream, int64_t *n_freed_out);
+
+/* Similarities of nq queries (q_dev nq x dim float32) to their candidate
+ * lists: CSR offsets_dev (nq+1 int64, offsets[0] = 0, offsets[nq] = total)
+ * and ids_dev (total int32 slots).  dist_dev (total float32, may be NULL when
+ * k > 0) receives one value per listed entry, computed also for tombstoned
+ * slots (lazy deletes are still traversed).  level LVQ_PRIMARY uses the first
+ * level, LVQ_FULL both levels (Sec. 2.3: first level during traversal,
+ * both to re-rank).  With k > 0 (k <= 1024) the best k entries of each list
+ * that are live at the call are written to topk_ids_dev / topk_dist_dev
+ * (nq x k), padded with slot -1 and the worst value (+inf for L2, -inf for
+ * IP).  Duplicate ids are scored once per entry.                           */
+int lvq_distances(lvq_index *index, const float *q_dev, int64_t nq, const int64_t *offsets_dev,
+                  const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev,
+                  int32_t k, int32_t *topk_ids_dev, float *topk_dist_dev, void *stream);
+
+/* Exhaustive top-k over every slot live at the call (Sec. 2.1 k-NN problem),
+ * for nq queries q_dev (nq x dim) of precision prec: LVQ_FP32 runs the FP32
+ * vector path; LVQ_BF16 / LVQ_FP16 take queries already in that type and run
+ * matrix-core (MFMA) products of queries and exactly converted integer codes
+ * with FP32 accumulation (first level only).  1 <= k <= 1024.  Output
+ * ids_dev / dist_dev nq x k, padded as for lvq_distances.                   */
+int lvq_topk(lvq_index *index, const void *q_dev, int32_t prec, int64_t nq, int32_t k,
+             int32_t level, int32_t *ids_dev, float *dist_dev, void *stream);
+
+/* Copy stored rows of n slots (slots_dev int32) into rows_dev / resid_dev. */
+int lvq_read_rows(lvq_index *index, const int32_t *slots_dev, int64_t n, uint8_t *rows_dev,
+                  uint8_t *resid_dev, void *stream);
+
+/* Store statistics (host values). */
+typedef struct {
+    int64_t capacity, free_slots, live_estimate, device_bytes;
+    int32_t n_means, row_bytes, resid_bytes, code_positions;
+    uint32_t epoch;
+} lvq_stats;
+int lvq_get_stats(lvq_index *index, lvq_stats *out);
+
+/* Measurement support.  While enabled, each launch of the main similarity
+ * kernel of lvq_distances / lvq_topk is bracketed by HIP events recorded on
+ * the call's stream.  lvq_kernel_time waits for those events and returns the
+ * summed kernel milliseconds and the number of launches since the previous
+ * read (or since enabling), then starts a new count.                       */
+int lvq_set_timing(lvq_index *index, int enable);
+int lvq_kernel_time(lvq_index *index, double *ms_out, int64_t *launches_out);
+
+/* Synchronise `stream` and return (then clear) the sticky kernel error. */
+int lvq_sync(lvq_index *index, void *stream);
+
+/* Column mean of n x dim float32 vectors (the global mean of Sec. 2.3),
+ * accumulated in binary64, rounded to float32.                            */
+int lvq_mean(const float *x_dev, int64_t n, int32_t dim, float *mean_out_dev, void *stream);
+
+/* k-means (Lloyd) for the M-LVQ centres (Sec. 3.2): start from the vectors at
+ * init_idx_host (k distinct indices, the seed's random draws), `iters`
+ * iterations of nearest-centre assignment and centroid update (an empty
+ * cluster keeps its centre).  means_out_dev k x dim float32.              */
+int lvq_kmeans(const float *x_dev, int64_t n, int32_t dim, int32_t k, const int64_t *init_idx_host,
+               int32_t iters, float *means_out_dev, void *stream);
+
+const char *lvq_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

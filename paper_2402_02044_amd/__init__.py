@@ -1,0 +1,315 @@
+"""MI355X (gfx950) LVQ library: Python binding of the C ABI in include/lvq.h.
+
+Locally-adaptive Vector Quantization after arXiv 2402.02044: encoding
+(Sec. 2.3, Eq. 1-3; two-level LVQ-B1xB2; multi-means Def. 1; Turbo layout
+Sec. 3.1) and similarities between float queries and LVQ codes (Sec. 3.2)
+over candidate lists and as an exhaustive top-k (Sec. 2.1).
+
+This module only marshals arguments: every step runs in the HIP kernels of
+``liblvq.so``.  Functions named ``lvq_*`` mirror the C entry points one to one
+(raw device pointers as ints, ``stream`` a hipStream_t as int, 0 = default).
+``Index`` is a convenience wrapper over torch tensors (PyTorch supplies device
+memory and streams).  There is no CPU fallback: importing fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblvq.so")
+
+LVQ_L2, LVQ_IP = 0, 1
+LVQ_SEQUENTIAL, LVQ_TURBO = 0, 1
+LVQ_PRIMARY, LVQ_FULL = 1, 2
+LVQ_FP32, LVQ_BF16, LVQ_FP16 = 0, 1, 2
+
+LVQ_OK = 0
+LVQ_ERR_INVALID_ARG = -1
+LVQ_ERR_UNSUPPORTED = -2
+LVQ_ERR_OOM = -3
+LVQ_ERR_CAPACITY = -4
+LVQ_ERR_DEVICE = -5
+LVQ_ERR_NONFINITE = -6
+LVQ_ERR_BAD_SLOT = -7
+
+EXPORTS = ["lvq_row_format", "lvq_create", "lvq_destroy", "lvq_set_means", "lvq_encode", "lvq_insert",
+           "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_topk", "lvq_read_rows",
+           "lvq_get_stats", "lvq_sync", "lvq_mean", "lvq_kmeans", "lvq_strerror", "lvq_set_timing",
+           "lvq_kernel_time"]
+
+
+class lvq_config(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("bits1", ctypes.c_int32), ("bits2", ctypes.c_int32),
+                ("metric", ctypes.c_int32), ("layout", ctypes.c_int32), ("align", ctypes.c_int32),
+                ("capacity", ctypes.c_int64), ("mem_budget_bytes", ctypes.c_int64)]
+
+
+class lvq_stats(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int64), ("free_slots", ctypes.c_int64),
+                ("live_estimate", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("n_means", ctypes.c_int32), ("row_bytes", ctypes.c_int32),
+                ("resid_bytes", ctypes.c_int32), ("code_positions", ctypes.c_int32),
+                ("epoch", ctypes.c_uint32)]
+
+
+class LVQError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (where, lvq_strerror(code), code))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblvq.so is not built (run __graft_entry__.build() or "
+                          "python paper_2402_02044_amd/build_lib.py); there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "lvq_row_format": [ctypes.POINTER(lvq_config), P, P, P],
+        "lvq_create": [ctypes.POINTER(lvq_config), P, i32, ctypes.POINTER(P)],
+        "lvq_destroy": [P],
+        "lvq_set_means": [P, P, i32, P],
+        "lvq_encode": [P, P, i64, P, P, P],
+        "lvq_insert": [P, P, i64, P, P, P],
+        "lvq_delete": [P, P, i64, P],
+        "lvq_consolidate": [P, P, P],
+        "lvq_distances": [P, P, i64, P, P, i64, i32, P, i32, P, P, P],
+        "lvq_topk": [P, P, i32, i64, i32, i32, P, P, P],
+        "lvq_read_rows": [P, P, i64, P, P, P],
+        "lvq_get_stats": [P, ctypes.POINTER(lvq_stats)],
+        "lvq_sync": [P, P],
+        "lvq_mean": [P, i64, i32, P, P],
+        "lvq_kmeans": [P, i64, i32, i32, P, i32, P, P],
+        "lvq_strerror": [ctypes.c_int],
+        "lvq_set_timing": [P, i32],
+        "lvq_kernel_time": [P, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name == "lvq_strerror" else ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def lvq_strerror(code: int) -> str:
+    return _lib.lvq_strerror(code).decode()
+
+
+def _chk(rc, where):
+    if rc != LVQ_OK:
+        raise LVQError(rc, where)
+    return rc
+
+
+# ---- one-to-one wrappers of the C entry points (raw pointers) -------------
+
+def lvq_row_format(cfg: lvq_config):
+    rb, rs, npos = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _chk(_lib.lvq_row_format(ctypes.byref(cfg), ctypes.byref(rb), ctypes.byref(rs), ctypes.byref(npos)),
+         "lvq_row_format")
+    return rb.value, rs.value, npos.value
+
+
+def lvq_create(cfg: lvq_config, means_host_ptr: int, n_means: int) -> int:
+    out = ctypes.c_void_p()
+    _chk(_lib.lvq_create(ctypes.byref(cfg), means_host_ptr, n_means, ctypes.byref(out)), "lvq_create")
+    return out.value
+
+
+def lvq_destroy(ix: int):
+    return _chk(_lib.lvq_destroy(ix), "lvq_destroy")
+
+
+def lvq_set_means(ix, means_host_ptr, n_means) -> int:
+    first = ctypes.c_int32()
+    _chk(_lib.lvq_set_means(ix, means_host_ptr, n_means, ctypes.byref(first)), "lvq_set_means")
+    return first.value
+
+
+def lvq_encode(ix, x, n, rows, resid, stream=0):
+    return _chk(_lib.lvq_encode(ix, x, n, rows, resid, stream), "lvq_encode")
+
+
+def lvq_insert(ix, x, n, ext_ids, slots_out, stream=0):
+    return _chk(_lib.lvq_insert(ix, x, n, ext_ids, slots_out, stream), "lvq_insert")
+
+
+def lvq_delete(ix, slots, n, stream=0):
+    return _chk(_lib.lvq_delete(ix, slots, n, stream), "lvq_delete")
+
+
+def lvq_consolidate(ix, stream=0) -> int:
+    freed = ctypes.c_int64()
+    _chk(_lib.lvq_consolidate(ix, stream, ctypes.byref(freed)), "lvq_consolidate")
+    return freed.value
+
+
+def lvq_distances(ix, q, nq, offsets, ids, total, level, dist, k, topk_ids, topk_dist, stream=0):
+    return _chk(_lib.lvq_distances(ix, q, nq, offsets, ids, total, level, dist, k, topk_ids, topk_dist,
+                                   stream), "lvq_distances")
+
+
+def lvq_topk(ix, q, prec, nq, k, level, ids, dist, stream=0):
+    return _chk(_lib.lvq_topk(ix, q, prec, nq, k, level, ids, dist, stream), "lvq_topk")
+
+
+def lvq_read_rows(ix, slots, n, rows, resid, stream=0):
+    return _chk(_lib.lvq_read_rows(ix, slots, n, rows, resid, stream), "lvq_read_rows")
+
+
+def lvq_get_stats(ix) -> lvq_stats:
+    st = lvq_stats()
+    _chk(_lib.lvq_get_stats(ix, ctypes.byref(st)), "lvq_get_stats")
+    return st
+
+
+def lvq_sync(ix, stream=0) -> int:
+    """Returns the sticky kernel error code (0 when none); raises nothing."""
+    return _lib.lvq_sync(ix, stream)
+
+
+def lvq_set_timing(ix, enable):
+    return _chk(_lib.lvq_set_timing(ix, int(enable)), "lvq_set_timing")
+
+
+def lvq_kernel_time(ix):
+    """(summed kernel milliseconds, launches) since the previous read."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _chk(_lib.lvq_kernel_time(ix, ctypes.byref(ms), ctypes.byref(n)), "lvq_kernel_time")
+    return ms.value, n.value
+
+
+def lvq_mean(x, n, dim, out, stream=0):
+    return _chk(_lib.lvq_mean(x, n, dim, out, stream), "lvq_mean")
+
+
+def lvq_kmeans(x, n, dim, k, init_idx_host_ptr, iters, out, stream=0):
+    return _chk(_lib.lvq_kmeans(x, n, dim, k, init_idx_host_ptr, iters, out, stream), "lvq_kmeans")
+
+
+# ---- torch convenience layer ------------------------------------------------
+
+def _stream(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _ptr(t):
+    return 0 if t is None else int(t.data_ptr())
+
+
+class Index:
+    """An LVQ store on the current GPU.  Tensors are torch CUDA tensors."""
+
+    def __init__(self, dim, bits1, bits2=0, metric=LVQ_IP, layout=LVQ_TURBO, align=32, capacity=0,
+                 means=None, mem_budget_bytes=0):
+        import numpy as np
+        self.cfg = lvq_config(dim, bits1, bits2, metric, layout, align, capacity, mem_budget_bytes)
+        self.row_bytes, self.resid_bytes, self.code_positions = lvq_row_format(self.cfg)
+        m = np.zeros((1, dim), np.float32) if means is None else np.ascontiguousarray(means, np.float32)
+        if m.ndim == 1:
+            m = m[None]
+        self._means = m
+        self.handle = lvq_create(self.cfg, m.ctypes.data, m.shape[0])
+        self.dim, self.bits1, self.bits2, self.metric = dim, bits1, bits2, metric
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lvq_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_means(self, means) -> int:
+        import numpy as np
+        m = np.ascontiguousarray(means, np.float32).reshape(-1, self.dim)
+        return lvq_set_means(self.handle, m.ctypes.data, m.shape[0])
+
+    def encode(self, x, stream=None):
+        import torch
+        n = x.shape[0]
+        rows = torch.empty((n, self.row_bytes), dtype=torch.uint8, device=x.device)
+        resid = torch.empty((n, self.resid_bytes), dtype=torch.uint8, device=x.device) if self.bits2 else None
+        lvq_encode(self.handle, _ptr(x), n, _ptr(rows), _ptr(resid), _stream(stream))
+        return rows, resid
+
+    def insert(self, x, ext_ids=None, stream=None):
+        import torch
+        n = x.shape[0]
+        slots = torch.empty(n, dtype=torch.int32, device=x.device)
+        lvq_insert(self.handle, _ptr(x), n, _ptr(ext_ids), _ptr(slots), _stream(stream))
+        return slots
+
+    def delete(self, slots, stream=None):
+        lvq_delete(self.handle, _ptr(slots), slots.shape[0], _stream(stream))
+
+    def consolidate(self, stream=None) -> int:
+        return lvq_consolidate(self.handle, _stream(stream))
+
+    def distances(self, q, offsets, ids, level=LVQ_PRIMARY, k=0, want_dist=True, stream=None):
+        import torch
+        nq = q.shape[0]
+        total = ids.shape[0]
+        dist = torch.empty(total, dtype=torch.float32, device=q.device) if want_dist or k == 0 else None
+        ti = td = None
+        if k > 0:
+            ti = torch.empty((nq, k), dtype=torch.int32, device=q.device)
+            td = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+        lvq_distances(self.handle, _ptr(q), nq, _ptr(offsets), _ptr(ids), total, level, _ptr(dist), k,
+                      _ptr(ti), _ptr(td), _stream(stream))
+        return dist, ti, td
+
+    def topk(self, q, k, level=LVQ_PRIMARY, stream=None):
+        import torch
+        prec = {torch.float32: LVQ_FP32, torch.bfloat16: LVQ_BF16, torch.float16: LVQ_FP16}[q.dtype]
+        nq = q.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int32, device=q.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+        lvq_topk(self.handle, _ptr(q), prec, nq, k, level, _ptr(ids), _ptr(dist), _stream(stream))
+        return ids, dist
+
+    def read_rows(self, slots, stream=None):
+        import torch
+        n = slots.shape[0]
+        rows = torch.empty((n, self.row_bytes), dtype=torch.uint8, device=slots.device)
+        resid = torch.empty((n, self.resid_bytes), dtype=torch.uint8, device=slots.device) if self.bits2 else None
+        lvq_read_rows(self.handle, _ptr(slots), n, _ptr(rows), _ptr(resid), _stream(stream))
+        return rows, resid
+
+    def stats(self) -> lvq_stats:
+        return lvq_get_stats(self.handle)
+
+    def sync(self, stream=None) -> int:
+        return lvq_sync(self.handle, _stream(stream))
+
+    def set_timing(self, enable=True):
+        lvq_set_timing(self.handle, enable)
+
+    def kernel_time(self):
+        return lvq_kernel_time(self.handle)
+
+
+def mean(x, stream=None):
+    import torch
+    out = torch.empty(x.shape[1], dtype=torch.float32, device=x.device)
+    lvq_mean(_ptr(x), x.shape[0], x.shape[1], _ptr(out), _stream(stream))
+    return out
+
+
+def kmeans(x, k, init_idx, iters=25, stream=None):
+    import numpy as np
+    import torch
+    idx = np.ascontiguousarray(init_idx, np.int64)
+    out = torch.empty((k, x.shape[1]), dtype=torch.float32, device=x.device)
+    lvq_kmeans(_ptr(x), x.shape[0], x.shape[1], k, idx.ctypes.data, iters, _ptr(out), _stream(stream))
+    return out

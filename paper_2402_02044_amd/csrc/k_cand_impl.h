@@ -1,0 +1,412 @@
+// k_cand_impl.h -- similarities between float queries and the stored LVQ rows
+// of per-query candidate lists (Sec. 3.2), with an optional fused per-list
+// top-k (Sec. 2.1; lazy deletes are scored but filtered, App. A).
+//
+// Arithmetic (binary32, FMA accumulation):
+//   IP  <q, x_hat> = c_m + l' sum(q) + Delta <q, c1> [+ Delta2 <q, c2>]
+//       with c_m = <q, mu_m> per query and mean, l' = l [- Delta/2 at FULL]
+//   L2  sum_p ((q - mu_m)_p - (l' + Delta c1_p [+ Delta2 c2_p]))^2   (direct
+//       form: no cancellation for near neighbours)
+//
+// Launch shape.  A workgroup of 256 lanes owns one candidate list at a time
+// (one list per workgroup, or a persistent loop popping lists from a work
+// counter in descending-length order).  A list's query data lives in LDS in a
+// bank-conflict-free layout; a group of G lanes scores one candidate: its
+// lanes fetch disjoint CH-byte pieces of the row (NCH pieces each, all issued
+// before any is consumed), decode nibbles/bytes with mask + byte conversion,
+// accumulate with FMAs, and reduce with DPP row operations.
+#pragma once
+
+#include "k_common.h"
+
+namespace lvq {
+
+template <int B1, int CH>
+struct CandGeom {
+    static constexpr int kWords = CH / 4;             // 32-bit words per piece
+    static constexpr int kSlots = CH * 8 / B1;        // code positions per piece
+    static constexpr int kF4 = kSlots / 4;            // float4 reads of q per piece
+};
+
+// residual bytes per piece for a residual of B2 bits
+template <int B1, int B2, int CH>
+struct ResGeom {
+    static constexpr int kBytes = B2 == 0 ? 0 : CH * 8 / B1 * B2 / 8;
+    static constexpr int kWords = kBytes / 4 > 0 ? kBytes / 4 : 1;
+};
+
+template <int N>
+struct Words {
+    uint32_t w[N];
+};
+
+template <int N>
+__device__ __forceinline__ Words<N> load_words(const uint8_t *p)
+{
+    Words<N> r;
+    if constexpr (N == 4) {
+        uint4 v = *reinterpret_cast<const uint4 *>(p);
+        r.w[0] = v.x; r.w[1] = v.y; r.w[2] = v.z; r.w[3] = v.w;
+    } else if constexpr (N == 8) {
+        uint4 v = *reinterpret_cast<const uint4 *>(p);
+        uint4 u = *reinterpret_cast<const uint4 *>(p + 16);
+        r.w[0] = v.x; r.w[1] = v.y; r.w[2] = v.z; r.w[3] = v.w;
+        r.w[4] = u.x; r.w[5] = u.y; r.w[6] = u.z; r.w[7] = u.w;
+    } else if constexpr (N == 2) {
+        uint2 v = *reinterpret_cast<const uint2 *>(p);
+        r.w[0] = v.x; r.w[1] = v.y;
+    } else {
+        for (int i = 0; i < N; ++i) r.w[i] = reinterpret_cast<const uint32_t *>(p)[i];
+    }
+    return r;
+}
+
+// Accumulators of one candidate.
+struct Acc {
+    float a_lo, a_hi;   // first level: low fields, high fields (x16 for 4-bit)
+    float r_lo, r_hi;   // residual level
+};
+
+// ---- IP: accumulate one first-level word and its residual ---------------
+// q: the 8 (B1 = 4) or 4 (B1 = 8) query values of the word's kernel slots.
+template <int B1, int B2>
+__device__ __forceinline__ void ip_word(uint32_t w, const float *q, const uint32_t *res, int wi, Acc &A)
+{
+    if constexpr (B1 == 4) {
+        const uint32_t lo = w & 0x0F0F0F0Fu, hi = w & 0xF0F0F0F0u;
+        A.a_lo = fmaf(q[0], ub<0>(lo), A.a_lo);
+        A.a_lo = fmaf(q[1], ub<1>(lo), A.a_lo);
+        A.a_lo = fmaf(q[2], ub<2>(lo), A.a_lo);
+        A.a_lo = fmaf(q[3], ub<3>(lo), A.a_lo);
+        A.a_hi = fmaf(q[4], ub<0>(hi), A.a_hi);
+        A.a_hi = fmaf(q[5], ub<1>(hi), A.a_hi);
+        A.a_hi = fmaf(q[6], ub<2>(hi), A.a_hi);
+        A.a_hi = fmaf(q[7], ub<3>(hi), A.a_hi);
+        if constexpr (B2 == 8) {
+            const uint32_t r0 = res[2 * wi], r1 = res[2 * wi + 1];
+            A.r_lo = fmaf(q[0], ub<0>(r0), A.r_lo);
+            A.r_lo = fmaf(q[1], ub<2>(r0), A.r_lo);
+            A.r_lo = fmaf(q[2], ub<0>(r1), A.r_lo);
+            A.r_lo = fmaf(q[3], ub<2>(r1), A.r_lo);
+            A.r_lo = fmaf(q[4], ub<1>(r0), A.r_lo);
+            A.r_lo = fmaf(q[5], ub<3>(r0), A.r_lo);
+            A.r_lo = fmaf(q[6], ub<1>(r1), A.r_lo);
+            A.r_lo = fmaf(q[7], ub<3>(r1), A.r_lo);
+        } else if constexpr (B2 == 4) {
+            const uint32_t r = res[wi];
+            const uint32_t rl = r & 0x0F0F0F0Fu, rh = r & 0xF0F0F0F0u;
+            A.r_lo = fmaf(q[0], ub<0>(rl), A.r_lo);
+            A.r_lo = fmaf(q[1], ub<1>(rl), A.r_lo);
+            A.r_lo = fmaf(q[2], ub<2>(rl), A.r_lo);
+            A.r_lo = fmaf(q[3], ub<3>(rl), A.r_lo);
+            A.r_hi = fmaf(q[4], ub<0>(rh), A.r_hi);
+            A.r_hi = fmaf(q[5], ub<1>(rh), A.r_hi);
+            A.r_hi = fmaf(q[6], ub<2>(rh), A.r_hi);
+            A.r_hi = fmaf(q[7], ub<3>(rh), A.r_hi);
+        }
+    } else {
+        A.a_lo = fmaf(q[0], ub<0>(w), A.a_lo);
+        A.a_lo = fmaf(q[1], ub<1>(w), A.a_lo);
+        A.a_lo = fmaf(q[2], ub<2>(w), A.a_lo);
+        A.a_lo = fmaf(q[3], ub<3>(w), A.a_lo);
+        if constexpr (B2 == 8) {
+            const uint32_t r = res[wi];
+            A.r_lo = fmaf(q[0], ub<0>(r), A.r_lo);
+            A.r_lo = fmaf(q[1], ub<1>(r), A.r_lo);
+            A.r_lo = fmaf(q[2], ub<2>(r), A.r_lo);
+            A.r_lo = fmaf(q[3], ub<3>(r), A.r_lo);
+        } else if constexpr (B2 == 4) {
+            const uint32_t h = (res[wi >> 1] >> (16 * (wi & 1))) & 0xFFFFu;
+            const uint32_t rl = h & 0x0F0Fu, rh = h & 0xF0F0u;
+            A.r_lo = fmaf(q[0], ub<0>(rl), A.r_lo);
+            A.r_lo = fmaf(q[2], ub<1>(rl), A.r_lo);
+            A.r_hi = fmaf(q[1], ub<0>(rh), A.r_hi);
+            A.r_hi = fmaf(q[3], ub<1>(rh), A.r_hi);
+        }
+    }
+}
+
+// ---- L2: accumulate one first-level word (direct form) --------------------
+// q: (q - mu_m) at the word's kernel slots; m: padding mask or nullptr.
+struct L2Row {
+    float lp;      // l' = l [- Delta/2]
+    float dl;      // Delta
+    float dl16;    // Delta / 16 (high nibbles arrive multiplied by 16)
+    float d2;      // Delta2 (FULL) or 0
+    float d216;    // Delta2 / 16
+};
+
+template <bool MASK, bool RES>
+__device__ __forceinline__ void l2_acc(float qv, float c1, float s1, float c2, float s2,
+                                       const L2Row &R, float mk, float &acc)
+{
+    float x = fmaf(s1, c1, R.lp);
+    if constexpr (RES) x = fmaf(s2, c2, x);
+    float t = qv - x;
+    if constexpr (MASK) t *= mk;
+    acc = fmaf(t, t, acc);
+}
+
+template <int B1, int B2, bool MASK>
+__device__ __forceinline__ void l2_word(uint32_t w, const float *q, const float *m, const uint32_t *res,
+                                        int wi, const L2Row &R, float &acc)
+{
+    if constexpr (B1 == 4) {
+        const uint32_t lo = w & 0x0F0F0F0Fu, hi = w & 0xF0F0F0F0u;
+        float c2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        float s2lo = R.d2, s2hi = R.d2;
+        if constexpr (B2 == 8) {
+            const uint32_t r0 = res[2 * wi], r1 = res[2 * wi + 1];
+            c2[0] = ub<0>(r0); c2[1] = ub<2>(r0); c2[2] = ub<0>(r1); c2[3] = ub<2>(r1);
+            c2[4] = ub<1>(r0); c2[5] = ub<3>(r0); c2[6] = ub<1>(r1); c2[7] = ub<3>(r1);
+        } else if constexpr (B2 == 4) {
+            const uint32_t r = res[wi];
+            const uint32_t rl = r & 0x0F0F0F0Fu, rh = r & 0xF0F0F0F0u;
+            c2[0] = ub<0>(rl); c2[1] = ub<1>(rl); c2[2] = ub<2>(rl); c2[3] = ub<3>(rl);
+            c2[4] = ub<0>(rh); c2[5] = ub<1>(rh); c2[6] = ub<2>(rh); c2[7] = ub<3>(rh);
+            s2hi = R.d216;
+        }
+        l2_acc<MASK, (B2 != 0)>(q[0], ub<0>(lo), R.dl, c2[0], s2lo, R, MASK ? m[0] : 1.f, acc);
+        l2_acc<MASK, (B2 != 0)>(q[1], ub<1>(lo), R.dl, c2[1], s2lo, R, MASK ? m[1] : 1.f, acc);
+        l2_acc<MASK, (B2 != 0)>(q[2], ub<2>(lo), R.dl, c2[2], s2lo, R, MASK ? m[2] : 1.f, acc);
+        l2_acc<MASK, (B2 != 0)>(q[3], ub<3>(lo), R.dl, c2[3], s2lo, R, MASK ? m[3] : 1.f, acc);
+        l2_acc<MASK, (B2 != 0)>(q[4], ub<0>(hi), R.dl16, c2[4], s2hi, R, MASK ? m[4] : 1.f, acc);
+        l2_acc<MASK, (B2 != 0)>(q[5], ub<1>(hi), R.dl16, c2[5], s2hi, R, MASK ? m[5] : 1.f, acc);
+        l2_acc<MASK, (B2 != 0)>(q[6], ub<2>(hi), R.dl16, c2[6], s2hi, R, MASK ? m[6] : 1.f, acc);
+        l2_acc<MASK, (B2 != 0)>(q[7], ub<3>(hi), R.dl16, c2[7], s2hi, R, MASK ? m[7] : 1.f, acc);
+    } else {
+        float c2[4] = {0, 0, 0, 0};
+        float s2[4] = {R.d2, R.d2, R.d2, R.d2};
+        if constexpr (B2 == 8) {
+            const uint32_t r = res[wi];
+            c2[0] = ub<0>(r); c2[1] = ub<1>(r); c2[2] = ub<2>(r); c2[3] = ub<3>(r);
+        } else if constexpr (B2 == 4) {
+            const uint32_t h = (res[wi >> 1] >> (16 * (wi & 1))) & 0xFFFFu;
+            const uint32_t rl = h & 0x0F0Fu, rh = h & 0xF0F0u;
+            c2[0] = ub<0>(rl); c2[2] = ub<1>(rl); c2[1] = ub<0>(rh); c2[3] = ub<1>(rh);
+            s2[1] = R.d216; s2[3] = R.d216;
+        }
+        l2_acc<MASK, (B2 != 0)>(q[0], ub<0>(w), R.dl, c2[0], s2[0], R, MASK ? m[0] : 1.f, acc);
+        l2_acc<MASK, (B2 != 0)>(q[1], ub<1>(w), R.dl, c2[1], s2[1], R, MASK ? m[1] : 1.f, acc);
+        l2_acc<MASK, (B2 != 0)>(q[2], ub<2>(w), R.dl, c2[2], s2[2], R, MASK ? m[2] : 1.f, acc);
+        l2_acc<MASK, (B2 != 0)>(q[3], ub<3>(w), R.dl, c2[3], s2[3], R, MASK ? m[3] : 1.f, acc);
+    }
+}
+
+// LDS query table layout: for a table of kpos floats split into pieces of
+// kSlots slots, the r-th float4 of piece u is stored at float4 index
+// r * npieces + u, so the lanes of a group (consecutive pieces) read
+// consecutive float4s.
+template <int B1, int CH>
+__device__ __forceinline__ int qtab_index(int s, int npieces)
+{
+    using Geo = CandGeom<B1, CH>;
+    const int u = s / Geo::kSlots, w = s % Geo::kSlots;
+    return ((w >> 2) * npieces + u) * 4 + (w & 3);
+}
+
+template <int B1, int B2, int METRIC, bool MULTI, bool MASK, int G, int CH, int NCH>
+__global__ __launch_bounds__(256) void k_cand(CandArgs a)
+{
+    using Geo = CandGeom<B1, CH>;
+    using RGeo = ResGeom<B1, B2, CH>;
+    constexpr int kPairsPerWave = 64 / G;
+    constexpr int kPairsPerBlock = 4 * kPairsPerWave;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int grp = lane / G;
+    const int g = lane % G;
+
+    const int npieces = a.kchunks * 16 / CH;
+    const int ntab = (METRIC == LVQ_L2 && MULTI) ? a.n_means : 1;
+    float *qtab = reinterpret_cast<float *>(smem);
+    float *mtab = qtab + (size_t)ntab * a.kpos;                 // mask (L2, MASK)
+    float *cmt = mtab + (MASK ? a.kpos : 0);                   // c_m (IP)
+    const int cm_n = METRIC == LVQ_IP ? a.n_means : 0;
+    uint64_t *keys = reinterpret_cast<uint64_t *>(cmt + ((cm_n + 1) & ~1));
+    __shared__ int s_item;
+    constexpr int kCap = 2048;
+
+    for (int iter = 0;; ++iter) {
+        int item;
+        if (a.queue) {
+            __syncthreads();
+            if (tid == 0) s_item = atomicAdd(a.queue, 1);
+            __syncthreads();
+            item = s_item;
+        } else {
+            item = iter == 0 ? (int)blockIdx.x : (int)a.nq;
+        }
+        if (item >= a.nq) break;
+        const int64_t list = a.order ? a.order[item] : item;
+        int64_t e0 = a.offsets[list], e1 = a.offsets[list + 1];
+        if (e0 < 0 || e1 < e0 || e1 > a.total) {
+            if (tid == 0) atomicOr(a.err, kErrBadOffsets);
+            e1 = e0 = 0;
+        }
+
+        // ---- per-list query tables in LDS
+        __syncthreads();
+        const float *qk = a.qk + list * a.kpos;
+        for (int t = 0; t < ntab; ++t)
+            for (int s = tid; s < a.kpos; s += 256) {
+                float v = qk[s];
+                if (METRIC == LVQ_L2) v -= a.muk[(int64_t)t * a.kpos + s];
+                qtab[(size_t)t * a.kpos + qtab_index<B1, CH>(s, npieces)] = v;
+            }
+        if (MASK)
+            for (int s = tid; s < a.kpos; s += 256) mtab[qtab_index<B1, CH>(s, npieces)] = a.kmask[s];
+        for (int m = tid; m < cm_n; m += 256) cmt[m] = a.cm[list * a.n_means + m];
+        __syncthreads();
+        const float qsum = METRIC == LVQ_IP ? a.qsum[list] : 0.0f;
+
+        int nbuf = 0;        // keys held in the LDS buffer (block-uniform)
+        const int k = a.k;
+        for (int64_t base = e0; base < e1; base += kPairsPerBlock) {
+            const int64_t e = base + wave * kPairsPerWave + grp;
+            const bool valid = e < e1;
+            int32_t slot = valid ? a.ids[e] : 0;
+            bool in_range = slot >= 0 && (int64_t)slot < a.capacity;
+            if (valid && !in_range && g == 0) atomicOr(a.err, kErrBadSlot);
+            const bool work = valid && in_range;
+            const uint8_t *row = a.rows + (int64_t)(work ? slot : 0) * a.row_bytes;
+            const uint8_t *res = B2 ? a.resid + (int64_t)(work ? slot : 0) * a.resid_bytes : nullptr;
+
+            float4 hdr = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (work) hdr = *reinterpret_cast<const float4 *>(row);
+            const float l = hdr.x, dl = hdr.y, dl2 = hdr.z;
+            const int mid = (int)(__float_as_uint(hdr.w) & 0xFFu);
+
+            Acc A{0.f, 0.f, 0.f, 0.f};
+            float l2acc = 0.0f;
+            L2Row R;
+            if constexpr (METRIC == LVQ_L2) {
+                R.lp = B2 ? l - 0.5f * dl : l;
+                R.dl = dl;
+                R.dl16 = dl * 0.0625f;
+                R.d2 = B2 ? dl2 : 0.0f;
+                R.d216 = dl2 * 0.0625f;
+            }
+            const float *tq = qtab + ((METRIC == LVQ_L2 && MULTI) ? (size_t)(mid < a.n_means ? mid : 0) * a.kpos : 0);
+
+            for (int p0 = 0; p0 < npieces; p0 += G * NCH) {
+                Words<Geo::kWords> wv[NCH];
+                Words<RGeo::kWords> rv[NCH];
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const int u = p0 + c * G + g;
+                    if (work && u < npieces) {
+                        wv[c] = load_words<Geo::kWords>(row + kHeaderBytes + u * CH);
+                        if constexpr (B2 != 0) rv[c] = load_words<RGeo::kWords>(res + u * RGeo::kBytes);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < Geo::kWords; ++i) wv[c].w[i] = 0;
+#pragma unroll
+                        for (int i = 0; i < RGeo::kWords; ++i) rv[c].w[i] = 0;
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const int u = p0 + c * G + g;
+                    if (u >= npieces) continue;
+                    float qv[Geo::kSlots];
+                    float mv[MASK ? Geo::kSlots : 1];
+#pragma unroll
+                    for (int r = 0; r < Geo::kF4; ++r) {
+                        float4 f = reinterpret_cast<const float4 *>(tq)[r * npieces + u];
+                        qv[4 * r] = f.x; qv[4 * r + 1] = f.y; qv[4 * r + 2] = f.z; qv[4 * r + 3] = f.w;
+                        if constexpr (MASK) {
+                            float4 mm = reinterpret_cast<const float4 *>(mtab)[r * npieces + u];
+                            mv[4 * r] = mm.x; mv[4 * r + 1] = mm.y; mv[4 * r + 2] = mm.z; mv[4 * r + 3] = mm.w;
+                        }
+                    }
+                    constexpr int kQW = B1 == 4 ? 8 : 4;   // query values per word
+#pragma unroll
+                    for (int wi = 0; wi < Geo::kWords; ++wi) {
+                        if constexpr (METRIC == LVQ_IP)
+                            ip_word<B1, B2>(wv[c].w[wi], qv + kQW * wi, rv[c].w, wi, A);
+                        else
+                            l2_word<B1, B2, MASK>(wv[c].w[wi], qv + kQW * wi, MASK ? mv + kQW * wi : nullptr,
+                                                  rv[c].w, wi, R, l2acc);
+                    }
+                }
+            }
+
+            float score;
+            if constexpr (METRIC == LVQ_IP) {
+                float a1 = fmaf(A.a_hi, 0.0625f, A.a_lo);
+                float a2 = fmaf(A.r_hi, 0.0625f, A.r_lo);
+                a1 = group_sum<G>(a1);
+                if constexpr (B2 != 0) a2 = group_sum<G>(a2);
+                const float lp = B2 ? l - 0.5f * dl : l;
+                const float cmv = cmt[mid < a.n_means ? mid : 0];
+                score = fmaf(lp, qsum, cmv);
+                score = fmaf(dl, a1, score);
+                if constexpr (B2 != 0) score = fmaf(dl2, a2, score);
+            } else {
+                score = group_sum<G>(l2acc);
+            }
+            if (valid && !in_range) score = __uint_as_float(0x7FC00000u);
+
+            if (valid && g == 0) {
+                if (a.dist) a.dist[e] = score;
+            }
+            if (k > 0) {
+                if (valid && g == 0) {
+                    uint64_t key = kNoKey;
+                    if (work) {
+                        uint2 ep = *reinterpret_cast<const uint2 *>(row + 16);
+                        const bool live = ((__float_as_uint(hdr.w) >> 8) & 1u) && ep.x <= a.epoch &&
+                                          a.epoch < ep.y;
+                        if (live) key = make_key(score, slot, LVQ_IP == METRIC ? LVQ_IP : LVQ_L2);
+                    }
+                    keys[nbuf + (int)(e - base)] = key;
+                }
+                nbuf += (int)min<int64_t>(kPairsPerBlock, e1 - base);
+                // compact the buffer when the next block of pairs might not fit
+                if (nbuf + kPairsPerBlock > kCap && base + kPairsPerBlock < e1) {
+                    __syncthreads();
+                    if (wave == 0) {
+                        uint64_t *tmp = keys + kCap;   // k entries of scratch
+                        int got = wave_select_smallest(keys, nbuf, k, tmp);
+                        for (int i = lane; i < k; i += 64) keys[i] = i < got ? tmp[i] : kNoKey;
+                    }
+                    __syncthreads();
+                    nbuf = k;
+                }
+            }
+        }
+
+        if (k > 0) {
+            __syncthreads();
+            if (wave == 0) {
+                uint64_t *tmp = keys + kCap;
+                int got = wave_select_smallest(keys, nbuf, k, tmp);
+                for (int i = lane; i < k; i += 64) {
+                    int32_t sid = -1;
+                    float sv = METRIC == LVQ_L2 ? __uint_as_float(0x7F800000u) : __uint_as_float(0xFF800000u);
+                    if (i < got) {
+                        sid = (int32_t)(uint32_t)tmp[i];
+                        sv = key_score(tmp[i], METRIC);
+                    }
+                    a.topk_ids[list * k + i] = sid;
+                    a.topk_dist[list * k + i] = sv;
+                }
+            }
+        }
+    }
+}
+
+// LDS bytes of one k_cand launch
+inline size_t cand_lds_bytes_impl(int kpos, int ntab, bool mask, int n_means_ip, int k)
+{
+    size_t b = (size_t)ntab * kpos * 4 + (mask ? (size_t)kpos * 4 : 0) + (size_t)((n_means_ip + 1) & ~1) * 4;
+    b = (b + 15) & ~(size_t)15;
+    if (k > 0) b += (size_t)(2048 + k) * 8;
+    return b;
+}
+
+}  // namespace lvq

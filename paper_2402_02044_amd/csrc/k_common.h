@@ -1,0 +1,110 @@
+// k_common.h -- device helpers shared by the similarity kernels.
+#pragma once
+
+#include "lvq_internal.h"
+
+namespace lvq {
+
+// Byte k of a 32-bit word as float; the backend selects v_cvt_f32_ubyte{k}.
+template <int K>
+__device__ __forceinline__ float ub(uint32_t w)
+{
+    return (float)((w >> (8 * K)) & 0xFFu);
+}
+
+// Sum over aligned groups of G lanes (G <= 16) with DPP row operations; every
+// lane of the group ends with the bitwise-identical total.
+template <int G>
+__device__ __forceinline__ float group_sum(float v)
+{
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group size");
+    if (G >= 2)  // quad_perm [1,0,3,2]
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+    if (G >= 4)  // quad_perm [2,3,0,1]
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+    if (G >= 8)  // row_half_mirror
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+    if (G >= 16)  // row_mirror
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
+    return v;
+}
+
+// Ranking key: the k best entries are the k smallest keys.  High word: the
+// score mapped to an order-preserving unsigned integer (ascending for L2,
+// descending for IP, NaN last); low word: the slot (ties to the lower slot).
+__device__ __forceinline__ uint32_t score_order(float s, int metric)
+{
+    if (s != s) return 0xFFFFFFFFu;
+    uint32_t u = __float_as_uint(metric == LVQ_IP ? -s : s);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ uint64_t make_key(float s, int32_t slot, int metric)
+{
+    return ((uint64_t)score_order(s, metric) << 32) | (uint32_t)slot;
+}
+
+constexpr uint64_t kNoKey = ~0ull;
+
+__device__ __forceinline__ float key_score(uint64_t key, int metric)
+{
+    uint32_t u = (uint32_t)(key >> 32);
+    uint32_t b = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+    float v = __uint_as_float(b);
+    return metric == LVQ_IP ? -v : v;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int o)
+{
+    uint32_t lo = __shfl_xor((uint32_t)v, o, 64);
+    uint32_t hi = __shfl_xor((uint32_t)(v >> 32), o, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        uint64_t w = shfl_xor_u64(v, o);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i32(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One wavefront selects the k smallest keys of keys[0..n) (LDS) in ascending
+// order into out[0..k); entries equal to a selected key are taken together
+// (duplicates of an entry are kept as separate results, as many as fit).
+// Returns the number of keys written (< k when fewer than k are valid).
+// keys[] is consumed (selected entries are overwritten with kNoKey).
+__device__ __forceinline__ int wave_select_smallest(uint64_t *keys, int n, int k, uint64_t *out)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t mine = kNoKey;
+    for (int i = lane; i < n; i += 64) mine = keys[i] < mine ? keys[i] : mine;
+    int r = 0;
+    while (r < k) {
+        uint64_t best = wave_min_u64(mine);
+        if (best == kNoKey) break;
+        int cnt = 0;
+        if (mine == best) {
+            for (int i = lane; i < n; i += 64)
+                if (keys[i] == best) {
+                    keys[i] = kNoKey;
+                    ++cnt;
+                }
+            mine = kNoKey;
+            for (int i = lane; i < n; i += 64) mine = keys[i] < mine ? keys[i] : mine;
+        }
+        cnt = wave_sum_i32(cnt);
+        for (int c = 0; c < cnt && r < k; ++c, ++r)
+            if (lane == 0) out[r] = best;
+    }
+    return r;
+}
+
+}  // namespace lvq

@@ -1,0 +1,809 @@
+// lvq_host.hip -- host side of the C ABI declared in include/lvq.h: argument
+// checks, the device store, per-stream workspaces, epochs, and kernel
+// dispatch.  Every computation of the path runs in the kernels; this file
+// only validates, allocates and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "lvq_internal.h"
+
+namespace lvq {
+
+bool make_format(const lvq_config &c, Format *f)
+{
+    if (c.dim < 1 || c.dim > 8192) return false;
+    if (c.bits1 != 4 && c.bits1 != 8) return false;
+    if (c.bits2 != 0 && c.bits2 != 4 && c.bits2 != 8) return false;
+    if (c.layout != LVQ_SEQUENTIAL && c.layout != LVQ_TURBO) return false;
+    if (c.align != 32 && c.align != 64 && c.align != 128) return false;
+    if (c.metric != LVQ_L2 && c.metric != LVQ_IP) return false;
+    auto up = [](int v, int m) { return (v + m - 1) / m * m; };
+    int blk = c.layout == LVQ_TURBO ? (c.bits1 == 4 ? 128 : 64) : (c.bits1 == 4 ? 8 : 4);
+    f->dim = c.dim;
+    f->bits1 = c.bits1;
+    f->bits2 = c.bits2;
+    f->layout = c.layout;
+    f->align = c.align;
+    f->npos = up(c.dim, blk);
+    f->code_bytes = f->npos * c.bits1 / 8;
+    f->row_bytes = up(kHeaderBytes + f->code_bytes, c.align);
+    f->resid_bytes = c.bits2 ? up(f->npos * c.bits2 / 8, c.align) : 0;
+    f->kchunks = up(f->code_bytes, 16) / 16;
+    f->kpos = f->kchunks * 16 * 8 / c.bits1;
+    return true;
+}
+
+// dimension held at code position p (the row format of lvq.h)
+static int pos_dim(const Format &f, int p)
+{
+    if (p >= f.npos) return -1;
+    int dim = p;
+    if (f.layout == LVQ_TURBO) {
+        const int per = 32 / f.bits1, blk = f.bits1 == 4 ? 128 : 64;
+        const int b = p / blk, r = p % blk, w = r / per, k = r % per;
+        dim = b * blk + 16 * k + w;
+    }
+    return dim < f.dim ? dim : -1;
+}
+
+void kernel_order_dims(const Format &f, int32_t *kdim)
+{
+    for (int s = 0; s < f.kpos; ++s) {
+        int p = s;
+        if (f.bits1 == 4) {
+            const int w = s / 8, r = s % 8;
+            p = 8 * w + (r < 4 ? 2 * r : 2 * (r - 4) + 1);
+        }
+        kdim[s] = pos_dim(f, p);
+    }
+}
+
+}  // namespace lvq
+
+using namespace lvq;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Workspace {
+    DevBuf qk, qsum, cm, order, queue, part, q16;
+};
+
+struct InFlight {
+    uint32_t epoch;
+    hipEvent_t ev;
+};
+
+}  // namespace
+
+struct lvq_index {
+    lvq_config cfg;
+    Format f;
+    int device = 0;
+    int n_cu = 256;
+    size_t lds_max = 65536;    // LDS bytes one workgroup may allocate
+    int n_means = 0;
+    // device store
+    DevBuf means, means_t, muk, kmask, kdim, pos_dim, rows, resid, stack, err, scratch;
+    int64_t free_top = 0;   // host view of the free-slot stack top
+    int64_t fresh = 0;      // never-used slots at the bottom of the stack
+    uint32_t epoch = 1;
+    int64_t device_bytes = 0;
+    std::map<hipStream_t, Workspace> ws;
+    std::deque<InFlight> inflight;
+    std::vector<hipEvent_t> spare_events;
+    hipEvent_t update_ev = nullptr;   // recorded after the latest store update
+    hipStream_t update_stream = nullptr;
+    bool have_update = false;
+    std::mutex mu;
+    int cand_shape[2][2] = {{-1, -1}, {-1, -1}};   // tuned [level][topk]
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
+};
+
+namespace {
+
+int map_hip(hipError_t e)
+{
+    if (e == hipSuccess) return LVQ_OK;
+    if (e == hipErrorOutOfMemory) return LVQ_ERR_OOM;
+    return LVQ_ERR_DEVICE;
+}
+
+#define LVQ_HIP(x)                         \
+    do {                                   \
+        hipError_t e_ = (x);               \
+        if (e_ != hipSuccess) return map_hip(e_); \
+    } while (0)
+
+int dev_alloc(lvq_index *ix, DevBuf &b, size_t bytes)
+{
+    if (b.bytes >= bytes && b.p) return LVQ_OK;
+    if (bytes == 0) bytes = 16;
+    const int64_t grow = (int64_t)bytes - (int64_t)b.bytes;
+    if (ix->cfg.mem_budget_bytes > 0 && ix->device_bytes + grow > ix->cfg.mem_budget_bytes)
+        return LVQ_ERR_OOM;
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return LVQ_ERR_OOM;
+    if (b.p) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(b.p);
+    }
+    ix->device_bytes += grow;
+    b.p = p;
+    b.bytes = bytes;
+    return LVQ_OK;
+}
+
+void dev_free(lvq_index *ix, DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    ix->device_bytes -= (int64_t)b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <class T>
+T *P(DevBuf &b)
+{
+    return reinterpret_cast<T *>(b.p);
+}
+
+bool finite_host(const float *v, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+// Rebuild the device means tables for ids [0, n_means).
+int upload_means(lvq_index *ix, const std::vector<float> &all)
+{
+    const Format &f = ix->f;
+    const int M = ix->n_means, d = f.dim;
+    std::vector<float> mt((size_t)d * M), mk((size_t)M * f.kpos, 0.0f);
+    std::vector<int32_t> kd(f.kpos);
+    kernel_order_dims(f, kd.data());
+    for (int m = 0; m < M; ++m)
+        for (int j = 0; j < d; ++j) mt[(size_t)j * M + m] = all[(size_t)m * d + j];
+    for (int m = 0; m < M; ++m)
+        for (int s = 0; s < f.kpos; ++s)
+            if (kd[s] >= 0) mk[(size_t)m * f.kpos + s] = all[(size_t)m * d + kd[s]];
+    int rc;
+    if ((rc = dev_alloc(ix, ix->means, sizeof(float) * (size_t)kMaxMeans * d))) return rc;
+    if ((rc = dev_alloc(ix, ix->means_t, sizeof(float) * (size_t)kMaxMeans * d))) return rc;
+    if ((rc = dev_alloc(ix, ix->muk, sizeof(float) * (size_t)kMaxMeans * f.kpos))) return rc;
+    LVQ_HIP(hipMemcpy(ix->means.p, all.data(), sizeof(float) * (size_t)M * d, hipMemcpyHostToDevice));
+    LVQ_HIP(hipMemcpy(ix->means_t.p, mt.data(), sizeof(float) * mt.size(), hipMemcpyHostToDevice));
+    LVQ_HIP(hipMemcpy(ix->muk.p, mk.data(), sizeof(float) * mk.size(), hipMemcpyHostToDevice));
+    return LVQ_OK;
+}
+
+Workspace &workspace(lvq_index *ix, hipStream_t s) { return ix->ws[s]; }
+
+// Make work on `s` wait for the latest store update issued on another stream.
+int order_after_updates(lvq_index *ix, hipStream_t s)
+{
+    if (ix->have_update && ix->update_stream != s) LVQ_HIP(hipStreamWaitEvent(s, ix->update_ev, 0));
+    return LVQ_OK;
+}
+
+int note_update(lvq_index *ix, hipStream_t s)
+{
+    LVQ_HIP(hipEventRecord(ix->update_ev, s));
+    ix->update_stream = s;
+    ix->have_update = true;
+    return LVQ_OK;
+}
+
+int note_query(lvq_index *ix, hipStream_t s, uint32_t epoch)
+{
+    hipEvent_t ev;
+    if (!ix->spare_events.empty()) {
+        ev = ix->spare_events.back();
+        ix->spare_events.pop_back();
+    } else {
+        LVQ_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    LVQ_HIP(hipEventRecord(ev, s));
+    ix->inflight.push_back({epoch, ev});
+    // retire completed entries from the front
+    while (!ix->inflight.empty() && hipEventQuery(ix->inflight.front().ev) == hipSuccess) {
+        ix->spare_events.push_back(ix->inflight.front().ev);
+        ix->inflight.pop_front();
+    }
+    return LVQ_OK;
+}
+
+// Bracket the main kernel with events when timing is enabled.
+int timing_begin(lvq_index *ix, hipStream_t s)
+{
+    if (!ix->timing) return LVQ_OK;
+    hipEvent_t a, b;
+    LVQ_HIP(hipEventCreate(&a));
+    LVQ_HIP(hipEventCreate(&b));
+    LVQ_HIP(hipEventRecord(a, s));
+    ix->tev.push_back({a, b});
+    return LVQ_OK;
+}
+
+int timing_end(lvq_index *ix, hipStream_t s)
+{
+    if (!ix->timing || ix->tev.empty()) return LVQ_OK;
+    LVQ_HIP(hipEventRecord(ix->tev.back().second, s));
+    return LVQ_OK;
+}
+
+int prep_queries(lvq_index *ix, Workspace &w, const float *q, int64_t nq, hipStream_t s)
+{
+    const Format &f = ix->f;
+    int rc;
+    if ((rc = dev_alloc(ix, w.qk, sizeof(float) * (size_t)std::max<int64_t>(nq, 1) * f.kpos))) return rc;
+    if ((rc = dev_alloc(ix, w.qsum, sizeof(float) * (size_t)std::max<int64_t>(nq, 1)))) return rc;
+    if ((rc = dev_alloc(ix, w.cm, sizeof(float) * (size_t)std::max<int64_t>(nq, 1) * ix->n_means))) return rc;
+    PrepArgs pa;
+    pa.q = q;
+    pa.nq = nq;
+    pa.dim = f.dim;
+    pa.kpos = f.kpos;
+    pa.n_means = ix->n_means;
+    pa.metric = ix->cfg.metric;
+    pa.kdim = P<int32_t>(ix->kdim);
+    pa.means = P<float>(ix->means);
+    pa.qk = P<float>(w.qk);
+    pa.qsum = P<float>(w.qsum);
+    pa.cm = P<float>(w.cm);
+    LVQ_HIP(launch_prep(pa, s));
+    return LVQ_OK;
+}
+
+// Default tile shape: the instantiated shape whose round covers the code
+// bytes with the least waste, preferring more lanes per candidate.
+int default_shape(const Format &f, void *(*lookup)(int, int, int), int bits2, int variant)
+{
+    const int bytes = f.kchunks * 16;
+    int best = -1;
+    double best_cost = 1e30;
+    for (int i = 0; i < num_tile_shapes(); ++i) {
+        if (!lookup(bits2, variant, i)) continue;
+        TileShape t = tile_shape(i);
+        const int round = t.g * t.ch * t.nch;
+        const int rounds = (bytes + round - 1) / round;
+        const double waste = (double)rounds * round / bytes;
+        const double cost = waste * 16.0 / t.g + (rounds > 1 ? 0.5 * rounds : 0.0);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = i;
+        }
+    }
+    return best;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lvq_strerror(int code)
+{
+    switch (code) {
+    case LVQ_OK: return "ok";
+    case LVQ_ERR_INVALID_ARG: return "invalid argument";
+    case LVQ_ERR_UNSUPPORTED: return "unsupported configuration";
+    case LVQ_ERR_OOM: return "out of device memory or over the memory budget";
+    case LVQ_ERR_CAPACITY: return "not enough free slots";
+    case LVQ_ERR_DEVICE: return "HIP runtime error";
+    case LVQ_ERR_NONFINITE: return "non-finite input vector";
+    case LVQ_ERR_BAD_SLOT: return "slot out of range or not live";
+    default: return "unknown error";
+    }
+}
+
+int lvq_row_format(const lvq_config *cfg, int32_t *row_bytes, int32_t *resid_bytes, int32_t *code_positions)
+{
+    Format f;
+    if (!cfg || !make_format(*cfg, &f)) return LVQ_ERR_INVALID_ARG;
+    if (row_bytes) *row_bytes = f.row_bytes;
+    if (resid_bytes) *resid_bytes = f.resid_bytes;
+    if (code_positions) *code_positions = f.npos;
+    return LVQ_OK;
+}
+
+int lvq_create(const lvq_config *cfg, const float *means_host, int32_t n_means, lvq_index **out)
+{
+    if (!cfg || !out || !means_host) return LVQ_ERR_INVALID_ARG;
+    *out = nullptr;
+    Format f;
+    if (!make_format(*cfg, &f)) return LVQ_ERR_INVALID_ARG;
+    if (n_means < 1 || n_means > kMaxMeans || cfg->capacity < 0 || cfg->capacity > INT32_MAX)
+        return LVQ_ERR_INVALID_ARG;
+    if (!finite_host(means_host, (size_t)n_means * cfg->dim)) return LVQ_ERR_NONFINITE;
+    lvq_index *ix = new (std::nothrow) lvq_index();
+    if (!ix) return LVQ_ERR_OOM;
+    ix->cfg = *cfg;
+    ix->f = f;
+    ix->n_means = n_means;
+    int rc = LVQ_OK;
+    do {
+        if (hipGetDevice(&ix->device) != hipSuccess) { rc = LVQ_ERR_DEVICE; break; }
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, ix->device) == hipSuccess) {
+            ix->n_cu = prop.multiProcessorCount;
+            ix->lds_max = prop.sharedMemPerBlock;
+        }
+        std::vector<float> all(means_host, means_host + (size_t)n_means * cfg->dim);
+        if ((rc = upload_means(ix, all))) break;
+        std::vector<int32_t> kd(f.kpos), pd(f.npos);
+        kernel_order_dims(f, kd.data());
+        for (int p = 0; p < f.npos; ++p) pd[p] = pos_dim(f, p);
+        std::vector<float> km(f.kpos);
+        for (int s = 0; s < f.kpos; ++s) km[s] = kd[s] >= 0 ? 1.0f : 0.0f;
+        if ((rc = dev_alloc(ix, ix->kdim, sizeof(int32_t) * f.kpos))) break;
+        if ((rc = dev_alloc(ix, ix->pos_dim, sizeof(int32_t) * f.npos))) break;
+        if ((rc = dev_alloc(ix, ix->kmask, sizeof(float) * f.kpos))) break;
+        if ((rc = dev_alloc(ix, ix->err, 16))) break;
+        if ((rc = dev_alloc(ix, ix->scratch, 4096))) break;
+        if (hipMemcpy(ix->kdim.p, kd.data(), sizeof(int32_t) * f.kpos, hipMemcpyHostToDevice) ||
+            hipMemcpy(ix->pos_dim.p, pd.data(), sizeof(int32_t) * f.npos, hipMemcpyHostToDevice) ||
+            hipMemcpy(ix->kmask.p, km.data(), sizeof(float) * f.kpos, hipMemcpyHostToDevice) ||
+            hipMemset(ix->err.p, 0, 16)) {
+            rc = LVQ_ERR_DEVICE;
+            break;
+        }
+        const int64_t cap = cfg->capacity;
+        if (cap > 0) {
+            if ((rc = dev_alloc(ix, ix->rows, (size_t)cap * f.row_bytes))) break;
+            if (f.resid_bytes && (rc = dev_alloc(ix, ix->resid, (size_t)cap * f.resid_bytes))) break;
+            if ((rc = dev_alloc(ix, ix->stack, sizeof(int32_t) * (size_t)cap))) break;
+            if (hipMemset(ix->rows.p, 0, (size_t)cap * f.row_bytes) ||
+                (f.resid_bytes && hipMemset(ix->resid.p, 0, (size_t)cap * f.resid_bytes))) {
+                rc = LVQ_ERR_DEVICE;
+                break;
+            }
+            std::vector<int32_t> st(cap);
+            for (int64_t i = 0; i < cap; ++i) st[i] = (int32_t)(cap - 1 - i);
+            if (hipMemcpy(ix->stack.p, st.data(), sizeof(int32_t) * cap, hipMemcpyHostToDevice)) {
+                rc = LVQ_ERR_DEVICE;
+                break;
+            }
+        }
+        ix->free_top = cap;
+        ix->fresh = cap;
+        if (hipEventCreateWithFlags(&ix->update_ev, hipEventDisableTiming)) { rc = LVQ_ERR_DEVICE; break; }
+    } while (0);
+    if (rc) {
+        lvq_destroy(ix);
+        return rc;
+    }
+    *out = ix;
+    return LVQ_OK;
+}
+
+int lvq_destroy(lvq_index *ix)
+{
+    if (!ix) return LVQ_ERR_INVALID_ARG;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : ix->ws) {
+        Workspace &w = kv.second;
+        for (DevBuf *b : {&w.qk, &w.qsum, &w.cm, &w.order, &w.queue, &w.part, &w.q16}) dev_free(ix, *b);
+    }
+    for (DevBuf *b : {&ix->means, &ix->means_t, &ix->muk, &ix->kmask, &ix->kdim, &ix->pos_dim, &ix->rows,
+                      &ix->resid, &ix->stack, &ix->err, &ix->scratch})
+        dev_free(ix, *b);
+    for (auto &f : ix->inflight) (void)hipEventDestroy(f.ev);
+    for (auto e : ix->spare_events) (void)hipEventDestroy(e);
+    if (ix->update_ev) (void)hipEventDestroy(ix->update_ev);
+    delete ix;
+    return LVQ_OK;
+}
+
+int lvq_set_means(lvq_index *ix, const float *means_host, int32_t n_means, int32_t *first_id_out)
+{
+    if (!ix || !means_host || n_means < 1) return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    if (ix->n_means + n_means > kMaxMeans) return LVQ_ERR_CAPACITY;
+    const int d = ix->f.dim;
+    if (!finite_host(means_host, (size_t)n_means * d)) return LVQ_ERR_NONFINITE;
+    LVQ_HIP(hipDeviceSynchronize());
+    std::vector<float> all((size_t)(ix->n_means + n_means) * d);
+    LVQ_HIP(hipMemcpy(all.data(), ix->means.p, sizeof(float) * (size_t)ix->n_means * d, hipMemcpyDeviceToHost));
+    std::memcpy(all.data() + (size_t)ix->n_means * d, means_host, sizeof(float) * (size_t)n_means * d);
+    const int first = ix->n_means;
+    ix->n_means += n_means;
+    int rc = upload_means(ix, all);
+    if (rc) return rc;
+    if (first_id_out) *first_id_out = first;
+    return LVQ_OK;
+}
+
+static int encode_common(lvq_index *ix, const float *x, int64_t n, uint8_t *rows, uint8_t *resid,
+                         const uint64_t *ext, int32_t *slots_out, bool store, hipStream_t s)
+{
+    EncodeArgs a;
+    a.x = x;
+    a.n = n;
+    a.means = P<float>(ix->means);
+    a.means_t = P<float>(ix->means_t);
+    a.n_means = ix->n_means;
+    a.pos_dim = P<int32_t>(ix->pos_dim);
+    a.f = ix->f;
+    a.rows = rows;
+    a.resid = resid;
+    a.free_stack = store ? P<int32_t>(ix->stack) : nullptr;
+    a.free_top = ix->free_top;
+    a.slots_out = slots_out;
+    a.ext_ids = ext;
+    a.epoch = ix->epoch;
+    a.err = P<uint32_t>(ix->err);
+    LVQ_HIP(launch_encode(a, s));
+    return LVQ_OK;
+}
+
+int lvq_encode(lvq_index *ix, const float *x_dev, int64_t n, uint8_t *rows_dev, uint8_t *resid_dev, void *stream)
+{
+    if (!ix || n < 0 || (n > 0 && (!x_dev || !rows_dev))) return LVQ_ERR_INVALID_ARG;
+    if (ix->f.bits2 && n > 0 && !resid_dev) return LVQ_ERR_INVALID_ARG;
+    if (n == 0) return LVQ_OK;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    return encode_common(ix, x_dev, n, rows_dev, resid_dev, nullptr, nullptr, false, (hipStream_t)stream);
+}
+
+int lvq_insert(lvq_index *ix, const float *x_dev, int64_t n, const uint64_t *ext_ids_dev, int32_t *slots_out_dev,
+               void *stream)
+{
+    if (!ix || n < 0 || (n > 0 && (!x_dev || !slots_out_dev))) return LVQ_ERR_INVALID_ARG;
+    if (n == 0) return LVQ_OK;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    if (n > ix->free_top) return LVQ_ERR_CAPACITY;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = order_after_updates(ix, s);
+    if (rc) return rc;
+    ix->epoch += 1;
+    rc = encode_common(ix, x_dev, n, P<uint8_t>(ix->rows), P<uint8_t>(ix->resid), ext_ids_dev, slots_out_dev,
+                       true, s);
+    if (rc) return rc;
+    ix->free_top -= n;
+    ix->fresh = std::min(ix->fresh, ix->free_top);
+    return note_update(ix, s);
+}
+
+static StoreArgs store_args(lvq_index *ix)
+{
+    StoreArgs a;
+    a.rows = P<uint8_t>(ix->rows);
+    a.resid = P<uint8_t>(ix->resid);
+    a.row_bytes = ix->f.row_bytes;
+    a.resid_bytes = ix->f.resid_bytes;
+    a.capacity = ix->cfg.capacity;
+    a.epoch = ix->epoch;
+    a.err = P<uint32_t>(ix->err);
+    return a;
+}
+
+int lvq_delete(lvq_index *ix, const int32_t *slots_dev, int64_t n, void *stream)
+{
+    if (!ix || n < 0 || (n > 0 && !slots_dev)) return LVQ_ERR_INVALID_ARG;
+    if (n == 0) return LVQ_OK;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = order_after_updates(ix, s);
+    if (rc) return rc;
+    ix->epoch += 1;
+    LVQ_HIP(launch_delete(store_args(ix), slots_dev, n, s));
+    return note_update(ix, s);
+}
+
+int lvq_consolidate(lvq_index *ix, void *stream, int64_t *n_freed_out)
+{
+    if (!ix) return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    if (n_freed_out) *n_freed_out = 0;
+    const int64_t cap = ix->cfg.capacity;
+    if (cap == 0) return LVQ_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = order_after_updates(ix, s);
+    if (rc) return rc;
+    // the oldest epoch an unfinished query may still observe
+    uint32_t safe = ix->epoch;
+    for (auto it = ix->inflight.begin(); it != ix->inflight.end();) {
+        if (hipEventQuery(it->ev) == hipSuccess) {
+            ix->spare_events.push_back(it->ev);
+            it = ix->inflight.erase(it);
+        } else {
+            safe = std::min(safe, it->epoch);
+            ++it;
+        }
+    }
+    const int nb = (int)((cap + 1023) / 1024);
+    if ((rc = dev_alloc(ix, ix->scratch, sizeof(int32_t) * (size_t)nb + 64))) return rc;
+    int32_t *counts = P<int32_t>(ix->scratch);
+    int64_t *new_top = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(ix->scratch.p) +
+                                                   ((sizeof(int32_t) * (size_t)nb + 15) & ~(size_t)15));
+    LVQ_HIP(launch_consolidate(store_args(ix), safe, P<int32_t>(ix->stack), ix->free_top, counts, new_top, s));
+    int64_t top = 0;
+    LVQ_HIP(hipMemcpyAsync(&top, new_top, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LVQ_HIP(hipStreamSynchronize(s));
+    if (n_freed_out) *n_freed_out = top - ix->free_top;
+    ix->free_top = top;
+    return note_update(ix, s);
+}
+
+int lvq_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev, const int32_t *ids_dev,
+                  int64_t total, int32_t level, float *dist_dev, int32_t k, int32_t *topk_ids_dev,
+                  float *topk_dist_dev, void *stream)
+{
+    if (!ix || nq < 0 || total < 0 || nq > INT32_MAX) return LVQ_ERR_INVALID_ARG;
+    if (level != LVQ_PRIMARY && level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
+    if (k < 0 || k > kMaxTopK) return LVQ_ERR_INVALID_ARG;
+    if (nq == 0) return LVQ_OK;
+    if (!q_dev || !offsets_dev || (total > 0 && !ids_dev)) return LVQ_ERR_INVALID_ARG;
+    if (k == 0 && !dist_dev) return LVQ_ERR_INVALID_ARG;
+    if (k > 0 && (!topk_ids_dev || !topk_dist_dev)) return LVQ_ERR_INVALID_ARG;
+    if (ix->cfg.capacity == 0) return LVQ_ERR_INVALID_ARG;
+    if (level == LVQ_FULL && ix->f.bits2 == 0) return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    const Format &f = ix->f;
+    const int bits2 = level == LVQ_FULL ? f.bits2 : 0;
+    const bool l2 = ix->cfg.metric == LVQ_L2;
+    const bool multi = l2 && ix->n_means > 1;
+    const bool masked = l2 && f.kpos != f.dim;
+    const int variant = !l2 ? 0 : (masked ? (multi ? 4 : 3) : (multi ? 2 : 1));
+    auto lookup = f.bits1 == 4 ? cand_kernel_b4 : cand_kernel_b8;
+    int shape = ix->cand_shape[level == LVQ_FULL][k > 0];
+    if (shape < 0 || !lookup(bits2, variant, shape)) shape = default_shape(f, lookup, bits2, variant);
+    void *kern = shape >= 0 ? lookup(bits2, variant, shape) : nullptr;
+    if (!kern) return LVQ_ERR_UNSUPPORTED;
+    const int ntab = multi ? ix->n_means : 1;
+    const size_t lds = cand_lds_bytes(f.kpos, ntab, masked, l2 ? 0 : ix->n_means, k);
+    if (lds > ix->lds_max) return LVQ_ERR_UNSUPPORTED;
+
+    int rc = order_after_updates(ix, s);
+    if (rc) return rc;
+    Workspace &w = workspace(ix, s);
+    if ((rc = prep_queries(ix, w, q_dev, nq, s))) return rc;
+    if ((rc = dev_alloc(ix, w.order, sizeof(int32_t) * (size_t)nq))) return rc;
+    if ((rc = dev_alloc(ix, w.queue, 64))) return rc;
+
+    CandArgs a;
+    a.rows = P<uint8_t>(ix->rows);
+    a.resid = P<uint8_t>(ix->resid);
+    a.row_bytes = f.row_bytes;
+    a.resid_bytes = f.resid_bytes;
+    a.kchunks = f.kchunks;
+    a.kpos = f.kpos;
+    a.capacity = ix->cfg.capacity;
+    a.qk = P<float>(w.qk);
+    a.qsum = P<float>(w.qsum);
+    a.cm = P<float>(w.cm);
+    a.muk = P<float>(ix->muk);
+    a.kmask = P<float>(ix->kmask);
+    a.n_means = ix->n_means;
+    a.offsets = offsets_dev;
+    a.ids = ids_dev;
+    a.nq = nq;
+    a.total = total;
+    a.dist = dist_dev;
+    a.k = k;
+    a.topk_ids = topk_ids_dev;
+    a.topk_dist = topk_dist_dev;
+    a.epoch = ix->epoch;
+    a.err = P<uint32_t>(ix->err);
+    // persistent launch: lists longest-first from a device work counter
+    a.order = P<int32_t>(w.order);
+    a.queue = P<int32_t>(w.queue);
+    LVQ_HIP(launch_fill_i32(a.queue, 0, 1, s));
+    LVQ_HIP(launch_list_order(offsets_dev, nq, P<int32_t>(w.order), nullptr, s));
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    const int64_t grid = std::min<int64_t>(nq, (int64_t)ix->n_cu * per_cu);
+    if ((rc = timing_begin(ix, s))) return rc;
+    hipLaunchKernelGGL(reinterpret_cast<void (*)(CandArgs)>(kern), dim3((unsigned)grid), dim3(256), lds, s, a);
+    LVQ_HIP(hipGetLastError());
+    if ((rc = timing_end(ix, s))) return rc;
+    return note_query(ix, s, ix->epoch);
+}
+
+int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level, int32_t *ids_dev,
+             float *dist_dev, void *stream)
+{
+    if (!ix || nq < 0 || nq > INT32_MAX || k < 1 || k > kMaxTopK) return LVQ_ERR_INVALID_ARG;
+    if (level != LVQ_PRIMARY && level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
+    if (prec != LVQ_FP32 && prec != LVQ_BF16 && prec != LVQ_FP16) return LVQ_ERR_INVALID_ARG;
+    if (nq == 0) return LVQ_OK;
+    if (!q_dev || !ids_dev || !dist_dev) return LVQ_ERR_INVALID_ARG;
+    if (level == LVQ_FULL && ix->f.bits2 == 0) return LVQ_ERR_INVALID_ARG;
+    if (prec != LVQ_FP32) return LVQ_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    const Format &f = ix->f;
+    const bool l2 = ix->cfg.metric == LVQ_L2;
+    if (l2 && ix->n_means > 1) return LVQ_ERR_UNSUPPORTED;
+    const bool masked = l2 && f.kpos != f.dim;
+    const int variant = !l2 ? 0 : (masked ? 2 : 1);
+    const int bits2 = level == LVQ_FULL ? f.bits2 : 0;
+    auto lookup = f.bits1 == 4 ? scan_kernel_b4 : scan_kernel_b8;
+    // a scan processes the whole row in one round
+    int shape = -1;
+    for (int i = 0; i < num_tile_shapes(); ++i) {
+        if (!lookup(bits2, variant, i)) continue;
+        TileShape t = tile_shape(i);
+        if (t.g * t.ch * t.nch < f.kchunks * 16) continue;
+        if (shape < 0) { shape = i; continue; }
+        TileShape b = tile_shape(shape);
+        if (t.g * t.ch * t.nch < b.g * b.ch * b.nch) shape = i;
+    }
+    if (shape < 0) return LVQ_ERR_UNSUPPORTED;
+    void *kern = lookup(bits2, variant, shape);
+    const TileShape sh = tile_shape(shape);
+    const int rpr = scan_rows_per_round(sh.g);
+    const size_t lds = scan_lds_bytes(f.kpos, l2 ? 0 : ix->n_means, k, rpr);
+    if (lds > ix->lds_max) return LVQ_ERR_UNSUPPORTED;
+
+    int rc = order_after_updates(ix, s);
+    if (rc) return rc;
+    Workspace &w = workspace(ix, s);
+    if ((rc = prep_queries(ix, w, (const float *)q_dev, nq, s))) return rc;
+    const int64_t n_rows = ix->cfg.capacity - ix->fresh;   // slots ever used
+    const int64_t qtiles = (nq + 15) / 16;
+    int64_t parts = std::max<int64_t>(1, (4 * (int64_t)ix->n_cu + qtiles - 1) / qtiles);
+    parts = std::min<int64_t>(parts, std::max<int64_t>(1, n_rows / 1024));
+    // the merge holds parts * k keys (+ k) of 8 bytes in one workgroup's LDS
+    parts = std::min<int64_t>(parts, std::max<int64_t>(1, (int64_t)(ix->lds_max / 8 - k) / k));
+    const int64_t rows_per_part = std::max<int64_t>(1, (n_rows + parts - 1) / parts);
+    if ((rc = dev_alloc(ix, w.part, sizeof(uint64_t) * (size_t)nq * parts * k))) return rc;
+
+    ScanArgs a;
+    a.rows = P<uint8_t>(ix->rows);
+    a.resid = P<uint8_t>(ix->resid);
+    a.row_bytes = f.row_bytes;
+    a.resid_bytes = f.resid_bytes;
+    a.kchunks = f.kchunks;
+    a.kpos = f.kpos;
+    a.n_rows = n_rows;
+    a.qk = P<float>(w.qk);
+    a.qsum = P<float>(w.qsum);
+    a.cm = P<float>(w.cm);
+    a.muk = P<float>(ix->muk);
+    a.kmask = P<float>(ix->kmask);
+    a.q16 = nullptr;
+    a.n_means = ix->n_means;
+    a.nq = nq;
+    a.k = k;
+    a.epoch = ix->epoch;
+    a.rows_per_part = rows_per_part;
+    a.n_parts = (int)parts;
+    a.part_keys = P<uint64_t>(w.part);
+    a.err = P<uint32_t>(ix->err);
+    if ((rc = timing_begin(ix, s))) return rc;
+    hipLaunchKernelGGL(reinterpret_cast<void (*)(ScanArgs)>(kern), dim3((unsigned)qtiles, (unsigned)parts), dim3(256),
+                       lds, s, a);
+    LVQ_HIP(hipGetLastError());
+    if ((rc = timing_end(ix, s))) return rc;
+    LVQ_HIP(launch_topk_merge(a.part_keys, nq, (int)parts, k, ix->cfg.metric, ids_dev, dist_dev, s));
+    return note_query(ix, s, ix->epoch);
+}
+
+int lvq_read_rows(lvq_index *ix, const int32_t *slots_dev, int64_t n, uint8_t *rows_dev, uint8_t *resid_dev,
+                  void *stream)
+{
+    if (!ix || n < 0 || (n > 0 && (!slots_dev || !rows_dev))) return LVQ_ERR_INVALID_ARG;
+    if (n == 0) return LVQ_OK;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = order_after_updates(ix, s);
+    if (rc) return rc;
+    LVQ_HIP(launch_gather_rows(store_args(ix), slots_dev, n, rows_dev, resid_dev, s));
+    return LVQ_OK;
+}
+
+int lvq_get_stats(lvq_index *ix, lvq_stats *out)
+{
+    if (!ix || !out) return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    out->capacity = ix->cfg.capacity;
+    out->free_slots = ix->free_top;
+    out->live_estimate = ix->cfg.capacity - ix->free_top;
+    out->device_bytes = ix->device_bytes;
+    out->n_means = ix->n_means;
+    out->row_bytes = ix->f.row_bytes;
+    out->resid_bytes = ix->f.resid_bytes;
+    out->code_positions = ix->f.npos;
+    out->epoch = ix->epoch;
+    return LVQ_OK;
+}
+
+int lvq_set_timing(lvq_index *ix, int enable)
+{
+    if (!ix) return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    ix->timing = enable != 0;
+    return LVQ_OK;
+}
+
+int lvq_kernel_time(lvq_index *ix, double *ms_out, int64_t *launches_out)
+{
+    if (!ix || !ms_out) return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    double total = 0.0;
+    for (auto &p : ix->tev) {
+        LVQ_HIP(hipEventSynchronize(p.second));
+        float ms = 0.0f;
+        LVQ_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+        total += ms;
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    if (launches_out) *launches_out = (int64_t)ix->tev.size();
+    ix->tev.clear();
+    *ms_out = total;
+    return LVQ_OK;
+}
+
+int lvq_sync(lvq_index *ix, void *stream)
+{
+    if (!ix) return LVQ_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    LVQ_HIP(hipStreamSynchronize(s));
+    uint32_t e = 0;
+    {
+        std::lock_guard<std::mutex> lk(ix->mu);
+        LVQ_HIP(hipMemcpy(&e, ix->err.p, sizeof(uint32_t), hipMemcpyDeviceToHost));
+        if (e) LVQ_HIP(hipMemset(ix->err.p, 0, sizeof(uint32_t)));
+    }
+    if (e & kErrNonFinite) return LVQ_ERR_NONFINITE;
+    if (e & kErrBadSlot) return LVQ_ERR_BAD_SLOT;
+    if (e & (kErrBadOffsets | kErrOverflow)) return LVQ_ERR_INVALID_ARG;
+    return LVQ_OK;
+}
+
+int lvq_mean(const float *x_dev, int64_t n, int32_t dim, float *mean_out_dev, void *stream)
+{
+    if (!x_dev || !mean_out_dev || n < 1 || dim < 1) return LVQ_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nchunks = (n + 4095) / 4096;
+    double *scratch = nullptr;
+    LVQ_HIP(hipMallocAsync((void **)&scratch, sizeof(double) * (size_t)nchunks * dim, s));
+    hipError_t e = launch_mean(x_dev, n, dim, mean_out_dev, scratch, s);
+    hipError_t e2 = hipFreeAsync(scratch, s);
+    LVQ_HIP(e);
+    LVQ_HIP(e2);
+    return LVQ_OK;
+}
+
+int lvq_kmeans(const float *x_dev, int64_t n, int32_t dim, int32_t k, const int64_t *init_idx_host, int32_t iters,
+               float *means_out_dev, void *stream)
+{
+    if (!x_dev || !means_out_dev || !init_idx_host || n < 1 || dim < 1 || k < 1 || k > n || iters < 0)
+        return LVQ_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    for (int m = 0; m < k; ++m) {
+        if (init_idx_host[m] < 0 || init_idx_host[m] >= n) return LVQ_ERR_INVALID_ARG;
+        LVQ_HIP(hipMemcpyAsync(means_out_dev + (size_t)m * dim, x_dev + (size_t)init_idx_host[m] * dim,
+                               sizeof(float) * dim, hipMemcpyDeviceToDevice, s));
+    }
+    int32_t *assign = nullptr;
+    LVQ_HIP(hipMallocAsync((void **)&assign, sizeof(int32_t) * (size_t)n, s));
+    hipError_t e = hipSuccess;
+    for (int it = 0; it < iters && e == hipSuccess; ++it) {
+        e = launch_kmeans_assign(x_dev, n, dim, means_out_dev, k, assign, s);
+        if (e == hipSuccess) e = launch_kmeans_update(x_dev, n, dim, assign, k, means_out_dev, s);
+    }
+    hipError_t e2 = hipFreeAsync(assign, s);
+    LVQ_HIP(e);
+    LVQ_HIP(e2);
+    return LVQ_OK;
+}
+
+}  // extern "C"

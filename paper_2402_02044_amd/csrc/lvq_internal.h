@@ -1,0 +1,160 @@
+// lvq_internal.h -- declarations shared by the host side of the library and
+// the kernel translation units.  Not part of the public ABI (see lvq.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lvq.h"
+
+namespace lvq {
+
+constexpr int kHeaderBytes = 32;
+constexpr uint32_t kLiveEpoch = 0xFFFFFFFFu;   // delete epoch of a live row
+constexpr int kMaxMeans = 256;
+constexpr int kMaxTopK = 1024;
+
+// sticky error bits raised by kernels
+enum : uint32_t { kErrNonFinite = 1u, kErrBadSlot = 2u, kErrBadOffsets = 4u, kErrOverflow = 8u };
+
+// Storage format (mirrors the row description in lvq.h).
+struct Format {
+    int dim, bits1, bits2, layout, align;
+    int npos;        // code positions (dims padded to the layout block)
+    int code_bytes;  // first-level code bytes
+    int row_bytes;   // header + codes, padded to align
+    int resid_bytes; // residual row stride (0 without a residual level)
+    int kchunks;     // 16-byte chunks of first-level codes read by the kernels
+    int kpos;        // code positions covered by those chunks
+};
+
+bool make_format(const lvq_config &cfg, Format *f);
+
+// Kernel order of code positions.  For 4-bit codes the fields of a 32-bit
+// word are visited as (0,2,4,6,1,3,5,7): the low nibble of each byte first,
+// then the high nibble, so one mask exposes four fields to byte-wise
+// conversion; 8-bit codes keep their natural order.  kdim[s] is the
+// dimension held at kernel slot s, or -1.
+void kernel_order_dims(const Format &f, int32_t *kdim /* kpos entries */);
+
+// ---- argument blocks -------------------------------------------------------
+
+struct EncodeArgs {
+    const float *x;          // n x dim
+    int64_t n;
+    const float *means;      // M x dim
+    const float *means_t;    // dim x M (transposed copy, coalesced assignment)
+    int n_means;
+    const int32_t *pos_dim;  // npos entries: dimension at code position, -1 pad
+    Format f;
+    uint8_t *rows;           // output rows (row i at rows + slot(i) * row_bytes)
+    uint8_t *resid;
+    // store mode (insert): slots popped from the free stack
+    const int32_t *free_stack;  // NULL for pure encode
+    int64_t free_top;           // stack top before the pop
+    int32_t *slots_out;
+    const uint64_t *ext_ids;
+    uint32_t epoch;
+    uint32_t *err;
+};
+
+struct PrepArgs {
+    const void *q;           // nq x dim (fp32)
+    int64_t nq;
+    int dim, kpos, n_means, metric;
+    const int32_t *kdim;     // kpos entries
+    const float *means;      // M x dim
+    float *qk;               // nq x kpos (kernel order, zero at padding)
+    float *qsum;             // nq
+    float *cm;               // nq x M (IP: <q, mu_m>)
+};
+
+struct CandArgs {
+    const uint8_t *rows;
+    const uint8_t *resid;
+    int row_bytes, resid_bytes;
+    int kchunks, kpos;
+    int64_t capacity;
+    const float *qk, *qsum, *cm;
+    const float *muk;        // M x kpos means in kernel order (L2)
+    const float *kmask;      // kpos: 1 at real positions, 0 at padding (L2)
+    int n_means;
+    const int64_t *offsets;
+    const int32_t *ids;
+    int64_t nq, total;
+    float *dist;             // may be NULL
+    int k;
+    int32_t *topk_ids;
+    float *topk_dist;
+    uint32_t epoch;
+    uint32_t *err;
+    const int32_t *order;    // list processing order (NULL: identity)
+    int32_t *queue;          // persistent work counter (NULL: one list per block)
+};
+
+struct ScanArgs {
+    const uint8_t *rows;
+    const uint8_t *resid;
+    int row_bytes, resid_bytes, kchunks, kpos;
+    int64_t n_rows;          // slots [0, n_rows) are scanned
+    const float *qk, *qsum, *cm, *muk, *kmask;
+    const void *q16;         // MFMA forms: nq x kpos bf16/fp16 in kernel order
+    int n_means;
+    int64_t nq;
+    int k;
+    uint32_t epoch;
+    int64_t rows_per_part;
+    int n_parts;
+    uint64_t *part_keys;     // nq x n_parts x k sortable keys
+    uint32_t *err;
+};
+
+struct StoreArgs {
+    uint8_t *rows;
+    uint8_t *resid;
+    int row_bytes, resid_bytes;
+    int64_t capacity;
+    uint32_t epoch;
+    uint32_t *err;
+};
+
+// ---- launchers (each returns hipSuccess or the launch error) --------------
+
+hipError_t launch_encode(const EncodeArgs &a, hipStream_t s);
+hipError_t launch_prep(const PrepArgs &a, hipStream_t s);
+// Kernel tables: k_cand / k_scan instantiations by first-level width, level
+// residual width (0 at the first level), variant and tile shape; nullptr when
+// not instantiated.  cand variants: 0 IP, 1 L2, 2 L2 several means, 3 L2
+// masked, 4 L2 masked several means.  scan variants: 0 IP, 1 L2, 2 L2 masked.
+struct TileShape {
+    int g, ch, nch;   // lanes per candidate, bytes per piece, pieces per lane and round
+};
+int num_tile_shapes();
+TileShape tile_shape(int i);
+void *cand_kernel_b4(int bits2, int variant, int shape);
+void *cand_kernel_b8(int bits2, int variant, int shape);
+void *scan_kernel_b4(int bits2, int variant, int shape);
+void *scan_kernel_b8(int bits2, int variant, int shape);
+size_t cand_lds_bytes(int kpos, int ntab, bool mask, int n_means_ip, int k);
+size_t scan_lds_bytes(int kpos, int n_means_ip, int k, int rows_per_round);
+int scan_rows_per_round(int g);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_list_order(const int64_t *offsets, int64_t nq, int32_t *order, int32_t *scratch,
+                             hipStream_t s);
+hipError_t launch_scan_mfma(const ScanArgs &a, int bits1, int prec, hipStream_t s);
+hipError_t launch_topk_merge(const uint64_t *part_keys, int64_t nq, int n_parts, int k, int metric,
+                             int32_t *ids, float *dist, hipStream_t s);
+hipError_t launch_delete(const StoreArgs &a, const int32_t *slots, int64_t n, hipStream_t s);
+hipError_t launch_consolidate(const StoreArgs &a, uint32_t safe_epoch, int32_t *free_stack,
+                              int64_t free_top, int32_t *block_counts, int64_t *new_top,
+                              hipStream_t s);
+hipError_t launch_gather_rows(const StoreArgs &a, const int32_t *slots, int64_t n, uint8_t *rows_out,
+                              uint8_t *resid_out, hipStream_t s);
+hipError_t launch_mean(const float *x, int64_t n, int dim, float *out, double *scratch, hipStream_t s);
+hipError_t launch_kmeans_assign(const float *x, int64_t n, int dim, const float *c, int k,
+                                int32_t *assign, hipStream_t s);
+hipError_t launch_kmeans_update(const float *x, int64_t n, int dim, const int32_t *assign, int k,
+                                float *c, hipStream_t s);
+
+}  // namespace lvq

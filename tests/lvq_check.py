@@ -1,0 +1,90 @@
+"""Comparison helpers: GPU results against the oracle, to the tolerances the
+tests state.
+
+Distances (binary32 on the GPU vs binary64 in the oracle):
+  L2: |g - r| <= 1e-4 * r + 1e-7 * (||q - mu*||^2 + ||x_hat - mu*||^2)
+  IP: |g - r| <= 1e-4 * S,  S = sum_j |q_j x_hat_j|
+The relative term is the bound the distances are held to; the second term
+covers values near zero, where a relative bound is meaningless (an IP between
+unrelated unit vectors, or L2 between near-duplicates), scaled by the
+magnitudes that enter the binary32 computation.
+"""
+import numpy as np
+
+import oracle
+
+
+def pair_tolerance(metric, Q, xhat, mean_rows, q_index):
+    """Tolerance per pair; xhat / mean_rows are (pairs, d), q_index (pairs,)."""
+    q = np.asarray(Q, np.float64)[q_index]
+    if metric == oracle.IP:
+        S = np.abs(q * xhat).sum(1)
+        return 1e-4 * S
+    r = ((q - xhat) ** 2).sum(1)
+    scale = ((q - mean_rows) ** 2).sum(1) + ((xhat - mean_rows) ** 2).sum(1)
+    return 1e-4 * r + 1e-7 * scale
+
+
+def pair_reference(fmt, metric, level, Q, rows, resid, means, offsets, ids):
+    """Oracle values and tolerances for every listed pair."""
+    ref = oracle.distances(fmt, metric, level, Q, rows, resid, means, offsets, ids)
+    ids = np.asarray(ids)
+    uniq, inv = np.unique(ids, return_inverse=True)
+    xh_u = oracle.reconstruct(fmt, rows[uniq], None if resid is None else resid[uniq], means, level)
+    mid_u = oracle.unpack(fmt, rows[uniq])[3]
+    mrow_u = np.asarray(means, np.float64)[mid_u]
+    q_index = np.repeat(np.arange(len(offsets) - 1), np.diff(offsets))
+    tol = pair_tolerance(metric, Q, xh_u[inv], mrow_u[inv], q_index)
+    return ref, tol
+
+
+def check_values(got, ref, tol, what="distances"):
+    got = np.asarray(got, np.float64)
+    bad = ~(np.abs(got - ref) <= tol)
+    bad &= ~(np.isnan(got) & np.isnan(ref))
+    if bad.any():
+        i = np.flatnonzero(bad)[:5]
+        raise AssertionError("%s: %d of %d outside tolerance, e.g. idx %s got %s ref %s tol %s"
+                             % (what, bad.sum(), bad.size, i, got[i], ref[i], tol[i]))
+
+
+def better(metric, a, b):
+    return a < b if metric == oracle.L2 else a > b
+
+
+def check_topk(metric, got_ids, got_dist, cand_ids, cand_ref, cand_tol, k, keep=None):
+    """One query: the GPU's k ids against the oracle's scores of the candidates.
+
+    Every id the oracle ranks clearly inside the top k (better than the k-th
+    value by more than the tolerance) must be returned; every returned id must
+    be a candidate whose oracle value is within tolerance of the k-th value or
+    better; returned values must match the oracle within tolerance and be
+    sorted.  Ids may be padded with -1 when fewer than k candidates survive."""
+    cand_ids = np.asarray(cand_ids)
+    m = np.ones(len(cand_ids), bool) if keep is None else np.asarray(keep, bool)
+    ids_v, ref_v, tol_v = cand_ids[m], np.asarray(cand_ref)[m], np.asarray(cand_tol)[m]
+    # ties and duplicates: rank by oracle value then slot
+    key = ref_v if metric == oracle.L2 else -ref_v
+    order = np.lexsort((ids_v, key))
+    n_valid = min(k, len(ids_v))
+    got_ids = np.asarray(got_ids)
+    got_dist = np.asarray(got_dist, np.float64)
+    assert np.all(got_ids[n_valid:] == -1), "padding"
+    if n_valid == 0:
+        return
+    kth = ref_v[order[n_valid - 1]]
+    tol_max = tol_v.max() if len(tol_v) else 0.0
+    clearly_in = ids_v[better(metric, ref_v, kth) & (np.abs(ref_v - kth) > 2 * tol_max)]
+    gi = got_ids[:n_valid]
+    assert set(clearly_in.tolist()) <= set(gi.tolist()), "missing a clear top-k member"
+    lookup = {}
+    for s, r, t in zip(ids_v, ref_v, tol_v):
+        lookup.setdefault(int(s), (r, t))
+    for s, dv in zip(gi, got_dist[:n_valid]):
+        assert int(s) in lookup, "returned id %d is not a live candidate" % s
+        r, t = lookup[int(s)]
+        assert abs(dv - r) <= t or (np.isnan(dv) and np.isnan(r)), "value of id %d" % s
+        assert not better(metric, kth, r) or abs(r - kth) <= 2 * tol_max, "id %d outside the top k" % s
+    gd = got_dist[:n_valid]
+    srt = gd if metric == oracle.L2 else -gd
+    assert np.all(np.diff(srt[~np.isnan(srt)]) >= 0), "not sorted"

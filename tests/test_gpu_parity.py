@@ -1,0 +1,299 @@
+"""GPU parity through the C ABI: encoded rows bit-exact with the oracle,
+similarities within the stated tolerance (tests/lvq_check.py), top-k sets
+equal up to near-ties."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from lvq_check import check_topk, check_values, pair_reference
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2402_02044_amd as lib
+    return lib
+
+
+def _special_rows(d, g):
+    rows = [np.full(d, 0.75, np.float32),                                   # u == l
+            (g.standard_normal(d) * 1e-38).astype(np.float32),              # subnormal spread
+            (1000.0 + 0.9 * 255 * 6.1e-5 * g.uniform(-1, 1, d)).astype(np.float32),  # far from mean
+            (g.standard_normal(d) * 3e37).astype(np.float32)]               # near overflow
+    return np.stack(rows)
+
+
+ENC_FORMATS = [(96, 8, 0, oracle.SEQUENTIAL), (96, 4, 8, oracle.TURBO), (768, 4, 8, oracle.TURBO),
+               (130, 4, 8, oracle.TURBO), (7, 8, 4, oracle.SEQUENTIAL), (200, 4, 4, oracle.SEQUENTIAL),
+               (64, 8, 8, oracle.TURBO), (1, 4, 0, oracle.SEQUENTIAL), (512, 8, 0, oracle.SEQUENTIAL),
+               (300, 8, 8, oracle.SEQUENTIAL)]
+
+
+@pytest.mark.parametrize("d,b1,b2,layout", ENC_FORMATS)
+@pytest.mark.parametrize("M", [1, 3, 16])
+def test_encode_bit_exact(L, d, b1, b2, layout, M):
+    g = synth.rng(1000 + d, b1 * 16 + b2 + M)
+    n = 301
+    X = np.concatenate([synth.small_vectors(d + M, n - 4, d, ["normal", "uniform", "wide", "lowcard"][d % 4]),
+                        _special_rows(d, g)])
+    means = (g.standard_normal((M, d)) * 0.5).astype(np.float32)
+    if M == 1:
+        means = X[:n - 4].astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    fmt = oracle.Format(d, b1, b2, layout)
+    ref_rows, ref_res, rej = oracle.encode_rows(fmt, X, means)
+    assert rej == 0
+    ix = L.Index(d, b1, b2, L.LVQ_L2, layout, means=means)
+    rows, res = ix.encode(torch.from_numpy(X).cuda())
+    assert ix.sync() == 0
+    np.testing.assert_array_equal(rows.cpu().numpy(), ref_rows)
+    if b2:
+        np.testing.assert_array_equal(res.cpu().numpy(), ref_res)
+    ix.close()
+
+
+def test_encode_nonfinite(L):
+    d = 40
+    X = synth.small_vectors(5, 9, d)
+    X[2, 5] = np.nan
+    X[7, 0] = -np.inf
+    mu = np.zeros((1, d), np.float32)
+    fmt = oracle.Format(d, 4, 8, oracle.TURBO)
+    ref_rows, ref_res, rej = oracle.encode_rows(fmt, X, mu)
+    assert rej == 2
+    ix = L.Index(d, 4, 8, L.LVQ_IP, L.LVQ_TURBO, means=mu)
+    rows, res = ix.encode(torch.from_numpy(X).cuda())
+    assert ix.sync() == L.LVQ_ERR_NONFINITE
+    assert ix.sync() == 0          # the sticky error is cleared by reading it
+    got = rows.cpu().numpy()
+    np.testing.assert_array_equal(got[:, 4:], ref_rows[:, 4:])
+    np.testing.assert_array_equal(np.isnan(got[:, :4].copy().view(np.float32)),
+                                  np.isnan(ref_rows[:, :4].copy().view(np.float32)))
+    np.testing.assert_array_equal(res.cpu().numpy(), ref_res)
+    ix.close()
+
+
+def _lists(g, nq, n, lens):
+    offs = np.zeros(nq + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    ids = np.concatenate([g.choice(n, L_, replace=False) for L_ in lens]).astype(np.int32) \
+        if offs[-1] else np.zeros(0, np.int32)
+    return offs, ids
+
+
+DIST_CASES = [
+    # d, b1, b2, layout, metric, M
+    (96, 8, 0, oracle.SEQUENTIAL, oracle.L2, 1),
+    (96, 8, 0, oracle.SEQUENTIAL, oracle.L2, 16),
+    (768, 4, 8, oracle.TURBO, oracle.IP, 1),
+    (768, 4, 8, oracle.TURBO, oracle.IP, 16),
+    (130, 4, 8, oracle.TURBO, oracle.L2, 1),
+    (130, 4, 8, oracle.TURBO, oracle.L2, 3),
+    (200, 4, 4, oracle.SEQUENTIAL, oracle.IP, 2),
+    (512, 8, 0, oracle.SEQUENTIAL, oracle.IP, 1),
+    (100, 8, 4, oracle.SEQUENTIAL, oracle.L2, 1),
+    (64, 8, 8, oracle.TURBO, oracle.IP, 1),
+]
+
+
+@pytest.mark.parametrize("d,b1,b2,layout,metric,M", DIST_CASES)
+def test_candidate_distances_and_topk(L, d, b1, b2, layout, metric, M):
+    g = synth.rng(2000 + d, b1 * 16 + b2 + M * 3 + metric)
+    n = 2600
+    cent = g.standard_normal((8, d)).astype(np.float32)
+    X = (cent[g.integers(0, 8, n)] + 0.4 * g.standard_normal((n, d))).astype(np.float32)
+    Q = (cent[g.integers(0, 8, 23)] + 0.4 * g.standard_normal((23, d))).astype(np.float32)
+    if metric == oracle.IP:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+        Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    means = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32) if M == 1 \
+        else X[g.choice(n, M, replace=False)]
+    fmt = oracle.Format(d, b1, b2, layout)
+    rows, resid, _ = oracle.encode_rows(fmt, X, means)
+    # ragged lists: empty, single, short, longer than one LDS buffer of keys
+    lens = [0, 1, 5, 64, 2500, 37, 1000, 3, 0, 129] + list(g.integers(1, 400, 13))
+    offs, ids = _lists(g, 23, n, lens)
+
+    ix = L.Index(d, b1, b2, metric, layout, capacity=n, means=means)
+    slots = ix.insert(torch.from_numpy(X).cuda())
+    assert ix.sync() == 0
+    np.testing.assert_array_equal(slots.cpu().numpy(), np.arange(n))
+    dead = np.sort(g.choice(n, 300, replace=False)).astype(np.int32)
+    ix.delete(torch.from_numpy(dead).cuda())
+    assert ix.sync() == 0
+    keep_slot = np.ones(n, bool)
+    keep_slot[dead] = False
+    qd = torch.from_numpy(Q).cuda()
+    od, idd = torch.from_numpy(offs).cuda(), torch.from_numpy(ids).cuda()
+    for level in ([oracle.PRIMARY, oracle.FULL] if b2 else [oracle.PRIMARY]):
+        ref, tol = pair_reference(fmt, metric, level, Q, rows, resid, means, offs, ids)
+        for k in (0, 10, 100):
+            dist, ti, td = ix.distances(qd, od, idd, level=level, k=k)
+            assert ix.sync() == 0
+            check_values(dist.cpu().numpy(), ref, tol)
+            if k == 0:
+                continue
+            ti, td = ti.cpu().numpy(), td.cpu().numpy()
+            for i in range(23):
+                a, b = offs[i], offs[i + 1]
+                check_topk(metric, ti[i], td[i], ids[a:b], ref[a:b], tol[a:b], k, keep_slot[ids[a:b]])
+    ix.close()
+
+
+def test_duplicate_ids_and_bad_slots(L):
+    d, n = 96, 500
+    X = synth.small_vectors(11, n, d)
+    mu = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    fmt = oracle.Format(d, 8, 0)
+    rows, _, _ = oracle.encode_rows(fmt, X, mu)
+    ix = L.Index(d, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=n, means=mu)
+    ix.insert(torch.from_numpy(X).cuda())
+    offs = np.array([0, 6], np.int64)
+    ids = np.array([4, 4, 9, 4, 0, 9], np.int32)
+    Q = synth.small_vectors(12, 1, d)
+    ref, tol = pair_reference(fmt, oracle.L2, oracle.PRIMARY, Q, rows, None, mu, offs, ids)
+    dist, ti, td = ix.distances(torch.from_numpy(Q).cuda(), torch.from_numpy(offs).cuda(),
+                                torch.from_numpy(ids).cuda(), k=4)
+    assert ix.sync() == 0
+    check_values(dist.cpu().numpy(), ref, tol)
+    # duplicates are scored once per entry
+    assert sorted(ti.cpu().numpy()[0].tolist()) == sorted(ids[np.lexsort((ids, ref))][:4].tolist())
+    bad = np.array([1, -3, n + 5], np.int32)
+    dist, _, _ = ix.distances(torch.from_numpy(Q).cuda(), torch.tensor([0, 3], dtype=torch.int64).cuda(),
+                              torch.from_numpy(bad).cuda())
+    assert ix.sync() == L.LVQ_ERR_BAD_SLOT
+    got = dist.cpu().numpy()
+    assert not np.isnan(got[0]) and np.isnan(got[1]) and np.isnan(got[2])
+    ix.close()
+
+
+EXH_CASES = [
+    (96, 8, 0, oracle.SEQUENTIAL, oracle.L2, 1),
+    (768, 4, 8, oracle.TURBO, oracle.IP, 16),
+    (512, 8, 0, oracle.SEQUENTIAL, oracle.IP, 1),
+    (130, 4, 8, oracle.TURBO, oracle.L2, 1),
+    (100, 8, 0, oracle.SEQUENTIAL, oracle.L2, 1),
+]
+
+
+@pytest.mark.parametrize("d,b1,b2,layout,metric,M", EXH_CASES)
+def test_exhaustive_topk(L, d, b1, b2, layout, metric, M):
+    g = synth.rng(3000 + d, M + metric)
+    n, nq = 3000, 21
+    cent = g.standard_normal((8, d)).astype(np.float32)
+    X = (cent[g.integers(0, 8, n)] + 0.4 * g.standard_normal((n, d))).astype(np.float32)
+    Q = (cent[g.integers(0, 8, nq)] + 0.4 * g.standard_normal((nq, d))).astype(np.float32)
+    means = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32) if M == 1 \
+        else X[g.choice(n, M, replace=False)]
+    fmt = oracle.Format(d, b1, b2, layout)
+    rows, resid, _ = oracle.encode_rows(fmt, X, means)
+    ix = L.Index(d, b1, b2, metric, layout, capacity=n + 100, means=means)
+    ix.insert(torch.from_numpy(X).cuda())
+    dead = np.sort(g.choice(n, 250, replace=False)).astype(np.int32)
+    ix.delete(torch.from_numpy(dead).cuda())
+    assert ix.sync() == 0
+    live = np.ones(n, bool)
+    live[dead] = False
+    offs = np.arange(nq + 1, dtype=np.int64) * n
+    allids = np.tile(np.arange(n, dtype=np.int32), nq)
+    for level in ([oracle.PRIMARY, oracle.FULL] if b2 else [oracle.PRIMARY]):
+        ref, tol = pair_reference(fmt, metric, level, Q, rows, resid, means, offs, allids)
+        for k in (1, 10, 100):
+            ti, td = ix.topk(torch.from_numpy(Q).cuda(), k, level=level)
+            assert ix.sync() == 0
+            ti, td = ti.cpu().numpy(), td.cpu().numpy()
+            for i in range(nq):
+                a, b = offs[i], offs[i + 1]
+                check_topk(metric, ti[i], td[i], allids[a:b], ref[a:b], tol[a:b], k, live)
+    ix.close()
+
+
+def test_store_sequence_matches_model(L):
+    """Insert / delete / consolidate: slots follow the free-stack order (pops
+    ascend from 0; consolidation pushes freed slots so they pop ascending),
+    stored rows equal the oracle's, tombstoned slots leave the top-k."""
+    d, cap = 64, 300
+    g = synth.rng(4000, 0)
+    mu = np.zeros((1, d), np.float32)
+    fmt = oracle.Format(d, 4, 8, oracle.TURBO)
+    ix = L.Index(d, 4, 8, L.LVQ_IP, L.LVQ_TURBO, capacity=cap, means=mu)
+    X1 = g.standard_normal((200, d)).astype(np.float32)
+    s1 = ix.insert(torch.from_numpy(X1).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(s1, np.arange(200))
+    dead = np.array([3, 50, 199, 120], np.int32)
+    ix.delete(torch.from_numpy(dead).cuda())
+    assert ix.consolidate() == 4
+    X2 = g.standard_normal((7, d)).astype(np.float32)
+    s2 = ix.insert(torch.from_numpy(X2).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(s2, [3, 50, 120, 199, 200, 201, 202])
+    assert ix.sync() == 0
+    rows, resid = ix.read_rows(torch.from_numpy(s2).cuda())
+    ref_rows, ref_res, _ = oracle.encode_rows(fmt, X2, mu)
+    got = rows.cpu().numpy()
+    np.testing.assert_array_equal(got[:, :16], ref_rows[:, :16])   # l, Delta, Delta2, mean id
+    np.testing.assert_array_equal(got[:, 32:], ref_rows[:, 32:])
+    np.testing.assert_array_equal(resid.cpu().numpy(), ref_res)
+    assert np.all(got[:, 13] == 1)                                  # occupied
+    assert np.all(got[:, 20:24].copy().view(np.uint32) == 0xFFFFFFFF)
+    # capacity: 300 - 203 = 97 free
+    with pytest.raises(L.LVQError) as e:
+        ix.insert(torch.from_numpy(g.standard_normal((98, d)).astype(np.float32)).cuda())
+    assert e.value.code == L.LVQ_ERR_CAPACITY
+    # deleting a dead slot is reported
+    ix.delete(torch.tensor([5, 5000], dtype=torch.int32).cuda())
+    ix.delete(torch.tensor([5], dtype=torch.int32).cuda())
+    assert ix.sync() == L.LVQ_ERR_BAD_SLOT
+    st = ix.stats()
+    assert st.free_slots == 97 and st.capacity == cap
+    ix.close()
+
+
+def test_invalid_arguments(L):
+    import ctypes
+    cfg = L.lvq_config(96, 5, 0, 0, 0, 32, 0, 0)
+    with pytest.raises(L.LVQError) as e:
+        L.lvq_row_format(cfg)
+    assert e.value.code == L.LVQ_ERR_INVALID_ARG
+    ix = L.Index(16, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=10, means=np.zeros(16, np.float32))
+    q = torch.zeros((1, 16), device="cuda")
+    offs = torch.tensor([0, 1], dtype=torch.int64, device="cuda")
+    ids = torch.zeros(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(L.LVQError) as e:      # FULL needs a residual level
+        ix.distances(q, offs, ids, level=L.LVQ_FULL)
+    assert e.value.code == L.LVQ_ERR_INVALID_ARG
+    with pytest.raises(L.LVQError):
+        ix.distances(q, offs, ids, k=5000)
+    with pytest.raises(L.LVQError) as e:
+        L.lvq_create(L.lvq_config(16, 8, 0, 0, 0, 32, 0, 0), np.zeros(16, np.float32).ctypes.data, 0)
+    assert e.value.code == L.LVQ_ERR_INVALID_ARG
+    bad = np.full(16, np.nan, np.float32)
+    with pytest.raises(L.LVQError) as e:
+        L.lvq_create(L.lvq_config(16, 8, 0, 0, 0, 32, 0, 0), bad.ctypes.data, 1)
+    assert e.value.code == L.LVQ_ERR_NONFINITE
+    with pytest.raises(L.LVQError) as e:       # memory budget below the store
+        L.Index(768, 4, 8, L.LVQ_IP, L.LVQ_TURBO, capacity=100000, mem_budget_bytes=1 << 20)
+    assert e.value.code == L.LVQ_ERR_OOM
+    assert ctypes is not None
+    ix.close()
+
+
+def test_mean_and_kmeans(L):
+    g = synth.rng(5000, 0)
+    X = (g.standard_normal((20000, 24)) + 3.0).astype(np.float32)
+    m = L.mean(torch.from_numpy(X).cuda()).cpu().numpy()
+    np.testing.assert_allclose(m, X.astype(np.float64).mean(0), rtol=0, atol=1e-6)
+    cent = (g.standard_normal((5, 24)) * 4).astype(np.float32)
+    lab = g.integers(0, 5, 5000)
+    Y = (cent[lab] + 0.2 * g.standard_normal((5000, 24))).astype(np.float32)
+    init = [int(np.flatnonzero(lab == c)[0]) for c in range(5)]
+    C = L.kmeans(torch.from_numpy(Y).cuda(), 5, init, iters=10).cpu().numpy()
+    np.testing.assert_allclose(C, cent, atol=0.05)
+    # a fixed point of Lloyd: every centre is the mean of its members
+    d2 = ((Y[:, None, :].astype(np.float64) - C[None]) ** 2).sum(-1)
+    a = d2.argmin(1)
+    for c in range(5):
+        np.testing.assert_allclose(C[c], Y[a == c].astype(np.float64).mean(0), atol=1e-5)
