@@ -45,7 +45,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(launch_pairs: int):
+def read_traffic(launch_pairs: int, tile: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source (else None)."""
     if not os.path.exists(PROFILE_TRAFFIC):
@@ -58,7 +58,7 @@ def read_traffic(launch_pairs: int):
     try:
         if vals.get("kernel_source_sha") != kernel_source_hash():
             return None
-        if int(vals["pairs_per_launch"]) != launch_pairs:
+        if int(vals["pairs_per_launch"]) != launch_pairs or int(vals["tile_shape"]) != tile:
             return None
         fetch = float(vals["fetch_kib_per_dispatch"]) * float(vals["fetch_scale"])
         write = float(vals["write_kib_per_dispatch"]) * float(vals["write_scale"])
@@ -131,6 +131,12 @@ def bench_c2(args):
 
     rc = ix.sync()
     assert rc == 0, L.lvq_strerror(rc)
+    if args.tile >= 0:
+        ix.set_tile(level, 1, args.tile)
+        tile = args.tile
+    else:
+        tile = ix.use_tuned_tile(level, 10, qd, od, idd, retune=args.retune)
+        log("tile shape %d (%s)" % (tile, "autotuned" if args.retune else "tuning cache or autotuner"))
     log("warmup %d steps" % args.warmup)
     for _ in range(args.warmup):
         step()
@@ -154,7 +160,7 @@ def bench_c2(args):
     per_pair = (384 + 768 + 12 + 4 + 4) if level == L.LVQ_FULL else (384 + 8 + 4 + 4)
     alg_bytes = per_pair * pairs
     achieved = alg_bytes / (k_avg_ms / 1000.0) / 1e9
-    traffic = read_traffic(pairs) if level == L.LVQ_FULL and args.align == 32 else None
+    traffic = read_traffic(pairs, tile) if level == L.LVQ_FULL and args.align == 32 else None
     log("step %.3f ms, kernel %.3f ms, %.1f GB/s algorithmic" % (ms_step, k_avg_ms, achieved))
     out = {
         "metric": METRIC, "value": value, "unit": "distances/s", "n_gpus": 1, "steps": args.steps,
@@ -163,7 +169,8 @@ def bench_c2(args):
         "config": {"workload": "LVQ-4x8 Turbo inner product, n=1,000,000, d=768, 10,000 queries x "
                                "1,000 candidates, %s level, distances + per-list top-10" % args.level,
                    "n": n, "dim": 768, "bits": "4x8", "layout": "turbo", "row_align": args.align,
-                   "queries": nq, "candidates_per_query": per, "k": 10, "level": args.level},
+                   "queries": nq, "candidates_per_query": per, "k": 10, "level": args.level,
+                   "tile_shape": tile},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_cand (candidate-list similarity + fused top-k)",
@@ -187,6 +194,10 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--nq", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", type=int, default=-1, help="fixed tile shape (default: tuning cache, else autotune)")
+    ap.add_argument("--retune", action="store_true", help="run the autotuner even when the cache has a shape")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run the same "
@@ -196,6 +207,17 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        n = 1 << 28
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": n * 4, "copy_bytes_written_per_launch": n * 4,
+                          "launches": 5}), flush=True)
+        return
     out = bench_c2(args)
     print(json.dumps(out), flush=True)
 

@@ -144,6 +144,20 @@ int lvq_distances(lvq_index *index, const float *q_dev, int64_t nq, const int64_
                   const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev,
                   int32_t k, int32_t *topk_ids_dev, float *topk_dist_dev, void *stream);
 
+/* Tile shapes of the candidate-list kernel (lanes per candidate, bytes per
+ * load, loads per lane, software pipelining; see the library source for the
+ * table).  lvq_autotune runs lvq_distances on the caller's representative
+ * batch with every shape the index's format admits (one warm-up, three timed
+ * repetitions each, HIP events on `stream`), keeps the fastest for this
+ * level and top-k mode (k > 0 or not), and returns its index and the
+ * milliseconds of one call.  It allocates and frees its own output buffers
+ * and synchronises `stream`.  lvq_set_tile selects a shape directly (-1
+ * restores the built-in choice), e.g. from a saved tuning result.          */
+int lvq_autotune(lvq_index *index, const float *q_dev, int64_t nq, const int64_t *offsets_dev,
+                 const int32_t *ids_dev, int64_t total, int32_t level, int32_t k, int32_t *shape_out,
+                 float *ms_out, void *stream);
+int lvq_set_tile(lvq_index *index, int32_t level, int32_t topk, int32_t shape);
+
 /* Exhaustive top-k over every slot live at the call (Sec. 2.1 k-NN problem),
  * for nq queries q_dev (nq x dim) of precision prec: LVQ_FP32 runs the FP32
  * vector path; LVQ_BF16 / LVQ_FP16 take queries already in that type and run

@@ -19,6 +19,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblvq.so")
+TILE_CACHE = os.path.join(HERE, "tile_cache.json")
 
 LVQ_L2, LVQ_IP = 0, 1
 LVQ_SEQUENTIAL, LVQ_TURBO = 0, 1
@@ -37,7 +38,7 @@ LVQ_ERR_BAD_SLOT = -7
 EXPORTS = ["lvq_row_format", "lvq_create", "lvq_destroy", "lvq_set_means", "lvq_encode", "lvq_insert",
            "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_topk", "lvq_read_rows",
            "lvq_get_stats", "lvq_sync", "lvq_mean", "lvq_kmeans", "lvq_strerror", "lvq_set_timing",
-           "lvq_kernel_time"]
+           "lvq_kernel_time", "lvq_autotune", "lvq_set_tile"]
 
 
 class lvq_config(ctypes.Structure):
@@ -84,6 +85,8 @@ def _load():
         "lvq_kmeans": [P, i64, i32, i32, P, i32, P, P],
         "lvq_strerror": [ctypes.c_int],
         "lvq_set_timing": [P, i32],
+        "lvq_autotune": [P, P, i64, P, P, i64, i32, i32, P, P, P],
+        "lvq_set_tile": [P, i32, i32, i32],
         "lvq_kernel_time": [P, P, P],
     }
     for name, args in sig.items():
@@ -171,6 +174,18 @@ def lvq_get_stats(ix) -> lvq_stats:
 def lvq_sync(ix, stream=0) -> int:
     """Returns the sticky kernel error code (0 when none); raises nothing."""
     return _lib.lvq_sync(ix, stream)
+
+
+def lvq_autotune(ix, q, nq, offsets, ids, total, level, k, stream=0):
+    """(chosen shape, milliseconds per call)."""
+    shape, ms = ctypes.c_int32(), ctypes.c_float()
+    _chk(_lib.lvq_autotune(ix, q, nq, offsets, ids, total, level, k, ctypes.byref(shape), ctypes.byref(ms),
+                           stream), "lvq_autotune")
+    return shape.value, ms.value
+
+
+def lvq_set_tile(ix, level, topk, shape):
+    return _chk(_lib.lvq_set_tile(ix, level, topk, shape), "lvq_set_tile")
 
 
 def lvq_set_timing(ix, enable):
@@ -291,6 +306,47 @@ class Index:
 
     def sync(self, stream=None) -> int:
         return lvq_sync(self.handle, _stream(stream))
+
+    def autotune(self, q, offsets, ids, level=LVQ_PRIMARY, k=0, stream=None):
+        return lvq_autotune(self.handle, _ptr(q), q.shape[0], _ptr(offsets), _ptr(ids), ids.shape[0], level, k,
+                            _stream(stream))
+
+    def set_tile(self, level, topk, shape):
+        lvq_set_tile(self.handle, level, int(topk), shape)
+
+    def tile_key(self, level, topk):
+        import torch
+        arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+        c = self.cfg
+        return "%s|d%d|b%dx%d|layout%d|metric%d|align%d|means%s|level%d|topk%d" % (
+            arch, c.dim, c.bits1, c.bits2, c.layout, c.metric, c.align,
+            "1" if self._means.shape[0] == 1 else "M", level, int(bool(topk)))
+
+    def use_tuned_tile(self, level, k, q=None, offsets=None, ids=None, retune=False, cache=TILE_CACHE):
+        """Apply the tile shape recorded for this device and format in the
+        tuning cache (a JSON file); when absent (or retune is set) and a
+        representative batch is given, run the autotuner and record it.
+        Returns the shape, or -1 when neither is available."""
+        import json
+        key = self.tile_key(level, k)
+        table = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if key in table and not retune:
+            shape = int(table[key]["shape"])
+            self.set_tile(level, k > 0, shape)
+            return shape
+        if q is None:
+            return -1
+        shape, ms = self.autotune(q, offsets, ids, level=level, k=k)
+        table[key] = {"shape": shape, "ms": round(ms, 4)}
+        try:
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        except OSError:
+            pass
+        return shape
 
     def set_timing(self, enable=True):
         lvq_set_timing(self.handle, enable)

@@ -61,6 +61,23 @@ __device__ __forceinline__ Words<N> load_words(const uint8_t *p)
     return r;
 }
 
+// w & m, opaque to the optimiser: it keeps the mask-then-convert decoding (one
+// AND per four fields, then v_cvt_f32_ubyte{0..3}) instead of rewriting it
+// into one bit-field extract per field.
+__device__ __forceinline__ uint32_t opaque_and(uint32_t w, uint32_t m)
+{
+    uint32_t r;
+    asm("v_and_b32 %0, %1, %2" : "=v"(r) : "s"(m), "v"(w));
+    return r;
+}
+
+template <int N>
+__device__ __forceinline__ void zero_unless(Words<N> &x, bool ok)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) x.w[i] = ok ? x.w[i] : 0u;
+}
+
 // Accumulators of one candidate.
 struct Acc {
     float a_lo, a_hi;   // first level: low fields, high fields (x16 for 4-bit)
@@ -73,7 +90,7 @@ template <int B1, int B2>
 __device__ __forceinline__ void ip_word(uint32_t w, const float *q, const uint32_t *res, int wi, Acc &A)
 {
     if constexpr (B1 == 4) {
-        const uint32_t lo = w & 0x0F0F0F0Fu, hi = w & 0xF0F0F0F0u;
+        const uint32_t lo = opaque_and(w, 0x0F0F0F0Fu), hi = opaque_and(w, 0xF0F0F0F0u);
         A.a_lo = fmaf(q[0], ub<0>(lo), A.a_lo);
         A.a_lo = fmaf(q[1], ub<1>(lo), A.a_lo);
         A.a_lo = fmaf(q[2], ub<2>(lo), A.a_lo);
@@ -94,7 +111,7 @@ __device__ __forceinline__ void ip_word(uint32_t w, const float *q, const uint32
             A.r_lo = fmaf(q[7], ub<3>(r1), A.r_lo);
         } else if constexpr (B2 == 4) {
             const uint32_t r = res[wi];
-            const uint32_t rl = r & 0x0F0F0F0Fu, rh = r & 0xF0F0F0F0u;
+            const uint32_t rl = opaque_and(r, 0x0F0F0F0Fu), rh = opaque_and(r, 0xF0F0F0F0u);
             A.r_lo = fmaf(q[0], ub<0>(rl), A.r_lo);
             A.r_lo = fmaf(q[1], ub<1>(rl), A.r_lo);
             A.r_lo = fmaf(q[2], ub<2>(rl), A.r_lo);
@@ -116,8 +133,8 @@ __device__ __forceinline__ void ip_word(uint32_t w, const float *q, const uint32
             A.r_lo = fmaf(q[2], ub<2>(r), A.r_lo);
             A.r_lo = fmaf(q[3], ub<3>(r), A.r_lo);
         } else if constexpr (B2 == 4) {
-            const uint32_t h = (res[wi >> 1] >> (16 * (wi & 1))) & 0xFFFFu;
-            const uint32_t rl = h & 0x0F0Fu, rh = h & 0xF0F0u;
+            const uint32_t h = res[wi >> 1] >> (16 * (wi & 1));
+            const uint32_t rl = opaque_and(h, 0x0F0Fu), rh = opaque_and(h, 0xF0F0u);
             A.r_lo = fmaf(q[0], ub<0>(rl), A.r_lo);
             A.r_lo = fmaf(q[2], ub<1>(rl), A.r_lo);
             A.r_hi = fmaf(q[1], ub<0>(rh), A.r_hi);
@@ -152,7 +169,7 @@ __device__ __forceinline__ void l2_word(uint32_t w, const float *q, const float 
                                         int wi, const L2Row &R, float &acc)
 {
     if constexpr (B1 == 4) {
-        const uint32_t lo = w & 0x0F0F0F0Fu, hi = w & 0xF0F0F0F0u;
+        const uint32_t lo = opaque_and(w, 0x0F0F0F0Fu), hi = opaque_and(w, 0xF0F0F0F0u);
         float c2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         float s2lo = R.d2, s2hi = R.d2;
         if constexpr (B2 == 8) {
@@ -161,7 +178,7 @@ __device__ __forceinline__ void l2_word(uint32_t w, const float *q, const float 
             c2[4] = ub<1>(r0); c2[5] = ub<3>(r0); c2[6] = ub<1>(r1); c2[7] = ub<3>(r1);
         } else if constexpr (B2 == 4) {
             const uint32_t r = res[wi];
-            const uint32_t rl = r & 0x0F0F0F0Fu, rh = r & 0xF0F0F0F0u;
+            const uint32_t rl = opaque_and(r, 0x0F0F0F0Fu), rh = opaque_and(r, 0xF0F0F0F0u);
             c2[0] = ub<0>(rl); c2[1] = ub<1>(rl); c2[2] = ub<2>(rl); c2[3] = ub<3>(rl);
             c2[4] = ub<0>(rh); c2[5] = ub<1>(rh); c2[6] = ub<2>(rh); c2[7] = ub<3>(rh);
             s2hi = R.d216;
@@ -181,8 +198,8 @@ __device__ __forceinline__ void l2_word(uint32_t w, const float *q, const float 
             const uint32_t r = res[wi];
             c2[0] = ub<0>(r); c2[1] = ub<1>(r); c2[2] = ub<2>(r); c2[3] = ub<3>(r);
         } else if constexpr (B2 == 4) {
-            const uint32_t h = (res[wi >> 1] >> (16 * (wi & 1))) & 0xFFFFu;
-            const uint32_t rl = h & 0x0F0Fu, rh = h & 0xF0F0u;
+            const uint32_t h = res[wi >> 1] >> (16 * (wi & 1));
+            const uint32_t rl = opaque_and(h, 0x0F0Fu), rh = opaque_and(h, 0xF0F0u);
             c2[0] = ub<0>(rl); c2[2] = ub<1>(rl); c2[1] = ub<0>(rh); c2[3] = ub<1>(rh);
             s2[1] = R.d216; s2[3] = R.d216;
         }
@@ -205,11 +222,141 @@ __device__ __forceinline__ int qtab_index(int s, int npieces)
     return ((w >> 2) * npieces + u) * 4 + (w & 3);
 }
 
-template <int B1, int B2, int METRIC, bool MULTI, bool MASK, int G, int CH, int NCH>
-__global__ __launch_bounds__(256) void k_cand(CandArgs a)
+// One candidate's row data as loaded by a lane of its group.
+template <int B1, int B2, int CH, int NCH>
+struct PairRegs {
+    Words<CandGeom<B1, CH>::kWords> wv[NCH];
+    Words<ResGeom<B1, B2, CH>::kWords> rv[NCH];
+    float4 hdr;
+    int32_t slot;
+    bool valid, work;
+};
+
+// Issue the loads of one candidate (entry e of a list ending at e1): the
+// header and the pieces p0 + c*G + g of the first-level and residual codes.
+// Branch-free: out-of-range pieces and invalid candidates load from a valid
+// address (slot 0, piece 0) and are zeroed by a select, so the values stay in
+// registers.
+template <int B1, int B2, int G, int CH, int NCH>
+__device__ __forceinline__ void load_pair(PairRegs<B1, B2, CH, NCH> &P, const CandArgs &a, int64_t e,
+                                          int64_t e1, int32_t slot, int p0, int g, int npieces)
 {
     using Geo = CandGeom<B1, CH>;
     using RGeo = ResGeom<B1, B2, CH>;
+    P.valid = e < e1;
+    P.slot = slot;
+    const bool in_range = slot >= 0 && (int64_t)slot < a.capacity;
+    P.work = P.valid && in_range;
+    const int64_t s = P.work ? slot : 0;
+    const uint8_t *row = a.rows + s * a.row_bytes;
+    const uint8_t *res = B2 ? a.resid + s * a.resid_bytes : nullptr;
+    if (p0 == 0) {
+        float4 h = *reinterpret_cast<const float4 *>(row);
+        P.hdr = P.work ? h : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int u = p0 + c * G + g;
+        const bool ok = P.work && u < npieces;
+        const int uu = u < npieces ? u : 0;
+        P.wv[c] = load_words<Geo::kWords>(row + kHeaderBytes + uu * CH);
+        zero_unless(P.wv[c], ok);
+        if constexpr (B2 != 0) {
+            P.rv[c] = load_words<RGeo::kWords>(res + uu * RGeo::kBytes);
+            zero_unless(P.rv[c], ok);
+        }
+    }
+}
+
+// Query values of the pieces a lane owns, held in registers for a whole list
+// (single-round shapes: a lane handles the same pieces for every candidate).
+template <int B1, int CH, int NCH>
+struct QRegs {
+    float4 v[NCH][CandGeom<B1, CH>::kF4];
+};
+
+// Accumulate the loaded pieces of one candidate; query values come from the
+// LDS table tq or, when QREG is set, from registers.  Pieces past the end
+// (u >= npieces) hold zero codes; their L2 contribution is dropped by a
+// select, their IP contribution is zero already.
+template <int B1, int B2, int METRIC, bool MASK, int G, int CH, int NCH, bool QREG>
+__device__ __forceinline__ void accumulate_pair(const PairRegs<B1, B2, CH, NCH> &P, const float *tq,
+                                                const QRegs<B1, CH, NCH> &qr, const float *mtab, int p0,
+                                                int g, int npieces, const L2Row &R, Acc &A, float &l2acc)
+{
+    using Geo = CandGeom<B1, CH>;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int u = p0 + c * G + g;
+        const bool ok = u < npieces;
+        const int uu = ok ? u : 0;
+        float qv[Geo::kSlots];
+        float mv[MASK ? Geo::kSlots : 1];
+#pragma unroll
+        for (int r = 0; r < Geo::kF4; ++r) {
+            float4 f = QREG ? qr.v[c][r] : reinterpret_cast<const float4 *>(tq)[r * npieces + uu];
+            qv[4 * r] = f.x; qv[4 * r + 1] = f.y; qv[4 * r + 2] = f.z; qv[4 * r + 3] = f.w;
+            if constexpr (MASK) {
+                float4 mm = reinterpret_cast<const float4 *>(mtab)[r * npieces + uu];
+                mv[4 * r] = mm.x; mv[4 * r + 1] = mm.y; mv[4 * r + 2] = mm.z; mv[4 * r + 3] = mm.w;
+            }
+        }
+        constexpr int kQW = B1 == 4 ? 8 : 4;   // query values per word
+        float part = 0.0f;
+#pragma unroll
+        for (int wi = 0; wi < Geo::kWords; ++wi) {
+            if constexpr (METRIC == LVQ_IP)
+                ip_word<B1, B2>(P.wv[c].w[wi], qv + kQW * wi, P.rv[c].w, wi, A);
+            else
+                l2_word<B1, B2, MASK>(P.wv[c].w[wi], qv + kQW * wi, MASK ? mv + kQW * wi : nullptr,
+                                      P.rv[c].w, wi, R, part);
+        }
+        if constexpr (METRIC == LVQ_L2) l2acc += ok ? part : 0.0f;
+    }
+}
+
+template <int B2>
+__device__ __forceinline__ L2Row l2_row(float4 hdr)
+{
+    L2Row R;
+    R.lp = B2 ? hdr.x - 0.5f * hdr.y : hdr.x;
+    R.dl = hdr.y;
+    R.dl16 = hdr.y * 0.0625f;
+    R.d2 = B2 ? hdr.z : 0.0f;
+    R.d216 = hdr.z * 0.0625f;
+    return R;
+}
+
+// Final value of one candidate from its group's accumulators (all lanes of
+// the group return the same value).
+template <int B2, int METRIC, int G>
+__device__ __forceinline__ float finish_pair(const Acc &A, float l2acc, float4 hdr, const float *cmt, int n_means,
+                                             float qsum)
+{
+    if constexpr (METRIC == LVQ_IP) {
+        float a1 = fmaf(A.a_hi, 0.0625f, A.a_lo);
+        a1 = group_sum<G>(a1);
+        const float l = hdr.x, dl = hdr.y, dl2 = hdr.z;
+        const int mid = (int)(__float_as_uint(hdr.w) & 0xFFu);
+        const float lp = B2 ? l - 0.5f * dl : l;
+        float score = fmaf(lp, qsum, cmt[mid < n_means ? mid : 0]);
+        score = fmaf(dl, a1, score);
+        if constexpr (B2 != 0) {
+            float a2 = fmaf(A.r_hi, 0.0625f, A.r_lo);
+            a2 = group_sum<G>(a2);
+            score = fmaf(dl2, a2, score);
+        }
+        return score;
+    } else {
+        return group_sum<G>(l2acc);
+    }
+}
+
+template <int B1, int B2, int METRIC, bool MULTI, bool MASK, int G, int CH, int NCH, bool PIPE, bool QREG>
+__global__ __launch_bounds__(256) void k_cand(CandArgs a)
+{
+    static_assert(!QREG || (PIPE && !MULTI && !MASK), "register-resident query needs one table, one round");
+    using Regs = PairRegs<B1, B2, CH, NCH>;
     constexpr int kPairsPerWave = 64 / G;
     constexpr int kPairsPerBlock = 4 * kPairsPerWave;
 
@@ -262,106 +409,91 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
         for (int m = tid; m < cm_n; m += 256) cmt[m] = a.cm[list * a.n_means + m];
         __syncthreads();
         const float qsum = METRIC == LVQ_IP ? a.qsum[list] : 0.0f;
+        QRegs<B1, CH, NCH> qr;
+        if constexpr (QREG) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int u = c * G + g;
+#pragma unroll
+                for (int r = 0; r < CandGeom<B1, CH>::kF4; ++r) {
+                    const float4 f = reinterpret_cast<const float4 *>(qtab)[r * npieces + (u < npieces ? u : 0)];
+                    qr.v[c][r] = u < npieces ? f : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+        }
 
         int nbuf = 0;        // keys held in the LDS buffer (block-uniform)
         const int k = a.k;
+        const int64_t my = (int64_t)wave * kPairsPerWave + grp;   // entry offset inside a block of pairs
+
+        Regs cur;
+        int32_t slot_next = 0;
+        if constexpr (PIPE) {
+            // two-stage software pipeline: the next candidate's id and row
+            // loads are in flight while the current one is consumed
+            const int64_t e = e0 + my;
+            const int32_t s0 = e < e1 ? a.ids[e] : 0;
+            load_pair<B1, B2, G, CH, NCH>(cur, a, e, e1, s0, 0, g, npieces);
+            slot_next = e + kPairsPerBlock < e1 ? a.ids[e + kPairsPerBlock] : 0;
+        }
         for (int64_t base = e0; base < e1; base += kPairsPerBlock) {
-            const int64_t e = base + wave * kPairsPerWave + grp;
-            const bool valid = e < e1;
-            int32_t slot = valid ? a.ids[e] : 0;
-            bool in_range = slot >= 0 && (int64_t)slot < a.capacity;
-            if (valid && !in_range && g == 0) atomicOr(a.err, kErrBadSlot);
-            const bool work = valid && in_range;
-            const uint8_t *row = a.rows + (int64_t)(work ? slot : 0) * a.row_bytes;
-            const uint8_t *res = B2 ? a.resid + (int64_t)(work ? slot : 0) * a.resid_bytes : nullptr;
-
-            float4 hdr = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (work) hdr = *reinterpret_cast<const float4 *>(row);
-            const float l = hdr.x, dl = hdr.y, dl2 = hdr.z;
-            const int mid = (int)(__float_as_uint(hdr.w) & 0xFFu);
-
+            const int64_t e = base + my;
             Acc A{0.f, 0.f, 0.f, 0.f};
             float l2acc = 0.0f;
-            L2Row R;
-            if constexpr (METRIC == LVQ_L2) {
-                R.lp = B2 ? l - 0.5f * dl : l;
-                R.dl = dl;
-                R.dl16 = dl * 0.0625f;
-                R.d2 = B2 ? dl2 : 0.0f;
-                R.d216 = dl2 * 0.0625f;
-            }
-            const float *tq = qtab + ((METRIC == LVQ_L2 && MULTI) ? (size_t)(mid < a.n_means ? mid : 0) * a.kpos : 0);
-
-            for (int p0 = 0; p0 < npieces; p0 += G * NCH) {
-                Words<Geo::kWords> wv[NCH];
-                Words<RGeo::kWords> rv[NCH];
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    const int u = p0 + c * G + g;
-                    if (work && u < npieces) {
-                        wv[c] = load_words<Geo::kWords>(row + kHeaderBytes + u * CH);
-                        if constexpr (B2 != 0) rv[c] = load_words<RGeo::kWords>(res + u * RGeo::kBytes);
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < Geo::kWords; ++i) wv[c].w[i] = 0;
-#pragma unroll
-                        for (int i = 0; i < RGeo::kWords; ++i) rv[c].w[i] = 0;
-                    }
-                }
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    const int u = p0 + c * G + g;
-                    if (u >= npieces) continue;
-                    float qv[Geo::kSlots];
-                    float mv[MASK ? Geo::kSlots : 1];
-#pragma unroll
-                    for (int r = 0; r < Geo::kF4; ++r) {
-                        float4 f = reinterpret_cast<const float4 *>(tq)[r * npieces + u];
-                        qv[4 * r] = f.x; qv[4 * r + 1] = f.y; qv[4 * r + 2] = f.z; qv[4 * r + 3] = f.w;
-                        if constexpr (MASK) {
-                            float4 mm = reinterpret_cast<const float4 *>(mtab)[r * npieces + u];
-                            mv[4 * r] = mm.x; mv[4 * r + 1] = mm.y; mv[4 * r + 2] = mm.z; mv[4 * r + 3] = mm.w;
-                        }
-                    }
-                    constexpr int kQW = B1 == 4 ? 8 : 4;   // query values per word
-#pragma unroll
-                    for (int wi = 0; wi < Geo::kWords; ++wi) {
-                        if constexpr (METRIC == LVQ_IP)
-                            ip_word<B1, B2>(wv[c].w[wi], qv + kQW * wi, rv[c].w, wi, A);
-                        else
-                            l2_word<B1, B2, MASK>(wv[c].w[wi], qv + kQW * wi, MASK ? mv + kQW * wi : nullptr,
-                                                  rv[c].w, wi, R, l2acc);
-                    }
-                }
-            }
-
-            float score;
-            if constexpr (METRIC == LVQ_IP) {
-                float a1 = fmaf(A.a_hi, 0.0625f, A.a_lo);
-                float a2 = fmaf(A.r_hi, 0.0625f, A.r_lo);
-                a1 = group_sum<G>(a1);
-                if constexpr (B2 != 0) a2 = group_sum<G>(a2);
-                const float lp = B2 ? l - 0.5f * dl : l;
-                const float cmv = cmt[mid < a.n_means ? mid : 0];
-                score = fmaf(lp, qsum, cmv);
-                score = fmaf(dl, a1, score);
-                if constexpr (B2 != 0) score = fmaf(dl2, a2, score);
+            float4 hdr;
+            bool valid, work;
+            int32_t slot;
+            if constexpr (PIPE) {
+                Regs nxt;
+                const int64_t en = e + kPairsPerBlock;
+                load_pair<B1, B2, G, CH, NCH>(nxt, a, en, e1, slot_next, 0, g, npieces);
+                slot_next = en + kPairsPerBlock < e1 ? a.ids[en + kPairsPerBlock] : 0;
+                hdr = cur.hdr;
+                const float *tq = qtab + ((METRIC == LVQ_L2 && MULTI)
+                                              ? (size_t)min((int)(__float_as_uint(hdr.w) & 0xFFu), a.n_means - 1) * a.kpos
+                                              : 0);
+                const L2Row R = l2_row<B2>(hdr);
+                accumulate_pair<B1, B2, METRIC, MASK, G, CH, NCH, QREG>(cur, tq, qr, mtab, 0, g, npieces, R, A,
+                                                                        l2acc);
+                valid = cur.valid;
+                work = cur.work;
+                slot = cur.slot;
+                cur = nxt;
             } else {
-                score = group_sum<G>(l2acc);
+                valid = e < e1;
+                slot = valid ? a.ids[e] : 0;
+                Regs P;
+                load_pair<B1, B2, G, CH, NCH>(P, a, e, e1, slot, 0, g, npieces);
+                hdr = P.hdr;
+                work = P.work;
+                const float *tq = qtab + ((METRIC == LVQ_L2 && MULTI)
+                                              ? (size_t)min((int)(__float_as_uint(hdr.w) & 0xFFu), a.n_means - 1) * a.kpos
+                                              : 0);
+                const L2Row R = l2_row<B2>(hdr);
+                accumulate_pair<B1, B2, METRIC, MASK, G, CH, NCH, false>(P, tq, qr, mtab, 0, g, npieces, R, A,
+                                                                         l2acc);
+                for (int p0 = G * NCH; p0 < npieces; p0 += G * NCH) {
+                    load_pair<B1, B2, G, CH, NCH>(P, a, e, e1, slot, p0, g, npieces);
+                    accumulate_pair<B1, B2, METRIC, MASK, G, CH, NCH, false>(P, tq, qr, mtab, p0, g, npieces, R,
+                                                                             A, l2acc);
+                }
             }
-            if (valid && !in_range) score = __uint_as_float(0x7FC00000u);
 
-            if (valid && g == 0) {
-                if (a.dist) a.dist[e] = score;
+            float score = finish_pair<B2, METRIC, G>(A, l2acc, hdr, cmt, a.n_means, qsum);
+            if (valid && !work) {
+                score = __uint_as_float(0x7FC00000u);
+                if (g == 0) atomicOr(a.err, kErrBadSlot);
             }
+            if (valid && g == 0 && a.dist) a.dist[e] = score;
             if (k > 0) {
                 if (valid && g == 0) {
                     uint64_t key = kNoKey;
                     if (work) {
+                        const uint8_t *row = a.rows + (int64_t)slot * a.row_bytes;
                         uint2 ep = *reinterpret_cast<const uint2 *>(row + 16);
                         const bool live = ((__float_as_uint(hdr.w) >> 8) & 1u) && ep.x <= a.epoch &&
                                           a.epoch < ep.y;
-                        if (live) key = make_key(score, slot, LVQ_IP == METRIC ? LVQ_IP : LVQ_L2);
+                        if (live) key = make_key(score, slot, METRIC);
                     }
                     keys[nbuf + (int)(e - base)] = key;
                 }

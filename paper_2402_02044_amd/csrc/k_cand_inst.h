@@ -9,13 +9,30 @@ namespace lvq {
 // (lanes per candidate, bytes per piece, pieces per lane and round)
 using CandShape = TileShape;
 constexpr CandShape kCandShapes[] = {
-    {16, 16, 4},  // generic: 1024 code bytes per round
-    {16, 8, 3},   // 384 bytes (4-bit d = 768)
-    {8, 16, 3},   // 384 bytes
-    {4, 8, 3},    // 96 bytes (8-bit d = 96)
-    {16, 16, 2},  // 512 bytes (8-bit d = 512)
-    {8, 16, 4},   // 512 bytes
-    {2, 16, 3},   // 96 bytes
+    {16, 16, 4, 0},  // generic: 1024 code bytes per round
+    {16, 8, 3, 0},   // 384 bytes (4-bit d = 768)
+    {8, 16, 3, 0},   // 384 bytes
+    {4, 8, 3, 0},    // 96 bytes (8-bit d = 96)
+    {16, 16, 2, 0},  // 512 bytes (8-bit d = 512)
+    {8, 16, 4, 0},   // 512 bytes
+    {2, 16, 3, 0},   // 96 bytes
+    // software-pipelined (next candidate's loads in flight), single round
+    {16, 8, 3, 1},   // 384 bytes
+    {8, 16, 3, 1},   // 384 bytes
+    {4, 8, 3, 1},    // 96 bytes
+    {16, 16, 2, 1},  // 512 bytes
+    {8, 16, 4, 1},   // 512 bytes
+    {2, 16, 3, 1},   // 96 bytes
+    {8, 8, 6, 1},    // 384 bytes
+    {4, 16, 6, 1},   // 384 bytes
+    // pipelined, query values in registers (inner product, one-mean L2)
+    {16, 8, 3, 3},   // 384 bytes
+    {8, 8, 6, 3},    // 384 bytes
+    {8, 16, 3, 3},   // 384 bytes
+    {16, 16, 2, 3},  // 512 bytes
+    {4, 8, 3, 3},    // 96 bytes
+    {2, 16, 3, 3},   // 96 bytes
+    {16, 8, 4, 3},   // 512 bytes
 };
 constexpr int kNumCandShapes = sizeof(kCandShapes) / sizeof(kCandShapes[0]);
 
@@ -28,14 +45,16 @@ constexpr CandKernel cand_kernel_for(int variant)
 {
     constexpr CandShape sh = kCandShapes[S];
     switch (variant) {
-    case 0: return k_cand<B1, B2, LVQ_IP, false, false, sh.g, sh.ch, sh.nch>;
-    case 1: return k_cand<B1, B2, LVQ_L2, false, false, sh.g, sh.ch, sh.nch>;
-    case 2: return k_cand<B1, B2, LVQ_L2, true, false, sh.g, sh.ch, sh.nch>;
+    case 0: return k_cand<B1, B2, LVQ_IP, false, false, sh.g, sh.ch, sh.nch, sh.pipe != 0, (sh.pipe & 2) != 0>;
+    case 1: return k_cand<B1, B2, LVQ_L2, false, false, sh.g, sh.ch, sh.nch, sh.pipe != 0, (sh.pipe & 2) != 0>;
+    case 2:
+        if constexpr ((sh.pipe & 2) == 0) return k_cand<B1, B2, LVQ_L2, true, false, sh.g, sh.ch, sh.nch, sh.pipe != 0, false>;
+        return nullptr;
     default: break;
     }
     if constexpr (S == 0) {
-        if (variant == 3) return k_cand<B1, B2, LVQ_L2, false, true, sh.g, sh.ch, sh.nch>;
-        if (variant == 4) return k_cand<B1, B2, LVQ_L2, true, true, sh.g, sh.ch, sh.nch>;
+        if (variant == 3) return k_cand<B1, B2, LVQ_L2, false, true, sh.g, sh.ch, sh.nch, false, false>;
+        if (variant == 4) return k_cand<B1, B2, LVQ_L2, true, true, sh.g, sh.ch, sh.nch, false, false>;
     }
     return nullptr;
 }
@@ -51,6 +70,21 @@ inline CandKernel cand_lookup(int variant, int shape)
     case 4: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 4>(variant);
     case 5: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 5>(variant);
     case 6: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 6>(variant);
+    case 7: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 7>(variant);
+    case 8: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 8>(variant);
+    case 9: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 9>(variant);
+    case 10: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 10>(variant);
+    case 11: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 11>(variant);
+    case 12: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 12>(variant);
+    case 13: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 13>(variant);
+    case 14: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 14>(variant);
+    case 15: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 15>(variant);
+    case 16: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 16>(variant);
+    case 17: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 17>(variant);
+    case 18: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 18>(variant);
+    case 19: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 19>(variant);
+    case 20: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 20>(variant);
+    case 21: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 21>(variant);
     default: return nullptr;
     }
 }

@@ -281,6 +281,7 @@ int default_shape(const Format &f, void *(*lookup)(int, int, int), int bits2, in
         TileShape t = tile_shape(i);
         const int round = t.g * t.ch * t.nch;
         const int rounds = (bytes + round - 1) / round;
+        if (t.pipe && rounds > 1) continue;
         const double waste = (double)rounds * round / bytes;
         const double cost = waste * 16.0 / t.g + (rounds > 1 ? 0.5 * rounds : 0.0);
         if (cost < best_cost) {
@@ -289,6 +290,13 @@ int default_shape(const Format &f, void *(*lookup)(int, int, int), int bits2, in
         }
     }
     return best;
+}
+
+bool shape_fits(const Format &f, void *(*lookup)(int, int, int), int bits2, int variant, int shape)
+{
+    if (shape < 0 || shape >= num_tile_shapes() || !lookup(bits2, variant, shape)) return false;
+    TileShape t = tile_shape(shape);
+    return !t.pipe || t.g * t.ch * t.nch >= f.kchunks * 16;
 }
 
 }  // namespace
@@ -539,9 +547,9 @@ int lvq_consolidate(lvq_index *ix, void *stream, int64_t *n_freed_out)
     return note_update(ix, s);
 }
 
-int lvq_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev, const int32_t *ids_dev,
-                  int64_t total, int32_t level, float *dist_dev, int32_t k, int32_t *topk_ids_dev,
-                  float *topk_dist_dev, void *stream)
+static int distances_impl(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev,
+                          const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev, int32_t k,
+                          int32_t *topk_ids_dev, float *topk_dist_dev, hipStream_t s, int force_shape)
 {
     if (!ix || nq < 0 || total < 0 || nq > INT32_MAX) return LVQ_ERR_INVALID_ARG;
     if (level != LVQ_PRIMARY && level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
@@ -552,8 +560,6 @@ int lvq_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *
     if (k > 0 && (!topk_ids_dev || !topk_dist_dev)) return LVQ_ERR_INVALID_ARG;
     if (ix->cfg.capacity == 0) return LVQ_ERR_INVALID_ARG;
     if (level == LVQ_FULL && ix->f.bits2 == 0) return LVQ_ERR_INVALID_ARG;
-    std::lock_guard<std::mutex> lk(ix->mu);
-    hipStream_t s = (hipStream_t)stream;
     const Format &f = ix->f;
     const int bits2 = level == LVQ_FULL ? f.bits2 : 0;
     const bool l2 = ix->cfg.metric == LVQ_L2;
@@ -561,8 +567,11 @@ int lvq_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *
     const bool masked = l2 && f.kpos != f.dim;
     const int variant = !l2 ? 0 : (masked ? (multi ? 4 : 3) : (multi ? 2 : 1));
     auto lookup = f.bits1 == 4 ? cand_kernel_b4 : cand_kernel_b8;
-    int shape = ix->cand_shape[level == LVQ_FULL][k > 0];
-    if (shape < 0 || !lookup(bits2, variant, shape)) shape = default_shape(f, lookup, bits2, variant);
+    int shape = force_shape >= 0 ? force_shape : ix->cand_shape[level == LVQ_FULL][k > 0];
+    if (!shape_fits(f, lookup, bits2, variant, shape)) {
+        if (force_shape >= 0) return LVQ_ERR_UNSUPPORTED;
+        shape = default_shape(f, lookup, bits2, variant);
+    }
     void *kern = shape >= 0 ? lookup(bits2, variant, shape) : nullptr;
     if (!kern) return LVQ_ERR_UNSUPPORTED;
     const int ntab = multi ? ix->n_means : 1;
@@ -613,6 +622,76 @@ int lvq_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *
     LVQ_HIP(hipGetLastError());
     if ((rc = timing_end(ix, s))) return rc;
     return note_query(ix, s, ix->epoch);
+}
+
+int lvq_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev, const int32_t *ids_dev,
+                  int64_t total, int32_t level, float *dist_dev, int32_t k, int32_t *topk_ids_dev,
+                  float *topk_dist_dev, void *stream)
+{
+    if (!ix) return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    return distances_impl(ix, q_dev, nq, offsets_dev, ids_dev, total, level, dist_dev, k, topk_ids_dev,
+                          topk_dist_dev, (hipStream_t)stream, -1);
+}
+
+int lvq_set_tile(lvq_index *ix, int32_t level, int32_t topk, int32_t shape)
+{
+    if (!ix || (level != LVQ_PRIMARY && level != LVQ_FULL) || shape < -1 || shape >= num_tile_shapes())
+        return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    ix->cand_shape[level == LVQ_FULL][topk != 0] = shape;
+    return LVQ_OK;
+}
+
+int lvq_autotune(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev, const int32_t *ids_dev,
+                 int64_t total, int32_t level, int32_t k, int32_t *shape_out, float *ms_out, void *stream)
+{
+    if (!ix || nq < 1 || total < 0 || k < 0 || k > kMaxTopK) return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    float *dist = nullptr;
+    int32_t *ti = nullptr;
+    float *td = nullptr;
+    LVQ_HIP(hipMalloc((void **)&dist, sizeof(float) * (size_t)std::max<int64_t>(total, 1)));
+    if (k > 0) {
+        LVQ_HIP(hipMalloc((void **)&ti, sizeof(int32_t) * (size_t)nq * k));
+        LVQ_HIP(hipMalloc((void **)&td, sizeof(float) * (size_t)nq * k));
+    }
+    hipEvent_t a, b;
+    LVQ_HIP(hipEventCreate(&a));
+    LVQ_HIP(hipEventCreate(&b));
+    int best = -1;
+    float best_ms = 0.0f;
+    int rc = LVQ_OK;
+    for (int i = 0; i < num_tile_shapes() && rc == LVQ_OK; ++i) {
+        if (distances_impl(ix, q_dev, nq, offsets_dev, ids_dev, total, level, dist, k, ti, td, s, i) != LVQ_OK)
+            continue;   // shape not available for this format
+        float ms = 0.0f;
+        if (hipEventRecord(a, s) != hipSuccess) { rc = LVQ_ERR_DEVICE; break; }
+        for (int r = 0; r < 3 && rc == LVQ_OK; ++r)
+            rc = distances_impl(ix, q_dev, nq, offsets_dev, ids_dev, total, level, dist, k, ti, td, s, i);
+        if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+            hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+            rc = LVQ_ERR_DEVICE;
+            break;
+        }
+        if (best < 0 || ms < best_ms) {
+            best = i;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(dist);
+    if (ti) (void)hipFree(ti);
+    if (td) (void)hipFree(td);
+    if (rc) return rc;
+    if (best < 0) return LVQ_ERR_UNSUPPORTED;
+    ix->cand_shape[level == LVQ_FULL][k > 0] = best;
+    if (shape_out) *shape_out = best;
+    if (ms_out) *ms_out = best_ms / 3.0f;
+    return LVQ_OK;
 }
 
 int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level, int32_t *ids_dev,

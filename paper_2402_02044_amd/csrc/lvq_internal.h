@@ -128,6 +128,8 @@ hipError_t launch_prep(const PrepArgs &a, hipStream_t s);
 // masked, 4 L2 masked several means.  scan variants: 0 IP, 1 L2, 2 L2 masked.
 struct TileShape {
     int g, ch, nch;   // lanes per candidate, bytes per piece, pieces per lane and round
+    int pipe;         // bit 0: software-pipelined single-round candidate loop;
+                      // bit 1: query values held in registers for a whole list
 };
 int num_tile_shapes();
 TileShape tile_shape(int i);
