@@ -694,6 +694,9 @@ int lvq_autotune(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *o
     return LVQ_OK;
 }
 
+static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level,
+                     int32_t *ids_dev, float *dist_dev, hipStream_t s);
+
 int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level, int32_t *ids_dev,
              float *dist_dev, void *stream)
 {
@@ -703,10 +706,10 @@ int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t
     if (nq == 0) return LVQ_OK;
     if (!q_dev || !ids_dev || !dist_dev) return LVQ_ERR_INVALID_ARG;
     if (level == LVQ_FULL && ix->f.bits2 == 0) return LVQ_ERR_INVALID_ARG;
-    if (prec != LVQ_FP32) return LVQ_ERR_UNSUPPORTED;
     std::lock_guard<std::mutex> lk(ix->mu);
     hipStream_t s = (hipStream_t)stream;
     const Format &f = ix->f;
+    if (prec != LVQ_FP32) return topk_mfma(ix, q_dev, prec, nq, k, level, ids_dev, dist_dev, s);
     const bool l2 = ix->cfg.metric == LVQ_L2;
     if (l2 && ix->n_means > 1) return LVQ_ERR_UNSUPPORTED;
     const bool masked = l2 && f.kpos != f.dim;
@@ -771,6 +774,63 @@ int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t
     LVQ_HIP(hipGetLastError());
     if ((rc = timing_end(ix, s))) return rc;
     LVQ_HIP(launch_topk_merge(a.part_keys, nq, (int)parts, k, ix->cfg.metric, ids_dev, dist_dev, s));
+    return note_query(ix, s, ix->epoch);
+}
+
+// Exhaustive top-k on the matrix cores: inner product, first level only.
+static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level,
+                     int32_t *ids_dev, float *dist_dev, hipStream_t s)
+{
+    const Format &f = ix->f;
+    if (ix->cfg.metric != LVQ_IP || level != LVQ_PRIMARY) return LVQ_ERR_UNSUPPORTED;
+    const int qb = mfma_query_block(f.bits1, f.kpos);
+    if (!qb) return LVQ_ERR_UNSUPPORTED;
+    const size_t lds = mfma_lds_bytes(qb, ix->n_means, k);
+    if (lds > ix->lds_max) return LVQ_ERR_UNSUPPORTED;
+    int rc = order_after_updates(ix, s);
+    if (rc) return rc;
+    Workspace &w = workspace(ix, s);
+    const int tq = 32 * qb;
+    const int64_t qtiles = (nq + tq - 1) / tq;
+    if ((rc = dev_alloc(ix, w.q16, (size_t)qtiles * tq * f.kpos * 2))) return rc;
+    if ((rc = dev_alloc(ix, w.qsum, sizeof(float) * (size_t)nq))) return rc;
+    if ((rc = dev_alloc(ix, w.cm, sizeof(float) * (size_t)nq * ix->n_means))) return rc;
+    LVQ_HIP(launch_prep16(q_dev, nq, f.dim, f.kpos, f.bits1, prec, P<int32_t>(ix->kdim), P<float>(ix->means),
+                          ix->n_means, w.q16.p, P<float>(w.qsum), P<float>(w.cm), s));
+    const int64_t n_rows = ix->cfg.capacity - ix->fresh;
+    // about eight rounds of one workgroup per compute unit, parts of at least
+    // a few row rounds, and a merge that fits one workgroup's LDS
+    int64_t parts = std::max<int64_t>(1, (8 * (int64_t)ix->n_cu + qtiles - 1) / qtiles);
+    parts = std::min<int64_t>(parts, std::max<int64_t>(1, n_rows / 1024));
+    parts = std::min<int64_t>(parts, std::max<int64_t>(1, (int64_t)(ix->lds_max / 8 - k) / k));
+    const int64_t rows_per_part = std::max<int64_t>(1, (n_rows + parts - 1) / parts);
+    if ((rc = dev_alloc(ix, w.part, sizeof(uint64_t) * (size_t)nq * parts * k))) return rc;
+    ScanArgs a;
+    a.rows = P<uint8_t>(ix->rows);
+    a.resid = P<uint8_t>(ix->resid);
+    a.row_bytes = f.row_bytes;
+    a.resid_bytes = f.resid_bytes;
+    a.kchunks = f.kchunks;
+    a.kpos = f.kpos;
+    a.n_rows = n_rows;
+    a.qk = nullptr;
+    a.qsum = P<float>(w.qsum);
+    a.cm = P<float>(w.cm);
+    a.muk = nullptr;
+    a.kmask = nullptr;
+    a.q16 = w.q16.p;
+    a.n_means = ix->n_means;
+    a.nq = nq;
+    a.k = k;
+    a.epoch = ix->epoch;
+    a.rows_per_part = rows_per_part;
+    a.n_parts = (int)parts;
+    a.part_keys = P<uint64_t>(w.part);
+    a.err = P<uint32_t>(ix->err);
+    if ((rc = timing_begin(ix, s))) return rc;
+    LVQ_HIP(launch_scan_mfma(a, f.bits1, prec, s));
+    if ((rc = timing_end(ix, s))) return rc;
+    LVQ_HIP(launch_topk_merge(a.part_keys, nq, (int)parts, k, LVQ_IP, ids_dev, dist_dev, s));
     return note_query(ix, s, ix->epoch);
 }
 

@@ -145,6 +145,13 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_list_order(const int64_t *offsets, int64_t nq, int32_t *order, int32_t *scratch,
                              hipStream_t s);
 hipError_t launch_scan_mfma(const ScanArgs &a, int bits1, int prec, hipStream_t s);
+// MFMA exhaustive scan: 32-query blocks per workgroup for a format (0 when
+// the code width / position count has no instantiation), its LDS bytes, and
+// the query-fragment precompute for bf16 / fp16 queries.
+int mfma_query_block(int bits1, int kpos);
+size_t mfma_lds_bytes(int qb, int n_means, int k);
+hipError_t launch_prep16(const void *q, int64_t nq, int dim, int kpos, int bits1, int prec, const int32_t *kdim,
+                         const float *means, int n_means, void *frag, float *qsum, float *cm, hipStream_t s);
 hipError_t launch_topk_merge(const uint64_t *part_keys, int64_t nq, int n_parts, int k, int metric,
                              int32_t *ids, float *dist, hipStream_t s);
 hipError_t launch_delete(const StoreArgs &a, const int32_t *slots, int64_t n, hipStream_t s);

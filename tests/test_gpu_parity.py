@@ -297,3 +297,64 @@ def test_mean_and_kmeans(L):
     a = d2.argmin(1)
     for c in range(5):
         np.testing.assert_allclose(C[c], Y[a == c].astype(np.float64).mean(0), atol=1e-5)
+
+
+MFMA_CASES = [
+    (512, 8, 0, oracle.SEQUENTIAL, 1),
+    (768, 4, 8, oracle.TURBO, 16),
+    (96, 8, 0, oracle.SEQUENTIAL, 1),
+    (256, 4, 0, oracle.TURBO, 2),
+]
+
+
+@pytest.mark.parametrize("d,b1,b2,layout,M", MFMA_CASES)
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_exhaustive_topk_mfma(L, d, b1, b2, layout, M, prec):
+    """Matrix-core form: 16-bit queries x exactly converted codes, FP32
+    accumulation.  The oracle runs on the same 16-bit query values (upcast
+    exactly), so the only difference left is FP32 accumulation order."""
+    g = synth.rng(3100 + d, M + (prec == "fp16"))
+    n, nq = 3000, 70
+    cent = g.standard_normal((8, d)).astype(np.float32)
+    X = (cent[g.integers(0, 8, n)] + 0.4 * g.standard_normal((n, d))).astype(np.float32)
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    Q = (cent[g.integers(0, 8, nq)] + 0.4 * g.standard_normal((nq, d))).astype(np.float32)
+    Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    tdt = torch.bfloat16 if prec == "bf16" else torch.float16
+    Qh = torch.from_numpy(Q).to(tdt)
+    Qr = Qh.float().numpy()
+    means = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32) if M == 1 \
+        else X[g.choice(n, M, replace=False)]
+    fmt = oracle.Format(d, b1, b2, layout)
+    rows, resid, _ = oracle.encode_rows(fmt, X, means)
+    ix = L.Index(d, b1, b2, L.LVQ_IP, layout, capacity=n + 50, means=means)
+    ix.insert(torch.from_numpy(X).cuda())
+    dead = np.sort(g.choice(n, 200, replace=False)).astype(np.int32)
+    ix.delete(torch.from_numpy(dead).cuda())
+    assert ix.sync() == 0
+    live = np.ones(n, bool)
+    live[dead] = False
+    offs = np.arange(nq + 1, dtype=np.int64) * n
+    allids = np.tile(np.arange(n, dtype=np.int32), nq)
+    ref, tol = pair_reference(fmt, oracle.IP, oracle.PRIMARY, Qr, rows, resid, means, offs, allids)
+    for k in (1, 10, 100):
+        ti, td = ix.topk(Qh.cuda(), k)
+        assert ix.sync() == 0
+        ti, td = ti.cpu().numpy(), td.cpu().numpy()
+        for i in range(nq):
+            a, b = offs[i], offs[i + 1]
+            check_topk(oracle.IP, ti[i], td[i], allids[a:b], ref[a:b], tol[a:b], k, live)
+    if b2:
+        with pytest.raises(L.LVQError) as e:
+            ix.topk(Qh.cuda(), 10, level=L.LVQ_FULL)
+        assert e.value.code == L.LVQ_ERR_UNSUPPORTED
+    ix.close()
+
+
+def test_mfma_rejects_l2(L):
+    ix = L.Index(96, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=100, means=np.zeros(96, np.float32))
+    ix.insert(torch.zeros((10, 96), device="cuda"))
+    with pytest.raises(L.LVQError) as e:
+        ix.topk(torch.zeros((4, 96), dtype=torch.bfloat16, device="cuda"), 5)
+    assert e.value.code == L.LVQ_ERR_UNSUPPORTED
+    ix.close()
