@@ -1,13 +1,20 @@
-"""Benchmark of the LVQ similarity hot path on one MI355X.
+"""Benchmarks of the LVQ hot path on one MI355X.
 
-Default workload (the headline configuration): an LVQ-4x8 store in the Turbo
-layout, inner product, n = 10^6 vectors of d = 768 (unit-normalised
-anisotropic Gaussian), 10^4 float queries each with a fixed list of 1,000
-distinct uniform candidate ids; one step = query precompute + similarities of
-all 10^7 (query, candidate) pairs at the full (two-level) level + fused
-per-list top-10.  Inputs are resident in HBM before the timed region.
+Default workload (the headline configuration, `--workload c2`): an LVQ-4x8
+store in the Turbo layout, inner product, n = 10^6 vectors of d = 768
+(unit-normalised anisotropic Gaussian), 10^4 float queries each with a fixed
+list of 1,000 distinct uniform candidate ids; one step = query precompute +
+similarities of all 10^7 (query, candidate) pairs at the full (two-level)
+level + fused per-list top-10.  Inputs are resident in HBM before the timed
+region.
 
-Prints one JSON line.  Progress goes to stderr.
+Other workloads (each prints its own line): c1 (LVQ-8 encode + exhaustive L2
+top-10, n = 10^4, d = 96), c3 (multi-means LVQ-8, L2, n = 10^7, d = 96, uneven
+lists in one persistent launch replayed from a HIP graph), c4 (exhaustive
+inner-product top-100 over n = 5 * 10^6, d = 512 LVQ-8 on the matrix cores in
+bf16 and fp16, against the FP32 vector kernel).
+
+Prints one JSON line per workload.  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -25,16 +32,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "LVQ distances/s + HBM GB/s vs peak; QPS and p99 at 10-recall@10≥0.9"
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+FP32_PEAK_TFLOPS = 157.3
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_cand_c2_full_traffic.md")
 KERNEL_SOURCES = ["paper_2402_02044_amd/csrc/k_cand_impl.h", "paper_2402_02044_amd/csrc/k_common.h",
                   "paper_2402_02044_amd/csrc/k_cand_inst.h"]
+T0 = time.time()
 
 
 def log(*a):
     print("[bench %.1fs]" % (time.time() - T0), *a, file=sys.stderr, flush=True)
-
-
-T0 = time.time()
 
 
 def kernel_source_hash() -> str:
@@ -47,13 +54,13 @@ def kernel_source_hash() -> str:
 
 def read_traffic(launch_pairs: int, tile: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source (else None)."""
+    was taken on the current kernel source and tile shape (else None)."""
     if not os.path.exists(PROFILE_TRAFFIC):
         return None
     vals = {}
-    for line in open(PROFILE_TRAFFIC):
-        if ":" in line and line.strip().startswith("- "):
-            k, v = line.strip()[2:].split(":", 1)
+    for ln in open(PROFILE_TRAFFIC):
+        if ":" in ln and ln.strip().startswith("- "):
+            k, v = ln.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip()
     try:
         if vals.get("kernel_source_sha") != kernel_source_hash():
@@ -67,6 +74,59 @@ def read_traffic(launch_pairs: int, tile: int):
         return None
 
 
+def line(value, unit, steps, warmup, ms_step, dtype, config, roofline, higher=True, **extra):
+    out = {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms_step, "higher_is_better": higher, "scaling": "weak", "vs_baseline": None,
+           "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline}
+    out.update(extra)
+    return out
+
+
+def timed(step, steps, warmup, ix):
+    """Wall time per step (synchronised on both sides) and the average kernel
+    time of the main similarity kernel (HIP events on its stream)."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ix.set_timing(True)
+    ix.kernel_time()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches = ix.kernel_time()
+    ix.set_timing(False)
+    return wall * 1000.0 / steps, (kms / launches if launches else None)
+
+
+def to_gpu_rows(ix, X, dev, chunk=1 << 20):
+    import torch
+    for a in range(0, X.shape[0], chunk):
+        ix.insert(torch.from_numpy(X[a:a + chunk]).to(dev))
+
+
+def host_kmeans(S, k, iters, seed_workload):
+    """Lloyd's k-means in binary64 on a sample (harness input for M-LVQ)."""
+    import synth
+    g = synth.rng(seed_workload, synth.S_SAMPLE, 1)
+    C = S[g.choice(S.shape[0], k, replace=False)].astype(np.float64)
+    Sd = S.astype(np.float64)
+    for _ in range(iters):
+        d2 = (Sd * Sd).sum(1)[:, None] - 2.0 * Sd @ C.T + (C * C).sum(1)[None, :]
+        a = d2.argmin(1)
+        for c in range(k):
+            m = a == c
+            if m.any():
+                C[c] = Sd[m].mean(0)
+    return C.astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# C2: candidate lists, LVQ-4x8 Turbo, inner product (the headline)
+# ---------------------------------------------------------------------------
+
 def c2_inputs(n, nq, per):
     import synth
     log("generating %d x 768 base vectors, %d queries, %d candidates each" % (n, nq, per))
@@ -77,20 +137,17 @@ def c2_inputs(n, nq, per):
     return X, Q, mu, offs, ids
 
 
-def cpu_baseline_c2(X, Q, mu, offs, ids, level, budget_s=12.0):
-    """The oracle (plain scalar C, binary64 distances) on a bounded sample of
-    the same workload: the first queries' candidate lists, timed on one core."""
+def cpu_baseline_lists(fmt, metric, level, X, Q, means, offs, ids, budget_s=12.0):
+    """The oracle (plain scalar C, binary64 similarities) on a bounded sample of
+    the same workload: the first queries' candidate lists, on one host core."""
     import oracle
-    fmt = oracle.Format(768, 4, 8, oracle.TURBO)
-    lvl = oracle.FULL if level == 2 else oracle.PRIMARY
 
     def run(nq_s):
         e = int(offs[nq_s])
-        sub_ids = ids[:e]
-        uniq, inv = np.unique(sub_ids, return_inverse=True)
-        rows, resid, _ = oracle.encode_rows(fmt, X[uniq], mu)
+        uniq, inv = np.unique(ids[:e], return_inverse=True)
+        rows, resid, _ = oracle.encode_rows(fmt, X[uniq], means)
         t = time.perf_counter()
-        oracle.distances(fmt, oracle.IP, lvl, Q[:nq_s], rows, resid, mu, offs[:nq_s + 1],
+        oracle.distances(fmt, metric, level, Q[:nq_s], rows, resid, means, offs[:nq_s + 1],
                          inv.astype(np.int32))
         return time.perf_counter() - t, e
 
@@ -98,32 +155,30 @@ def cpu_baseline_c2(X, Q, mu, offs, ids, level, budget_s=12.0):
     nq_s = int(min(len(offs) - 1, max(4, 4 * budget_s / max(dt, 1e-6))))
     dt, e = run(nq_s)
     return {"value": e / dt, "unit": "distances/s", "cores": 1, "kind": "oracle",
-            "sample": "%d queries x %d candidates (%d pairs) of the same workload, %s level, "
+            "sample": "first %d queries' candidate lists (%d pairs) of the same workload, %s level, "
                       "binary64 scalar C on one host core, %.1f s" %
-                      (nq_s, int(offs[1] - offs[0]), e, "full" if level == 2 else "primary", dt)}
+                      (nq_s, e, "full" if level == 2 else "primary", dt)}
 
 
 def bench_c2(args):
     import torch
 
+    import oracle
     import paper_2402_02044_amd as L
-    n, nq, per = args.n, args.nq, 1000
+    n, nq, per = args.n or 1_000_000, args.nq or 10_000, 1000
     X, Q, mu, offs, ids = c2_inputs(n, nq, per)
     level = L.LVQ_FULL if args.level == "full" else L.LVQ_PRIMARY
     dev = torch.device("cuda:0")
     log("uploading and encoding the store")
     ix = L.Index(768, 4, 8, L.LVQ_IP, L.LVQ_TURBO, align=args.align, capacity=n, means=mu)
-    xd = torch.from_numpy(X).to(dev)
-    ix.insert(xd)
-    del xd
+    to_gpu_rows(ix, X, dev)
     qd = torch.from_numpy(Q).to(dev)
     od = torch.from_numpy(offs).to(dev)
     idd = torch.from_numpy(ids).to(dev)
     dist = torch.empty(ids.shape[0], dtype=torch.float32, device=dev)
     ti = torch.empty((nq, 10), dtype=torch.int32, device=dev)
     td = torch.empty((nq, 10), dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream()
-    s = int(stream.cuda_stream)
+    s = int(torch.cuda.current_stream().cuda_stream)
 
     def step():
         L.lvq_distances(ix.handle, qd.data_ptr(), nq, od.data_ptr(), idd.data_ptr(), ids.shape[0], level,
@@ -136,49 +191,229 @@ def bench_c2(args):
         tile = args.tile
     else:
         tile = ix.use_tuned_tile(level, 10, qd, od, idd, retune=args.retune)
-        log("tile shape %d (%s)" % (tile, "autotuned" if args.retune else "tuning cache or autotuner"))
-    log("warmup %d steps" % args.warmup)
-    for _ in range(args.warmup):
-        step()
+    log("tile shape %d; warmup %d, timing %d steps" % (tile, args.warmup, args.steps))
+    ms_step, k_ms = timed(step, args.steps, args.warmup, ix)
     assert ix.sync() == 0
-    ix.set_timing(True)
-    ix.kernel_time()
-    torch.cuda.synchronize()
-    log("timing %d steps" % args.steps)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kms, launches = ix.kernel_time()
-    ix.set_timing(False)
-    assert ix.sync() == 0
-    ms_step = wall * 1000.0 / args.steps
     pairs = int(ids.shape[0])
-    value = pairs / (ms_step / 1000.0)
-    k_avg_ms = kms / max(launches, 1)
     per_pair = (384 + 768 + 12 + 4 + 4) if level == L.LVQ_FULL else (384 + 8 + 4 + 4)
-    alg_bytes = per_pair * pairs
-    achieved = alg_bytes / (k_avg_ms / 1000.0) / 1e9
+    achieved = per_pair * pairs / (k_ms / 1000.0) / 1e9
     traffic = read_traffic(pairs, tile) if level == L.LVQ_FULL and args.align == 32 else None
-    log("step %.3f ms, kernel %.3f ms, %.1f GB/s algorithmic" % (ms_step, k_avg_ms, achieved))
-    out = {
-        "metric": METRIC, "value": value, "unit": "distances/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "LVQ-4x8 Turbo inner product, n=1,000,000, d=768, 10,000 queries x "
-                               "1,000 candidates, %s level, distances + per-list top-10" % args.level,
-                   "n": n, "dim": 768, "bits": "4x8", "layout": "turbo", "row_align": args.align,
-                   "queries": nq, "candidates_per_query": per, "k": 10, "level": args.level,
-                   "tile_shape": tile},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_cand (candidate-list similarity + fused top-k)",
-                     "kernel_ms": k_avg_ms, "algorithmic_bytes_per_pair": per_pair},
-    }
+    log("step %.3f ms, kernel %.3f ms, %.1f GB/s algorithmic" % (ms_step, k_ms, achieved))
+    out = line(pairs / (ms_step / 1000.0), "distances/s", args.steps, args.warmup, ms_step, "f32",
+               {"workload": "LVQ-4x8 Turbo inner product, n=1,000,000, d=768, 10,000 queries x 1,000 "
+                            "candidates, %s level, distances + per-list top-10" % args.level,
+                "n": n, "dim": 768, "bits": "4x8", "layout": "turbo", "row_align": args.align, "queries": nq,
+                "candidates_per_query": per, "k": 10, "level": args.level, "tile_shape": tile},
+               {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "k_cand (candidate-list similarity + fused top-k)", "kernel_ms": k_ms,
+                "algorithmic_bytes_per_pair": per_pair})
     if not args.no_cpu_baseline:
         log("timing the oracle on a host-core sample")
-        out["cpu_baseline"] = cpu_baseline_c2(X, Q, mu, offs, ids, level)
+        fmt = oracle.Format(768, 4, 8, oracle.TURBO)
+        out["cpu_baseline"] = cpu_baseline_lists(fmt, oracle.IP, level, X, Q, mu, offs, ids)
+    ix.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# C1: LVQ-8 encode + exhaustive L2 top-10, n = 10^4, d = 96
+# ---------------------------------------------------------------------------
+
+def bench_c1(args):
+    import torch
+
+    import oracle
+    import paper_2402_02044_amd as L
+    import synth
+    n, nq, d = 10_000, 100, 96
+    X = synth.vectors("C1", synth.S_BASE, 0, n)
+    Q = synth.vectors("C1", synth.S_QUERY, 0, nq)
+    mu = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    dev = torch.device("cuda:0")
+    ix = L.Index(d, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=n, means=mu)
+    xd = torch.from_numpy(X).to(dev)
+    ix.insert(xd)
+    qd = torch.from_numpy(Q).to(dev)
+    rows = torch.empty((n, ix.row_bytes), dtype=torch.uint8, device=dev)
+    ids = torch.empty((nq, 10), dtype=torch.int32, device=dev)
+    dist = torch.empty((nq, 10), dtype=torch.float32, device=dev)
+    s = int(torch.cuda.current_stream().cuda_stream)
+
+    def step():
+        L.lvq_encode(ix.handle, xd.data_ptr(), n, rows.data_ptr(), 0, s)
+        L.lvq_topk(ix.handle, qd.data_ptr(), L.LVQ_FP32, nq, 10, L.LVQ_PRIMARY, ids.data_ptr(), dist.data_ptr(), s)
+
+    ms_step, k_ms = timed(step, args.steps * 10, args.warmup, ix)
+    assert ix.sync() == 0
+    gt = oracle.float_groundtruth(oracle.L2, Q, X, 10)
+    rec = oracle.recall(ids.cpu().numpy(), gt)
+    flops = 3.0 * d * n * nq          # subtract, multiply, add per (pair, dim)
+    achieved = flops / (k_ms / 1000.0) / 1e12
+    fmt = oracle.Format(d, 8, 0)
+    orows, _, _ = oracle.encode_rows(fmt, X, mu)
+    t = time.perf_counter()
+    oracle.topk_exhaustive(fmt, oracle.L2, oracle.PRIMARY, Q, orows, None, mu, 10)
+    ct = time.perf_counter() - t
+    out = line(n * nq / (ms_step / 1000.0), "distances/s", args.steps * 10, args.warmup, ms_step, "f32",
+               {"workload": "LVQ-8 encode of 10,000 x 96 vectors (32 Gaussian clusters) + exhaustive L2 top-10 "
+                            "of 100 queries", "n": n, "dim": d, "queries": nq, "k": 10},
+               {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None, "kernel": "k_scan (FP32 exhaustive top-k)",
+                "kernel_ms": k_ms, "note": "store of 1.28 MB is cache resident: latency-bound, not a roofline claim"},
+               recall_at_10=rec,
+               cpu_baseline={"value": n * nq / ct, "unit": "distances/s", "cores": 1, "kind": "oracle",
+                             "sample": "all 100 queries x 10,000 rows, binary64 scalar C, %.2f s" % ct})
+    ix.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# C3: multi-means LVQ-8, L2, n = 10^7, d = 96, uneven lists, one persistent
+# launch replayed from a HIP graph
+# ---------------------------------------------------------------------------
+
+def bench_c3(args):
+    import torch
+
+    import oracle
+    import paper_2402_02044_amd as L
+    import synth
+    n, nq, d, M = args.n or 10_000_000, args.nq or 10_000, 96, 16
+    log("generating %d x %d base vectors (256 clusters), %d queries" % (n, d, nq))
+    X = synth.vectors("C3", synth.S_BASE, 0, n)
+    Q = synth.vectors("C3", synth.S_QUERY, 0, nq)
+    sample = X[synth.sample_indices(3, n, 100_000)]
+    log("k-means (M = %d) on a 100k sample" % M)
+    means = host_kmeans(sample, M, 25, 3)
+    offs, ids = synth.candidate_lists(3, nq, n, lmin=64, lmax=4096)
+    dev = torch.device("cuda:0")
+    log("uploading and encoding the store (%d lists, %d pairs)" % (nq, ids.shape[0]))
+    ix = L.Index(d, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=n, means=means)
+    to_gpu_rows(ix, X, dev)
+    qd = torch.from_numpy(Q).to(dev)
+    od = torch.from_numpy(offs).to(dev)
+    idd = torch.from_numpy(ids).to(dev)
+    dist = torch.empty(ids.shape[0], dtype=torch.float32, device=dev)
+    ti = torch.empty((nq, 10), dtype=torch.int32, device=dev)
+    td = torch.empty((nq, 10), dtype=torch.float32, device=dev)
+    assert ix.sync() == 0
+    tile = ix.use_tuned_tile(L.LVQ_PRIMARY, 10, qd, od, idd, retune=args.retune)
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+
+    def call(stream):
+        L.lvq_distances(ix.handle, qd.data_ptr(), nq, od.data_ptr(), idd.data_ptr(), ids.shape[0], L.LVQ_PRIMARY,
+                        dist.data_ptr(), 10, ti.data_ptr(), td.data_ptr(), int(stream.cuda_stream))
+
+    with torch.cuda.stream(cs):
+        call(cs)
+    torch.cuda.synchronize()
+    ms_eager, k_ms = timed(lambda: call(torch.cuda.current_stream()), args.steps, args.warmup, ix)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=cs):
+        call(cs)
+    ms_graph, _ = timed(graph.replay, args.steps, args.warmup, ix)
+    assert ix.sync() == 0
+    pairs = int(ids.shape[0])
+    per_pair = 96 + 8 + 1 + 4 + 4
+    achieved = per_pair * pairs / (k_ms / 1000.0) / 1e9
+    log("eager step %.3f ms, graph step %.3f ms, kernel %.3f ms" % (ms_eager, ms_graph, k_ms))
+    fmt = oracle.Format(d, 8, 0)
+    out = line(pairs / (ms_graph / 1000.0), "distances/s", args.steps, args.warmup, ms_graph, "f32",
+               {"workload": "multi-means LVQ-8 L2, n=10,000,000, d=96 (256 clusters), 16 means (k-means on a "
+                            "100k sample), 10,000 queries with log-uniform 64..4096 candidate lists, top-10, one "
+                            "persistent launch per step, steps replayed from a HIP graph",
+                "n": n, "dim": d, "means": M, "queries": nq, "pairs": pairs, "k": 10, "tile_shape": tile},
+               {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_cand (persistent, longest lists first)", "kernel_ms": k_ms,
+                "algorithmic_bytes_per_pair": per_pair},
+               ms_per_step_eager=ms_eager)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_lists(fmt, oracle.L2, oracle.PRIMARY, X, Q, means, offs, ids)
+    ix.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# C4: exhaustive inner-product top-100, n = 5 * 10^6, d = 512, LVQ-8, MFMA
+# ---------------------------------------------------------------------------
+
+def bench_c4(args):
+    import torch
+
+    import oracle
+    import paper_2402_02044_amd as L
+    import synth
+    n, nq, d, k = args.n or 5_000_000, args.nq or 10_000, 512, 100
+    log("generating %d x %d base vectors, %d queries" % (n, d, nq))
+    X = synth.vectors("C4", synth.S_BASE, 0, n)
+    Q = synth.vectors("C4", synth.S_QUERY, 0, nq)
+    mu = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    dev = torch.device("cuda:0")
+    log("uploading and encoding the store")
+    ix = L.Index(d, 8, 0, L.LVQ_IP, L.LVQ_SEQUENTIAL, capacity=n, means=mu)
+    to_gpu_rows(ix, X, dev)
+    assert ix.sync() == 0
+    qf = torch.from_numpy(Q).to(dev)
+    res = {}
+    for name, q in (("bf16", qf.to(torch.bfloat16)), ("fp16", qf.to(torch.float16)), ("fp32", qf)):
+        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        prec = {"bf16": L.LVQ_BF16, "fp16": L.LVQ_FP16, "fp32": L.LVQ_FP32}[name]
+        s = int(torch.cuda.current_stream().cuda_stream)
+
+        def step():
+            L.lvq_topk(ix.handle, q.data_ptr(), prec, nq, k, L.LVQ_PRIMARY, ids.data_ptr(), dist.data_ptr(), s)
+
+        steps = args.steps if name != "fp32" else max(1, args.steps // 5)
+        ms, k_ms = timed(step, steps, 1, ix)
+        assert ix.sync() == 0
+        res[name] = (ms, k_ms, ids.cpu().numpy(), dist.cpu().numpy())
+        log("%s: step %.2f ms, kernel %.2f ms" % (name, ms, k_ms))
+    # accuracy on a query sample: error of returned values against the binary64
+    # oracle with the float32 queries, recall@100 against float ground truth
+    ns = 20
+    Qd = Q[:ns]
+    best = None
+    for a in range(0, n, 1 << 20):
+        sc = Qd @ X[a:a + (1 << 20)].T
+        idx = np.argsort(-sc, axis=1)[:, :k] + a
+        val = np.take_along_axis(sc, idx - a, 1)
+        if best is None:
+            best = (val, idx)
+        else:
+            v = np.concatenate([best[0], val], 1)
+            i = np.concatenate([best[1], idx], 1)
+            o = np.argsort(-v, axis=1)[:, :k]
+            best = (np.take_along_axis(v, o, 1), np.take_along_axis(i, o, 1))
+    gt = best[1]
+    fmt = oracle.Format(d, 8, 0)
+    acc = {}
+    for name, (ms, k_ms, ids, dist) in res.items():
+        rec = oracle.recall(ids[:ns], gt)
+        uniq, inv = np.unique(ids[:ns].ravel(), return_inverse=True)
+        rows, _, _ = oracle.encode_rows(fmt, X[uniq], mu)
+        offs = np.arange(ns + 1, dtype=np.int64) * k
+        ref = oracle.distances(fmt, oracle.IP, oracle.PRIMARY, Qd, rows, None, mu, offs, inv.astype(np.int32))
+        xh = oracle.reconstruct(fmt, rows, None, mu)[inv]
+        S = np.abs(np.repeat(Qd.astype(np.float64), k, 0) * xh).sum(1)
+        err = np.abs(dist[:ns].ravel().astype(np.float64) - ref) / S
+        acc[name] = {"recall_at_100": rec, "max_err_over_S": float(err.max()), "mean_err_over_S": float(err.mean()),
+                     "ms_per_step": ms, "kernel_ms": k_ms, "distances_per_s": n * nq / (ms / 1000.0)}
+    ms, k_ms = res["bf16"][0], res["bf16"][1]
+    flops = 2.0 * d * n * nq
+    achieved = flops / (k_ms / 1000.0) / 1e12
+    out = line(n * nq / (ms / 1000.0), "distances/s", args.steps, 1, ms, "bf16",
+               {"workload": "exhaustive inner-product top-100 over n=5,000,000 d=512 LVQ-8 codes (anisotropic "
+                            "unit vectors), 10,000 queries in bf16 on MFMA with FP32 accumulation; fp16 and the "
+                            "FP32 vector kernel on the same store", "n": n, "dim": d, "queries": nq, "k": k},
+               {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
+                "kernel": "k_scan_mfma (bf16, fused top-100)", "kernel_ms": k_ms},
+               precision=acc, accuracy_sample="%d queries: errors |gpu - binary64 oracle (float32 query)| / "
+                                              "sum_j |q_j x_hat_j|; recall@100 vs float ground truth" % ns)
     ix.close()
     return out
 
@@ -188,11 +423,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c2"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--level", default="full", choices=["full", "primary"])
     ap.add_argument("--align", type=int, default=32)
-    ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--nq", type=int, default=10_000)
+    ap.add_argument("--n", type=int, default=0, help="override the store size (testing)")
+    ap.add_argument("--nq", type=int, default=0, help="override the query count (testing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=-1, help="fixed tile shape (default: tuning cache, else autotune)")
     ap.add_argument("--retune", action="store_true", help="run the autotuner even when the cache has a shape")
@@ -218,8 +453,8 @@ def main():
         print(json.dumps({"copy_bytes_read_per_launch": n * 4, "copy_bytes_written_per_launch": n * 4,
                           "launches": 5}), flush=True)
         return
-    out = bench_c2(args)
-    print(json.dumps(out), flush=True)
+    fn = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4}[args.workload]
+    print(json.dumps(fn(args)), flush=True)
 
 
 if __name__ == "__main__":

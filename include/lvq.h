@@ -21,6 +21,12 @@
  *  - The library owns the store (rows, residual rows, means, free-slot list)
  *    and its workspace, all in device memory it allocates itself, counted
  *    against lvq_config.mem_budget_bytes.
+ *  - HIP graphs: lvq_distances and lvq_topk may be captured into a graph on
+ *    `stream` once an uncaptured call of the same size has sized the
+ *    workspace (a captured call allocates nothing and otherwise fails with
+ *    LVQ_ERR_INVALID_ARG).  A captured call replays at the store epoch of
+ *    capture and does not order itself after store updates on other
+ *    streams; no other entry point may be captured.
  *  - Matrices are row-major and dense: x_dev is n x dim float32, q_dev is
  *    nq x dim (float32, or bfloat16 / float16 for lvq_topk's MFMA forms).
  *  - Similarity: LVQ_L2 returns the squared Euclidean distance to the

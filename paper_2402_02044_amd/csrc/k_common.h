@@ -107,4 +107,80 @@ __device__ __forceinline__ int wave_select_smallest(uint64_t *keys, int n, int k
     return r;
 }
 
+// Bitonic sort, ascending, of 64*E keys held E per lane (element i = e*64 +
+// lane); fully unrolled so every register index is static.
+template <int E>
+__device__ __forceinline__ void wave_bitonic_sort(uint64_t (&v)[E])
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int N = 64 * E;
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+                const int je = j >> 6;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int pe = e ^ je;
+                    if (pe > e) {
+                        const bool asc = ((e * 64) & size) == 0;
+                        const uint64_t a = v[e], b = v[pe];
+                        const bool swap = asc ? (a > b) : (a < b);
+                        v[e] = swap ? b : a;
+                        v[pe] = swap ? a : b;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = e * 64 + lane;
+                    const uint64_t o = shfl_xor_u64(v[e], j);
+                    const bool asc = (i & size) == 0;
+                    const bool lower = (lane & j) == 0;
+                    const bool take_min = lower == asc;
+                    const uint64_t mn = o < v[e] ? o : v[e], mx = o < v[e] ? v[e] : o;
+                    v[e] = take_min ? mn : mx;
+                }
+            }
+        }
+    }
+}
+
+template <int E>
+__device__ __forceinline__ int wave_sort_compact_e(uint64_t *buf, int n, int k)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = e * 64 + lane;
+        v[e] = i < n ? buf[i] : kNoKey;
+    }
+    wave_bitonic_sort<E>(v);
+    int valid = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = e * 64 + lane;
+        if (i < k) buf[i] = v[e];
+        valid += v[e] != kNoKey;
+    }
+    valid = wave_sum_i32(valid);
+    return valid < k ? valid : k;
+}
+
+// Keep the k smallest of buf[0..n) (ascending) in buf[0..k) and return how
+// many are valid keys (< k when fewer survive).  One wavefront.
+__device__ __forceinline__ int wave_compact(uint64_t *buf, int n, int k, uint64_t *scratch)
+{
+    if (n <= 64 && k <= 64) return wave_sort_compact_e<1>(buf, n, k);
+    if (n <= 128 && k <= 128) return wave_sort_compact_e<2>(buf, n, k);
+    if (n <= 256 && k <= 256) return wave_sort_compact_e<4>(buf, n, k);
+    if (n <= 512 && k <= 512) return wave_sort_compact_e<8>(buf, n, k);
+    const int lane = threadIdx.x & 63;
+    const int got = wave_select_smallest(buf, n, k, scratch);
+    for (int i = lane; i < k; i += 64) buf[i] = i < got ? scratch[i] : kNoKey;
+    return got;
+}
+
 }  // namespace lvq

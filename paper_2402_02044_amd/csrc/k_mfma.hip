@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int half = lane >> 5, col = lane & 31;
     const int k = a.k;
-    const int capq = k + kRowsPerIter;
+    const int capq = a.capq;   // >= k + kRowsPerIter
     const int nm = a.n_means;
 
     // XCD-aware tile mapping: workgroup w runs on XCD w % 8; XCD x walks the
@@ -118,11 +118,13 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
     const int64_t r1 = min<int64_t>(a.n_rows, r0 + a.rows_per_part);
 
     // LDS: per-query sum(q), c_m table, thresholds, counts, key buffers
+    // (offsets are taken from the LDS base so every pointer stays in the LDS
+    // address space: a round trip through an integer would turn the accesses
+    // into flat ones, which wait for all outstanding global loads)
     float *qsum = reinterpret_cast<float *>(smem);              // TQ
     float *cmt = qsum + TQ;                                      // TQ x nm
-    uintptr_t off = (uintptr_t)(cmt + (size_t)TQ * nm);
-    off = (off + 15) & ~(uintptr_t)15;
-    uint64_t *thr = reinterpret_cast<uint64_t *>(off);           // TQ
+    const size_t off = (((size_t)TQ * (1 + nm)) * sizeof(float) + 15) & ~(size_t)15;
+    uint64_t *thr = reinterpret_cast<uint64_t *>(smem + off);    // TQ
     float *thr_f = reinterpret_cast<float *>(thr + TQ);          // TQ
     int *cnt = reinterpret_cast<int *>(thr_f + TQ);              // TQ
     uint64_t *buf = reinterpret_cast<uint64_t *>(cnt + TQ + (TQ & 1));
@@ -180,12 +182,11 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
     for (int64_t base = r0; base < r1; base += kRowsPerIter) {
         const bool mine = rb < r1;
         const int64_t rb_next = rb + kRowsPerIter;
-        const bool have_next = rb_next < r1;
-        const uint8_t *nrow = row_ptr(have_next ? rb_next : r0, inext);
-        if (have_next) {
-            hnext = *reinterpret_cast<const float4 *>(nrow);
-            enext = *reinterpret_cast<const uint2 *>(nrow + 16);
-        }
+        // unconditional (clamped) prefetch: a load under a branch would make
+        // every later wait count it as the most recent outstanding load
+        const uint8_t *nrow = row_ptr(rb_next, inext);
+        hnext = *reinterpret_cast<const float4 *>(nrow);
+        enext = *reinterpret_cast<const uint2 *>(nrow + 16);
         if (mine) {
             f32x16 acc[QB];
 #pragma unroll
@@ -200,40 +201,88 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
 #pragma unroll
                     for (int b = 0; b < QB; ++b) acc[b] = mfma<FP16>(afr[b][c][s], bfr, acc[b]);
                 }
-                if (have_next) vcur[c] = *reinterpret_cast<const uint4 *>(nrow + kHeaderBytes + c * 32 + half * 16);
+                vcur[c] = *reinterpret_cast<const uint4 *>(nrow + kHeaderBytes + c * 32 + half * 16);
             }
-        // epilogue: lane holds row col of the block, 16 queries per block
+            // Epilogue: lane holds row `col` of the block and, per query block,
+            // 16 queries: 8*g + 4*half + r (g, r < 4), i.e. four runs of four
+            // consecutive queries, whose constants are read as float4.  All
+            // scores are formed first; the append path runs only when some
+            // lane has a score reaching its query's threshold.
             const int64_t slot = rb + col;
             const bool live = icur && ((__float_as_uint(hcur.w) >> 8) & 1u) && ecur.x <= a.epoch &&
                               a.epoch < ecur.y;
             const int mid = min((int)(__float_as_uint(hcur.w) & 0xFFu), nm - 1);
 #pragma unroll
-            for (int b = 0; b < QB; ++b)
+            for (int b = 0; b < QB; ++b) {
+                float sc[16];
+                bool pass[16];
+                bool any = false;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int qi = 32 * b + 8 * (i >> 2) + 4 * half + (i & 3);
-                    const float sc = fmaf(hcur.y, acc[b][i], fmaf(hcur.x, qsum[qi], cmt[qi * nm + mid]));
-                    if (live && qi < nqt && sc >= thr_f[qi]) {
-                        const uint64_t key = make_key(sc, (int32_t)slot, LVQ_IP);
+                for (int g = 0; g < 4; ++g) {
+                    const int q4 = 32 * b + 8 * g + 4 * half;
+                    const float4 qs = *reinterpret_cast<const float4 *>(qsum + q4);
+                    const float4 tf = *reinterpret_cast<const float4 *>(thr_f + q4);
+                    float4 cmv;
+                    if (nm == 1) {
+                        cmv = *reinterpret_cast<const float4 *>(cmt + q4);
+                    } else {
+                        cmv.x = cmt[(q4 + 0) * nm + mid];
+                        cmv.y = cmt[(q4 + 1) * nm + mid];
+                        cmv.z = cmt[(q4 + 2) * nm + mid];
+                        cmv.w = cmt[(q4 + 3) * nm + mid];
+                    }
+                    const float qsv[4] = {qs.x, qs.y, qs.z, qs.w};
+                    const float tfv[4] = {tf.x, tf.y, tf.z, tf.w};
+                    const float cmq[4] = {cmv.x, cmv.y, cmv.z, cmv.w};
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = 4 * g + r;
+                        sc[i] = fmaf(hcur.y, acc[b][i], fmaf(hcur.x, qsv[r], cmq[r]));
+                        // tfv never rejects a score that can enter the top k
+                        pass[i] = live && (q4 + r) < nqt && sc[i] >= tfv[r];
+                        any |= pass[i];
+                    }
+                }
+                if (__ballot(any)) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        if (!pass[i]) continue;
+                        const int qi = 32 * b + 8 * (i >> 2) + 4 * half + (i & 3);
+                        const uint64_t key = make_key(sc[i], (int32_t)slot, LVQ_IP);
                         if (key < thr[qi]) {
                             const int pos = atomicAdd(&cnt[qi], 1);
                             if (pos < capq) buf[(size_t)qi * capq + pos] = key;
                         }
                     }
                 }
+            }
         }
         __syncthreads();
+        // compaction: one LDS read per lane finds the queries whose buffer
+        // could overflow next round; wave w compacts the ones with qi % 4 == w
         const bool last = base + kRowsPerIter >= r1;
-        for (int qi = wave; qi < nqt; qi += kWaves) {
-            const int n = min(cnt[qi], capq);
-            if (last || n > capq - kRowsPerIter) {
-                uint64_t *w_tmp = tmp + (size_t)wave * k;
-                const int got = wave_select_smallest(buf + (size_t)qi * capq, n, k, w_tmp);
-                for (int i = lane; i < k; i += 64) buf[(size_t)qi * capq + i] = i < got ? w_tmp[i] : kNoKey;
+        for (int q0w = 0; q0w < TQ; q0w += 64) {
+            const int qi_l = q0w + lane;
+            const bool need = qi_l < nqt && (last || min(cnt[qi_l], capq) > capq - kRowsPerIter) &&
+                              (qi_l & (kWaves - 1)) == wave;
+            uint64_t m = __ballot(need);
+            while (m) {
+                const int bit = __builtin_ctzll(m);
+                m &= m - 1;
+                const int qi = q0w + bit;
+                const int n = min(cnt[qi], capq);
+                uint64_t *qb = buf + (size_t)qi * capq;
+                const int got = wave_compact(qb, n, k, tmp + (size_t)wave * k);
                 if (lane == 0) {
                     cnt[qi] = got;
-                    thr[qi] = got == k ? w_tmp[k - 1] : kNoKey;
-                    thr_f[qi] = got == k ? key_score(w_tmp[k - 1], LVQ_IP) : -__builtin_inff();
+                    thr[qi] = got == k ? qb[k - 1] : kNoKey;
+                    // Share the bound: this part holds k candidates whose score
+                    // order is <= that of its k-th key, so no candidate with a
+                    // larger score order (worse score) can reach the final top
+                    // k in any part.  Ties stay admitted.
+                    uint32_t gb = a.gthr[q0 + qi];
+                    if (got == k) gb = min(gb, atomicMin(&a.gthr[q0 + qi], (uint32_t)(qb[k - 1] >> 32)));
+                    thr_f[qi] = gb == 0xFFFFFFFFu ? -__builtin_inff() : key_score((uint64_t)gb << 32, LVQ_IP);
                 }
             }
         }
@@ -330,15 +379,27 @@ int mfma_query_block(int bits1, int kpos)
     return (bits1 == 8 ? mfma_lookup<8, false>(kpos, &qb) : mfma_lookup<4, false>(kpos, &qb)) ? qb : 0;
 }
 
-size_t mfma_lds_bytes(int qb, int n_means, int k)
+size_t mfma_lds_bytes(int qb, int n_means, int k, int capq)
 {
     const int tq = 32 * qb;
     size_t b = (size_t)tq * 4 + (size_t)tq * n_means * 4;
     b = (b + 15) & ~(size_t)15;
     b += (size_t)tq * (8 + 4 + 4) + (tq & 1) * 4 + 8;
-    b += (size_t)tq * (k + kRowsPerIter) * 8;
+    b += (size_t)tq * capq * 8;
     b += (size_t)kWaves * k * 8;
     return b;
+}
+
+// Largest per-query key buffer (<= 512 keys, the register sort's reach, or
+// k + one round when k is larger) that fits lds_max; 0 if even k + one round
+// does not.
+int mfma_capq(int qb, int n_means, int k, size_t lds_max)
+{
+    const int need = k + kRowsPerIter;
+    int cap = need > 512 ? need : 512;
+    while (cap > need && mfma_lds_bytes(qb, n_means, k, cap) > lds_max) cap -= 16;
+    if (cap < need) cap = need;
+    return mfma_lds_bytes(qb, n_means, k, cap) <= lds_max ? cap : 0;
 }
 
 hipError_t launch_prep16(const void *q, int64_t nq, int dim, int kpos, int bits1, int prec, const int32_t *kdim,
@@ -365,7 +426,7 @@ hipError_t launch_scan_mfma(const ScanArgs &a, int bits1, int prec, hipStream_t 
     const int64_t qtiles = (a.nq + 32 * qb - 1) / (32 * qb);
     const int64_t ntiles = qtiles * a.n_parts;
     const int64_t grid = (ntiles + 7) / 8 * 8;
-    const size_t lds = mfma_lds_bytes(qb, a.n_means, a.k);
+    const size_t lds = mfma_lds_bytes(qb, a.n_means, a.k, a.capq);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, a);
     return hipGetLastError();
 }

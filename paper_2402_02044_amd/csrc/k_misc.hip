@@ -389,9 +389,13 @@ size_t cand_lds_bytes(int kpos, int ntab, bool mask, int n_means_ip, int k)
 {
     return cand_lds_bytes_impl(kpos, ntab, mask, n_means_ip, k);
 }
-size_t scan_lds_bytes(int kpos, int n_means_ip, int k, int rows_per_round)
+size_t scan_lds_bytes(int kpos, int n_means_ip, int k, int capq)
 {
-    return scan_lds_bytes_impl(kpos, n_means_ip, k, rows_per_round);
+    return scan_lds_bytes_impl(kpos, n_means_ip, k, capq);
+}
+int scan_capq(int kpos, int n_means_ip, int k, int rows_per_round, size_t lds_max)
+{
+    return scan_capq_impl(kpos, n_means_ip, k, rows_per_round, lds_max);
 }
 int scan_rows_per_round(int g) { return 256 / g * kScanR; }
 

@@ -21,17 +21,27 @@ namespace lvq {
 constexpr int kScanTQ = 16;  // queries per workgroup
 constexpr int kScanR = 2;    // rows per lane group and round
 
-__host__ __device__ inline int scan_capq(int k, int rows_per_round) { return k + 2 * rows_per_round; }
-
-inline size_t scan_lds_bytes_impl(int kpos, int n_means_ip, int k, int rows_per_round)
+inline size_t scan_lds_bytes_impl(int kpos, int n_means_ip, int k, int capq)
 {
     size_t b = (size_t)kScanTQ * kpos * 4;                  // query tables
     b += (size_t)kScanTQ * (((n_means_ip + 1) & ~1) + 2) * 4; // c_m, sum q
     b = (b + 15) & ~(size_t)15;
     b += (size_t)kScanTQ * 16;                              // thresholds + counts
-    b += (size_t)kScanTQ * scan_capq(k, rows_per_round) * 8; // candidate buffers
+    b += (size_t)kScanTQ * capq * 8;                        // candidate buffers
     b += (size_t)4 * k * 8;                                  // per-wave select scratch
     return b;
+}
+
+// Per-query key buffer: up to 512 keys (the register sort's reach) while the
+// workgroup keeps room for two resident workgroups per CU, at least k + one
+// round of rows; 0 when that does not fit.
+inline int scan_capq_impl(int kpos, int n_means_ip, int k, int rows_per_round, size_t lds_max)
+{
+    const int need = k + rows_per_round;
+    int cap = need > 512 ? need : 512;
+    while (cap > need && scan_lds_bytes_impl(kpos, n_means_ip, k, cap) > lds_max / 2) cap -= 16;
+    if (cap < need) cap = need;
+    return scan_lds_bytes_impl(kpos, n_means_ip, k, cap) <= lds_max ? cap : 0;
 }
 
 template <int B1, int B2, int METRIC, bool MASK, int G, int CH, int NCH>
@@ -52,13 +62,13 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
     const int cm_n = METRIC == LVQ_IP ? a.n_means : 0;
     const int cm_stride = ((cm_n + 1) & ~1) + 2;
     const int k = a.k;
-    const int capq = scan_capq(k, kRows);
+    const int capq = a.capq;   // >= k + kRows
 
+    // offsets from the LDS base keep every pointer in the LDS address space
     float *qtab = reinterpret_cast<float *>(smem);
     float *qc = qtab + (size_t)TQ * a.kpos;                 // [TQ][cm_stride]: c_m..., sum q
-    uintptr_t off = (uintptr_t)(qc + (size_t)TQ * cm_stride);
-    off = (off + 15) & ~(uintptr_t)15;
-    uint64_t *thr = reinterpret_cast<uint64_t *>(off);
+    const size_t off = (((size_t)TQ * a.kpos + (size_t)TQ * cm_stride) * sizeof(float) + 15) & ~(size_t)15;
+    uint64_t *thr = reinterpret_cast<uint64_t *>(smem + off);
     int *cnt = reinterpret_cast<int *>(thr + TQ);
     uint64_t *buf = reinterpret_cast<uint64_t *>(cnt + 2 * TQ);
     uint64_t *tmp = buf + (size_t)TQ * capq;
@@ -239,12 +249,11 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
         for (int qi = wave; qi < nqt; qi += 4) {
             const int n = min(cnt[qi], capq);
             if (last || n > capq - kRows) {
-                uint64_t *w_tmp = tmp + (size_t)wave * k;
-                const int got = wave_select_smallest(buf + (size_t)qi * capq, n, k, w_tmp);
-                for (int i = lane; i < k; i += 64) buf[(size_t)qi * capq + i] = i < got ? w_tmp[i] : kNoKey;
+                uint64_t *qb = buf + (size_t)qi * capq;
+                const int got = wave_compact(qb, n, k, tmp + (size_t)wave * k);
                 if (lane == 0) {
                     cnt[qi] = got;
-                    thr[qi] = got == k ? w_tmp[k - 1] : kNoKey;
+                    thr[qi] = got == k ? qb[k - 1] : kNoKey;
                 }
             }
         }

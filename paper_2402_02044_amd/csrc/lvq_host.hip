@@ -78,7 +78,7 @@ struct DevBuf {
 };
 
 struct Workspace {
-    DevBuf qk, qsum, cm, order, queue, part, q16;
+    DevBuf qk, qsum, cm, order, queue, part, q16, gthr;
 };
 
 struct InFlight {
@@ -109,6 +109,7 @@ struct lvq_index {
     bool have_update = false;
     std::mutex mu;
     int cand_shape[2][2] = {{-1, -1}, {-1, -1}};   // tuned [level][topk]
+    bool capturing = false;   // the current call's stream is capturing a HIP graph
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
 };
@@ -131,6 +132,7 @@ int map_hip(hipError_t e)
 int dev_alloc(lvq_index *ix, DevBuf &b, size_t bytes)
 {
     if (b.bytes >= bytes && b.p) return LVQ_OK;
+    if (ix->capturing) return LVQ_ERR_INVALID_ARG;   // no allocation inside graph capture
     if (bytes == 0) bytes = 16;
     const int64_t grow = (int64_t)bytes - (int64_t)b.bytes;
     if (ix->cfg.mem_budget_bytes > 0 && ix->device_bytes + grow > ix->cfg.mem_budget_bytes)
@@ -193,9 +195,21 @@ int upload_means(lvq_index *ix, const std::vector<float> &all)
 
 Workspace &workspace(lvq_index *ix, hipStream_t s) { return ix->ws[s]; }
 
+// Record whether `s` is capturing a HIP graph: captured calls allocate
+// nothing, skip cross-stream ordering and in-flight bookkeeping, and replay
+// at the epoch of capture.
+int begin_call(lvq_index *ix, hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    LVQ_HIP(hipStreamIsCapturing(s, &st));
+    ix->capturing = st != hipStreamCaptureStatusNone;
+    return LVQ_OK;
+}
+
 // Make work on `s` wait for the latest store update issued on another stream.
 int order_after_updates(lvq_index *ix, hipStream_t s)
 {
+    if (ix->capturing) return LVQ_OK;
     if (ix->have_update && ix->update_stream != s) LVQ_HIP(hipStreamWaitEvent(s, ix->update_ev, 0));
     return LVQ_OK;
 }
@@ -210,6 +224,7 @@ int note_update(lvq_index *ix, hipStream_t s)
 
 int note_query(lvq_index *ix, hipStream_t s, uint32_t epoch)
 {
+    if (ix->capturing) return LVQ_OK;
     hipEvent_t ev;
     if (!ix->spare_events.empty()) {
         ev = ix->spare_events.back();
@@ -230,7 +245,7 @@ int note_query(lvq_index *ix, hipStream_t s, uint32_t epoch)
 // Bracket the main kernel with events when timing is enabled.
 int timing_begin(lvq_index *ix, hipStream_t s)
 {
-    if (!ix->timing) return LVQ_OK;
+    if (!ix->timing || ix->capturing) return LVQ_OK;
     hipEvent_t a, b;
     LVQ_HIP(hipEventCreate(&a));
     LVQ_HIP(hipEventCreate(&b));
@@ -241,7 +256,7 @@ int timing_begin(lvq_index *ix, hipStream_t s)
 
 int timing_end(lvq_index *ix, hipStream_t s)
 {
-    if (!ix->timing || ix->tev.empty()) return LVQ_OK;
+    if (!ix->timing || ix->capturing || ix->tev.empty()) return LVQ_OK;
     LVQ_HIP(hipEventRecord(ix->tev.back().second, s));
     return LVQ_OK;
 }
@@ -404,7 +419,7 @@ int lvq_destroy(lvq_index *ix)
     (void)hipDeviceSynchronize();
     for (auto &kv : ix->ws) {
         Workspace &w = kv.second;
-        for (DevBuf *b : {&w.qk, &w.qsum, &w.cm, &w.order, &w.queue, &w.part, &w.q16}) dev_free(ix, *b);
+        for (DevBuf *b : {&w.qk, &w.qsum, &w.cm, &w.order, &w.queue, &w.part, &w.q16, &w.gthr}) dev_free(ix, *b);
     }
     for (DevBuf *b : {&ix->means, &ix->means_t, &ix->muk, &ix->kmask, &ix->kdim, &ix->pos_dim, &ix->rows,
                       &ix->resid, &ix->stack, &ix->err, &ix->scratch})
@@ -630,8 +645,12 @@ int lvq_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *
 {
     if (!ix) return LVQ_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(ix->mu);
-    return distances_impl(ix, q_dev, nq, offsets_dev, ids_dev, total, level, dist_dev, k, topk_ids_dev,
-                          topk_dist_dev, (hipStream_t)stream, -1);
+    int rc = begin_call(ix, (hipStream_t)stream);
+    if (rc) return rc;
+    rc = distances_impl(ix, q_dev, nq, offsets_dev, ids_dev, total, level, dist_dev, k, topk_ids_dev,
+                        topk_dist_dev, (hipStream_t)stream, -1);
+    ix->capturing = false;
+    return rc;
 }
 
 int lvq_set_tile(lvq_index *ix, int32_t level, int32_t topk, int32_t shape)
@@ -649,6 +668,7 @@ int lvq_autotune(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *o
     if (!ix || nq < 1 || total < 0 || k < 0 || k > kMaxTopK) return LVQ_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(ix->mu);
     hipStream_t s = (hipStream_t)stream;
+    ix->capturing = false;
     float *dist = nullptr;
     int32_t *ti = nullptr;
     float *td = nullptr;
@@ -708,6 +728,12 @@ int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t
     if (level == LVQ_FULL && ix->f.bits2 == 0) return LVQ_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(ix->mu);
     hipStream_t s = (hipStream_t)stream;
+    int rc0 = begin_call(ix, s);
+    if (rc0) return rc0;
+    struct Reset {
+        lvq_index *ix;
+        ~Reset() { ix->capturing = false; }
+    } reset{ix};
     const Format &f = ix->f;
     if (prec != LVQ_FP32) return topk_mfma(ix, q_dev, prec, nq, k, level, ids_dev, dist_dev, s);
     const bool l2 = ix->cfg.metric == LVQ_L2;
@@ -730,8 +756,9 @@ int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t
     void *kern = lookup(bits2, variant, shape);
     const TileShape sh = tile_shape(shape);
     const int rpr = scan_rows_per_round(sh.g);
-    const size_t lds = scan_lds_bytes(f.kpos, l2 ? 0 : ix->n_means, k, rpr);
-    if (lds > ix->lds_max) return LVQ_ERR_UNSUPPORTED;
+    const int capq = scan_capq(f.kpos, l2 ? 0 : ix->n_means, k, rpr, ix->lds_max);
+    if (!capq) return LVQ_ERR_UNSUPPORTED;
+    const size_t lds = scan_lds_bytes(f.kpos, l2 ? 0 : ix->n_means, k, capq);
 
     int rc = order_after_updates(ix, s);
     if (rc) return rc;
@@ -766,6 +793,8 @@ int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t
     a.epoch = ix->epoch;
     a.rows_per_part = rows_per_part;
     a.n_parts = (int)parts;
+    a.capq = capq;
+    a.gthr = nullptr;
     a.part_keys = P<uint64_t>(w.part);
     a.err = P<uint32_t>(ix->err);
     if ((rc = timing_begin(ix, s))) return rc;
@@ -785,8 +814,8 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     if (ix->cfg.metric != LVQ_IP || level != LVQ_PRIMARY) return LVQ_ERR_UNSUPPORTED;
     const int qb = mfma_query_block(f.bits1, f.kpos);
     if (!qb) return LVQ_ERR_UNSUPPORTED;
-    const size_t lds = mfma_lds_bytes(qb, ix->n_means, k);
-    if (lds > ix->lds_max) return LVQ_ERR_UNSUPPORTED;
+    const int capq = mfma_capq(qb, ix->n_means, k, ix->lds_max);
+    if (!capq) return LVQ_ERR_UNSUPPORTED;
     int rc = order_after_updates(ix, s);
     if (rc) return rc;
     Workspace &w = workspace(ix, s);
@@ -798,13 +827,28 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     LVQ_HIP(launch_prep16(q_dev, nq, f.dim, f.kpos, f.bits1, prec, P<int32_t>(ix->kdim), P<float>(ix->means),
                           ix->n_means, w.q16.p, P<float>(w.qsum), P<float>(w.cm), s));
     const int64_t n_rows = ix->cfg.capacity - ix->fresh;
-    // about eight rounds of one workgroup per compute unit, parts of at least
-    // a few row rounds, and a merge that fits one workgroup's LDS
-    int64_t parts = std::max<int64_t>(1, (8 * (int64_t)ix->n_cu + qtiles - 1) / qtiles);
-    parts = std::min<int64_t>(parts, std::max<int64_t>(1, n_rows / 1024));
-    parts = std::min<int64_t>(parts, std::max<int64_t>(1, (int64_t)(ix->lds_max / 8 - k) / k));
+    // One resident workgroup per compute unit: pick the number of parts (few,
+    // long parts: every part starts with a loose top-k threshold) whose
+    // workgroup count fills the compute units in whole rounds best; parts of
+    // at least 64 row rounds; a merge that fits one workgroup's LDS.
+    const int64_t max_parts = std::max<int64_t>(
+        1, std::min<int64_t>({16, n_rows / (64 * 128), (int64_t)(ix->lds_max / 8 - k) / k}));
+    int64_t parts = 1;
+    double best = -1.0;
+    for (int64_t p = 1; p <= max_parts; ++p) {
+        const int64_t wg = qtiles * p;
+        const int64_t rounds = (wg + ix->n_cu - 1) / ix->n_cu;
+        const double fill = (double)wg / (double)(rounds * ix->n_cu);   // busy fraction of the last rounds
+        const double score = fill - 0.02 * (double)p;                    // prefer fewer parts on ties
+        if (score > best) {
+            best = score;
+            parts = p;
+        }
+    }
     const int64_t rows_per_part = std::max<int64_t>(1, (n_rows + parts - 1) / parts);
     if ((rc = dev_alloc(ix, w.part, sizeof(uint64_t) * (size_t)nq * parts * k))) return rc;
+    if ((rc = dev_alloc(ix, w.gthr, sizeof(uint32_t) * (size_t)nq))) return rc;
+    LVQ_HIP(launch_fill_u32(P<uint32_t>(w.gthr), 0xFFFFFFFFu, nq, s));
     ScanArgs a;
     a.rows = P<uint8_t>(ix->rows);
     a.resid = P<uint8_t>(ix->resid);
@@ -825,6 +869,8 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     a.epoch = ix->epoch;
     a.rows_per_part = rows_per_part;
     a.n_parts = (int)parts;
+    a.capq = capq;
+    a.gthr = P<uint32_t>(w.gthr);
     a.part_keys = P<uint64_t>(w.part);
     a.err = P<uint32_t>(ix->err);
     if ((rc = timing_begin(ix, s))) return rc;

@@ -105,6 +105,8 @@ struct ScanArgs {
     uint32_t epoch;
     int64_t rows_per_part;
     int n_parts;
+    int capq;                // per-query key buffer capacity in LDS
+    uint32_t *gthr;          // nq: order key bound of the k-th best score seen by any part
     uint64_t *part_keys;     // nq x n_parts x k sortable keys
     uint32_t *err;
 };
@@ -138,7 +140,8 @@ void *cand_kernel_b8(int bits2, int variant, int shape);
 void *scan_kernel_b4(int bits2, int variant, int shape);
 void *scan_kernel_b8(int bits2, int variant, int shape);
 size_t cand_lds_bytes(int kpos, int ntab, bool mask, int n_means_ip, int k);
-size_t scan_lds_bytes(int kpos, int n_means_ip, int k, int rows_per_round);
+size_t scan_lds_bytes(int kpos, int n_means_ip, int k, int capq);
+int scan_capq(int kpos, int n_means_ip, int k, int rows_per_round, size_t lds_max);
 int scan_rows_per_round(int g);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
@@ -149,7 +152,8 @@ hipError_t launch_scan_mfma(const ScanArgs &a, int bits1, int prec, hipStream_t 
 // the code width / position count has no instantiation), its LDS bytes, and
 // the query-fragment precompute for bf16 / fp16 queries.
 int mfma_query_block(int bits1, int kpos);
-size_t mfma_lds_bytes(int qb, int n_means, int k);
+size_t mfma_lds_bytes(int qb, int n_means, int k, int capq);
+int mfma_capq(int qb, int n_means, int k, size_t lds_max);
 hipError_t launch_prep16(const void *q, int64_t nq, int dim, int kpos, int bits1, int prec, const int32_t *kdim,
                          const float *means, int n_means, void *frag, float *qsum, float *cm, hipStream_t s);
 hipError_t launch_topk_merge(const uint64_t *part_keys, int64_t nq, int n_parts, int k, int metric,

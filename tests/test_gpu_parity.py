@@ -358,3 +358,50 @@ def test_mfma_rejects_l2(L):
         ix.topk(torch.zeros((4, 96), dtype=torch.bfloat16, device="cuda"), 5)
     assert e.value.code == L.LVQ_ERR_UNSUPPORTED
     ix.close()
+
+
+def test_graph_capture_replays_match_eager(L):
+    """A captured lvq_distances (query prep, list ordering, persistent
+    candidate kernel) replays to the eager result, several times, with eager
+    work and synchronisation between replays."""
+    d, n, nq = 96, 4000, 40
+    g = synth.rng(6000, 0)
+    X = g.standard_normal((n, d)).astype(np.float32)
+    Q = g.standard_normal((nq, d)).astype(np.float32)
+    means = X[g.choice(n, 4, replace=False)]
+    ix = L.Index(d, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=n, means=means)
+    ix.insert(torch.from_numpy(X).cuda())
+    offs, ids = synth.candidate_lists(7, nq, n, lmin=5, lmax=900)
+    qd = torch.from_numpy(Q).cuda()
+    od, idd = torch.from_numpy(offs).cuda(), torch.from_numpy(ids).cuda()
+    assert ix.sync() == 0
+    dist0, ti0, td0 = ix.distances(qd, od, idd, k=10)
+    assert ix.sync() == 0
+    dist = torch.empty_like(dist0)
+    ti = torch.empty_like(ti0)
+    td = torch.empty_like(td0)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+
+    def call(stream):
+        L.lvq_distances(ix.handle, qd.data_ptr(), nq, od.data_ptr(), idd.data_ptr(), ids.shape[0], L.LVQ_PRIMARY,
+                        dist.data_ptr(), 10, ti.data_ptr(), td.data_ptr(), int(stream.cuda_stream))
+
+    with torch.cuda.stream(s):
+        call(s)                               # sizes this stream's workspace
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        call(s)
+    torch.cuda.synchronize()
+    for r in range(4):
+        dist.fill_(-1.0)
+        ti.fill_(-7)
+        td.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(dist, dist0), r
+        assert torch.equal(ti, ti0) and torch.equal(td, td0), r
+    assert ix.sync() == 0
+    ix.close()
