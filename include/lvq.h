@@ -103,11 +103,14 @@ int lvq_create(const lvq_config *cfg, const float *means_host, int32_t n_means,
                lvq_index **out);
 int lvq_destroy(lvq_index *index);
 
-/* Append means (M-LVQ re-estimation, Sec. 3.2); existing rows keep their
- * mean ids.  *first_id_out receives the id of the first appended mean.
- * Synchronises the device.                                                 */
+/* Append means (M-LVQ re-estimation, Sec. 3.2): the new centres get ids
+ * n_old .. n_old + n_means - 1 (*first_id_out, may be NULL, receives n_old);
+ * existing rows keep their mean ids and the table never drops an entry, so
+ * at most 256 means exist over the index's life.  The copies are enqueued
+ * on `stream` and later calls on any stream are ordered after them; work
+ * already queued reads only the old ids.  Synchronises `stream`.          */
 int lvq_set_means(lvq_index *index, const float *means_host, int32_t n_means,
-                  int32_t *first_id_out);
+                  int32_t *first_id_out, void *stream);
 
 /* Encode n vectors (Eq. 1-3, residual level, Def. 1) into caller buffers:
  * rows_dev n x row_bytes, resid_dev n x resid_bytes (NULL when bits2 == 0).
@@ -206,6 +209,75 @@ int lvq_mean(const float *x_dev, int64_t n, int32_t dim, float *mean_out_dev, vo
  * cluster keeps its centre).  means_out_dev k x dim float32.              */
 int lvq_kmeans(const float *x_dev, int64_t n, int32_t dim, int32_t k, const int64_t *init_idx_host,
                int32_t iters, float *means_out_dev, void *stream);
+
+/* ---- Request server -------------------------------------------------------
+ * Continuous batching of k-NN query batches (the problem of Sec. 2.1) over an
+ * index that changes meanwhile (inserts and deletes, Sec. 2.2).  A server
+ * owns `slots` HIP streams and a device pool of pool_bytes (drawn from the
+ * index's memory budget).  lvq_server_submit copies a batch of nq float32
+ * queries (host memory, nq x dim) and queues it; batches are admitted in
+ * arrival order as soon as a stream slot is free and the pool can hold the
+ * batch's buffers (admission by memory: small batches take less), and
+ * admitted batches run concurrently, one per stream.  Each batch is answered
+ * at the store epoch current at its admission: an exhaustive first-level
+ * top-k_first (as lvq_topk, at `precision`) and, with rerank_level =
+ * LVQ_FULL, both-level similarities of those candidates and their top-k (as
+ * lvq_distances, Sec. 2.3: the second level re-ranks).  The result of a batch
+ * equals that of the same batch run alone at the same epoch.  Store updates
+ * (lvq_insert, lvq_delete, lvq_consolidate, lvq_set_means) may be issued on
+ * the index from other threads at any time; batches admitted after an update
+ * see it, and consolidation keeps every slot an unfinished batch may see.
+ * Sticky kernel errors are reported by lvq_sync as usual.  Destroy the
+ * server before its index.                                                 */
+typedef struct lvq_server lvq_server;
+
+typedef struct {
+    int32_t slots;         /* batches in flight at once (streams), 1..64 */
+    int32_t max_batch;     /* largest nq of one batch, 1..65536 */
+    int32_t k;             /* results per query, 1..1024 */
+    int32_t k_first;       /* first-level candidates per query, k..1024 (LVQ_FULL) */
+    int32_t precision;     /* first-level scan: LVQ_FP32, LVQ_BF16 or LVQ_FP16 (IP) */
+    int32_t rerank_level;  /* LVQ_FULL: re-rank with both levels (needs bits2 > 0);
+                              LVQ_PRIMARY: the first-level top-k is the result */
+    int64_t pool_bytes;    /* device memory of admitted batches together;
+                              0 = room for `slots` batches of max_batch */
+} lvq_server_config;
+
+/* Per-batch record: status (LVQ_OK or the error the batch met), its size,
+ * the epoch it was answered at, the slot that ran it, and times in seconds
+ * since the server's creation (steady clock) of submission, admission and
+ * observed completion.                                                     */
+typedef struct {
+    int32_t status, nq;
+    uint32_t epoch;
+    int32_t slot;
+    double t_submit, t_admit, t_done;
+} lvq_request_info;
+
+typedef struct {
+    int64_t submitted, completed;
+    int64_t pool_bytes, pool_peak, batch_bytes_max;
+    int32_t slots, peak_in_flight, peak_queue, queued, in_flight;
+} lvq_server_stats;
+
+/* Create a server on the index's device: streams, the pool, pinned staging
+ * buffers, and every stream's scan workspace for all batch sizes up to
+ * max_batch, so that serving allocates no device memory.                  */
+int lvq_server_create(lvq_index *index, const lvq_server_config *cfg, lvq_server **out);
+/* Queue a batch (1 <= nq <= max_batch); q_host is copied before return.
+ * *ticket_out identifies it to lvq_server_wait.                           */
+int lvq_server_submit(lvq_server *server, const float *q_host, int32_t nq, int64_t *ticket_out);
+/* Block until the batch is done; copy its nq x k results (ids_host int32,
+ * dist_host float32, ordered best first, padded as for lvq_topk; either may
+ * be NULL) and its record (may be NULL); forget the ticket.  Returns the
+ * batch's status; LVQ_ERR_INVALID_ARG for an unknown ticket.              */
+int lvq_server_wait(lvq_server *server, int64_t ticket, int32_t *ids_host, float *dist_host,
+                    lvq_request_info *info);
+/* Block until every submitted batch is done. */
+int lvq_server_drain(lvq_server *server);
+int lvq_server_get_stats(lvq_server *server, lvq_server_stats *out);
+/* Finish every submitted batch, then release the server. */
+int lvq_server_destroy(lvq_server *server);
 
 const char *lvq_strerror(int code);
 

@@ -38,7 +38,8 @@ LVQ_ERR_BAD_SLOT = -7
 EXPORTS = ["lvq_row_format", "lvq_create", "lvq_destroy", "lvq_set_means", "lvq_encode", "lvq_insert",
            "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_topk", "lvq_read_rows",
            "lvq_get_stats", "lvq_sync", "lvq_mean", "lvq_kmeans", "lvq_strerror", "lvq_set_timing",
-           "lvq_kernel_time", "lvq_autotune", "lvq_set_tile"]
+           "lvq_kernel_time", "lvq_autotune", "lvq_set_tile", "lvq_server_create", "lvq_server_submit",
+           "lvq_server_wait", "lvq_server_drain", "lvq_server_get_stats", "lvq_server_destroy"]
 
 
 class lvq_config(ctypes.Structure):
@@ -53,6 +54,25 @@ class lvq_stats(ctypes.Structure):
                 ("n_means", ctypes.c_int32), ("row_bytes", ctypes.c_int32),
                 ("resid_bytes", ctypes.c_int32), ("code_positions", ctypes.c_int32),
                 ("epoch", ctypes.c_uint32)]
+
+
+class lvq_server_config(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("k_first", ctypes.c_int32), ("precision", ctypes.c_int32), ("rerank_level", ctypes.c_int32),
+                ("pool_bytes", ctypes.c_int64)]
+
+
+class lvq_request_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("nq", ctypes.c_int32), ("epoch", ctypes.c_uint32),
+                ("slot", ctypes.c_int32), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class lvq_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("pool_bytes", ctypes.c_int64),
+                ("pool_peak", ctypes.c_int64), ("batch_bytes_max", ctypes.c_int64), ("slots", ctypes.c_int32),
+                ("peak_in_flight", ctypes.c_int32), ("peak_queue", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("in_flight", ctypes.c_int32)]
 
 
 class LVQError(RuntimeError):
@@ -71,7 +91,7 @@ def _load():
         "lvq_row_format": [ctypes.POINTER(lvq_config), P, P, P],
         "lvq_create": [ctypes.POINTER(lvq_config), P, i32, ctypes.POINTER(P)],
         "lvq_destroy": [P],
-        "lvq_set_means": [P, P, i32, P],
+        "lvq_set_means": [P, P, i32, P, P],
         "lvq_encode": [P, P, i64, P, P, P],
         "lvq_insert": [P, P, i64, P, P, P],
         "lvq_delete": [P, P, i64, P],
@@ -88,6 +108,12 @@ def _load():
         "lvq_autotune": [P, P, i64, P, P, i64, i32, i32, P, P, P],
         "lvq_set_tile": [P, i32, i32, i32],
         "lvq_kernel_time": [P, P, P],
+        "lvq_server_create": [P, ctypes.POINTER(lvq_server_config), ctypes.POINTER(P)],
+        "lvq_server_submit": [P, P, i32, P],
+        "lvq_server_wait": [P, i64, P, P, ctypes.POINTER(lvq_request_info)],
+        "lvq_server_drain": [P],
+        "lvq_server_get_stats": [P, ctypes.POINTER(lvq_server_stats)],
+        "lvq_server_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -128,9 +154,9 @@ def lvq_destroy(ix: int):
     return _chk(_lib.lvq_destroy(ix), "lvq_destroy")
 
 
-def lvq_set_means(ix, means_host_ptr, n_means) -> int:
+def lvq_set_means(ix, means_host_ptr, n_means, stream=0) -> int:
     first = ctypes.c_int32()
-    _chk(_lib.lvq_set_means(ix, means_host_ptr, n_means, ctypes.byref(first)), "lvq_set_means")
+    _chk(_lib.lvq_set_means(ix, means_host_ptr, n_means, ctypes.byref(first), stream), "lvq_set_means")
     return first.value
 
 
@@ -199,6 +225,39 @@ def lvq_kernel_time(ix):
     return ms.value, n.value
 
 
+def lvq_server_create(ix, cfg: lvq_server_config) -> int:
+    out = ctypes.c_void_p()
+    _chk(_lib.lvq_server_create(ix, ctypes.byref(cfg), ctypes.byref(out)), "lvq_server_create")
+    return out.value
+
+
+def lvq_server_submit(sv, q_host_ptr, nq) -> int:
+    t = ctypes.c_int64()
+    _chk(_lib.lvq_server_submit(sv, q_host_ptr, nq, ctypes.byref(t)), "lvq_server_submit")
+    return t.value
+
+
+def lvq_server_wait(sv, ticket, ids_host_ptr, dist_host_ptr) -> lvq_request_info:
+    """Blocks until the batch is done; returns its record (status included)."""
+    info = lvq_request_info()
+    _lib.lvq_server_wait(sv, ticket, ids_host_ptr, dist_host_ptr, ctypes.byref(info))
+    return info
+
+
+def lvq_server_drain(sv):
+    return _chk(_lib.lvq_server_drain(sv), "lvq_server_drain")
+
+
+def lvq_server_get_stats(sv) -> lvq_server_stats:
+    st = lvq_server_stats()
+    _chk(_lib.lvq_server_get_stats(sv, ctypes.byref(st)), "lvq_server_get_stats")
+    return st
+
+
+def lvq_server_destroy(sv):
+    return _chk(_lib.lvq_server_destroy(sv), "lvq_server_destroy")
+
+
 def lvq_mean(x, n, dim, out, stream=0):
     return _chk(_lib.lvq_mean(x, n, dim, out, stream), "lvq_mean")
 
@@ -245,10 +304,10 @@ class Index:
         except Exception:
             pass
 
-    def set_means(self, means) -> int:
+    def set_means(self, means, stream=None) -> int:
         import numpy as np
         m = np.ascontiguousarray(means, np.float32).reshape(-1, self.dim)
-        return lvq_set_means(self.handle, m.ctypes.data, m.shape[0])
+        return lvq_set_means(self.handle, m.ctypes.data, m.shape[0], _stream(stream))
 
     def encode(self, x, stream=None):
         import torch
@@ -353,6 +412,52 @@ class Index:
 
     def kernel_time(self):
         return lvq_kernel_time(self.handle)
+
+
+class Server:
+    """Request server over an Index (lvq_server_* of lvq.h): batches of host
+    float32 queries are admitted by free stream slots and pool memory, run
+    concurrently, and answered at their admission epoch."""
+
+    def __init__(self, index: Index, slots=8, max_batch=512, k=10, k_first=64, precision=LVQ_FP32,
+                 rerank_level=LVQ_FULL, pool_bytes=0):
+        self.index = index
+        self.k = k
+        self.cfg = lvq_server_config(slots, max_batch, k, k_first, precision, rerank_level, pool_bytes)
+        self.handle = lvq_server_create(index.handle, self.cfg)
+
+    def submit(self, q) -> int:
+        """q: host (numpy) nq x dim float32; copied before return."""
+        import numpy as np
+        q = np.ascontiguousarray(q, np.float32)
+        return lvq_server_submit(self.handle, q.ctypes.data, q.shape[0])
+
+    def wait(self, ticket, nq):
+        """(ids nq x k int32, dist nq x k float32, record); raises on a failed batch."""
+        import numpy as np
+        ids = np.empty((nq, self.k), np.int32)
+        dist = np.empty((nq, self.k), np.float32)
+        info = lvq_server_wait(self.handle, ticket, ids.ctypes.data, dist.ctypes.data)
+        if info.status != LVQ_OK:
+            raise LVQError(info.status, "lvq_server_wait")
+        return ids, dist, info
+
+    def drain(self):
+        lvq_server_drain(self.handle)
+
+    def stats(self) -> lvq_server_stats:
+        return lvq_server_get_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lvq_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mean(x, stream=None):

@@ -12,7 +12,7 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "liblvq.so")
 
 SOURCES = ["lvq_host.hip", "k_encode.hip", "k_misc.hip", "k_cand4.hip", "k_cand8.hip",
-           "k_scan4.hip", "k_scan8.hip", "k_mfma.hip"]
+           "k_scan4.hip", "k_scan8.hip", "k_mfma.hip", "lvq_serve.hip"]
 # binary32 encoding must round every operation on its own
 EXTRA = {"k_encode.hip": ["-ffp-contract=off"]}
 
@@ -48,7 +48,7 @@ def build(jobs: int | None = None) -> str:
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", tmp]
+    cmd = [_hipcc(), "-shared", "-fPIC", "-pthread", "--offload-arch=" + ARCH] + objs + ["-o", tmp]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

@@ -482,7 +482,7 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
             float score = finish_pair<B2, METRIC, G>(A, l2acc, hdr, cmt, a.n_means, qsum);
             if (valid && !work) {
                 score = __uint_as_float(0x7FC00000u);
-                if (g == 0) atomicOr(a.err, kErrBadSlot);
+                if (g == 0 && !(a.neg_empty && slot < 0)) atomicOr(a.err, kErrBadSlot);
             }
             if (valid && g == 0 && a.dist) a.dist[e] = score;
             if (k > 0) {

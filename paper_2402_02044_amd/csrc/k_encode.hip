@@ -132,7 +132,7 @@ __global__ __launch_bounds__(64) void k_encode(EncodeArgs a)
         for (int m = g; m < a.n_means; m += G) {
             float s = 0.0f;
             for (int j = 0; j < d; ++j) {
-                float e = ts[j] - a.means_t[(int64_t)j * a.n_means + m];
+                float e = ts[j] - a.means_t[(int64_t)j * a.means_t_stride + m];
                 float e2 = e * e;
                 s = s + e2;
             }
@@ -214,6 +214,16 @@ __global__ __launch_bounds__(64) void k_encode(EncodeArgs a)
     const int row_words = a.f.row_bytes / 4;
     const int code_words = a.f.code_bytes / 4;
     for (int w = g; w < row_words; w += G) {
+        if (store && w == 4) {
+            // insert and delete epochs in one 64-bit store: a scan running
+            // beside this insert reads the pair whole (old or new), and
+            // either way finds the row invisible at its own, older epoch
+            const uint64_t ep = ((uint64_t)(finite ? kLiveEpoch : a.epoch) << 32) | a.epoch;
+            __hip_atomic_store(reinterpret_cast<uint64_t *>(row + 4), ep, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            continue;
+        }
+        if (store && w == 5) continue;
         uint32_t v = 0;
         if (w < 8) {
             uint64_t ext = store ? (a.ext_ids ? a.ext_ids[i] : (uint64_t)slot) : 0ull;
@@ -222,8 +232,7 @@ __global__ __launch_bounds__(64) void k_encode(EncodeArgs a)
             case 1: v = finite ? __float_as_uint(delta) : 0u; break;
             case 2: v = finite ? __float_as_uint(delta2) : 0u; break;
             case 3: v = (finite ? (uint32_t)mstar : 0u) | (store ? 0x100u : 0u); break;
-            case 4: v = store ? a.epoch : 0u; break;
-            case 5: v = store ? (finite ? kLiveEpoch : a.epoch) : 0u; break;
+            case 4: case 5: v = 0u; break;   // epochs of an encode-only row
             case 6: v = (uint32_t)ext; break;
             default: v = (uint32_t)(ext >> 32); break;
             }

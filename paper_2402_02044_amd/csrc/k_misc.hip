@@ -56,6 +56,26 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
         p[i] = v;
 }
 
+// fp32 -> bf16 (upper half, round to nearest even; NaN stays a quiet NaN) or
+// fp16 (the hardware conversion, round to nearest even).
+__global__ void k_cast16(const float *x, int64_t n, int prec, uint16_t *out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = x[i];
+        uint16_t h;
+        if (prec == LVQ_BF16) {
+            const uint32_t u = __float_as_uint(v);
+            h = (u & 0x7FFFFFFFu) > 0x7F800000u ? (uint16_t)((u >> 16) | 0x40u)
+                                                 : (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+        } else {
+            const _Float16 f = (_Float16)v;
+            h = __builtin_bit_cast(uint16_t, f);
+        }
+        out[i] = h;
+    }
+}
+
 // ---- list order for the persistent launch ---------------------------------
 // Lists are bucketed by floor(log2(length)), longest bucket first, so the
 // work counter hands out long lists before short ones (longest-first
@@ -306,6 +326,13 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast16(const float *x, int64_t n, int prec, void *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cast16, dim3(fill_blocks(n)), dim3(256), 0, s, x, n, prec, reinterpret_cast<uint16_t *>(out));
     return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@
 #include <new>
 #include <vector>
 
-#include "lvq_internal.h"
+#include "lvq_index.h"
 
 namespace lvq {
 
@@ -69,50 +69,6 @@ void kernel_order_dims(const Format &f, int32_t *kdim)
 }  // namespace lvq
 
 using namespace lvq;
-
-namespace {
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-
-struct Workspace {
-    DevBuf qk, qsum, cm, order, queue, part, q16, gthr;
-};
-
-struct InFlight {
-    uint32_t epoch;
-    hipEvent_t ev;
-};
-
-}  // namespace
-
-struct lvq_index {
-    lvq_config cfg;
-    Format f;
-    int device = 0;
-    int n_cu = 256;
-    size_t lds_max = 65536;    // LDS bytes one workgroup may allocate
-    int n_means = 0;
-    // device store
-    DevBuf means, means_t, muk, kmask, kdim, pos_dim, rows, resid, stack, err, scratch;
-    int64_t free_top = 0;   // host view of the free-slot stack top
-    int64_t fresh = 0;      // never-used slots at the bottom of the stack
-    uint32_t epoch = 1;
-    int64_t device_bytes = 0;
-    std::map<hipStream_t, Workspace> ws;
-    std::deque<InFlight> inflight;
-    std::vector<hipEvent_t> spare_events;
-    hipEvent_t update_ev = nullptr;   // recorded after the latest store update
-    hipStream_t update_stream = nullptr;
-    bool have_update = false;
-    std::mutex mu;
-    int cand_shape[2][2] = {{-1, -1}, {-1, -1}};   // tuned [level][topk]
-    bool capturing = false;   // the current call's stream is capturing a HIP graph
-    bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
-};
 
 namespace {
 
@@ -175,11 +131,11 @@ int upload_means(lvq_index *ix, const std::vector<float> &all)
 {
     const Format &f = ix->f;
     const int M = ix->n_means, d = f.dim;
-    std::vector<float> mt((size_t)d * M), mk((size_t)M * f.kpos, 0.0f);
+    std::vector<float> mt((size_t)d * kMaxMeans, 0.0f), mk((size_t)M * f.kpos, 0.0f);
     std::vector<int32_t> kd(f.kpos);
     kernel_order_dims(f, kd.data());
     for (int m = 0; m < M; ++m)
-        for (int j = 0; j < d; ++j) mt[(size_t)j * M + m] = all[(size_t)m * d + j];
+        for (int j = 0; j < d; ++j) mt[(size_t)j * kMaxMeans + m] = all[(size_t)m * d + j];
     for (int m = 0; m < M; ++m)
         for (int s = 0; s < f.kpos; ++s)
             if (kd[s] >= 0) mk[(size_t)m * f.kpos + s] = all[(size_t)m * d + kd[s]];
@@ -316,6 +272,15 @@ bool shape_fits(const Format &f, void *(*lookup)(int, int, int), int bits2, int 
 
 }  // namespace
 
+namespace lvq {
+
+int host_begin_call(lvq_index *ix, hipStream_t s) { return begin_call(ix, s); }
+int host_note_query(lvq_index *ix, hipStream_t s, uint32_t epoch) { return note_query(ix, s, epoch); }
+int host_alloc(lvq_index *ix, DevBuf &b, size_t bytes) { return dev_alloc(ix, b, bytes); }
+void host_free(lvq_index *ix, DevBuf &b) { dev_free(ix, b); }
+
+}  // namespace lvq
+
 extern "C" {
 
 const char *lvq_strerror(int code)
@@ -431,21 +396,45 @@ int lvq_destroy(lvq_index *ix)
     return LVQ_OK;
 }
 
-int lvq_set_means(lvq_index *ix, const float *means_host, int32_t n_means, int32_t *first_id_out)
+int lvq_set_means(lvq_index *ix, const float *means_host, int32_t n_means, int32_t *first_id_out, void *stream)
 {
-    if (!ix || !means_host || n_means < 1) return LVQ_ERR_INVALID_ARG;
-    std::lock_guard<std::mutex> lk(ix->mu);
-    if (ix->n_means + n_means > kMaxMeans) return LVQ_ERR_CAPACITY;
-    const int d = ix->f.dim;
+    if (!ix || !means_host || n_means < 1 || n_means > kMaxMeans) return LVQ_ERR_INVALID_ARG;
+    const Format &f = ix->f;
+    const int d = f.dim;
     if (!finite_host(means_host, (size_t)n_means * d)) return LVQ_ERR_NONFINITE;
-    LVQ_HIP(hipDeviceSynchronize());
-    std::vector<float> all((size_t)(ix->n_means + n_means) * d);
-    LVQ_HIP(hipMemcpy(all.data(), ix->means.p, sizeof(float) * (size_t)ix->n_means * d, hipMemcpyDeviceToHost));
-    std::memcpy(all.data() + (size_t)ix->n_means * d, means_host, sizeof(float) * (size_t)n_means * d);
-    const int first = ix->n_means;
-    ix->n_means += n_means;
-    int rc = upload_means(ix, all);
-    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    // tables for the new ids only: work already queued reads ids below the old count
+    std::vector<float> mt((size_t)d * n_means), mk((size_t)n_means * f.kpos, 0.0f);
+    std::vector<int32_t> kd(f.kpos);
+    kernel_order_dims(f, kd.data());
+    for (int m = 0; m < n_means; ++m)
+        for (int j = 0; j < d; ++j) mt[(size_t)j * n_means + m] = means_host[(size_t)m * d + j];
+    for (int m = 0; m < n_means; ++m)
+        for (int t = 0; t < f.kpos; ++t)
+            if (kd[t] >= 0) mk[(size_t)m * f.kpos + t] = means_host[(size_t)m * d + kd[t]];
+    int first = 0;
+    {
+        std::lock_guard<std::mutex> lk(ix->mu);
+        if (ix->n_means + n_means > kMaxMeans) return LVQ_ERR_CAPACITY;
+        int rc = begin_call(ix, s);
+        if (rc) return rc;
+        if (ix->capturing) {
+            ix->capturing = false;
+            return LVQ_ERR_INVALID_ARG;
+        }
+        if ((rc = order_after_updates(ix, s))) return rc;
+        first = ix->n_means;
+        LVQ_HIP(hipMemcpyAsync(P<float>(ix->means) + (size_t)first * d, means_host, sizeof(float) * mt.size(),
+                               hipMemcpyHostToDevice, s));
+        LVQ_HIP(hipMemcpy2DAsync(P<float>(ix->means_t) + first, sizeof(float) * kMaxMeans, mt.data(),
+                                 sizeof(float) * n_means, sizeof(float) * n_means, d, hipMemcpyHostToDevice, s));
+        LVQ_HIP(hipMemcpyAsync(P<float>(ix->muk) + (size_t)first * f.kpos, mk.data(), sizeof(float) * mk.size(),
+                               hipMemcpyHostToDevice, s));
+        ix->n_means += n_means;
+        if ((rc = note_update(ix, s))) return rc;
+    }
+    // the host sources must outlive the copies
+    LVQ_HIP(hipStreamSynchronize(s));
     if (first_id_out) *first_id_out = first;
     return LVQ_OK;
 }
@@ -458,6 +447,7 @@ static int encode_common(lvq_index *ix, const float *x, int64_t n, uint8_t *rows
     a.n = n;
     a.means = P<float>(ix->means);
     a.means_t = P<float>(ix->means_t);
+    a.means_t_stride = kMaxMeans;
     a.n_means = ix->n_means;
     a.pos_dim = P<int32_t>(ix->pos_dim);
     a.f = ix->f;
@@ -562,9 +552,12 @@ int lvq_consolidate(lvq_index *ix, void *stream, int64_t *n_freed_out)
     return note_update(ix, s);
 }
 
-static int distances_impl(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev,
-                          const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev, int32_t k,
-                          int32_t *topk_ids_dev, float *topk_dist_dev, hipStream_t s, int force_shape)
+}  // extern "C"
+
+int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev,
+                        const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev, int32_t k,
+                        int32_t *topk_ids_dev, float *topk_dist_dev, hipStream_t s, int force_shape,
+                        uint32_t epoch, bool neg_empty)
 {
     if (!ix || nq < 0 || total < 0 || nq > INT32_MAX) return LVQ_ERR_INVALID_ARG;
     if (level != LVQ_PRIMARY && level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
@@ -622,8 +615,9 @@ static int distances_impl(lvq_index *ix, const float *q_dev, int64_t nq, const i
     a.k = k;
     a.topk_ids = topk_ids_dev;
     a.topk_dist = topk_dist_dev;
-    a.epoch = ix->epoch;
+    a.epoch = epoch;
     a.err = P<uint32_t>(ix->err);
+    a.neg_empty = neg_empty ? 1 : 0;
     // persistent launch: lists longest-first from a device work counter
     a.order = P<int32_t>(w.order);
     a.queue = P<int32_t>(w.queue);
@@ -635,9 +629,10 @@ static int distances_impl(lvq_index *ix, const float *q_dev, int64_t nq, const i
     if ((rc = timing_begin(ix, s))) return rc;
     hipLaunchKernelGGL(reinterpret_cast<void (*)(CandArgs)>(kern), dim3((unsigned)grid), dim3(256), lds, s, a);
     LVQ_HIP(hipGetLastError());
-    if ((rc = timing_end(ix, s))) return rc;
-    return note_query(ix, s, ix->epoch);
+    return timing_end(ix, s);
 }
+
+extern "C" {
 
 int lvq_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev, const int32_t *ids_dev,
                   int64_t total, int32_t level, float *dist_dev, int32_t k, int32_t *topk_ids_dev,
@@ -647,8 +642,9 @@ int lvq_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *
     std::lock_guard<std::mutex> lk(ix->mu);
     int rc = begin_call(ix, (hipStream_t)stream);
     if (rc) return rc;
-    rc = distances_impl(ix, q_dev, nq, offsets_dev, ids_dev, total, level, dist_dev, k, topk_ids_dev,
-                        topk_dist_dev, (hipStream_t)stream, -1);
+    rc = host_distances(ix, q_dev, nq, offsets_dev, ids_dev, total, level, dist_dev, k, topk_ids_dev,
+                        topk_dist_dev, (hipStream_t)stream, -1, ix->epoch, false);
+    if (rc == LVQ_OK) rc = note_query(ix, (hipStream_t)stream, ix->epoch);
     ix->capturing = false;
     return rc;
 }
@@ -684,12 +680,14 @@ int lvq_autotune(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *o
     float best_ms = 0.0f;
     int rc = LVQ_OK;
     for (int i = 0; i < num_tile_shapes() && rc == LVQ_OK; ++i) {
-        if (distances_impl(ix, q_dev, nq, offsets_dev, ids_dev, total, level, dist, k, ti, td, s, i) != LVQ_OK)
+        if (host_distances(ix, q_dev, nq, offsets_dev, ids_dev, total, level, dist, k, ti, td, s, i, ix->epoch,
+                           false) != LVQ_OK)
             continue;   // shape not available for this format
         float ms = 0.0f;
         if (hipEventRecord(a, s) != hipSuccess) { rc = LVQ_ERR_DEVICE; break; }
         for (int r = 0; r < 3 && rc == LVQ_OK; ++r)
-            rc = distances_impl(ix, q_dev, nq, offsets_dev, ids_dev, total, level, dist, k, ti, td, s, i);
+            rc = host_distances(ix, q_dev, nq, offsets_dev, ids_dev, total, level, dist, k, ti, td, s, i, ix->epoch,
+                                false);
         if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
             hipEventElapsedTime(&ms, a, b) != hipSuccess) {
             rc = LVQ_ERR_DEVICE;
@@ -714,28 +712,56 @@ int lvq_autotune(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *o
     return LVQ_OK;
 }
 
-static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level,
-                     int32_t *ids_dev, float *dist_dev, hipStream_t s);
+}  // extern "C"
 
-int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level, int32_t *ids_dev,
-             float *dist_dev, void *stream)
+static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level,
+                     int32_t *ids_dev, float *dist_dev, hipStream_t s, uint32_t epoch);
+
+// Row parts of the FP32 scan: enough workgroups (query tiles x parts) for
+// about four per compute unit, parts of at least 1024 rows, and a merge that
+// holds parts * k keys (+ k) of 8 bytes in one workgroup's LDS.
+static int64_t scan_parts_fp32(const lvq_index *ix, int64_t nq, int32_t k, int64_t n_rows)
 {
-    if (!ix || nq < 0 || nq > INT32_MAX || k < 1 || k > kMaxTopK) return LVQ_ERR_INVALID_ARG;
+    const int64_t qtiles = (nq + 15) / 16;
+    int64_t parts = std::max<int64_t>(1, (4 * (int64_t)ix->n_cu + qtiles - 1) / qtiles);
+    parts = std::min<int64_t>(parts, std::max<int64_t>(1, n_rows / 1024));
+    return std::min<int64_t>(parts, std::max<int64_t>(1, (int64_t)(ix->lds_max / 8 - k) / k));
+}
+
+// Row parts of the MFMA scan (one resident workgroup per compute unit): few,
+// long parts, since every part starts with a loose top-k bound; the count
+// whose workgroups fill the compute units in whole rounds best, parts of at
+// least 64 row rounds, a merge that fits one workgroup's LDS.
+static int64_t scan_parts_mfma(const lvq_index *ix, int64_t qtiles, int32_t k, int64_t n_rows)
+{
+    const int64_t max_parts = std::max<int64_t>(
+        1, std::min<int64_t>({16, n_rows / (64 * 128), (int64_t)(ix->lds_max / 8 - k) / k}));
+    int64_t parts = 1;
+    double best = -1.0;
+    for (int64_t p = 1; p <= max_parts; ++p) {
+        const int64_t wg = qtiles * p;
+        const int64_t rounds = (wg + ix->n_cu - 1) / ix->n_cu;
+        const double fill = (double)wg / (double)(rounds * ix->n_cu);   // busy fraction of the last rounds
+        const double score = fill - 0.02 * (double)p;                    // prefer fewer parts on ties
+        if (score > best) {
+            best = score;
+            parts = p;
+        }
+    }
+    return parts;
+}
+
+int lvq::host_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level,
+                   int32_t *ids_dev, float *dist_dev, hipStream_t s, uint32_t epoch)
+{
+    if (nq < 0 || nq > INT32_MAX || k < 1 || k > kMaxTopK) return LVQ_ERR_INVALID_ARG;
     if (level != LVQ_PRIMARY && level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
     if (prec != LVQ_FP32 && prec != LVQ_BF16 && prec != LVQ_FP16) return LVQ_ERR_INVALID_ARG;
     if (nq == 0) return LVQ_OK;
     if (!q_dev || !ids_dev || !dist_dev) return LVQ_ERR_INVALID_ARG;
     if (level == LVQ_FULL && ix->f.bits2 == 0) return LVQ_ERR_INVALID_ARG;
-    std::lock_guard<std::mutex> lk(ix->mu);
-    hipStream_t s = (hipStream_t)stream;
-    int rc0 = begin_call(ix, s);
-    if (rc0) return rc0;
-    struct Reset {
-        lvq_index *ix;
-        ~Reset() { ix->capturing = false; }
-    } reset{ix};
     const Format &f = ix->f;
-    if (prec != LVQ_FP32) return topk_mfma(ix, q_dev, prec, nq, k, level, ids_dev, dist_dev, s);
+    if (prec != LVQ_FP32) return topk_mfma(ix, q_dev, prec, nq, k, level, ids_dev, dist_dev, s, epoch);
     const bool l2 = ix->cfg.metric == LVQ_L2;
     if (l2 && ix->n_means > 1) return LVQ_ERR_UNSUPPORTED;
     const bool masked = l2 && f.kpos != f.dim;
@@ -766,10 +792,7 @@ int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t
     if ((rc = prep_queries(ix, w, (const float *)q_dev, nq, s))) return rc;
     const int64_t n_rows = ix->cfg.capacity - ix->fresh;   // slots ever used
     const int64_t qtiles = (nq + 15) / 16;
-    int64_t parts = std::max<int64_t>(1, (4 * (int64_t)ix->n_cu + qtiles - 1) / qtiles);
-    parts = std::min<int64_t>(parts, std::max<int64_t>(1, n_rows / 1024));
-    // the merge holds parts * k keys (+ k) of 8 bytes in one workgroup's LDS
-    parts = std::min<int64_t>(parts, std::max<int64_t>(1, (int64_t)(ix->lds_max / 8 - k) / k));
+    const int64_t parts = scan_parts_fp32(ix, nq, k, n_rows);
     const int64_t rows_per_part = std::max<int64_t>(1, (n_rows + parts - 1) / parts);
     if ((rc = dev_alloc(ix, w.part, sizeof(uint64_t) * (size_t)nq * parts * k))) return rc;
 
@@ -790,7 +813,7 @@ int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t
     a.n_means = ix->n_means;
     a.nq = nq;
     a.k = k;
-    a.epoch = ix->epoch;
+    a.epoch = epoch;
     a.rows_per_part = rows_per_part;
     a.n_parts = (int)parts;
     a.capq = capq;
@@ -803,12 +826,30 @@ int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t
     LVQ_HIP(hipGetLastError());
     if ((rc = timing_end(ix, s))) return rc;
     LVQ_HIP(launch_topk_merge(a.part_keys, nq, (int)parts, k, ix->cfg.metric, ids_dev, dist_dev, s));
-    return note_query(ix, s, ix->epoch);
+    return LVQ_OK;
 }
+
+extern "C" {
+
+int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level, int32_t *ids_dev,
+             float *dist_dev, void *stream)
+{
+    if (!ix) return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = begin_call(ix, s);
+    if (rc) return rc;
+    rc = host_topk(ix, q_dev, prec, nq, k, level, ids_dev, dist_dev, s, ix->epoch);
+    if (rc == LVQ_OK && nq > 0) rc = note_query(ix, s, ix->epoch);
+    ix->capturing = false;
+    return rc;
+}
+
+}  // extern "C"
 
 // Exhaustive top-k on the matrix cores: inner product, first level only.
 static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level,
-                     int32_t *ids_dev, float *dist_dev, hipStream_t s)
+                     int32_t *ids_dev, float *dist_dev, hipStream_t s, uint32_t epoch)
 {
     const Format &f = ix->f;
     if (ix->cfg.metric != LVQ_IP || level != LVQ_PRIMARY) return LVQ_ERR_UNSUPPORTED;
@@ -827,24 +868,7 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     LVQ_HIP(launch_prep16(q_dev, nq, f.dim, f.kpos, f.bits1, prec, P<int32_t>(ix->kdim), P<float>(ix->means),
                           ix->n_means, w.q16.p, P<float>(w.qsum), P<float>(w.cm), s));
     const int64_t n_rows = ix->cfg.capacity - ix->fresh;
-    // One resident workgroup per compute unit: pick the number of parts (few,
-    // long parts: every part starts with a loose top-k threshold) whose
-    // workgroup count fills the compute units in whole rounds best; parts of
-    // at least 64 row rounds; a merge that fits one workgroup's LDS.
-    const int64_t max_parts = std::max<int64_t>(
-        1, std::min<int64_t>({16, n_rows / (64 * 128), (int64_t)(ix->lds_max / 8 - k) / k}));
-    int64_t parts = 1;
-    double best = -1.0;
-    for (int64_t p = 1; p <= max_parts; ++p) {
-        const int64_t wg = qtiles * p;
-        const int64_t rounds = (wg + ix->n_cu - 1) / ix->n_cu;
-        const double fill = (double)wg / (double)(rounds * ix->n_cu);   // busy fraction of the last rounds
-        const double score = fill - 0.02 * (double)p;                    // prefer fewer parts on ties
-        if (score > best) {
-            best = score;
-            parts = p;
-        }
-    }
+    const int64_t parts = scan_parts_mfma(ix, qtiles, k, n_rows);
     const int64_t rows_per_part = std::max<int64_t>(1, (n_rows + parts - 1) / parts);
     if ((rc = dev_alloc(ix, w.part, sizeof(uint64_t) * (size_t)nq * parts * k))) return rc;
     if ((rc = dev_alloc(ix, w.gthr, sizeof(uint32_t) * (size_t)nq))) return rc;
@@ -866,7 +890,7 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     a.n_means = ix->n_means;
     a.nq = nq;
     a.k = k;
-    a.epoch = ix->epoch;
+    a.epoch = epoch;
     a.rows_per_part = rows_per_part;
     a.n_parts = (int)parts;
     a.capq = capq;
@@ -877,8 +901,52 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     LVQ_HIP(launch_scan_mfma(a, f.bits1, prec, s));
     if ((rc = timing_end(ix, s))) return rc;
     LVQ_HIP(launch_topk_merge(a.part_keys, nq, (int)parts, k, LVQ_IP, ids_dev, dist_dev, s));
-    return note_query(ix, s, ix->epoch);
+    return LVQ_OK;
 }
+
+int lvq::host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_first, int32_t prec,
+                      int32_t k_rerank, int32_t rerank_level)
+{
+    if (max_nq < 1 || max_nq > INT32_MAX || k_first < 1 || k_first > kMaxTopK || k_rerank < 0 ||
+        k_rerank > kMaxTopK)
+        return LVQ_ERR_INVALID_ARG;
+    if (k_rerank > 0 && rerank_level != LVQ_PRIMARY && rerank_level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
+    const Format &f = ix->f;
+    const int64_t n_rows = ix->cfg.capacity;   // the part counts grow with the rows scanned
+    size_t qk = 0, part = 0, q16 = 0, gthr = 0, order = 0;
+    const size_t qsum = sizeof(float) * (size_t)max_nq;
+    const size_t cm = sizeof(float) * (size_t)max_nq * kMaxMeans;   // any mean count the index may reach
+    if (prec == LVQ_FP32 || k_rerank > 0) qk = sizeof(float) * (size_t)max_nq * f.kpos;
+    if (prec == LVQ_FP32) {
+        for (int64_t nq = 1; nq <= max_nq; ++nq)
+            part = std::max(part, sizeof(uint64_t) * (size_t)(nq * scan_parts_fp32(ix, nq, k_first, n_rows) * k_first));
+    } else {
+        const int qb = mfma_query_block(f.bits1, f.kpos);
+        if (!qb) return LVQ_ERR_UNSUPPORTED;
+        const int64_t tq = 32 * qb;
+        q16 = (size_t)((max_nq + tq - 1) / tq) * tq * f.kpos * 2;
+        gthr = sizeof(uint32_t) * (size_t)max_nq;
+        for (int64_t nq = 1; nq <= max_nq; ++nq) {
+            const int64_t qtiles = (nq + tq - 1) / tq;
+            part = std::max(part,
+                            sizeof(uint64_t) * (size_t)(nq * scan_parts_mfma(ix, qtiles, k_first, n_rows) * k_first));
+        }
+    }
+    if (k_rerank > 0) order = sizeof(int32_t) * (size_t)max_nq;
+    Workspace &w = workspace(ix, s);
+    int rc;
+    if (qk && (rc = dev_alloc(ix, w.qk, qk))) return rc;
+    if ((rc = dev_alloc(ix, w.qsum, qsum))) return rc;
+    if ((rc = dev_alloc(ix, w.cm, cm))) return rc;
+    if (part && (rc = dev_alloc(ix, w.part, part))) return rc;
+    if (q16 && (rc = dev_alloc(ix, w.q16, q16))) return rc;
+    if (gthr && (rc = dev_alloc(ix, w.gthr, gthr))) return rc;
+    if (order && (rc = dev_alloc(ix, w.order, order))) return rc;
+    if (k_rerank > 0 && (rc = dev_alloc(ix, w.queue, 64))) return rc;
+    return LVQ_OK;
+}
+
+extern "C" {
 
 int lvq_read_rows(lvq_index *ix, const int32_t *slots_dev, int64_t n, uint8_t *rows_dev, uint8_t *resid_dev,
                   void *stream)

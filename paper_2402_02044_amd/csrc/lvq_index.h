@@ -1,0 +1,98 @@
+// lvq_index.h -- the library-owned index object and the host-side entry
+// points shared by lvq_host.hip (the C ABI) and lvq_serve.hip (the request
+// server).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <deque>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "lvq_internal.h"
+
+namespace lvq {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// Per-stream scratch of the query entry points.
+struct Workspace {
+    DevBuf qk, qsum, cm, order, queue, part, q16, gthr;
+};
+
+// A query launch that may still be reading the store, and the epoch it reads.
+struct InFlight {
+    uint32_t epoch;
+    hipEvent_t ev;
+};
+
+}  // namespace lvq
+
+struct lvq_index {
+    lvq_config cfg;
+    lvq::Format f;
+    int device = 0;
+    int n_cu = 256;
+    size_t lds_max = 65536;    // LDS bytes one workgroup may allocate
+    int n_means = 0;
+    // device store
+    lvq::DevBuf means, means_t, muk, kmask, kdim, pos_dim, rows, resid, stack, err, scratch;
+    int64_t free_top = 0;   // host view of the free-slot stack top
+    int64_t fresh = 0;      // never-used slots at the bottom of the stack
+    uint32_t epoch = 1;
+    int64_t device_bytes = 0;
+    std::map<hipStream_t, lvq::Workspace> ws;
+    std::deque<lvq::InFlight> inflight;
+    std::vector<hipEvent_t> spare_events;
+    hipEvent_t update_ev = nullptr;   // recorded after the latest store update
+    hipStream_t update_stream = nullptr;
+    bool have_update = false;
+    std::mutex mu;                    // guards every field above
+    int cand_shape[2][2] = {{-1, -1}, {-1, -1}};   // tuned [level][topk]
+    bool capturing = false;   // the current call's stream is capturing a HIP graph
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
+};
+
+namespace lvq {
+
+// The functions below expect the caller to hold ix->mu.
+
+// Record whether `s` is capturing a HIP graph (captured calls allocate
+// nothing and keep no in-flight record).
+int host_begin_call(lvq_index *ix, hipStream_t s);
+
+// Exhaustive top-k over the slots live at `epoch` (lvq_topk's semantics);
+// records no in-flight entry (host_note_query does).
+int host_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level,
+              int32_t *ids_dev, float *dist_dev, hipStream_t s, uint32_t epoch);
+
+// Candidate-list similarities (lvq_distances' semantics) with the fused top-k
+// filtered at `epoch`.  neg_empty: a negative slot marks an empty list entry
+// (no error, left out of the top-k) instead of an invalid one.
+int host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev,
+                   const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev, int32_t k,
+                   int32_t *topk_ids_dev, float *topk_dist_dev, hipStream_t s, int force_shape, uint32_t epoch,
+                   bool neg_empty);
+
+// Mark the work queued so far on `s` as a query reading the store at `epoch`
+// (consolidation keeps the slots that query may still see).
+int host_note_query(lvq_index *ix, hipStream_t s, uint32_t epoch);
+
+// Size the workspace of stream `s` for every query batch of up to max_nq
+// queries through host_topk (k_first, prec, first level) followed by
+// host_distances (k_rerank at `rerank_level`, 0 for none), so that such calls
+// on `s` allocate nothing.
+int host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_first, int32_t prec, int32_t k_rerank,
+                 int32_t rerank_level);
+
+// Device buffers not tied to a stream, drawn from the index's memory budget.
+int host_alloc(lvq_index *ix, DevBuf &b, size_t bytes);
+void host_free(lvq_index *ix, DevBuf &b);
+
+}  // namespace lvq

@@ -43,7 +43,8 @@ struct EncodeArgs {
     const float *x;          // n x dim
     int64_t n;
     const float *means;      // M x dim
-    const float *means_t;    // dim x M (transposed copy, coalesced assignment)
+    const float *means_t;    // dim rows of means_t_stride (transposed copy, coalesced assignment)
+    int means_t_stride;
     int n_means;
     const int32_t *pos_dim;  // npos entries: dimension at code position, -1 pad
     Format f;
@@ -90,6 +91,7 @@ struct CandArgs {
     uint32_t *err;
     const int32_t *order;    // list processing order (NULL: identity)
     int32_t *queue;          // persistent work counter (NULL: one list per block)
+    int neg_empty;           // a negative id is an empty entry, not an error
 };
 
 struct ScanArgs {
@@ -156,6 +158,8 @@ size_t mfma_lds_bytes(int qb, int n_means, int k, int capq);
 int mfma_capq(int qb, int n_means, int k, size_t lds_max);
 hipError_t launch_prep16(const void *q, int64_t nq, int dim, int kpos, int bits1, int prec, const int32_t *kdim,
                          const float *means, int n_means, void *frag, float *qsum, float *cm, hipStream_t s);
+// fp32 -> bf16 / fp16 (LVQ_BF16 / LVQ_FP16), round to nearest even, n values.
+hipError_t launch_cast16(const float *x, int64_t n, int prec, void *out, hipStream_t s);
 hipError_t launch_topk_merge(const uint64_t *part_keys, int64_t nq, int n_parts, int k, int metric,
                              int32_t *ids, float *dist, hipStream_t s);
 hipError_t launch_delete(const StoreArgs &a, const int32_t *slots, int64_t n, hipStream_t s);
