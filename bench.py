@@ -418,12 +418,318 @@ def bench_c4(args):
     return out
 
 
+# ---------------------------------------------------------------------------
+# C5: streaming serving (request server beside inserts, deletes, drift)
+# ---------------------------------------------------------------------------
+
+class C5Store:
+    """The served index plus what the harness needs to judge it: the float
+    vectors by slot (device copy for the ground truth, host copy for spot
+    checks) and which slots are live."""
+
+    def __init__(self, L, X0, means, cap, dev):
+        import torch
+        self.L, self.dev, self.cap = L, dev, cap
+        self.ix = L.Index(768, 4, 8, L.LVQ_IP, L.LVQ_TURBO, capacity=cap, means=means)
+        self.stream = torch.cuda.Stream()
+        self.Xd = torch.zeros((cap, 768), dtype=torch.float32, device=dev)
+        self.Xh = np.zeros((cap, 768), np.float32)
+        self.live = np.zeros(cap, bool)
+        self.n_means = means.shape[0]
+        for a in range(0, X0.shape[0], 1 << 18):
+            self.insert(X0[a:a + (1 << 18)])
+
+    def insert(self, X):
+        import torch
+        with torch.cuda.stream(self.stream):
+            xd = torch.from_numpy(X).to(self.dev)
+            slots_d = self.ix.insert(xd)
+            self.Xd[slots_d.long()] = xd
+            slots = slots_d.cpu().numpy()
+        self.Xh[slots] = X
+        self.live[slots] = True
+        return slots
+
+    def delete(self, slots):
+        import torch
+        with torch.cuda.stream(self.stream):
+            self.ix.delete(torch.from_numpy(slots.astype(np.int32)).to(self.dev))
+        self.live[slots] = False
+
+    def consolidate(self):
+        return self.ix.consolidate(stream=self.stream)
+
+    def refit_means(self, round_, k=16, sample=100_000, iters=25):
+        """k-means (Lloyd, on the GPU) over a uniform sample of live vectors,
+        appended to the index's means."""
+        import torch
+        import synth
+        g = synth.rng(5, synth.S_SAMPLE, 100 + round_)
+        cand = np.flatnonzero(self.live)
+        pick = np.sort(g.choice(cand, min(sample, cand.size), replace=False))
+        init = g.choice(pick.size, k, replace=False)
+        with torch.cuda.stream(self.stream):
+            S = self.Xd[torch.from_numpy(pick).to(self.dev)]
+            C = self.L.kmeans(S, k, init, iters=iters, stream=self.stream).cpu().numpy()
+        self.ix.set_means(C, stream=self.stream)
+        self.n_means += k
+
+    def groundtruth(self, Q, k=10, chunk=65536):
+        """Exact top-k by inner product over the live float vectors, binary64
+        products and sums (torch float64 on the GPU)."""
+        import torch
+        live = torch.from_numpy(np.flatnonzero(self.live)).to(self.dev)
+        with torch.cuda.stream(self.stream):
+            q = torch.from_numpy(Q).to(self.dev, torch.float64)
+            bv = bi = None
+            for a in range(0, live.numel(), chunk):
+                idx = live[a:a + chunk]
+                sc = q @ self.Xd[idx].double().T
+                v, i = sc.topk(k, dim=1)
+                i = idx[i]
+                if bv is not None:
+                    v = torch.cat([bv, v], 1)
+                    i = torch.cat([bi, i], 1)
+                    v, o = v.topk(k, dim=1)
+                    i = torch.gather(i, 1, o)
+                bv, bi = v, i
+            out = bi.cpu().numpy()
+        return out
+
+
+def c5_cpu_groundtruth(store, Q, k=10):
+    import oracle
+    return oracle.float_groundtruth(oracle.IP, Q, store.Xh, k, live=store.live)
+
+
+def c5_load(sv, batches, arrivals, waiter_out):
+    """Submit `batches` (host arrays) at the given arrival offsets in seconds
+    (None: all at once) and collect (nq, record) per batch, in order."""
+    import threading
+    tickets = []
+    lock = threading.Condition()
+
+    def waiter():
+        got = 0
+        while got < len(batches):
+            with lock:
+                while len(tickets) <= got:
+                    lock.wait()
+                t, nq = tickets[got]
+            _, _, info = sv.wait(t, nq)
+            waiter_out.append((nq, info))
+            got += 1
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    lag = []
+    for b, q in enumerate(batches):
+        if arrivals is not None:
+            due = t0 + arrivals[b]
+            while True:
+                dt = due - time.perf_counter()
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 0.002) if dt > 0.0003 else 0)
+            lag.append(time.perf_counter() - due)
+        t = sv.submit(q)
+        with lock:
+            tickets.append((t, q.shape[0]))
+            lock.notify()
+    th.join()
+    return float(np.mean(lag)) if lag else 0.0
+
+
+def bench_c5(args):
+    import threading
+
+    import torch
+
+    import oracle
+    import paper_2402_02044_amd as L
+    import synth
+    n0 = args.n or 1_000_000
+    rounds = args.rounds
+    ins = max(100, n0 // 100)
+    K, KF, MAXB, SLOTS = 10, 64, 512, 8
+    dev = torch.device("cuda:0")
+    log("generating %d x 768 C5 base vectors" % n0)
+    X0 = synth.vectors("C5", synth.S_BASE, 0, n0)
+    log("M-LVQ means: k-means (16) on a 100k sample")
+    samp = synth.sample_indices(5, n0, 100_000)
+    init = synth.rng(5, synth.S_SAMPLE, 2).choice(samp.size, 16, replace=False)
+    means = L.kmeans(torch.from_numpy(X0[samp]).to(dev), 16, init, iters=25).cpu().numpy()
+    cap = n0 + 5 * ins + 4096
+    log("encoding the store (capacity %d)" % cap)
+    st = C5Store(L, X0, means, cap, dev)
+    del X0
+    torch.cuda.synchronize()
+    assert st.ix.sync() == 0
+    # plain (FP32 vector) and matrix-core (bf16 MFMA) exhaustive scans at both
+    # levels, and the two-stage form: first-level MFMA top-K' re-ranked with
+    # both levels
+    forms = {"fp32": (L.LVQ_FP32, L.LVQ_FULL), "bf16": (L.LVQ_BF16, L.LVQ_FULL),
+             "bf16_rerank%d" % KF: (L.LVQ_BF16, L.LVQ_PRIMARY)}
+    servers = {f: L.Server(st.ix, slots=SLOTS, max_batch=MAXB, k=K, k_first=KF, precision=p, scan_level=lv)
+               for f, (p, lv) in forms.items()}
+    qpool = synth.c5_points(synth.S_QUERY, rounds // 2, 4096, part=1)
+    g = synth.rng(5, synth.S_ARRIVAL, 0)
+
+    def make_batches(nb):
+        sizes = g.integers(1, MAXB + 1, nb)
+        starts = g.integers(0, qpool.shape[0] - MAXB, nb)
+        return [qpool[a:a + s] for a, s in zip(starts, sizes)]
+
+    # ---- the update stream: rounds of delete / insert / consolidate / drift
+    progress = {"done": 0.0}
+    rec = {"live": [], "freed": [], "n_means": [], "update_ms": [], "epoch": [],
+           "recall": {f: [] for f in forms}, "gt_spot_checks": 0}
+    err = []
+
+    def updates():
+        try:
+            for r in range(rounds):
+                while progress["done"] < r / rounds:
+                    time.sleep(0.005)
+                t = time.perf_counter()
+                cand = np.flatnonzero(st.live)
+                dead = np.sort(synth.rng(5, synth.S_DELETE, r).choice(cand, cand.size // 10, replace=False))
+                st.delete(dead)
+                st.insert(synth.c5_points(synth.S_INSERT, r + 1, ins))
+                freed = st.consolidate()
+                if (r + 1) % 10 == 0:
+                    st.refit_means(r)
+                rec["update_ms"].append((time.perf_counter() - t) * 1000.0)
+                rec["live"].append(int(st.live.sum()))
+                rec["freed"].append(int(freed))
+                rec["n_means"].append(st.n_means)
+                # served recall at this round's state: 200 queries of the drifted mixture
+                Qr = synth.c5_points(synth.S_QUERY, r + 1, 200, part=0)
+                tk = {f: servers[f].submit(Qr) for f in forms}
+                res = {f: servers[f].wait(tk[f], Qr.shape[0]) for f in forms}
+                epoch = st.ix.stats().epoch
+                gt = st.groundtruth(Qr)
+                if r % 10 == 0:   # the GPU ground truth against the host definition on a few queries
+                    cpu = c5_cpu_groundtruth(st, Qr[:3])
+                    assert np.array_equal(np.sort(cpu, 1), np.sort(gt[:3], 1)), "ground truth mismatch"
+                    rec["gt_spot_checks"] += 1
+                for f in forms:
+                    ids, _, info = res[f]
+                    assert info.epoch == epoch
+                    rec["recall"][f].append(oracle.recall(ids, gt))
+                rec["epoch"].append(int(epoch))
+                log("round %d: live %d, freed %d, means %d, update %.0f ms, recall %s" %
+                    (r, rec["live"][-1], freed, st.n_means, rec["update_ms"][-1],
+                     " ".join("%s %.3f" % (f, rec["recall"][f][-1]) for f in forms)))
+        except BaseException as e:   # surfaced by the main thread
+            err.append(e)
+
+    upd = threading.Thread(target=updates)
+    upd.start()
+
+    # ---- the query load: saturation, then Poisson arrivals at 50/80/95 % of it
+    n_sat, n_lat = args.sat_batches, args.lat_batches
+    total = len(forms) * (n_sat + 3 * n_lat)
+    served = 0
+    serving = {}
+    for f in forms:
+        sv = servers[f]
+        out = []
+        c5_load(sv, make_batches(max(8, n_sat // 8)), None, [])    # warm-up
+        c5_load(sv, make_batches(n_sat), None, out)
+        served += n_sat
+        progress["done"] = served / total
+        q = sum(nq for nq, _ in out)
+        span = max(i.t_done for _, i in out) - min(i.t_submit for _, i in out)
+        qps = q / span
+        ent = {"qps_saturation": qps, "batches_saturation": n_sat, "latency_ms": {}}
+        log("%s: saturation %.0f queries/s over %d batches" % (f, qps, n_sat))
+        mean_nq = (MAXB + 1) / 2.0
+        for frac in (0.5, 0.8, 0.95):
+            rate = frac * qps / mean_nq
+            arr = np.cumsum(g.exponential(1.0 / rate, n_lat))
+            out = []
+            lag = c5_load(sv, make_batches(n_lat), arr, out)
+            served += n_lat
+            progress["done"] = served / total
+            lat = np.array([(i.t_done - i.t_submit) * 1000.0 for _, i in out])
+            q = sum(nq for nq, _ in out)
+            span = max(i.t_done for _, i in out) - min(i.t_submit for _, i in out)
+            ent["latency_ms"]["%d%%" % round(frac * 100)] = {
+                "offered_qps": frac * qps, "achieved_qps": q / span, "p50": float(np.percentile(lat, 50)),
+                "p99": float(np.percentile(lat, 99)), "mean": float(lat.mean()), "batches": n_lat,
+                "mean_submit_lag_ms": lag * 1000.0}
+            log("%s at %d%%: p50 %.2f ms, p99 %.2f ms" % (f, frac * 100, np.percentile(lat, 50),
+                                                          np.percentile(lat, 99)))
+        ent["peak_in_flight"] = sv.stats().peak_in_flight
+        serving[f] = ent
+    progress["done"] = 1.0
+    upd.join()
+    if err:
+        raise err[0]
+    for f in forms:
+        r = np.array(rec["recall"][f])
+        serving[f]["recall_at_10"] = {"mean": float(r.mean()), "min": float(r.min()),
+                                      "per_round": [round(float(v), 4) for v in r]}
+    assert st.ix.sync() == 0
+
+    # cpu baseline: the oracle serving queries on a bounded slice of the store
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a host-core sample")
+        fmt = oracle.Format(768, 4, 8, oracle.TURBO)
+        live = np.flatnonzero(st.live)
+        sl = live[:100_000]
+        rows, resid, _ = oracle.encode_rows(fmt, st.Xh[sl], means)
+        Qs = synth.c5_points(synth.S_QUERY, rounds, 4, part=2)
+        t = time.perf_counter()
+        nq_s = 0
+        while nq_s < Qs.shape[0] and time.perf_counter() - t < 15.0:
+            oracle.topk_exhaustive(fmt, oracle.IP, oracle.FULL, Qs[nq_s:nq_s + 1], rows, resid, means, K)
+            nq_s += 1
+        dt = time.perf_counter() - t
+        per_q = dt / nq_s * (live.size / sl.size)
+        cpu = {"value": 1.0 / per_q, "unit": "queries/s", "cores": 1, "kind": "oracle",
+               "sample": "%d queries, each an exhaustive two-level top-%d over a 100,000-row slice of the live "
+                         "store (binary64 scalar C, one host core, %.1f s), scaled to the %d live rows"
+                         % (nq_s, K, dt, live.size)}
+    for sv in servers.values():
+        sv.close()
+    st.ix.close()
+    bf = serving["bf16"]
+    rows_scanned = int(np.mean(rec["live"]))
+    out = line(bf["qps_saturation"], "queries/s", n_sat, max(8, n_sat // 8), 1000.0 / bf["qps_saturation"], "bf16",
+               {"workload": "C5 streaming serving: LVQ-4x8 Turbo inner product, d=768, start 1,000,000 vectors "
+                            "(64 drifting unit clusters), M-LVQ 16 means re-fitted every 10 rounds; each round "
+                            "deletes 10%% of live, inserts %d, consolidates; batches of U{1..512} queries; "
+                            "exhaustive two-level top-%d on the FP32 vector path and on MFMA (bf16), and "
+                            "first-level MFMA top-%d re-ranked with both levels" % (ins, K, KF),
+                "n0": n0, "dim": 768, "rounds": rounds, "inserts_per_round": ins, "slots": SLOTS,
+                "max_batch": MAXB, "k": K, "k_first": KF},
+               {"bound": "mfma", "achieved": None, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                "traffic": None, "kernel": "k_scan_mfma (two-level exhaustive scan of every batch)"},
+               serving=serving, rounds_record=rec, rows_scanned_mean=rows_scanned)
+    flops = 2.0 * 2 * 768 * rows_scanned * bf["qps_saturation"] / 1e12
+    out["roofline"]["achieved"] = flops
+    out["roofline"]["frac"] = flops / MFMA_BF16_PEAK_TFLOPS
+    out["roofline"]["note"] = ("whole-server rate at saturation: 2 levels x 2*d flops per (query, live row), "
+                               "mean live rows over the rounds, times served queries/s; kernels of concurrent "
+                               "batches overlap")
+    if cpu:
+        out["cpu_baseline"] = cpu
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--rounds", type=int, default=30, help="c5: update rounds")
+    ap.add_argument("--sat-batches", type=int, default=120, help="c5: batches of the saturation phase")
+    ap.add_argument("--lat-batches", type=int, default=120, help="c5: batches of each latency phase")
     ap.add_argument("--level", default="full", choices=["full", "primary"])
     ap.add_argument("--align", type=int, default=32)
     ap.add_argument("--n", type=int, default=0, help="override the store size (testing)")
@@ -453,7 +759,7 @@ def main():
         print(json.dumps({"copy_bytes_read_per_launch": n * 4, "copy_bytes_written_per_launch": n * 4,
                           "launches": 5}), flush=True)
         return
-    fn = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4}[args.workload]
+    fn = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

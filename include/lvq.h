@@ -168,11 +168,13 @@ int lvq_autotune(lvq_index *index, const float *q_dev, int64_t nq, const int64_t
 int lvq_set_tile(lvq_index *index, int32_t level, int32_t topk, int32_t shape);
 
 /* Exhaustive top-k over every slot live at the call (Sec. 2.1 k-NN problem),
- * for nq queries q_dev (nq x dim) of precision prec: LVQ_FP32 runs the FP32
- * vector path; LVQ_BF16 / LVQ_FP16 take queries already in that type and run
- * matrix-core (MFMA) products of queries and exactly converted integer codes
- * with FP32 accumulation (first level only).  1 <= k <= 1024.  Output
- * ids_dev / dist_dev nq x k, padded as for lvq_distances.                   */
+ * for nq queries q_dev (nq x dim) of precision prec at `level`: LVQ_FP32 runs
+ * the FP32 vector path; LVQ_BF16 / LVQ_FP16 take queries already in that type
+ * and run matrix-core (MFMA) products of queries and exactly converted integer
+ * codes with FP32 accumulation (inner product; both levels need 8-bit
+ * residual codes).  1 <= k <= 1024 (the per-query candidate buffers must fit
+ * the LDS: LVQ_ERR_UNSUPPORTED otherwise).  Output ids_dev / dist_dev nq x k,
+ * padded as for lvq_distances.                                             */
 int lvq_topk(lvq_index *index, const void *q_dev, int32_t prec, int64_t nq, int32_t k,
              int32_t level, int32_t *ids_dev, float *dist_dev, void *stream);
 
@@ -219,10 +221,10 @@ int lvq_kmeans(const float *x_dev, int64_t n, int32_t dim, int32_t k, const int6
  * arrival order as soon as a stream slot is free and the pool can hold the
  * batch's buffers (admission by memory: small batches take less), and
  * admitted batches run concurrently, one per stream.  Each batch is answered
- * at the store epoch current at its admission: an exhaustive first-level
- * top-k_first (as lvq_topk, at `precision`) and, with rerank_level =
- * LVQ_FULL, both-level similarities of those candidates and their top-k (as
- * lvq_distances, Sec. 2.3: the second level re-ranks).  The result of a batch
+ * at the store epoch current at its admission: an exhaustive top-k (as
+ * lvq_topk, at `precision` and scan_level), or a first-level top-k_first
+ * whose candidates are re-ranked with both levels (as lvq_distances with a
+ * top-k, Sec. 2.3: the second level re-ranks).  The result of a batch
  * equals that of the same batch run alone at the same epoch.  Store updates
  * (lvq_insert, lvq_delete, lvq_consolidate, lvq_set_means) may be issued on
  * the index from other threads at any time; batches admitted after an update
@@ -236,9 +238,12 @@ typedef struct {
     int32_t max_batch;     /* largest nq of one batch, 1..65536 */
     int32_t k;             /* results per query, 1..1024 */
     int32_t k_first;       /* first-level candidates per query, k..1024 (LVQ_FULL) */
-    int32_t precision;     /* first-level scan: LVQ_FP32, LVQ_BF16 or LVQ_FP16 (IP) */
-    int32_t rerank_level;  /* LVQ_FULL: re-rank with both levels (needs bits2 > 0);
-                              LVQ_PRIMARY: the first-level top-k is the result */
+    int32_t precision;     /* exhaustive scan: LVQ_FP32, LVQ_BF16 or LVQ_FP16 (IP) */
+    int32_t scan_level;    /* level of the exhaustive scan: LVQ_PRIMARY, or LVQ_FULL
+                              (one stage: its top-k is the result) */
+    int32_t rerank_level;  /* with scan_level LVQ_PRIMARY: LVQ_FULL re-ranks the
+                              k_first candidates with both levels (needs bits2 > 0);
+                              LVQ_PRIMARY takes the first-level top-k as the result */
     int64_t pool_bytes;    /* device memory of admitted batches together;
                               0 = room for `slots` batches of max_batch */
 } lvq_server_config;

@@ -58,8 +58,8 @@ class lvq_stats(ctypes.Structure):
 
 class lvq_server_config(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("k", ctypes.c_int32),
-                ("k_first", ctypes.c_int32), ("precision", ctypes.c_int32), ("rerank_level", ctypes.c_int32),
-                ("pool_bytes", ctypes.c_int64)]
+                ("k_first", ctypes.c_int32), ("precision", ctypes.c_int32), ("scan_level", ctypes.c_int32),
+                ("rerank_level", ctypes.c_int32), ("pool_bytes", ctypes.c_int64)]
 
 
 class lvq_request_info(ctypes.Structure):
@@ -420,10 +420,10 @@ class Server:
     concurrently, and answered at their admission epoch."""
 
     def __init__(self, index: Index, slots=8, max_batch=512, k=10, k_first=64, precision=LVQ_FP32,
-                 rerank_level=LVQ_FULL, pool_bytes=0):
+                 scan_level=LVQ_PRIMARY, rerank_level=LVQ_FULL, pool_bytes=0):
         self.index = index
         self.k = k
-        self.cfg = lvq_server_config(slots, max_batch, k, k_first, precision, rerank_level, pool_bytes)
+        self.cfg = lvq_server_config(slots, max_batch, k, k_first, precision, scan_level, rerank_level, pool_bytes)
         self.handle = lvq_server_create(index.handle, self.cfg)
 
     def submit(self, q) -> int:

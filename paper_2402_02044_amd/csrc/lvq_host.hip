@@ -728,23 +728,23 @@ static int64_t scan_parts_fp32(const lvq_index *ix, int64_t nq, int32_t k, int64
     return std::min<int64_t>(parts, std::max<int64_t>(1, (int64_t)(ix->lds_max / 8 - k) / k));
 }
 
-// Row parts of the MFMA scan (one resident workgroup per compute unit): few,
-// long parts, since every part starts with a loose top-k bound; the count
-// whose workgroups fill the compute units in whole rounds best, parts of at
-// least 64 row rounds, a merge that fits one workgroup's LDS.
+// Row parts of the MFMA scan (one resident workgroup per compute unit).
+// Time model: whole rounds of workgroups over the compute units, each
+// workgroup streaming n_rows / parts rows, plus a per-part overhead (a part
+// starts with a loose top-k bound and adds k keys to the merge) of 2% of a
+// part's scan per extra part.  Parts keep at least 64 row rounds, and the
+// merge (parts * k keys, + k) fits one workgroup's LDS.
 static int64_t scan_parts_mfma(const lvq_index *ix, int64_t qtiles, int32_t k, int64_t n_rows)
 {
     const int64_t max_parts = std::max<int64_t>(
-        1, std::min<int64_t>({16, n_rows / (64 * 128), (int64_t)(ix->lds_max / 8 - k) / k}));
+        1, std::min<int64_t>(n_rows / (64 * 128), (int64_t)(ix->lds_max / 8 - k) / k));
     int64_t parts = 1;
-    double best = -1.0;
+    double best = 0.0;
     for (int64_t p = 1; p <= max_parts; ++p) {
-        const int64_t wg = qtiles * p;
-        const int64_t rounds = (wg + ix->n_cu - 1) / ix->n_cu;
-        const double fill = (double)wg / (double)(rounds * ix->n_cu);   // busy fraction of the last rounds
-        const double score = fill - 0.02 * (double)p;                    // prefer fewer parts on ties
-        if (score > best) {
-            best = score;
+        const int64_t rounds = (qtiles * p + ix->n_cu - 1) / ix->n_cu;
+        const double cost = (double)rounds / (double)p * (1.0 + 0.02 * (double)p);
+        if (p == 1 || cost < best) {
+            best = cost;
             parts = p;
         }
     }
@@ -852,8 +852,10 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
                      int32_t *ids_dev, float *dist_dev, hipStream_t s, uint32_t epoch)
 {
     const Format &f = ix->f;
-    if (ix->cfg.metric != LVQ_IP || level != LVQ_PRIMARY) return LVQ_ERR_UNSUPPORTED;
-    const int qb = mfma_query_block(f.bits1, f.kpos);
+    if (ix->cfg.metric != LVQ_IP) return LVQ_ERR_UNSUPPORTED;
+    const int bits2 = level == LVQ_FULL ? f.bits2 : 0;
+    if (bits2 != 0 && bits2 != 8) return LVQ_ERR_UNSUPPORTED;   // both levels need 8-bit residual codes
+    const int qb = mfma_query_block(f.bits1, bits2, f.kpos);
     if (!qb) return LVQ_ERR_UNSUPPORTED;
     const int capq = mfma_capq(qb, ix->n_means, k, ix->lds_max);
     if (!capq) return LVQ_ERR_UNSUPPORTED;
@@ -865,7 +867,7 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     if ((rc = dev_alloc(ix, w.q16, (size_t)qtiles * tq * f.kpos * 2))) return rc;
     if ((rc = dev_alloc(ix, w.qsum, sizeof(float) * (size_t)nq))) return rc;
     if ((rc = dev_alloc(ix, w.cm, sizeof(float) * (size_t)nq * ix->n_means))) return rc;
-    LVQ_HIP(launch_prep16(q_dev, nq, f.dim, f.kpos, f.bits1, prec, P<int32_t>(ix->kdim), P<float>(ix->means),
+    LVQ_HIP(launch_prep16(q_dev, nq, f.dim, f.kpos, f.bits1, qb, prec, P<int32_t>(ix->kdim), P<float>(ix->means),
                           ix->n_means, w.q16.p, P<float>(w.qsum), P<float>(w.cm), s));
     const int64_t n_rows = ix->cfg.capacity - ix->fresh;
     const int64_t parts = scan_parts_mfma(ix, qtiles, k, n_rows);
@@ -898,18 +900,19 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     a.part_keys = P<uint64_t>(w.part);
     a.err = P<uint32_t>(ix->err);
     if ((rc = timing_begin(ix, s))) return rc;
-    LVQ_HIP(launch_scan_mfma(a, f.bits1, prec, s));
+    LVQ_HIP(launch_scan_mfma(a, f.bits1, bits2, prec, s));
     if ((rc = timing_end(ix, s))) return rc;
     LVQ_HIP(launch_topk_merge(a.part_keys, nq, (int)parts, k, LVQ_IP, ids_dev, dist_dev, s));
     return LVQ_OK;
 }
 
 int lvq::host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_first, int32_t prec,
-                      int32_t k_rerank, int32_t rerank_level)
+                      int32_t scan_level, int32_t k_rerank, int32_t rerank_level)
 {
     if (max_nq < 1 || max_nq > INT32_MAX || k_first < 1 || k_first > kMaxTopK || k_rerank < 0 ||
         k_rerank > kMaxTopK)
         return LVQ_ERR_INVALID_ARG;
+    if (scan_level != LVQ_PRIMARY && scan_level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
     if (k_rerank > 0 && rerank_level != LVQ_PRIMARY && rerank_level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
     const Format &f = ix->f;
     const int64_t n_rows = ix->cfg.capacity;   // the part counts grow with the rows scanned
@@ -921,7 +924,7 @@ int lvq::host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_fi
         for (int64_t nq = 1; nq <= max_nq; ++nq)
             part = std::max(part, sizeof(uint64_t) * (size_t)(nq * scan_parts_fp32(ix, nq, k_first, n_rows) * k_first));
     } else {
-        const int qb = mfma_query_block(f.bits1, f.kpos);
+        const int qb = mfma_query_block(f.bits1, scan_level == LVQ_FULL ? f.bits2 : 0, f.kpos);
         if (!qb) return LVQ_ERR_UNSUPPORTED;
         const int64_t tq = 32 * qb;
         q16 = (size_t)((max_nq + tq - 1) / tq) * tq * f.kpos * 2;

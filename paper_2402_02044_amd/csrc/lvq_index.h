@@ -85,11 +85,11 @@ int host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t 
 int host_note_query(lvq_index *ix, hipStream_t s, uint32_t epoch);
 
 // Size the workspace of stream `s` for every query batch of up to max_nq
-// queries through host_topk (k_first, prec, first level) followed by
+// queries through host_topk (k_first, prec, scan_level) followed by
 // host_distances (k_rerank at `rerank_level`, 0 for none), so that such calls
 // on `s` allocate nothing.
-int host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_first, int32_t prec, int32_t k_rerank,
-                 int32_t rerank_level);
+int host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_first, int32_t prec, int32_t scan_level,
+                 int32_t k_rerank, int32_t rerank_level);
 
 // Device buffers not tied to a stream, drawn from the index's memory budget.
 int host_alloc(lvq_index *ix, DevBuf &b, size_t bytes);

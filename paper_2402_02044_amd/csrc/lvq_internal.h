@@ -149,15 +149,20 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_list_order(const int64_t *offsets, int64_t nq, int32_t *order, int32_t *scratch,
                              hipStream_t s);
-hipError_t launch_scan_mfma(const ScanArgs &a, int bits1, int prec, hipStream_t s);
+// bits2: 0 scans the first level, 8 both levels (8-bit residual codes).
+hipError_t launch_scan_mfma(const ScanArgs &a, int bits1, int bits2, int prec, hipStream_t s);
+typedef void (*MfmaKernelPtr)(ScanArgs);
+MfmaKernelPtr mfma_kernel_first(int bits1, int kpos, int fp16, int *qb);
+MfmaKernelPtr mfma_kernel_full(int bits1, int kpos, int fp16, int *qb);
 // MFMA exhaustive scan: 32-query blocks per workgroup for a format (0 when
 // the code width / position count has no instantiation), its LDS bytes, and
 // the query-fragment precompute for bf16 / fp16 queries.
-int mfma_query_block(int bits1, int kpos);
+int mfma_query_block(int bits1, int bits2, int kpos);
 size_t mfma_lds_bytes(int qb, int n_means, int k, int capq);
 int mfma_capq(int qb, int n_means, int k, size_t lds_max);
-hipError_t launch_prep16(const void *q, int64_t nq, int dim, int kpos, int bits1, int prec, const int32_t *kdim,
-                         const float *means, int n_means, void *frag, float *qsum, float *cm, hipStream_t s);
+hipError_t launch_prep16(const void *q, int64_t nq, int dim, int kpos, int bits1, int qb, int prec,
+                         const int32_t *kdim, const float *means, int n_means, void *frag, float *qsum, float *cm,
+                         hipStream_t s);
 // fp32 -> bf16 / fp16 (LVQ_BF16 / LVQ_FP16), round to nearest even, n values.
 hipError_t launch_cast16(const float *x, int64_t n, int prec, void *out, hipStream_t s);
 hipError_t launch_topk_merge(const uint64_t *part_keys, int64_t nq, int n_parts, int k, int metric,

@@ -199,8 +199,8 @@ int lvq_server::launch(Slot &sl, Request &r)
         std::lock_guard<std::mutex> lk(ix->mu);
         if ((rc = host_begin_call(ix, s))) return rc;
         r.epoch = ix->epoch;   // the batch reads the store as of its admission
-        rc = host_topk(ix, q16 ? q16 : (const void *)q32, cfg.precision, nq, cfg.k_first, LVQ_PRIMARY, cand_ids,
-                       cand_dist, s, r.epoch);
+        rc = host_topk(ix, q16 ? q16 : (const void *)q32, cfg.precision, nq, cfg.k_first, cfg.scan_level,
+                       cand_ids, cand_dist, s, r.epoch);
         if (rc == LVQ_OK && rerank)
             rc = host_distances(ix, q32, nq, static_cast<const int64_t *>(offsets.p), cand_ids,
                                 nq * (int64_t)cfg.k_first, cfg.rerank_level, nullptr, cfg.k, out_ids, out_dist, s,
@@ -316,17 +316,20 @@ int lvq_server_create(lvq_index *ix, const lvq_server_config *cfg, lvq_server **
     if (c.slots < 1 || c.slots > 64 || c.max_batch < 1 || c.max_batch > 65536 || c.k < 1 || c.k > kMaxTopK)
         return LVQ_ERR_INVALID_ARG;
     if (c.precision != LVQ_FP32 && c.precision != LVQ_BF16 && c.precision != LVQ_FP16) return LVQ_ERR_INVALID_ARG;
-    if (c.rerank_level == LVQ_PRIMARY) {
+    if (c.scan_level != LVQ_PRIMARY && c.scan_level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
+    if (c.rerank_level != LVQ_PRIMARY && c.rerank_level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
+    if (c.scan_level == LVQ_FULL || c.rerank_level == LVQ_PRIMARY) {
+        c.rerank_level = LVQ_PRIMARY;   // one stage: the scan's top-k is the result
         c.k_first = c.k;
-    } else if (c.rerank_level == LVQ_FULL) {
-        if (c.k_first < c.k || c.k_first > kMaxTopK) return LVQ_ERR_INVALID_ARG;
-        if (ix->f.bits2 == 0) return LVQ_ERR_INVALID_ARG;
-    } else {
+    } else if (c.k_first < c.k || c.k_first > kMaxTopK) {
         return LVQ_ERR_INVALID_ARG;
     }
+    if ((c.scan_level == LVQ_FULL || c.rerank_level == LVQ_FULL) && ix->f.bits2 == 0) return LVQ_ERR_INVALID_ARG;
     if (c.pool_bytes < 0) return LVQ_ERR_INVALID_ARG;
     if (ix->cfg.capacity == 0) return LVQ_ERR_INVALID_ARG;
-    if (c.precision != LVQ_FP32 && (ix->cfg.metric != LVQ_IP || !mfma_query_block(ix->f.bits1, ix->f.kpos)))
+    if (c.precision != LVQ_FP32 &&
+        (ix->cfg.metric != LVQ_IP ||
+         !mfma_query_block(ix->f.bits1, c.scan_level == LVQ_FULL ? ix->f.bits2 : 0, ix->f.kpos)))
         return LVQ_ERR_UNSUPPORTED;
 
     lvq_server *sv = new (std::nothrow) lvq_server();
@@ -359,8 +362,8 @@ int lvq_server_create(lvq_index *ix, const lvq_server_config *cfg, lvq_server **
                 break;
             }
             // size the stream's scan workspace for every batch size up front
-            rc = host_reserve(ix, sl.stream, c.max_batch, c.k_first, c.precision, sv->rerank ? c.k : 0,
-                              c.rerank_level);
+            rc = host_reserve(ix, sl.stream, c.max_batch, c.k_first, c.precision, c.scan_level,
+                              sv->rerank ? c.k : 0, c.rerank_level);
         }
     }
     if (rc == LVQ_OK) {

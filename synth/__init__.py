@@ -158,6 +158,33 @@ def drift_directions(workload: int, k: int, dim: int) -> np.ndarray:
     return v.astype(np.float32)
 
 
+C5_DRIFT_PER_COORD = 0.05   # centre displacement per round, RMS per coordinate
+
+
+def c5_centres(round_: int) -> np.ndarray:
+    """C5 cluster centres after `round_` rounds of drift: each centre moves
+    C5_DRIFT_PER_COORD * sqrt(d) per round along its own fixed unit direction."""
+    w = WORKLOADS["C5"]
+    cent = centres(w["id"], w["clusters"], w["dim"])
+    step = np.float32(C5_DRIFT_PER_COORD * np.sqrt(w["dim"]))
+    return (cent + np.float32(round_) * step * drift_directions(w["id"], w["clusters"], w["dim"])).astype(np.float32)
+
+
+def c5_points(stream: int, round_: int, count: int, part: int = 0) -> np.ndarray:
+    """`count` C5 vectors from the round's (drifted) mixture: a uniform centre
+    plus spread * N(0, I), unit normalised.  One generator per (stream, round,
+    part), so rounds are independent of each other and of the base store."""
+    w = WORKLOADS["C5"]
+    cent = c5_centres(round_)
+    g = rng(w["id"], stream, 1 + round_ * 64 + part)
+    lab = g.integers(0, w["clusters"], count)
+    x = g.standard_normal((count, w["dim"]), dtype=np.float32)
+    x *= np.float32(w["spread"])
+    x += cent[lab]
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    return x
+
+
 def small_vectors(seed: int, n: int, dim: int, kind: str = "normal") -> np.ndarray:
     """Small seeded test inputs of a few distributions (tests only)."""
     g = rng(900 + seed, 0)

@@ -304,6 +304,9 @@ MFMA_CASES = [
     (768, 4, 8, oracle.TURBO, 16),
     (96, 8, 0, oracle.SEQUENTIAL, 1),
     (256, 4, 0, oracle.TURBO, 2),
+    (256, 8, 8, oracle.SEQUENTIAL, 3),
+    (512, 4, 8, oracle.TURBO, 1),
+    (128, 4, 4, oracle.TURBO, 1),
 ]
 
 
@@ -311,8 +314,9 @@ MFMA_CASES = [
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 def test_exhaustive_topk_mfma(L, d, b1, b2, layout, M, prec):
     """Matrix-core form: 16-bit queries x exactly converted codes, FP32
-    accumulation.  The oracle runs on the same 16-bit query values (upcast
-    exactly), so the only difference left is FP32 accumulation order."""
+    accumulation, at the first level and (8-bit residual codes) at both
+    levels.  The oracle runs on the same 16-bit query values (upcast exactly),
+    so the only difference left is FP32 accumulation order."""
     g = synth.rng(3100 + d, M + (prec == "fp16"))
     n, nq = 3000, 70
     cent = g.standard_normal((8, d)).astype(np.float32)
@@ -336,15 +340,17 @@ def test_exhaustive_topk_mfma(L, d, b1, b2, layout, M, prec):
     live[dead] = False
     offs = np.arange(nq + 1, dtype=np.int64) * n
     allids = np.tile(np.arange(n, dtype=np.int32), nq)
-    ref, tol = pair_reference(fmt, oracle.IP, oracle.PRIMARY, Qr, rows, resid, means, offs, allids)
-    for k in (1, 10, 100):
-        ti, td = ix.topk(Qh.cuda(), k)
-        assert ix.sync() == 0
-        ti, td = ti.cpu().numpy(), td.cpu().numpy()
-        for i in range(nq):
-            a, b = offs[i], offs[i + 1]
-            check_topk(oracle.IP, ti[i], td[i], allids[a:b], ref[a:b], tol[a:b], k, live)
-    if b2:
+    levels = [(oracle.PRIMARY, L.LVQ_PRIMARY)] + ([(oracle.FULL, L.LVQ_FULL)] if b2 == 8 else [])
+    for olev, glev in levels:
+        ref, tol = pair_reference(fmt, oracle.IP, olev, Qr, rows, resid, means, offs, allids)
+        for k in (1, 10, 100):
+            ti, td = ix.topk(Qh.cuda(), k, level=glev)
+            assert ix.sync() == 0
+            ti, td = ti.cpu().numpy(), td.cpu().numpy()
+            for i in range(nq):
+                a, b = offs[i], offs[i + 1]
+                check_topk(oracle.IP, ti[i], td[i], allids[a:b], ref[a:b], tol[a:b], k, live)
+    if b2 == 4:   # both levels on the matrix cores need 8-bit residual codes
         with pytest.raises(L.LVQError) as e:
             ix.topk(Qh.cuda(), 10, level=L.LVQ_FULL)
         assert e.value.code == L.LVQ_ERR_UNSUPPORTED

@@ -96,13 +96,14 @@ class Store:
         return self.ix.stats().epoch
 
 
-def _run_mix(L, prec, slots, pool_batches):
+def _run_mix(L, prec, scan_level, slots, pool_batches):
     X0, means, ops = _data()
     st = Store(L, X0, means)
-    probe = L.Server(st.ix, slots=1, max_batch=MAXB, k=K, k_first=KF, precision=prec)
+    kw = dict(max_batch=MAXB, k=K, k_first=KF, precision=prec, scan_level=scan_level)
+    probe = L.Server(st.ix, slots=1, **kw)
     pool = int(probe.stats().batch_bytes_max * pool_batches)
     probe.close()
-    sv = L.Server(st.ix, slots=slots, max_batch=MAXB, k=K, k_first=KF, precision=prec, pool_bytes=pool)
+    sv = L.Server(st.ix, slots=slots, pool_bytes=pool, **kw)
     tickets = []
     for op in ops:
         if op[0] == "batch":
@@ -117,12 +118,12 @@ def _run_mix(L, prec, slots, pool_batches):
     return ops, out, stats
 
 
-def _replay_alone(L, prec, ops, epochs):
+def _replay_alone(L, prec, scan_level, ops, epochs):
     """Serve each batch alone (one slot) on a store replayed to its epoch;
     also run the direct calls the server stands for."""
     X0, means, _ = _data()
     st = Store(L, X0, means)
-    sv = L.Server(st.ix, slots=1, max_batch=MAXB, k=K, k_first=KF, precision=prec)
+    sv = L.Server(st.ix, slots=1, max_batch=MAXB, k=K, k_first=KF, precision=prec, scan_level=scan_level)
     updates = [op for op in ops if op[0] != "batch"]
     batches = [op[1] for op in ops if op[0] == "batch"]
     order = np.argsort(np.asarray(epochs), kind="stable")
@@ -139,18 +140,25 @@ def _replay_alone(L, prec, ops, epochs):
         t = sv.submit(q)
         ids, dist, info = sv.wait(t, q.shape[0])
         assert info.epoch == epochs[b]
-        # the direct calls: first-level top-k', both-level re-rank
+        # the direct calls: an exhaustive scan at both levels, or first-level
+        # top-k' and both-level re-rank
         qd = torch.from_numpy(q).cuda()
-        cid, _ = st.ix.topk(qd.to(tdt), KF)
-        offs = torch.arange(0, (q.shape[0] + 1) * KF, KF, dtype=torch.int64, device="cuda")
-        _, ti, td = st.ix.distances(qd, offs, cid.reshape(-1), level=L.LVQ_FULL, k=K, want_dist=False)
+        if scan_level == L.LVQ_FULL:
+            ti, td = st.ix.topk(qd.to(tdt), K, level=L.LVQ_FULL)
+        else:
+            cid, _ = st.ix.topk(qd.to(tdt), KF)
+            offs = torch.arange(0, (q.shape[0] + 1) * KF, KF, dtype=torch.int64, device="cuda")
+            _, ti, td = st.ix.distances(qd, offs, cid.reshape(-1), level=L.LVQ_FULL, k=K, want_dist=False)
         assert np.array_equal(ti.cpu().numpy(), ids) and np.array_equal(td.cpu().numpy(), dist), b
         # oracle values of the returned slots, all live at the epoch
         assert st.live[ids].all() and (ids >= 0).all()
         rows, resid, _ = oracle.encode_rows(fmt, st.X[ids.reshape(-1)], means)
         loc = np.arange(ids.size, dtype=np.int32)
         offs_h = np.arange(q.shape[0] + 1, dtype=np.int64) * K
-        ref, tol = pair_reference(fmt, oracle.IP, oracle.FULL, q, rows, resid, means, offs_h, loc)
+        # values: two-level similarities of the fp32 queries after a re-rank,
+        # of the 16-bit queries when the matrix-core scan produced them
+        qv = q if (prec == L.LVQ_FP32 or scan_level != L.LVQ_FULL) else torch.from_numpy(q).to(tdt).float().numpy()
+        ref, tol = pair_reference(fmt, oracle.IP, oracle.FULL, qv, rows, resid, means, offs_h, loc)
         check_values(dist.reshape(-1), ref, tol, "served distances")
         assert np.all(np.diff(dist, axis=1) <= 0), "results ordered best first"
         res[b] = (ids, dist)
@@ -160,15 +168,16 @@ def _replay_alone(L, prec, ops, epochs):
     return res
 
 
-@pytest.mark.parametrize("prec_name", ["fp32", "bf16"])
-def test_mix_equals_alone(L, prec_name):
-    prec = {"fp32": L.LVQ_FP32, "bf16": L.LVQ_BF16}[prec_name]
-    ops, mixed, stats = _run_mix(L, prec, slots=5, pool_batches=2.5)
+@pytest.mark.parametrize("form", ["fp32-rerank", "bf16-rerank", "fp32-full", "bf16-full"])
+def test_mix_equals_alone(L, form):
+    prec = {"fp32": L.LVQ_FP32, "bf16": L.LVQ_BF16}[form.split("-")[0]]
+    scan_level = L.LVQ_FULL if form.endswith("full") else L.LVQ_PRIMARY
+    ops, mixed, stats = _run_mix(L, prec, scan_level, slots=5, pool_batches=2.5)
     assert stats.completed == len(mixed) and stats.peak_in_flight >= 1
     assert stats.pool_peak <= stats.pool_bytes
     epochs = [info.epoch for _, _, info in mixed]
     assert len(set(epochs)) > 1, "updates should interleave with the batches"
-    alone = _replay_alone(L, prec, ops, epochs)
+    alone = _replay_alone(L, prec, scan_level, ops, epochs)
     for b, ((ids, dist, info), (ids1, dist1)) in enumerate(zip(mixed, alone)):
         assert np.array_equal(ids, ids1), "batch %d (epoch %d): ids differ from the alone run" % (b, info.epoch)
         assert np.array_equal(dist, dist1), "batch %d (epoch %d): values differ" % (b, info.epoch)
