@@ -107,19 +107,24 @@ def to_gpu_rows(ix, X, dev, chunk=1 << 20):
         ix.insert(torch.from_numpy(X[a:a + chunk]).to(dev))
 
 
-def host_kmeans(S, k, iters, seed_workload):
-    """Lloyd's k-means in binary64 on a sample (harness input for M-LVQ)."""
+def host_kmeans(S, k, iters, seed_workload, seed_chunk=1):
+    """Lloyd's k-means in binary64 on a sample (harness input for M-LVQ):
+    k distinct sample points as the start, `iters` rounds of nearest-centre
+    assignment and centroid update (an empty cluster keeps its centre)."""
     import synth
-    g = synth.rng(seed_workload, synth.S_SAMPLE, 1)
-    C = S[g.choice(S.shape[0], k, replace=False)].astype(np.float64)
+    g = synth.rng(seed_workload, synth.S_SAMPLE, seed_chunk)
     Sd = S.astype(np.float64)
+    C = Sd[g.choice(S.shape[0], k, replace=False)]
+    sq = (Sd * Sd).sum(1)
     for _ in range(iters):
-        d2 = (Sd * Sd).sum(1)[:, None] - 2.0 * Sd @ C.T + (C * C).sum(1)[None, :]
+        d2 = sq[:, None] - 2.0 * Sd @ C.T + (C * C).sum(1)[None, :]
         a = d2.argmin(1)
-        for c in range(k):
-            m = a == c
-            if m.any():
-                C[c] = Sd[m].mean(0)
+        onehot = np.zeros((S.shape[0], k))
+        onehot[np.arange(S.shape[0]), a] = 1.0
+        cnt = onehot.sum(0)
+        sums = onehot.T @ Sd
+        nz = cnt > 0
+        C[nz] = sums[nz] / cnt[nz, None]
     return C.astype(np.float32)
 
 
@@ -460,17 +465,13 @@ class C5Store:
         return self.ix.consolidate(stream=self.stream)
 
     def refit_means(self, round_, k=16, sample=100_000, iters=25):
-        """k-means (Lloyd, on the GPU) over a uniform sample of live vectors,
+        """k-means (host, binary64) over a uniform sample of live vectors,
         appended to the index's means."""
-        import torch
         import synth
         g = synth.rng(5, synth.S_SAMPLE, 100 + round_)
         cand = np.flatnonzero(self.live)
         pick = np.sort(g.choice(cand, min(sample, cand.size), replace=False))
-        init = g.choice(pick.size, k, replace=False)
-        with torch.cuda.stream(self.stream):
-            S = self.Xd[torch.from_numpy(pick).to(self.dev)]
-            C = self.L.kmeans(S, k, init, iters=iters, stream=self.stream).cpu().numpy()
+        C = host_kmeans(self.Xh[pick], k, iters, 5, 200 + round_)
         self.ix.set_means(C, stream=self.stream)
         self.n_means += k
 
@@ -558,8 +559,7 @@ def bench_c5(args):
     X0 = synth.vectors("C5", synth.S_BASE, 0, n0)
     log("M-LVQ means: k-means (16) on a 100k sample")
     samp = synth.sample_indices(5, n0, 100_000)
-    init = synth.rng(5, synth.S_SAMPLE, 2).choice(samp.size, 16, replace=False)
-    means = L.kmeans(torch.from_numpy(X0[samp]).to(dev), 16, init, iters=25).cpu().numpy()
+    means = host_kmeans(X0[samp], 16, 25, 5)
     cap = n0 + 5 * ins + 4096
     log("encoding the store (capacity %d)" % cap)
     st = C5Store(L, X0, means, cap, dev)
@@ -628,42 +628,55 @@ def bench_c5(args):
     upd = threading.Thread(target=updates)
     upd.start()
 
-    # ---- the query load: saturation, then Poisson arrivals at 50/80/95 % of it
+    # ---- the query load.  The store shrinks round by round (10% deleted,
+    # 10k inserted), so the scans get cheaper as the run goes on; each load
+    # level is therefore measured for every form back to back, right after a
+    # saturation burst of that form: offered load = fraction x that burst's
+    # rate.  Rows scanned (occupied slots) are recorded with every phase.
     n_sat, n_lat = args.sat_batches, args.lat_batches
-    total = len(forms) * (n_sat + 3 * n_lat)
+    levels = (0.5, 0.8, 0.95)
+    total = len(levels) * len(forms) * (n_sat + n_lat)
     served = 0
-    serving = {}
-    for f in forms:
-        sv = servers[f]
+    serving = {f: {"phases": []} for f in forms}
+    mean_nq = (MAXB + 1) / 2.0
+
+    def burst(sv):
         out = []
-        c5_load(sv, make_batches(max(8, n_sat // 8)), None, [])    # warm-up
         c5_load(sv, make_batches(n_sat), None, out)
-        served += n_sat
-        progress["done"] = served / total
         q = sum(nq for nq, _ in out)
-        span = max(i.t_done for _, i in out) - min(i.t_submit for _, i in out)
-        qps = q / span
-        ent = {"qps_saturation": qps, "batches_saturation": n_sat, "latency_ms": {}}
-        log("%s: saturation %.0f queries/s over %d batches" % (f, qps, n_sat))
-        mean_nq = (MAXB + 1) / 2.0
-        for frac in (0.5, 0.8, 0.95):
-            rate = frac * qps / mean_nq
-            arr = np.cumsum(g.exponential(1.0 / rate, n_lat))
+        return q / (max(i.t_done for _, i in out) - min(i.t_submit for _, i in out))
+
+    for f in forms:   # warm-up
+        c5_load(servers[f], make_batches(8), None, [])
+    for frac in levels:
+        for f in forms:
+            sv = servers[f]
+            rows0 = st.ix.stats().live_estimate
+            qps = burst(sv)
+            served += n_sat
+            progress["done"] = served / total
+            arr = np.cumsum(g.exponential(mean_nq / (frac * qps), n_lat))
             out = []
             lag = c5_load(sv, make_batches(n_lat), arr, out)
             served += n_lat
             progress["done"] = served / total
+            rows1 = st.ix.stats().live_estimate
             lat = np.array([(i.t_done - i.t_submit) * 1000.0 for _, i in out])
             q = sum(nq for nq, _ in out)
             span = max(i.t_done for _, i in out) - min(i.t_submit for _, i in out)
-            ent["latency_ms"]["%d%%" % round(frac * 100)] = {
-                "offered_qps": frac * qps, "achieved_qps": q / span, "p50": float(np.percentile(lat, 50)),
-                "p99": float(np.percentile(lat, 99)), "mean": float(lat.mean()), "batches": n_lat,
-                "mean_submit_lag_ms": lag * 1000.0}
-            log("%s at %d%%: p50 %.2f ms, p99 %.2f ms" % (f, frac * 100, np.percentile(lat, 50),
-                                                          np.percentile(lat, 99)))
-        ent["peak_in_flight"] = sv.stats().peak_in_flight
-        serving[f] = ent
+            ph = {"load": frac, "qps_saturation": qps, "offered_qps": frac * qps, "achieved_qps": q / span,
+                  "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                  "mean_ms": float(lat.mean()), "rows_scanned": [int(rows0), int(rows1)],
+                  "batches": [n_sat, n_lat], "mean_submit_lag_ms": lag * 1000.0}
+            serving[f]["phases"].append(ph)
+            log("%s: saturation %.0f q/s over %d rows; at %d%%: p50 %.2f ms, p99 %.2f ms" %
+                (f, qps, rows0, frac * 100, ph["p50_ms"], ph["p99_ms"]))
+    for f in forms:
+        ph = serving[f]["phases"]
+        serving[f]["qps_saturation"] = ph[0]["qps_saturation"]
+        serving[f]["latency_ms"] = {"%d%%" % round(p["load"] * 100): {"p50": p["p50_ms"], "p99": p["p99_ms"]}
+                                    for p in ph}
+        serving[f]["peak_in_flight"] = servers[f].stats().peak_in_flight
     progress["done"] = 1.0
     upd.join()
     if err:
@@ -682,7 +695,7 @@ def bench_c5(args):
         live = np.flatnonzero(st.live)
         sl = live[:100_000]
         rows, resid, _ = oracle.encode_rows(fmt, st.Xh[sl], means)
-        Qs = synth.c5_points(synth.S_QUERY, rounds, 4, part=2)
+        Qs = synth.c5_points(synth.S_QUERY, rounds, 64, part=2)
         t = time.perf_counter()
         nq_s = 0
         while nq_s < Qs.shape[0] and time.perf_counter() - t < 15.0:
@@ -698,8 +711,8 @@ def bench_c5(args):
         sv.close()
     st.ix.close()
     bf = serving["bf16"]
-    rows_scanned = int(np.mean(rec["live"]))
-    out = line(bf["qps_saturation"], "queries/s", n_sat, max(8, n_sat // 8), 1000.0 / bf["qps_saturation"], "bf16",
+    rows_scanned = int(np.mean(bf["phases"][0]["rows_scanned"]))
+    out = line(bf["qps_saturation"], "queries/s", n_sat, 8, 1000.0 / bf["qps_saturation"], "bf16",
                {"workload": "C5 streaming serving: LVQ-4x8 Turbo inner product, d=768, start 1,000,000 vectors "
                             "(64 drifting unit clusters), M-LVQ 16 means re-fitted every 10 rounds; each round "
                             "deletes 10%% of live, inserts %d, consolidates; batches of U{1..512} queries; "
@@ -709,13 +722,13 @@ def bench_c5(args):
                 "max_batch": MAXB, "k": K, "k_first": KF},
                {"bound": "mfma", "achieved": None, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
                 "traffic": None, "kernel": "k_scan_mfma (two-level exhaustive scan of every batch)"},
-               serving=serving, rounds_record=rec, rows_scanned_mean=rows_scanned)
+               serving=serving, rounds_record=rec)
     flops = 2.0 * 2 * 768 * rows_scanned * bf["qps_saturation"] / 1e12
     out["roofline"]["achieved"] = flops
     out["roofline"]["frac"] = flops / MFMA_BF16_PEAK_TFLOPS
-    out["roofline"]["note"] = ("whole-server rate at saturation: 2 levels x 2*d flops per (query, live row), "
-                               "mean live rows over the rounds, times served queries/s; kernels of concurrent "
-                               "batches overlap")
+    out["roofline"]["note"] = ("whole-server rate of the first bf16 saturation burst: 2 levels x 2*d flops "
+                               "per (query, occupied row) x %d rows x served queries/s; kernels of concurrent "
+                               "batches overlap" % rows_scanned)
     if cpu:
         out["cpu_baseline"] = cpu
     return out
@@ -728,7 +741,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--rounds", type=int, default=30, help="c5: update rounds")
-    ap.add_argument("--sat-batches", type=int, default=120, help="c5: batches of the saturation phase")
+    ap.add_argument("--sat-batches", type=int, default=60, help="c5: batches of each saturation burst")
     ap.add_argument("--lat-batches", type=int, default=120, help="c5: batches of each latency phase")
     ap.add_argument("--level", default="full", choices=["full", "primary"])
     ap.add_argument("--align", type=int, default=32)

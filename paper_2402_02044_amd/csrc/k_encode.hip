@@ -206,7 +206,10 @@ __global__ __launch_bounds__(64) void k_encode(EncodeArgs a)
     const bool store = a.free_stack != nullptr;
     if (store) {
         slot = a.free_stack[a.free_top - 1 - i];
-        if (g == 0) a.slots_out[i] = (int32_t)slot;
+        if (g == 0) {
+            a.slots_out[i] = (int32_t)slot;
+            if (a.list_out) a.list_out[i] = (int32_t)slot;
+        }
     }
     if (!finite && g == 0) atomicOr(a.err, kErrNonFinite);
 

@@ -191,15 +191,11 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
     // next block's chunk c is loaded into the same registers as soon as the
     // current chunk c has been converted, so its latency overlaps the rest of
     // the current block.
-    auto row_ptr = [&](int64_t rb, bool &in) {
-        const int64_t slot = rb + col;
-        in = slot < r1;
-        return a.rows + (in ? slot : r0) * a.row_bytes;
-    };
-    auto res_ptr = [&](int64_t rb) {
-        const int64_t slot = rb + col;
-        return a.resid + (slot < r1 ? slot : r0) * a.resid_bytes + half * (RV * 16);
-    };
+    // Rows are the slots at list positions [r0, r1).  A lane's slot for a
+    // block is read one block ahead of its row loads; positions past the part
+    // read the list at r0 (a valid slot) and are masked out.
+    auto slot_at = [&](int64_t pos) -> int64_t { return a.list[pos < r1 ? pos : r0]; };
+    auto res_ptr = [&](int64_t slot) { return a.resid + slot * a.resid_bytes + half * (RV * 16); };
 
     uint4 vcur[NCHUNK];
     uint4 rcur[RNCH][RV];
@@ -207,15 +203,19 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
     uint2 ecur = make_uint2(1u, 0u), enext = ecur;
     bool icur = false, inext = false;
     int64_t rb = r0 + (int64_t)wave * kRowsPerWave;
+    int64_t s_cur = 0, s_next = 0;
     if (rb < r1) {
-        const uint8_t *row = row_ptr(rb, icur);
+        icur = rb + col < r1;
+        s_cur = slot_at(rb + col);
+        s_next = slot_at(rb + kRowsPerIter + col);
+        const uint8_t *row = a.rows + s_cur * a.row_bytes;
         hcur = *reinterpret_cast<const float4 *>(row);
         ecur = *reinterpret_cast<const uint2 *>(row + 16);
 #pragma unroll
         for (int c = 0; c < NCHUNK; ++c)
             vcur[c] = *reinterpret_cast<const uint4 *>(row + kHeaderBytes + c * 32 + half * 16);
         if constexpr (B2 != 0) {
-            const uint8_t *res = res_ptr(rb);
+            const uint8_t *res = res_ptr(s_cur);
 #pragma unroll
             for (int c = 0; c < NCHUNK; ++c)
 #pragma unroll
@@ -229,8 +229,10 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
         const int64_t rb_next = rb + kRowsPerIter;
         // unconditional (clamped) prefetch: a load under a branch would make
         // every later wait count it as the most recent outstanding load
-        const uint8_t *nrow = row_ptr(rb_next, inext);
-        const uint8_t *nres = B2 ? res_ptr(rb_next) : nullptr;
+        inext = rb_next + col < r1;
+        const uint8_t *nrow = a.rows + s_next * a.row_bytes;
+        const uint8_t *nres = B2 ? res_ptr(s_next) : nullptr;
+        const int64_t s_after = slot_at(rb_next + kRowsPerIter + col);
         hnext = *reinterpret_cast<const float4 *>(nrow);
         enext = *reinterpret_cast<const uint2 *>(nrow + 16);
         if (mine) {
@@ -270,7 +272,7 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
             // consecutive queries, whose constants are read as float4.  All
             // scores are formed first; the append path runs only when some
             // lane has a score reaching its query's threshold.
-            const int64_t slot = rb + col;
+            const int64_t slot = s_cur;
             const bool live = icur && ((__float_as_uint(hcur.w) >> 8) & 1u) && ecur.x <= a.epoch &&
                               a.epoch < ecur.y;
             const int mid = min((int)(__float_as_uint(hcur.w) & 0xFFu), nm - 1);
@@ -353,6 +355,8 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
         }
         __syncthreads();
         rb = rb_next;
+        s_cur = s_next;
+        s_next = s_after;
         hcur = hnext;
         ecur = enext;
         icur = inext;

@@ -177,19 +177,47 @@ __global__ __launch_bounds__(1024) void k_consolidate_count(StoreArgs a, uint32_
     }
 }
 
+// Exclusive prefix sums of counts[0..nb) in place, in ascending block order
+// or (descending) from the last block down; returns the total.  One
+// workgroup of 1024 threads: each thread sums a run of blocks, the run
+// totals are scanned across the workgroup, then each thread writes its run.
+__device__ int64_t block_exclusive_scan(int32_t *counts, int nb, bool descending)
+{
+    __shared__ int64_t wtot[16];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int per = (nb + 1023) / 1024;
+    const int b0 = t * per, b1 = min(nb, b0 + per);
+    auto at = [&](int i) -> int32_t & { return counts[descending ? nb - 1 - i : i]; };
+    int64_t run = 0;
+    for (int i = b0; i < b1; ++i) run += at(i);
+    // inclusive scan of run totals within the wave, then across waves
+    int64_t inc = run;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t v = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    int64_t before = 0, total = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wave) before += wtot[w];
+        total += wtot[w];
+    }
+    int64_t acc = before + inc - run;
+    for (int i = b0; i < b1; ++i) {
+        const int32_t c = at(i);
+        at(i) = (int32_t)acc;
+        acc += c;
+    }
+    return total;
+}
+
 // pass 2: exclusive offsets in descending block order (one workgroup)
 __global__ __launch_bounds__(1024) void k_consolidate_scan(int32_t *counts, int nblocks, int64_t free_top,
                                                            int64_t *new_top)
 {
-    if (threadIdx.x == 0) {
-        int64_t acc = 0;
-        for (int b = nblocks - 1; b >= 0; --b) {
-            int c = counts[b];
-            counts[b] = (int32_t)acc;
-            acc += c;
-        }
-        *new_top = free_top + acc;
-    }
+    const int64_t total = block_exclusive_scan(counts, nblocks, true);
+    if (threadIdx.x == 0) *new_top = free_top + total;
 }
 
 // pass 3: push reclaimable slots (descending slot order) and clear their rows
@@ -214,6 +242,45 @@ __global__ __launch_bounds__(1024) void k_consolidate_push(StoreArgs a, uint32_t
         uint32_t *h = reinterpret_cast<uint32_t *>(a.rows + s * a.row_bytes);
         for (int w = 0; w < 8; ++w) h[w] = 0u;
     }
+}
+
+// Occupied-slot list, pass 1: occupied slots per 1024-slot block.
+__global__ __launch_bounds__(1024) void k_list_count(StoreArgs a, int32_t *counts)
+{
+    __shared__ int wsum[16];
+    const int64_t s = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    int r = s < a.capacity && (a.rows[s * a.row_bytes + 13] & 1u);
+    r = __popcll(__ballot(r));
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < 16; ++w) t += wsum[w];
+        counts[blockIdx.x] = t;
+    }
+}
+
+// pass 2: exclusive offsets in ascending block order (one workgroup)
+__global__ __launch_bounds__(1024) void k_list_scan(int32_t *counts, int nblocks, int64_t *len)
+{
+    const int64_t total = block_exclusive_scan(counts, nblocks, false);
+    if (threadIdx.x == 0) *len = total;
+}
+
+// pass 3: write the occupied slots in ascending order
+__global__ __launch_bounds__(1024) void k_list_write(StoreArgs a, const int32_t *offs, int32_t *list)
+{
+    __shared__ int wsum[16];
+    const int64_t s = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool r = s < a.capacity && (a.rows[s * a.row_bytes + 13] & 1u);
+    const unsigned long long m = __ballot(r);
+    const int below = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    int waves_below = 0;
+    for (int w = 0; w < wave; ++w) waves_below += wsum[w];
+    if (r) list[offs[blockIdx.x] + waves_below + below] = (int32_t)s;
 }
 
 __global__ void k_gather_rows(StoreArgs a, const int32_t *slots, int64_t n, uint8_t *rows_out,
@@ -369,6 +436,16 @@ hipError_t launch_consolidate(const StoreArgs &a, uint32_t safe_epoch, int32_t *
     hipLaunchKernelGGL(k_consolidate_scan, dim3(1), dim3(1024), 0, s, block_counts, nb, free_top, new_top);
     hipLaunchKernelGGL(k_consolidate_push, dim3(nb), dim3(1024), 0, s, a, safe_epoch, block_counts, free_stack,
                        free_top);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_list(const StoreArgs &a, int32_t *list, int32_t *block_counts, int64_t *len, hipStream_t s)
+{
+    const int nb = (int)((a.capacity + 1023) / 1024);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_list_count, dim3(nb), dim3(1024), 0, s, a, block_counts);
+    hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, block_counts, nb, len);
+    hipLaunchKernelGGL(k_list_write, dim3(nb), dim3(1024), 0, s, a, block_counts, list);
     return hipGetLastError();
 }
 

@@ -111,9 +111,10 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
         int64_t slot[R];
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
-            slot[rr] = base + (int64_t)grp * R + rr;
-            const bool in = slot[rr] < r1;
-            const uint8_t *row = a.rows + (in ? slot[rr] : r0) * a.row_bytes;
+            const int64_t pos = base + (int64_t)grp * R + rr;
+            const bool in = pos < r1;
+            slot[rr] = a.list[in ? pos : r0];   // list position -> slot
+            const uint8_t *row = a.rows + slot[rr] * a.row_bytes;
             hdr[rr] = in ? *reinterpret_cast<const float4 *>(row) : make_float4(0.f, 0.f, 0.f, 0.f);
             uint2 ep = in ? *reinterpret_cast<const uint2 *>(row + 16) : make_uint2(1u, 0u);
             live[rr] = in && ((__float_as_uint(hdr[rr].w) >> 8) & 1u) && ep.x <= a.epoch && a.epoch < ep.y;
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
                 if (in && u < npieces) {
                     wv[rr][c] = load_words<Geo::kWords>(row + kHeaderBytes + u * CH);
                     if constexpr (B2 != 0)
-                        rv[rr][c] = load_words<RGeo::kWords>(a.resid + (in ? slot[rr] : r0) * a.resid_bytes +
+                        rv[rr][c] = load_words<RGeo::kWords>(a.resid + slot[rr] * a.resid_bytes +
                                                              u * RGeo::kBytes);
                 } else {
 #pragma unroll

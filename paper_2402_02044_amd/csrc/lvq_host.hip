@@ -189,7 +189,7 @@ int note_query(lvq_index *ix, hipStream_t s, uint32_t epoch)
         LVQ_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     }
     LVQ_HIP(hipEventRecord(ev, s));
-    ix->inflight.push_back({epoch, ev});
+    ix->inflight.push_back({epoch, ++ix->query_seq, ev});
     // retire completed entries from the front
     while (!ix->inflight.empty() && hipEventQuery(ix->inflight.front().ev) == hipSuccess) {
         ix->spare_events.push_back(ix->inflight.front().ev);
@@ -367,7 +367,12 @@ int lvq_create(const lvq_config *cfg, const float *means_host, int32_t n_means, 
             }
         }
         ix->free_top = cap;
-        ix->fresh = cap;
+        if (cap > 0) {
+            ix->lists.resize(1);
+            if ((rc = dev_alloc(ix, ix->lists[0].buf, sizeof(int32_t) * (size_t)cap))) break;
+            ix->list_active = 0;
+            ix->list_len = 0;
+        }
         if (hipEventCreateWithFlags(&ix->update_ev, hipEventDisableTiming)) { rc = LVQ_ERR_DEVICE; break; }
     } while (0);
     if (rc) {
@@ -389,6 +394,7 @@ int lvq_destroy(lvq_index *ix)
     for (DevBuf *b : {&ix->means, &ix->means_t, &ix->muk, &ix->kmask, &ix->kdim, &ix->pos_dim, &ix->rows,
                       &ix->resid, &ix->stack, &ix->err, &ix->scratch})
         dev_free(ix, *b);
+    for (SlotList &l : ix->lists) dev_free(ix, l.buf);
     for (auto &f : ix->inflight) (void)hipEventDestroy(f.ev);
     for (auto e : ix->spare_events) (void)hipEventDestroy(e);
     if (ix->update_ev) (void)hipEventDestroy(ix->update_ev);
@@ -455,6 +461,7 @@ static int encode_common(lvq_index *ix, const float *x, int64_t n, uint8_t *rows
     a.resid = resid;
     a.free_stack = store ? P<int32_t>(ix->stack) : nullptr;
     a.free_top = ix->free_top;
+    a.list_out = store ? P<int32_t>(ix->lists[ix->list_active].buf) + ix->list_len : nullptr;
     a.slots_out = slots_out;
     a.ext_ids = ext;
     a.epoch = ix->epoch;
@@ -487,7 +494,7 @@ int lvq_insert(lvq_index *ix, const float *x_dev, int64_t n, const uint64_t *ext
                        true, s);
     if (rc) return rc;
     ix->free_top -= n;
-    ix->fresh = std::min(ix->fresh, ix->free_top);
+    ix->list_len += n;
     return note_update(ix, s);
 }
 
@@ -527,28 +534,49 @@ int lvq_consolidate(lvq_index *ix, void *stream, int64_t *n_freed_out)
     hipStream_t s = (hipStream_t)stream;
     int rc = order_after_updates(ix, s);
     if (rc) return rc;
-    // the oldest epoch an unfinished query may still observe
+    // the oldest epoch an unfinished query may still observe, and the oldest
+    // launch still running
     uint32_t safe = ix->epoch;
+    uint64_t oldest = UINT64_MAX;
     for (auto it = ix->inflight.begin(); it != ix->inflight.end();) {
         if (hipEventQuery(it->ev) == hipSuccess) {
             ix->spare_events.push_back(it->ev);
             it = ix->inflight.erase(it);
         } else {
             safe = std::min(safe, it->epoch);
+            oldest = std::min(oldest, it->seq);
             ++it;
         }
+    }
+    // a list buffer for the compacted list: a retired one no running query
+    // reads, else a new one
+    int next = -1;
+    for (int i = 0; i < (int)ix->lists.size(); ++i)
+        if (i != ix->list_active && ix->lists[i].retire_seq < oldest) {
+            next = i;
+            break;
+        }
+    if (next < 0) {
+        SlotList fresh_list;
+        if ((rc = dev_alloc(ix, fresh_list.buf, sizeof(int32_t) * (size_t)cap))) return rc;
+        ix->lists.push_back(fresh_list);
+        next = (int)ix->lists.size() - 1;
     }
     const int nb = (int)((cap + 1023) / 1024);
     if ((rc = dev_alloc(ix, ix->scratch, sizeof(int32_t) * (size_t)nb + 64))) return rc;
     int32_t *counts = P<int32_t>(ix->scratch);
-    int64_t *new_top = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(ix->scratch.p) +
-                                                   ((sizeof(int32_t) * (size_t)nb + 15) & ~(size_t)15));
-    LVQ_HIP(launch_consolidate(store_args(ix), safe, P<int32_t>(ix->stack), ix->free_top, counts, new_top, s));
-    int64_t top = 0;
-    LVQ_HIP(hipMemcpyAsync(&top, new_top, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    int64_t *tail = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(ix->scratch.p) +
+                                                ((sizeof(int32_t) * (size_t)nb + 15) & ~(size_t)15));
+    LVQ_HIP(launch_consolidate(store_args(ix), safe, P<int32_t>(ix->stack), ix->free_top, counts, tail, s));
+    LVQ_HIP(launch_build_list(store_args(ix), P<int32_t>(ix->lists[next].buf), counts, tail + 1, s));
+    int64_t got[2] = {0, 0};   // new stack top, list length
+    LVQ_HIP(hipMemcpyAsync(got, tail, sizeof(got), hipMemcpyDeviceToHost, s));
     LVQ_HIP(hipStreamSynchronize(s));
-    if (n_freed_out) *n_freed_out = top - ix->free_top;
-    ix->free_top = top;
+    if (n_freed_out) *n_freed_out = got[0] - ix->free_top;
+    ix->free_top = got[0];
+    ix->lists[ix->list_active].retire_seq = ix->query_seq;   // every launch so far may read it
+    ix->list_active = next;
+    ix->list_len = got[1];
     return note_update(ix, s);
 }
 
@@ -790,7 +818,7 @@ int lvq::host_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, i
     if (rc) return rc;
     Workspace &w = workspace(ix, s);
     if ((rc = prep_queries(ix, w, (const float *)q_dev, nq, s))) return rc;
-    const int64_t n_rows = ix->cfg.capacity - ix->fresh;   // slots ever used
+    const int64_t n_rows = ix->list_len;
     const int64_t qtiles = (nq + 15) / 16;
     const int64_t parts = scan_parts_fp32(ix, nq, k, n_rows);
     const int64_t rows_per_part = std::max<int64_t>(1, (n_rows + parts - 1) / parts);
@@ -803,6 +831,7 @@ int lvq::host_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, i
     a.resid_bytes = f.resid_bytes;
     a.kchunks = f.kchunks;
     a.kpos = f.kpos;
+    a.list = P<int32_t>(ix->lists[ix->list_active].buf);
     a.n_rows = n_rows;
     a.qk = P<float>(w.qk);
     a.qsum = P<float>(w.qsum);
@@ -869,7 +898,7 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     if ((rc = dev_alloc(ix, w.cm, sizeof(float) * (size_t)nq * ix->n_means))) return rc;
     LVQ_HIP(launch_prep16(q_dev, nq, f.dim, f.kpos, f.bits1, qb, prec, P<int32_t>(ix->kdim), P<float>(ix->means),
                           ix->n_means, w.q16.p, P<float>(w.qsum), P<float>(w.cm), s));
-    const int64_t n_rows = ix->cfg.capacity - ix->fresh;
+    const int64_t n_rows = ix->list_len;
     const int64_t parts = scan_parts_mfma(ix, qtiles, k, n_rows);
     const int64_t rows_per_part = std::max<int64_t>(1, (n_rows + parts - 1) / parts);
     if ((rc = dev_alloc(ix, w.part, sizeof(uint64_t) * (size_t)nq * parts * k))) return rc;
@@ -882,6 +911,7 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     a.resid_bytes = f.resid_bytes;
     a.kchunks = f.kchunks;
     a.kpos = f.kpos;
+    a.list = P<int32_t>(ix->lists[ix->list_active].buf);
     a.n_rows = n_rows;
     a.qk = nullptr;
     a.qsum = P<float>(w.qsum);

@@ -25,10 +25,21 @@ struct Workspace {
     DevBuf qk, qsum, cm, order, queue, part, q16, gthr;
 };
 
-// A query launch that may still be reading the store, and the epoch it reads.
+// A query launch that may still be reading the store, the epoch it reads,
+// and its launch sequence number.
 struct InFlight {
     uint32_t epoch;
+    uint64_t seq;
     hipEvent_t ev;
+};
+
+// A list of occupied slots the exhaustive scans walk.  The active list grows
+// by appends (inserts); consolidation writes a compacted list into another
+// buffer and retires the active one, which is reused once every query
+// launched before the switch (seq <= retire_seq) has completed.
+struct SlotList {
+    DevBuf buf;
+    uint64_t retire_seq = 0;
 };
 
 }  // namespace lvq
@@ -43,8 +54,11 @@ struct lvq_index {
     // device store
     lvq::DevBuf means, means_t, muk, kmask, kdim, pos_dim, rows, resid, stack, err, scratch;
     int64_t free_top = 0;   // host view of the free-slot stack top
-    int64_t fresh = 0;      // never-used slots at the bottom of the stack
     uint32_t epoch = 1;
+    std::vector<lvq::SlotList> lists;
+    int list_active = -1;
+    int64_t list_len = 0;   // entries of the active list
+    uint64_t query_seq = 0; // launches recorded as in flight so far
     int64_t device_bytes = 0;
     std::map<hipStream_t, lvq::Workspace> ws;
     std::deque<lvq::InFlight> inflight;

@@ -55,6 +55,7 @@ struct EncodeArgs {
     int64_t free_top;           // stack top before the pop
     int32_t *slots_out;
     const uint64_t *ext_ids;
+    int32_t *list_out;          // store mode: vector i's slot is appended at list_out[i]
     uint32_t epoch;
     uint32_t *err;
 };
@@ -98,7 +99,8 @@ struct ScanArgs {
     const uint8_t *rows;
     const uint8_t *resid;
     int row_bytes, resid_bytes, kchunks, kpos;
-    int64_t n_rows;          // slots [0, n_rows) are scanned
+    const int32_t *list;     // occupied slots; entries [0, n_rows) are scanned
+    int64_t n_rows;
     const float *qk, *qsum, *cm, *muk, *kmask;
     const void *q16;         // MFMA forms: nq x kpos bf16/fp16 in kernel order
     int n_means;
@@ -171,6 +173,9 @@ hipError_t launch_delete(const StoreArgs &a, const int32_t *slots, int64_t n, hi
 hipError_t launch_consolidate(const StoreArgs &a, uint32_t safe_epoch, int32_t *free_stack,
                               int64_t free_top, int32_t *block_counts, int64_t *new_top,
                               hipStream_t s);
+// The occupied slots (flags bit 0), ascending, into list; count to *len.
+hipError_t launch_build_list(const StoreArgs &a, int32_t *list, int32_t *block_counts, int64_t *len,
+                             hipStream_t s);
 hipError_t launch_gather_rows(const StoreArgs &a, const int32_t *slots, int64_t n, uint8_t *rows_out,
                               uint8_t *resid_out, hipStream_t s);
 hipError_t launch_mean(const float *x, int64_t n, int dim, float *out, double *scratch, hipStream_t s);
