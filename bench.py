@@ -102,9 +102,34 @@ def timed(step, steps, warmup, ix):
 
 
 def to_gpu_rows(ix, X, dev, chunk=1 << 20):
+    """Insert X in chunks; returns the milliseconds of the encode-and-insert
+    calls alone (HIP events on the current stream around each call, uploads
+    excluded)."""
     import torch
+    # the first launch of a kernel loads its code object: warm the encoder on
+    # a few vectors (pure encode, same kernel) before timing
+    w = torch.from_numpy(X[:64]).to(dev)
+    ix.encode(w)
+    torch.cuda.synchronize()
+    ms = 0.0
     for a in range(0, X.shape[0], chunk):
-        ix.insert(torch.from_numpy(X[a:a + chunk]).to(dev))
+        xd = torch.from_numpy(X[a:a + chunk]).to(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ix.insert(xd)
+        e1.record()
+        e1.synchronize()
+        ms += e0.elapsed_time(e1)
+    return ms
+
+
+def encode_roofline(ms, n, dim, row_bytes, resid_bytes):
+    """k_encode against the HBM roofline: reads 4d bytes and writes a row and
+    a residual row per vector."""
+    per = 4 * dim + row_bytes + resid_bytes
+    gbs = per * n / (ms / 1000.0) / 1e9
+    return {"kernel": "k_encode (insert)", "ms": ms, "vectors": n, "bytes_per_vector": per,
+            "achieved_GBs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
 
 
 def host_kmeans(S, k, iters, seed_workload, seed_chunk=1):
@@ -176,7 +201,7 @@ def bench_c2(args):
     dev = torch.device("cuda:0")
     log("uploading and encoding the store")
     ix = L.Index(768, 4, 8, L.LVQ_IP, L.LVQ_TURBO, align=args.align, capacity=n, means=mu)
-    to_gpu_rows(ix, X, dev)
+    enc_ms = to_gpu_rows(ix, X, dev)
     qd = torch.from_numpy(Q).to(dev)
     od = torch.from_numpy(offs).to(dev)
     idd = torch.from_numpy(ids).to(dev)
@@ -212,7 +237,8 @@ def bench_c2(args):
                {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "k_cand (candidate-list similarity + fused top-k)", "kernel_ms": k_ms,
-                "algorithmic_bytes_per_pair": per_pair})
+                "algorithmic_bytes_per_pair": per_pair},
+               encode=encode_roofline(enc_ms, n, 768, ix.row_bytes, ix.resid_bytes))
     if not args.no_cpu_baseline:
         log("timing the oracle on a host-core sample")
         fmt = oracle.Format(768, 4, 8, oracle.TURBO)
@@ -295,7 +321,7 @@ def bench_c3(args):
     dev = torch.device("cuda:0")
     log("uploading and encoding the store (%d lists, %d pairs)" % (nq, ids.shape[0]))
     ix = L.Index(d, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=n, means=means)
-    to_gpu_rows(ix, X, dev)
+    enc_ms = to_gpu_rows(ix, X, dev)
     qd = torch.from_numpy(Q).to(dev)
     od = torch.from_numpy(offs).to(dev)
     idd = torch.from_numpy(ids).to(dev)
@@ -335,6 +361,7 @@ def bench_c3(args):
                 "kernel": "k_cand (persistent, longest lists first)", "kernel_ms": k_ms,
                 "algorithmic_bytes_per_pair": per_pair},
                ms_per_step_eager=ms_eager)
+    out["encode"] = encode_roofline(enc_ms, n, d, ix.row_bytes, ix.resid_bytes)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_lists(fmt, oracle.L2, oracle.PRIMARY, X, Q, means, offs, ids)
     ix.close()
@@ -359,7 +386,7 @@ def bench_c4(args):
     dev = torch.device("cuda:0")
     log("uploading and encoding the store")
     ix = L.Index(d, 8, 0, L.LVQ_IP, L.LVQ_SEQUENTIAL, capacity=n, means=mu)
-    to_gpu_rows(ix, X, dev)
+    enc_ms = to_gpu_rows(ix, X, dev)
     assert ix.sync() == 0
     qf = torch.from_numpy(Q).to(dev)
     res = {}
@@ -419,6 +446,7 @@ def bench_c4(args):
                 "kernel": "k_scan_mfma (bf16, fused top-100)", "kernel_ms": k_ms},
                precision=acc, accuracy_sample="%d queries: errors |gpu - binary64 oracle (float32 query)| / "
                                               "sum_j |q_j x_hat_j|; recall@100 vs float ground truth" % ns)
+    out["encode"] = encode_roofline(enc_ms, n, d, ix.row_bytes, ix.resid_bytes)
     ix.close()
     return out
 

@@ -14,9 +14,10 @@
 //   residual       Delta2 = Delta / (2^B2 - 1), r = t - (Delta c1 + l),
 //                  c2 = clamp(floor((r + Delta/2) * (1/Delta2) + 1/2), 0, 2^B2 - 1)
 //
-// Launch shape: one 64-lane wavefront per workgroup; a vector is handled by a
-// group of G lanes (G = 16 for d <= 256, else 64), staged through LDS so the
-// packed words are written with coalesced 32-bit stores.
+// Launch shape: four waves per workgroup; a vector is handled by a group of G
+// lanes (G = 16 for d <= 256, else 64), staged through LDS so the packed words
+// are written with coalesced 32-bit stores.  Code positions map to dimensions
+// arithmetically (no table lookups on the packing path).
 #pragma clang fp contract(off)
 
 #include <float.h>
@@ -25,18 +26,6 @@
 
 namespace lvq {
 namespace {
-
-__device__ __forceinline__ unsigned quantize(float t, float lo, float inv, unsigned top)
-{
-#pragma clang fp contract(off)
-    float a = t - lo;
-    float b = a * inv;
-    float c = b + 0.5f;
-    float v = floorf(c);
-    if (!(v > 0.0f)) return 0u;
-    if (v > (float)top) return top;
-    return (unsigned)v;
-}
 
 template <int G>
 __device__ __forceinline__ float group_max(float v)
@@ -65,60 +54,138 @@ __device__ __forceinline__ int group_and(int v)
     return v;
 }
 
-// Codes of one packed 32-bit word at word index `wi` of a code array of
-// `bits`-bit fields.  `residual` selects the second level.
-__device__ __forceinline__ uint32_t pack_word(const float *ts, const int32_t *pos_dim, int npos,
-                                              int wi, int bits, bool residual, float l, float delta,
-                                              float inv, unsigned top1, float half, float inv2,
-                                              unsigned top2, bool have_step, bool have_step2)
+// Dimension held at code position p of the first-level layout (-1 for
+// padding): sequential layouts hold dimension p; Turbo holds dimension
+// 16k + w of its block in field k of word w (blocks of 128 positions at 4
+// bits, 64 at 8 bits).  Residual codes use the same positions.
+__device__ __forceinline__ int pos_dim_of(const Format &f, int p)
 {
-#pragma clang fp contract(off)
-    const int per = 32 / bits;
-    uint32_t word = 0;
-    for (int k = 0; k < per; ++k) {
-        int p = wi * per + k;
-        if (p >= npos) break;
-        int j = pos_dim[p];
-        if (j < 0) continue;
-        float t = ts[j];
-        unsigned c1 = have_step ? quantize(t, l, inv, top1) : 0u;
-        unsigned v = c1;
-        if (residual) {
-            v = 0u;
-            if (have_step2) {
-                float y = delta * (float)c1;
-                y = y + l;
-                float r = t - y;
-                v = quantize(r, -half, inv2, top2);
-            }
-        }
-        word |= v << (bits * k);
+    if (p >= f.npos) return -1;
+    int dim = p;
+    if (f.layout == LVQ_TURBO) {
+        const int bsh = f.bits1 == 4 ? 7 : 6;   // positions per block: 128 or 64
+        const int fsh = f.bits1 == 4 ? 3 : 2;   // fields per word: 8 or 4
+        const int r = p & ((1 << bsh) - 1);
+        dim = ((p >> bsh) << bsh) + 16 * (r & ((1 << fsh) - 1)) + (r >> fsh);
     }
-    return word;
+    return dim < f.dim ? dim : -1;
 }
 
-template <int G>
-__global__ __launch_bounds__(64) void k_encode(EncodeArgs a)
+// Per-vector quantisation constants.
+struct Steps {
+    float l, delta, inv, half, inv2;
+    unsigned top1, top2;
+    bool step1, step2;
+};
+
+// One packing unit: U consecutive code positions, i.e. PW = U*B1/32 words of
+// first-level codes and RW = U*B2/32 words of residual codes (U = 8 when a
+// level is 4-bit, else 4).  Each field's codes are computed once: the
+// first-level code, then the residual code from the same t.  Positions past
+// the code area or holding no dimension get code 0.
+template <int B1, int B2>
+__device__ __forceinline__ void pack_unit(const float *ts, const Format &f, int unit, const Steps &st,
+                                          uint32_t (&pw)[(B1 == 4 || B2 == 4 ? 8 : 4) * B1 / 32],
+                                          uint32_t (&rw)[B2 ? (B1 == 4 || B2 == 4 ? 8 : 4) * B2 / 32 : 1])
+{
+#pragma clang fp contract(off)
+    constexpr int U = (B1 == 4 || B2 == 4) ? 8 : 4;
+    constexpr int PER1 = 32 / B1;
+#pragma unroll
+    for (int w = 0; w < U * B1 / 32; ++w) pw[w] = 0u;
+#pragma unroll
+    for (int w = 0; w < (B2 ? U * B2 / 32 : 1); ++w) rw[w] = 0u;
+    const bool turbo = f.layout == LVQ_TURBO;
+#pragma unroll
+    for (int h = 0; h < U / PER1; ++h) {          // first-level words of the unit
+        const int p0 = unit * U + h * PER1;       // first position of the word
+        const int base = pos_dim_of(f, p0);       // its dimension (field 0)
+        const int ds = turbo ? 16 : 1;            // dimension step between fields
+#pragma unroll
+        for (int k = 0; k < PER1; ++k) {
+            const int dim = base + ds * k;
+            if (base < 0 || dim >= f.dim || p0 + k >= f.npos) continue;
+            const float t = ts[dim];
+            unsigned c1 = 0u, c2 = 0u;
+            if (st.step1) {
+                float a = t - st.l;
+                float b = a * st.inv;
+                float c = b + 0.5f;
+                float v = floorf(c);
+                v = v > 0.0f ? v : 0.0f;
+                v = v > (float)st.top1 ? (float)st.top1 : v;
+                c1 = (unsigned)v;
+                if (B2 != 0 && st.step2) {
+                    float y = st.delta * v;
+                    y = y + st.l;
+                    const float r = t - y;
+                    float a2 = r - (-st.half);
+                    float b2 = a2 * st.inv2;
+                    float c2f = b2 + 0.5f;
+                    float v2 = floorf(c2f);
+                    v2 = v2 > 0.0f ? v2 : 0.0f;
+                    v2 = v2 > (float)st.top2 ? (float)st.top2 : v2;
+                    c2 = (unsigned)v2;
+                }
+            }
+            const int q = h * PER1 + k;            // field index within the unit
+            pw[q / PER1] |= c1 << (B1 * (q % PER1));
+            if constexpr (B2 != 0) rw[q / (32 / B2)] |= c2 << (B2 * (q % (32 / B2)));
+        }
+    }
+}
+
+template <int B1, int B2, int G>
+__global__ __launch_bounds__(256) void k_encode(EncodeArgs a)
 {
 #pragma clang fp contract(off)
     extern __shared__ float lds[];
-    constexpr int V = 64 / G;
-    const int lane = threadIdx.x;
-    const int grp = lane / G;
-    const int g = lane % G;
+    constexpr int V = 256 / G;   // vectors per workgroup (four waves)
+    const int grp = threadIdx.x / G;
+    const int g = threadIdx.x % G;
     const int d = a.f.dim;
     const int64_t i = (int64_t)blockIdx.x * V + grp;
     const bool active = i < a.n;
     float *ts = lds + (size_t)grp * d;
 
-    // stage x, check finiteness
+    // stage x, check finiteness.  Rows of a multiple of four floats are read
+    // as float4, four loads per lane issued before any is used.
     int finite = 1;
+    const bool vec4 = (d & 3) == 0;
     if (active) {
         const float *x = a.x + i * d;
-        for (int j = g; j < d; j += G) {
-            float v = x[j];
-            ts[j] = v;
-            if (!isfinite(v)) finite = 0;
+        if (vec4) {
+            const int d4 = d >> 2;
+            const float4 *x4 = reinterpret_cast<const float4 *>(x);
+            float4 *t4 = reinterpret_cast<float4 *>(ts);
+            for (int q0 = g; q0 < d4; q0 += 4 * G) {
+                float4 v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = x4[min(q0 + u * G, d4 - 1)];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (q0 + u * G < d4) {
+                        t4[q0 + u * G] = v[u];
+                        if (!isfinite(v[u].x) || !isfinite(v[u].y) || !isfinite(v[u].z) || !isfinite(v[u].w))
+                            finite = 0;
+                    }
+            }
+        } else {
+            for (int j = g; j < d; j += G) {
+                float v = x[j];
+                ts[j] = v;
+                if (!isfinite(v)) finite = 0;
+            }
+        }
+    }
+    // means for the nearest-mean search, staged in LDS as [dim][mean] when
+    // they fit (conflict-free: the lanes of a group read consecutive means)
+    const int M = a.n_means;
+    float *mt = lds + (size_t)V * d;
+    if (a.means_lds) {
+        for (int e = threadIdx.x; e < M * d; e += 256) {
+            const int j = e / M, m = e - j * M;
+            mt[e] = a.means_t[(int64_t)j * a.means_t_stride + m];
         }
     }
     finite = group_and<G>(finite);
@@ -126,15 +193,25 @@ __global__ __launch_bounds__(64) void k_encode(EncodeArgs a)
 
     // Def. 1: nearest mean, sequential binary32 sum per mean, ties to lower m
     int mstar = 0;
-    if (a.n_means > 1 && finite) {
+    if (M > 1 && active && finite) {
         float best = 0.0f;
         int bm = -1;
-        for (int m = g; m < a.n_means; m += G) {
+        for (int m = g; m < M; m += G) {
             float s = 0.0f;
-            for (int j = 0; j < d; ++j) {
-                float e = ts[j] - a.means_t[(int64_t)j * a.means_t_stride + m];
-                float e2 = e * e;
-                s = s + e2;
+            if (a.means_lds) {
+#pragma unroll 8
+                for (int j = 0; j < d; ++j) {
+                    float e = ts[j] - mt[j * M + m];
+                    float e2 = e * e;
+                    s = s + e2;
+                }
+            } else {
+#pragma unroll 8
+                for (int j = 0; j < d; ++j) {
+                    float e = ts[j] - a.means_t[(int64_t)j * a.means_t_stride + m];
+                    float e2 = e * e;
+                    s = s + e2;
+                }
             }
             if (bm < 0 || s < best) {
                 best = s;
@@ -159,12 +236,37 @@ __global__ __launch_bounds__(64) void k_encode(EncodeArgs a)
     float u = -FLT_MAX, l = FLT_MAX;
     if (active) {
         const float *mu = a.means + (int64_t)mstar * d;
-        for (int j = g; j < d; j += G) {
-            float t = ts[j] - mu[j];
-            ts[j] = t;
-            if (!isfinite(t)) finite = 0;
-            u = t > u ? t : u;
-            l = t < l ? t : l;
+        if (vec4) {
+            const int d4 = d >> 2;
+            const float4 *mu4 = reinterpret_cast<const float4 *>(mu);
+            float4 *t4 = reinterpret_cast<float4 *>(ts);
+            for (int q0 = g; q0 < d4; q0 += 4 * G) {
+                float4 mv[4];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) mv[w] = mu4[min(q0 + w * G, d4 - 1)];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int q = q0 + w * G;
+                    if (q >= d4) continue;
+                    float4 t = t4[q];
+                    t.x = t.x - mv[w].x;
+                    t.y = t.y - mv[w].y;
+                    t.z = t.z - mv[w].z;
+                    t.w = t.w - mv[w].w;
+                    t4[q] = t;
+                    if (!isfinite(t.x) || !isfinite(t.y) || !isfinite(t.z) || !isfinite(t.w)) finite = 0;
+                    u = fmaxf(fmaxf(u, fmaxf(t.x, t.y)), fmaxf(t.z, t.w));
+                    l = fminf(fminf(l, fminf(t.x, t.y)), fminf(t.z, t.w));
+                }
+            }
+        } else {
+            for (int j = g; j < d; j += G) {
+                float t = ts[j] - mu[j];
+                ts[j] = t;
+                if (!isfinite(t)) finite = 0;
+                u = t > u ? t : u;
+                l = t < l ? t : l;
+            }
         }
     }
     u = group_max<G>(u);
@@ -173,20 +275,21 @@ __global__ __launch_bounds__(64) void k_encode(EncodeArgs a)
     __syncthreads();
     if (!active) return;
 
-    const unsigned top1 = (1u << a.f.bits1) - 1u;
-    const unsigned top2 = a.f.bits2 ? (1u << a.f.bits2) - 1u : 0u;
+    Steps st;
+    st.top1 = (1u << B1) - 1u;
+    st.top2 = B2 ? (1u << B2) - 1u : 0u;
     float delta = 0.0f, inv = 0.0f, delta2 = 0.0f, inv2 = 0.0f, half = 0.0f;
     bool have_step = false, have_step2 = false;
     if (finite) {
         float span = u - l;
         if (!isfinite(span)) finite = 0;
         else {
-            delta = span / (float)top1;
+            delta = span / (float)st.top1;
             if (delta >= FLT_MIN) {
                 have_step = true;
                 inv = 1.0f / delta;
-                if (a.f.bits2) {
-                    delta2 = delta / (float)top2;
+                if (B2) {
+                    delta2 = delta / (float)st.top2;
                     if (delta2 >= FLT_MIN) {
                         have_step2 = true;
                         inv2 = 1.0f / delta2;
@@ -200,6 +303,13 @@ __global__ __launch_bounds__(64) void k_encode(EncodeArgs a)
             }
         }
     }
+    st.l = l;
+    st.delta = delta;
+    st.inv = inv;
+    st.half = half;
+    st.inv2 = inv2;
+    st.step1 = have_step;
+    st.step2 = have_step2;
 
     // destination slot
     int64_t slot = i;
@@ -214,9 +324,9 @@ __global__ __launch_bounds__(64) void k_encode(EncodeArgs a)
     if (!finite && g == 0) atomicOr(a.err, kErrNonFinite);
 
     uint32_t *row = reinterpret_cast<uint32_t *>(a.rows + slot * a.f.row_bytes);
-    const int row_words = a.f.row_bytes / 4;
-    const int code_words = a.f.code_bytes / 4;
-    for (int w = g; w < row_words; w += G) {
+    // header: lanes 0..7 of the group
+    if (g < 8) {
+        const int w = g;
         if (store && w == 4) {
             // insert and delete epochs in one 64-bit store: a scan running
             // beside this insert reads the pair whole (old or new), and
@@ -224,12 +334,9 @@ __global__ __launch_bounds__(64) void k_encode(EncodeArgs a)
             const uint64_t ep = ((uint64_t)(finite ? kLiveEpoch : a.epoch) << 32) | a.epoch;
             __hip_atomic_store(reinterpret_cast<uint64_t *>(row + 4), ep, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-            continue;
-        }
-        if (store && w == 5) continue;
-        uint32_t v = 0;
-        if (w < 8) {
-            uint64_t ext = store ? (a.ext_ids ? a.ext_ids[i] : (uint64_t)slot) : 0ull;
+        } else if (!(store && w == 5)) {
+            uint32_t v = 0;
+            const uint64_t ext = store ? (a.ext_ids ? a.ext_ids[i] : (uint64_t)slot) : 0ull;
             switch (w) {
             case 0: v = finite ? __float_as_uint(l) : 0x7FC00000u; break;
             case 1: v = finite ? __float_as_uint(delta) : 0u; break;
@@ -239,39 +346,76 @@ __global__ __launch_bounds__(64) void k_encode(EncodeArgs a)
             case 6: v = (uint32_t)ext; break;
             default: v = (uint32_t)(ext >> 32); break;
             }
-        } else if (finite && w - 8 < code_words) {
-            v = pack_word(ts, a.pos_dim, a.f.npos, w - 8, a.f.bits1, false, l, delta, inv, top1,
-                          half, inv2, top2, have_step, have_step2);
+            row[w] = v;
         }
-        row[w] = v;
     }
-    if (a.f.bits2 && a.resid) {
-        uint32_t *res = reinterpret_cast<uint32_t *>(a.resid + slot * a.f.resid_bytes);
-        const int rwords = a.f.resid_bytes / 4;
-        for (int w = g; w < rwords; w += G) {
-            uint32_t v = 0;
-            if (finite)
-                v = pack_word(ts, a.pos_dim, a.f.npos, w, a.f.bits2, true, l, delta, inv, top1,
-                              half, inv2, top2, have_step, have_step2);
-            res[w] = v;
+    // codes: unit u covers positions [U u, U u + U); a non-finite vector
+    // stores zero codes
+    constexpr int U = (B1 == 4 || B2 == 4) ? 8 : 4;
+    constexpr int PW = U * B1 / 32, RW = B2 ? U * B2 / 32 : 0;
+    const int row_words = a.f.row_bytes / 4;
+    const int units = (a.f.npos + U - 1) / U;
+    uint32_t *codes = row + 8;
+    uint32_t *res = B2 && a.resid ? reinterpret_cast<uint32_t *>(a.resid + slot * a.f.resid_bytes) : nullptr;
+    const int res_words = a.f.resid_bytes / 4;
+    if (!finite) st.step1 = false;
+    for (int unit = g; unit < units; unit += G) {
+        uint32_t pw[PW], rw[B2 ? RW : 1];
+        pack_unit<B1, B2>(ts, a.f, unit, st, pw, rw);
+#pragma unroll
+        for (int w = 0; w < PW; ++w)
+            if (8 + unit * PW + w < row_words) codes[unit * PW + w] = pw[w];
+        if constexpr (B2 != 0) {
+            if (res) {
+#pragma unroll
+                for (int w = 0; w < RW; ++w)
+                    if (unit * RW + w < res_words) res[unit * RW + w] = rw[w];
+            }
         }
+    }
+    // zero padding after the last unit
+    for (int w = 8 + units * PW + g; w < row_words; w += G) row[w] = 0u;
+    if constexpr (B2 != 0) {
+        if (res)
+            for (int w = units * RW + g; w < res_words; w += G) res[w] = 0u;
     }
 }
 
 }  // namespace
 
+template <int B1, int B2>
+static hipError_t launch_encode_t(const EncodeArgs &a, int G, size_t lds, int64_t blocks, hipStream_t s)
+{
+    switch (G) {
+    case 8: hipLaunchKernelGGL((k_encode<B1, B2, 8>), dim3((unsigned)blocks), dim3(256), lds, s, a); break;
+    case 16: hipLaunchKernelGGL((k_encode<B1, B2, 16>), dim3((unsigned)blocks), dim3(256), lds, s, a); break;
+    case 32: hipLaunchKernelGGL((k_encode<B1, B2, 32>), dim3((unsigned)blocks), dim3(256), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_encode<B1, B2, 64>), dim3((unsigned)blocks), dim3(256), lds, s, a); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_encode(const EncodeArgs &a, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
-    const int G = a.f.dim <= 256 ? 16 : 64;
-    const int V = 64 / G;
-    const size_t lds = (size_t)V * a.f.dim * sizeof(float);
+    // lanes per vector: the fewest (8..64) giving each lane at most four
+    // packing units
+    const int U = (a.f.bits1 == 4 || a.f.bits2 == 4) ? 8 : 4;
+    const int units = (a.f.npos + U - 1) / U;
+    int G = 8;
+    while (G < 64 && units > 4 * G) G *= 2;
+    const int V = 256 / G;
+    size_t lds = (size_t)V * a.f.dim * sizeof(float);
+    if (a.means_lds) lds += (size_t)a.n_means * a.f.dim * sizeof(float);
     const int64_t blocks = (a.n + V - 1) / V;
-    if (G == 16)
-        hipLaunchKernelGGL(k_encode<16>, dim3((unsigned)blocks), dim3(64), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_encode<64>, dim3((unsigned)blocks), dim3(64), lds, s, a);
-    return hipGetLastError();
+    const int b1 = a.f.bits1, b2 = a.f.bits2;
+    if (b1 == 4 && b2 == 0) return launch_encode_t<4, 0>(a, G, lds, blocks, s);
+    if (b1 == 4 && b2 == 4) return launch_encode_t<4, 4>(a, G, lds, blocks, s);
+    if (b1 == 4 && b2 == 8) return launch_encode_t<4, 8>(a, G, lds, blocks, s);
+    if (b1 == 8 && b2 == 0) return launch_encode_t<8, 0>(a, G, lds, blocks, s);
+    if (b1 == 8 && b2 == 4) return launch_encode_t<8, 4>(a, G, lds, blocks, s);
+    if (b1 == 8 && b2 == 8) return launch_encode_t<8, 8>(a, G, lds, blocks, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace lvq

@@ -332,18 +332,15 @@ int lvq_create(const lvq_config *cfg, const float *means_host, int32_t n_means, 
         }
         std::vector<float> all(means_host, means_host + (size_t)n_means * cfg->dim);
         if ((rc = upload_means(ix, all))) break;
-        std::vector<int32_t> kd(f.kpos), pd(f.npos);
+        std::vector<int32_t> kd(f.kpos);
         kernel_order_dims(f, kd.data());
-        for (int p = 0; p < f.npos; ++p) pd[p] = pos_dim(f, p);
         std::vector<float> km(f.kpos);
         for (int s = 0; s < f.kpos; ++s) km[s] = kd[s] >= 0 ? 1.0f : 0.0f;
         if ((rc = dev_alloc(ix, ix->kdim, sizeof(int32_t) * f.kpos))) break;
-        if ((rc = dev_alloc(ix, ix->pos_dim, sizeof(int32_t) * f.npos))) break;
         if ((rc = dev_alloc(ix, ix->kmask, sizeof(float) * f.kpos))) break;
         if ((rc = dev_alloc(ix, ix->err, 16))) break;
         if ((rc = dev_alloc(ix, ix->scratch, 4096))) break;
         if (hipMemcpy(ix->kdim.p, kd.data(), sizeof(int32_t) * f.kpos, hipMemcpyHostToDevice) ||
-            hipMemcpy(ix->pos_dim.p, pd.data(), sizeof(int32_t) * f.npos, hipMemcpyHostToDevice) ||
             hipMemcpy(ix->kmask.p, km.data(), sizeof(float) * f.kpos, hipMemcpyHostToDevice) ||
             hipMemset(ix->err.p, 0, 16)) {
             rc = LVQ_ERR_DEVICE;
@@ -391,7 +388,7 @@ int lvq_destroy(lvq_index *ix)
         Workspace &w = kv.second;
         for (DevBuf *b : {&w.qk, &w.qsum, &w.cm, &w.order, &w.queue, &w.part, &w.q16, &w.gthr}) dev_free(ix, *b);
     }
-    for (DevBuf *b : {&ix->means, &ix->means_t, &ix->muk, &ix->kmask, &ix->kdim, &ix->pos_dim, &ix->rows,
+    for (DevBuf *b : {&ix->means, &ix->means_t, &ix->muk, &ix->kmask, &ix->kdim, &ix->rows,
                       &ix->resid, &ix->stack, &ix->err, &ix->scratch})
         dev_free(ix, *b);
     for (SlotList &l : ix->lists) dev_free(ix, l.buf);
@@ -455,7 +452,7 @@ static int encode_common(lvq_index *ix, const float *x, int64_t n, uint8_t *rows
     a.means_t = P<float>(ix->means_t);
     a.means_t_stride = kMaxMeans;
     a.n_means = ix->n_means;
-    a.pos_dim = P<int32_t>(ix->pos_dim);
+    a.means_lds = ix->n_means > 1 && (size_t)ix->n_means * ix->f.dim * sizeof(float) <= 32768 ? 1 : 0;
     a.f = ix->f;
     a.rows = rows;
     a.resid = resid;

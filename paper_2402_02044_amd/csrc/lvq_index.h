@@ -52,7 +52,7 @@ struct lvq_index {
     size_t lds_max = 65536;    // LDS bytes one workgroup may allocate
     int n_means = 0;
     // device store
-    lvq::DevBuf means, means_t, muk, kmask, kdim, pos_dim, rows, resid, stack, err, scratch;
+    lvq::DevBuf means, means_t, muk, kmask, kdim, rows, resid, stack, err, scratch;
     int64_t free_top = 0;   // host view of the free-slot stack top
     uint32_t epoch = 1;
     std::vector<lvq::SlotList> lists;

@@ -46,7 +46,7 @@ struct EncodeArgs {
     const float *means_t;    // dim rows of means_t_stride (transposed copy, coalesced assignment)
     int means_t_stride;
     int n_means;
-    const int32_t *pos_dim;  // npos entries: dimension at code position, -1 pad
+    int means_lds;           // stage the transposed means in LDS (small M x dim)
     Format f;
     uint8_t *rows;           // output rows (row i at rows + slot(i) * row_bytes)
     uint8_t *resid;
