@@ -166,6 +166,12 @@ int lvq_autotune(lvq_index *index, const float *q_dev, int64_t nq, const int64_t
                  const int32_t *ids_dev, int64_t total, int32_t level, int32_t k, int32_t *shape_out,
                  float *ms_out, void *stream);
 int lvq_set_tile(lvq_index *index, int32_t level, int32_t topk, int32_t shape);
+/* Number of tile shapes (valid shape indices are 0 .. count - 1) and the
+ * parameters of one: lanes per candidate, bytes per load, loads per lane and
+ * round, pipeline flags (bit 0 software-pipelined, bit 1 query in
+ * registers, bit 2 two blocks ahead).  Outputs may be NULL.               */
+int lvq_num_tile_shapes(void);
+int lvq_tile_shape(int32_t shape, int32_t *lanes, int32_t *piece_bytes, int32_t *pieces, int32_t *pipe);
 
 /* Exhaustive top-k over every slot live at the call (Sec. 2.1 k-NN problem),
  * for nq queries q_dev (nq x dim) of precision prec at `level`: LVQ_FP32 runs

@@ -39,7 +39,8 @@ EXPORTS = ["lvq_row_format", "lvq_create", "lvq_destroy", "lvq_set_means", "lvq_
            "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_topk", "lvq_read_rows",
            "lvq_get_stats", "lvq_sync", "lvq_mean", "lvq_kmeans", "lvq_strerror", "lvq_set_timing",
            "lvq_kernel_time", "lvq_autotune", "lvq_set_tile", "lvq_server_create", "lvq_server_submit",
-           "lvq_server_wait", "lvq_server_drain", "lvq_server_get_stats", "lvq_server_destroy"]
+           "lvq_server_wait", "lvq_server_drain", "lvq_server_get_stats", "lvq_server_destroy",
+           "lvq_num_tile_shapes", "lvq_tile_shape"]
 
 
 class lvq_config(ctypes.Structure):
@@ -114,6 +115,8 @@ def _load():
         "lvq_server_drain": [P],
         "lvq_server_get_stats": [P, ctypes.POINTER(lvq_server_stats)],
         "lvq_server_destroy": [P],
+        "lvq_num_tile_shapes": [],
+        "lvq_tile_shape": [i32, P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -212,6 +215,17 @@ def lvq_autotune(ix, q, nq, offsets, ids, total, level, k, stream=0):
 
 def lvq_set_tile(ix, level, topk, shape):
     return _chk(_lib.lvq_set_tile(ix, level, topk, shape), "lvq_set_tile")
+
+
+def lvq_num_tile_shapes() -> int:
+    return _lib.lvq_num_tile_shapes()
+
+
+def lvq_tile_shape(shape):
+    """(lanes per candidate, bytes per load, loads per lane, pipeline flags)."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    _chk(_lib.lvq_tile_shape(shape, *[ctypes.byref(x) for x in v]), "lvq_tile_shape")
+    return tuple(x.value for x in v)
 
 
 def lvq_set_timing(ix, enable):

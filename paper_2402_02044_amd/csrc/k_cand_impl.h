@@ -352,10 +352,13 @@ __device__ __forceinline__ float finish_pair(const Acc &A, float l2acc, float4 h
     }
 }
 
-template <int B1, int B2, int METRIC, bool MULTI, bool MASK, int G, int CH, int NCH, bool PIPE, bool QREG>
+// PIPE: 0 = no software pipeline; 1 or 2 = the loads of the candidates one
+// or two blocks ahead are in flight while the current block is consumed.
+template <int B1, int B2, int METRIC, bool MULTI, bool MASK, int G, int CH, int NCH, int PIPE, bool QREG>
 __global__ __launch_bounds__(256) void k_cand(CandArgs a)
 {
     static_assert(!QREG || (PIPE && !MULTI && !MASK), "register-resident query needs one table, one round");
+    static_assert(PIPE >= 0 && PIPE <= 2, "pipeline depth");
     using Regs = PairRegs<B1, B2, CH, NCH>;
     constexpr int kPairsPerWave = 64 / G;
     constexpr int kPairsPerBlock = 4 * kPairsPerWave;
@@ -426,15 +429,21 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
         const int k = a.k;
         const int64_t my = (int64_t)wave * kPairsPerWave + grp;   // entry offset inside a block of pairs
 
-        Regs cur;
+        Regs cur, nx1;
         int32_t slot_next = 0;
         if constexpr (PIPE) {
-            // two-stage software pipeline: the next candidate's id and row
-            // loads are in flight while the current one is consumed
+            // software pipeline: the rows of the candidates PIPE blocks ahead
+            // and the id after them are in flight while the current one is
+            // consumed
             const int64_t e = e0 + my;
             const int32_t s0 = e < e1 ? a.ids[e] : 0;
             load_pair<B1, B2, G, CH, NCH>(cur, a, e, e1, s0, 0, g, npieces);
-            slot_next = e + kPairsPerBlock < e1 ? a.ids[e + kPairsPerBlock] : 0;
+            if constexpr (PIPE == 2) {
+                const int64_t e_1 = e + kPairsPerBlock;
+                const int32_t s1 = e_1 < e1 ? a.ids[e_1] : 0;
+                load_pair<B1, B2, G, CH, NCH>(nx1, a, e_1, e1, s1, 0, g, npieces);
+            }
+            slot_next = e + PIPE * kPairsPerBlock < e1 ? a.ids[e + PIPE * kPairsPerBlock] : 0;
         }
         for (int64_t base = e0; base < e1; base += kPairsPerBlock) {
             const int64_t e = base + my;
@@ -445,7 +454,7 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
             int32_t slot;
             if constexpr (PIPE) {
                 Regs nxt;
-                const int64_t en = e + kPairsPerBlock;
+                const int64_t en = e + PIPE * kPairsPerBlock;
                 load_pair<B1, B2, G, CH, NCH>(nxt, a, en, e1, slot_next, 0, g, npieces);
                 slot_next = en + kPairsPerBlock < e1 ? a.ids[en + kPairsPerBlock] : 0;
                 hdr = cur.hdr;
@@ -458,7 +467,12 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
                 valid = cur.valid;
                 work = cur.work;
                 slot = cur.slot;
-                cur = nxt;
+                if constexpr (PIPE == 2) {
+                    cur = nx1;
+                    nx1 = nxt;
+                } else {
+                    cur = nxt;
+                }
             } else {
                 valid = e < e1;
                 slot = valid ? a.ids[e] : 0;

@@ -33,6 +33,13 @@ constexpr CandShape kCandShapes[] = {
     {4, 8, 3, 3},    // 96 bytes
     {2, 16, 3, 3},   // 96 bytes
     {16, 8, 4, 3},   // 512 bytes
+    // pipelined two blocks ahead, single round
+    {16, 8, 3, 5},   // 384 bytes
+    {8, 16, 3, 5},   // 384 bytes
+    {4, 8, 3, 5},    // 96 bytes
+    {2, 16, 3, 5},   // 96 bytes
+    {8, 8, 6, 5},    // 384 bytes
+    {16, 16, 2, 5},  // 512 bytes
 };
 constexpr int kNumCandShapes = sizeof(kCandShapes) / sizeof(kCandShapes[0]);
 
@@ -40,21 +47,23 @@ using CandKernel = void (*)(CandArgs);
 
 // variant: 0 = IP, 1 = L2 one mean, 2 = L2 several means, 3 = L2 masked,
 //          4 = L2 masked several means
+// pipe bits: 1 = software-pipelined, 2 = query in registers, 4 = two blocks ahead
 template <int B1, int B2, int S>
 constexpr CandKernel cand_kernel_for(int variant)
 {
     constexpr CandShape sh = kCandShapes[S];
+    constexpr int depth = (sh.pipe & 1) ? ((sh.pipe & 4) ? 2 : 1) : 0;
     switch (variant) {
-    case 0: return k_cand<B1, B2, LVQ_IP, false, false, sh.g, sh.ch, sh.nch, sh.pipe != 0, (sh.pipe & 2) != 0>;
-    case 1: return k_cand<B1, B2, LVQ_L2, false, false, sh.g, sh.ch, sh.nch, sh.pipe != 0, (sh.pipe & 2) != 0>;
+    case 0: return k_cand<B1, B2, LVQ_IP, false, false, sh.g, sh.ch, sh.nch, depth, (sh.pipe & 2) != 0>;
+    case 1: return k_cand<B1, B2, LVQ_L2, false, false, sh.g, sh.ch, sh.nch, depth, (sh.pipe & 2) != 0>;
     case 2:
-        if constexpr ((sh.pipe & 2) == 0) return k_cand<B1, B2, LVQ_L2, true, false, sh.g, sh.ch, sh.nch, sh.pipe != 0, false>;
+        if constexpr ((sh.pipe & 2) == 0) return k_cand<B1, B2, LVQ_L2, true, false, sh.g, sh.ch, sh.nch, depth, false>;
         return nullptr;
     default: break;
     }
     if constexpr (S == 0) {
-        if (variant == 3) return k_cand<B1, B2, LVQ_L2, false, true, sh.g, sh.ch, sh.nch, false, false>;
-        if (variant == 4) return k_cand<B1, B2, LVQ_L2, true, true, sh.g, sh.ch, sh.nch, false, false>;
+        if (variant == 3) return k_cand<B1, B2, LVQ_L2, false, true, sh.g, sh.ch, sh.nch, 0, false>;
+        if (variant == 4) return k_cand<B1, B2, LVQ_L2, true, true, sh.g, sh.ch, sh.nch, 0, false>;
     }
     return nullptr;
 }
@@ -85,6 +94,12 @@ inline CandKernel cand_lookup(int variant, int shape)
     case 19: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 19>(variant);
     case 20: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 20>(variant);
     case 21: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 21>(variant);
+    case 22: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 22>(variant);
+    case 23: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 23>(variant);
+    case 24: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 24>(variant);
+    case 25: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 25>(variant);
+    case 26: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 26>(variant);
+    case 27: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 27>(variant);
     default: return nullptr;
     }
 }

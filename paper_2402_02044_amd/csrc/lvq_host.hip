@@ -683,6 +683,19 @@ int lvq_set_tile(lvq_index *ix, int32_t level, int32_t topk, int32_t shape)
     return LVQ_OK;
 }
 
+int lvq_num_tile_shapes(void) { return num_tile_shapes(); }
+
+int lvq_tile_shape(int32_t shape, int32_t *lanes, int32_t *piece_bytes, int32_t *pieces, int32_t *pipe)
+{
+    if (shape < 0 || shape >= num_tile_shapes()) return LVQ_ERR_INVALID_ARG;
+    const TileShape t = tile_shape(shape);
+    if (lanes) *lanes = t.g;
+    if (piece_bytes) *piece_bytes = t.ch;
+    if (pieces) *pieces = t.nch;
+    if (pipe) *pipe = t.pipe;
+    return LVQ_OK;
+}
+
 int lvq_autotune(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev, const int32_t *ids_dev,
                  int64_t total, int32_t level, int32_t k, int32_t *shape_out, float *ms_out, void *stream)
 {

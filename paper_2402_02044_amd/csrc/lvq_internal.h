@@ -135,7 +135,8 @@ hipError_t launch_prep(const PrepArgs &a, hipStream_t s);
 struct TileShape {
     int g, ch, nch;   // lanes per candidate, bytes per piece, pieces per lane and round
     int pipe;         // bit 0: software-pipelined single-round candidate loop;
-                      // bit 1: query values held in registers for a whole list
+                      // bit 1: query values held in registers for a whole list;
+                      // bit 2: the pipeline runs two blocks of candidates ahead
 };
 int num_tile_shapes();
 TileShape tile_shape(int i);

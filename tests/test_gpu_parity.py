@@ -144,6 +144,60 @@ def test_candidate_distances_and_topk(L, d, b1, b2, layout, metric, M):
     ix.close()
 
 
+SHAPE_CASES = [
+    (768, 4, 8, oracle.TURBO, oracle.IP, 1),
+    (96, 8, 0, oracle.SEQUENTIAL, oracle.L2, 16),
+    (512, 8, 0, oracle.SEQUENTIAL, oracle.IP, 1),
+]
+
+
+@pytest.mark.parametrize("d,b1,b2,layout,metric,M", SHAPE_CASES)
+def test_every_tile_shape(L, d, b1, b2, layout, metric, M):
+    """Every tile shape the format admits (forced with lvq_set_tile) gives the
+    oracle's values and top-k on ragged lists."""
+    g = synth.rng(2100 + d, b1 + b2 + M)
+    n = 1500
+    X = g.standard_normal((n, d)).astype(np.float32)
+    Q = g.standard_normal((9, d)).astype(np.float32)
+    if metric == oracle.IP:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+        Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    means = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32) if M == 1 \
+        else X[g.choice(n, M, replace=False)]
+    fmt = oracle.Format(d, b1, b2, layout)
+    rows, resid, _ = oracle.encode_rows(fmt, X, means)
+    lens = [0, 1, 3, 64, 65, 130, 700, 1500, 31]
+    offs, ids = _lists(g, 9, n, lens)
+    ix = L.Index(d, b1, b2, metric, layout, capacity=n, means=means)
+    ix.insert(torch.from_numpy(X).cuda())
+    assert ix.sync() == 0
+    qd = torch.from_numpy(Q).cuda()
+    od, idd = torch.from_numpy(offs).cuda(), torch.from_numpy(ids).cuda()
+    tested = 0
+    for level in ([oracle.PRIMARY, oracle.FULL] if b2 else [oracle.PRIMARY]):
+        ref, tol = pair_reference(fmt, metric, level, Q, rows, resid, means, offs, ids)
+        for shape in range(L.lvq_num_tile_shapes()):
+            for k in (0, 10):
+                try:
+                    ix.set_tile(level, k > 0, shape)
+                    dist, ti, td = ix.distances(qd, od, idd, level=level, k=k)
+                except L.LVQError as e:
+                    assert e.code == L.LVQ_ERR_UNSUPPORTED
+                    continue
+                assert ix.sync() == 0
+                check_values(dist.cpu().numpy(), ref, tol, "shape %d" % shape)
+                tested += 1
+                if k:
+                    ti, td = ti.cpu().numpy(), td.cpu().numpy()
+                    for i in range(9):
+                        a, b = offs[i], offs[i + 1]
+                        check_topk(metric, ti[i], td[i], ids[a:b], ref[a:b], tol[a:b], k)
+        ix.set_tile(level, 0, -1)
+        ix.set_tile(level, 1, -1)
+    assert tested >= 10
+    ix.close()
+
+
 def test_duplicate_ids_and_bad_slots(L):
     d, n = 96, 500
     X = synth.small_vectors(11, n, d)
