@@ -226,6 +226,14 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
 
     for (int64_t base = r0; base < r1; base += kRowsPerIter) {
         const bool mine = rb < r1;
+        // shared per-query bounds for this round's compactions, loaded now so
+        // their latency hides behind the round's products
+        uint32_t gb_lane[(TQ + 63) / 64];
+#pragma unroll
+        for (int h = 0; h < (TQ + 63) / 64; ++h) {
+            const int qi_l = 64 * h + lane;
+            gb_lane[h] = a.gthr[q0 + (qi_l < nqt ? qi_l : 0)];
+        }
         const int64_t rb_next = rb + kRowsPerIter;
         // unconditional (clamped) prefetch: a load under a branch would make
         // every later wait count it as the most recent outstanding load
@@ -280,46 +288,55 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
             const float lp = B2 ? hcur.x - 0.5f * hcur.y : hcur.x;
 #pragma unroll
             for (int b = 0; b < QB; ++b) {
-                float sc[16];
-                bool pass[16];
-                bool any = false;
+                // the block's per-query constants, all read before any is used
+                float4 qsA[4], tfA[4], cmA[4];
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const int q4 = 32 * b + 8 * g + 4 * half;
-                    const float4 qs = *reinterpret_cast<const float4 *>(qsum + q4);
-                    const float4 tf = *reinterpret_cast<const float4 *>(thr_f + q4);
-                    float4 cmv;
-                    if (nm == 1) {
-                        cmv = *reinterpret_cast<const float4 *>(cmt + q4);
-                    } else {
-                        cmv.x = cmt[(q4 + 0) * nm + mid];
-                        cmv.y = cmt[(q4 + 1) * nm + mid];
-                        cmv.z = cmt[(q4 + 2) * nm + mid];
-                        cmv.w = cmt[(q4 + 3) * nm + mid];
+                    qsA[g] = *reinterpret_cast<const float4 *>(qsum + q4);
+                    tfA[g] = *reinterpret_cast<const float4 *>(thr_f + q4);
+                }
+                if (nm == 1) {
+#pragma unroll
+                    for (int g = 0; g < 4; ++g)
+                        cmA[g] = *reinterpret_cast<const float4 *>(cmt + 32 * b + 8 * g + 4 * half);
+                } else {
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const int q4 = 32 * b + 8 * g + 4 * half;
+                        cmA[g] = make_float4(cmt[(q4 + 0) * nm + mid], cmt[(q4 + 1) * nm + mid],
+                                             cmt[(q4 + 2) * nm + mid], cmt[(q4 + 3) * nm + mid]);
                     }
-                    const float qsv[4] = {qs.x, qs.y, qs.z, qs.w};
-                    const float tfv[4] = {tf.x, tf.y, tf.z, tf.w};
-                    const float cmq[4] = {cmv.x, cmv.y, cmv.z, cmv.w};
+                }
+                float sc[16];
+                uint32_t passm = 0u;   // bit i: score i reaches its query's bound
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int q4 = 32 * b + 8 * g + 4 * half;
+                    const float qsv[4] = {qsA[g].x, qsA[g].y, qsA[g].z, qsA[g].w};
+                    const float tfv[4] = {tfA[g].x, tfA[g].y, tfA[g].z, tfA[g].w};
+                    const float cmv[4] = {cmA[g].x, cmA[g].y, cmA[g].z, cmA[g].w};
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int i = 4 * g + r;
-                        sc[i] = fmaf(hcur.y, acc[b][i], fmaf(lp, qsv[r], cmq[r]));
-                        if constexpr (B2 != 0) sc[i] = fmaf(hcur.z, acc2[b][i], sc[i]);
+                        const float cmq = cmv[r];
+                        float v = fmaf(hcur.y, acc[b][i], fmaf(lp, qsv[r], cmq));
+                        if constexpr (B2 != 0) v = fmaf(hcur.z, acc2[b][i], v);
+                        sc[i] = v;
                         // tfv never rejects a score that can enter the top k
-                        pass[i] = live && (q4 + r) < nqt && sc[i] >= tfv[r];
-                        any |= pass[i];
+                        passm |= (live && (q4 + r) < nqt && v >= tfv[r]) ? 1u << i : 0u;
                     }
                 }
-                if (__ballot(any)) {
+                if (__ballot(passm != 0u)) {
+                    // Append: the bound test above already admits only
+                    // scores that can reach the top k; the buffer keeps room
+                    // for one round of appends, so no key is lost.
 #pragma unroll
                     for (int i = 0; i < 16; ++i) {
-                        if (!pass[i]) continue;
+                        if (!((passm >> i) & 1u)) continue;
                         const int qi = 32 * b + 8 * (i >> 2) + 4 * half + (i & 3);
-                        const uint64_t key = make_key(sc[i], (int32_t)slot, LVQ_IP);
-                        if (key < thr[qi]) {
-                            const int pos = atomicAdd(&cnt[qi], 1);
-                            if (pos < capq) buf[(size_t)qi * capq + pos] = key;
-                        }
+                        const int pos = atomicAdd(&cnt[qi], 1);
+                        if (pos < capq) buf[(size_t)qi * capq + pos] = make_key(sc[i], (int32_t)slot, LVQ_IP);
                     }
                 }
             }
@@ -330,6 +347,7 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
         const bool last = base + kRowsPerIter >= r1;
         for (int q0w = 0; q0w < TQ; q0w += 64) {
             const int qi_l = q0w + lane;
+            const uint32_t gpre = gb_lane[q0w / 64];
             const bool need = qi_l < nqt && (last || min(cnt[qi_l], capq) > capq - kRowsPerIter) &&
                               (qi_l & (kWaves - 1)) == wave;
             uint64_t m = __ballot(need);
@@ -340,15 +358,22 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
                 const int n = min(cnt[qi], capq);
                 uint64_t *qb = buf + (size_t)qi * capq;
                 const int got = wave_compact(qb, n, k, tmp + (size_t)wave * k);
+                // the shared bound as read at the start of this round
+                uint32_t gb = __shfl(gpre, bit, 64);
                 if (lane == 0) {
                     cnt[qi] = got;
                     thr[qi] = got == k ? qb[k - 1] : kNoKey;
                     // Share the bound: this part holds k candidates whose score
                     // order is <= that of its k-th key, so no candidate with a
                     // larger score order (worse score) can reach the final top
-                    // k in any part.  Ties stay admitted.
-                    uint32_t gb = a.gthr[q0 + qi];
-                    if (got == k) gb = min(gb, atomicMin(&a.gthr[q0 + qi], (uint32_t)(qb[k - 1] >> 32)));
+                    // k in any part.  Ties stay admitted.  The update does not
+                    // wait for the atomic (no return value): other parts see it
+                    // at their next round.
+                    if (got == k) {
+                        const uint32_t mine = (uint32_t)(qb[k - 1] >> 32);
+                        gb = min(gb, mine);
+                        __hip_atomic_fetch_min(&a.gthr[q0 + qi], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
                     thr_f[qi] = gb == 0xFFFFFFFFu ? -__builtin_inff() : key_score((uint64_t)gb << 32, LVQ_IP);
                 }
             }
