@@ -452,6 +452,55 @@ def bench_c4(args):
 
 
 # ---------------------------------------------------------------------------
+# Turbo vs sequential 4-bit layout (the GPU analogue of the paper's Turbo
+# table, Sec. 3.1): first-level inner products over candidate lists
+# ---------------------------------------------------------------------------
+
+def bench_layouts(args):
+    import torch
+
+    import paper_2402_02044_amd as L
+    import synth
+    n, nq, per = args.n or 1_000_000, args.nq or 2_000, 1000
+    dev = torch.device("cuda:0")
+    rows = []
+    for d in (64, 128, 256, 512, 768, 1024):
+        X = synth.anisotropic(2, synth.S_BASE, 0, n, d)
+        Q = synth.anisotropic(2, synth.S_QUERY, 0, nq, d)
+        mu = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+        offs, ids = synth.candidate_lists(2, nq, n, length=per)
+        qd = torch.from_numpy(Q).to(dev)
+        od = torch.from_numpy(offs).to(dev)
+        idd = torch.from_numpy(ids).to(dev)
+        ent = {"dim": d}
+        for name, layout in (("turbo", L.LVQ_TURBO), ("sequential", L.LVQ_SEQUENTIAL)):
+            ix = L.Index(d, 4, 0, L.LVQ_IP, layout, capacity=n, means=mu)
+            to_gpu_rows(ix, X, dev)
+            shape, _ = ix.autotune(qd, od, idd, level=L.LVQ_PRIMARY, k=0)
+            dist = torch.empty(ids.shape[0], dtype=torch.float32, device=dev)
+            s = int(torch.cuda.current_stream().cuda_stream)
+
+            def step():
+                L.lvq_distances(ix.handle, qd.data_ptr(), nq, od.data_ptr(), idd.data_ptr(), ids.shape[0],
+                                L.LVQ_PRIMARY, dist.data_ptr(), 0, 0, 0, s)
+
+            _, k_ms = timed(step, args.steps, args.warmup, ix)
+            assert ix.sync() == 0
+            ent[name] = {"kernel_ms": k_ms, "ns_per_distance": k_ms * 1e6 / ids.shape[0], "tile_shape": shape,
+                         "row_bytes": ix.row_bytes}
+            ix.close()
+        ent["time_reduction"] = 1.0 - ent["turbo"]["kernel_ms"] / ent["sequential"]["kernel_ms"]
+        log("d=%d: turbo %.4f ns, sequential %.4f ns per distance (reduction %.1f%%)" %
+            (d, ent["turbo"]["ns_per_distance"], ent["sequential"]["ns_per_distance"], 100 * ent["time_reduction"]))
+        rows.append(ent)
+    t768 = [r for r in rows if r["dim"] == 768][0]["turbo"]
+    return line(1e9 / t768["ns_per_distance"], "distances/s", args.steps, args.warmup, None, "f32",
+                {"workload": "first-level LVQ-4 inner products, Turbo vs sequential 4-bit layout, n=%d, %d queries x "
+                             "%d candidates, d in 64..1024 (value: Turbo at d=768)" % (n, nq, per)},
+                None, layouts=rows)
+
+
+# ---------------------------------------------------------------------------
 # C5: streaming serving (request server beside inserts, deletes, drift)
 # ---------------------------------------------------------------------------
 
@@ -767,7 +816,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "layouts"])
     ap.add_argument("--rounds", type=int, default=30, help="c5: update rounds")
     ap.add_argument("--sat-batches", type=int, default=60, help="c5: batches of each saturation burst")
     ap.add_argument("--lat-batches", type=int, default=120, help="c5: batches of each latency phase")
@@ -800,7 +849,8 @@ def main():
         print(json.dumps({"copy_bytes_read_per_launch": n * 4, "copy_bytes_written_per_launch": n * 4,
                           "launches": 5}), flush=True)
         return
-    fn = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload]
+    fn = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
+          "layouts": bench_layouts}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 
