@@ -228,6 +228,7 @@ struct PairRegs {
     Words<CandGeom<B1, CH>::kWords> wv[NCH];
     Words<ResGeom<B1, B2, CH>::kWords> rv[NCH];
     float4 hdr;
+    uint2 ep;      // insertion / deletion epochs (loaded when a top-k is fused)
     int32_t slot;
     bool valid, work;
 };
@@ -253,6 +254,14 @@ __device__ __forceinline__ void load_pair(PairRegs<B1, B2, CH, NCH> &P, const Ca
     if (p0 == 0) {
         float4 h = *reinterpret_cast<const float4 *>(row);
         P.hdr = P.work ? h : make_float4(0.f, 0.f, 0.f, 0.f);
+        // the epoch pair is one 64-bit load (it is written as one 64-bit
+        // store), issued with the row so the fused top-k never waits on it
+        if (a.k > 0) {
+            const uint2 ep = *reinterpret_cast<const uint2 *>(row + 16);
+            P.ep = P.work ? ep : make_uint2(1u, 0u);
+        } else {
+            P.ep = make_uint2(1u, 0u);
+        }
     }
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -376,9 +385,13 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
     float *mtab = qtab + (size_t)ntab * a.kpos;                 // mask (L2, MASK)
     float *cmt = mtab + (MASK ? a.kpos : 0);                   // c_m (IP)
     const int cm_n = METRIC == LVQ_IP ? a.n_means : 0;
+    // fused top-k: one key buffer of a.cw entries per wave, then 4k entries
+    // for the merge of the four waves (also each wave's selection scratch)
     uint64_t *keys = reinterpret_cast<uint64_t *>(cmt + ((cm_n + 1) & ~1));
+    uint64_t *wbuf = keys + (size_t)wave * a.cw;
+    uint64_t *merge = keys + (size_t)4 * a.cw;
     __shared__ int s_item;
-    constexpr int kCap = 2048;
+    __shared__ int s_got[4];
 
     for (int iter = 0;; ++iter) {
         int item;
@@ -425,7 +438,11 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
             }
         }
 
-        int nbuf = 0;        // keys held in the LDS buffer (block-uniform)
+        // Per-wave pruned top-k: a wave appends the keys of its candidates
+        // that beat its bound thr (its k-th best so far) to its own buffer and
+        // compacts the buffer to its k best when the next block might not fit.
+        int nw = 0;                 // keys in this wave's buffer (wave-uniform)
+        uint64_t thr = kNoKey;      // this wave's bound (wave-uniform)
         const int k = a.k;
         const int64_t my = (int64_t)wave * kPairsPerWave + grp;   // entry offset inside a block of pairs
 
@@ -450,6 +467,7 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
             Acc A{0.f, 0.f, 0.f, 0.f};
             float l2acc = 0.0f;
             float4 hdr;
+            uint2 ep;
             bool valid, work;
             int32_t slot;
             if constexpr (PIPE) {
@@ -458,6 +476,7 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
                 load_pair<B1, B2, G, CH, NCH>(nxt, a, en, e1, slot_next, 0, g, npieces);
                 slot_next = en + kPairsPerBlock < e1 ? a.ids[en + kPairsPerBlock] : 0;
                 hdr = cur.hdr;
+                ep = cur.ep;
                 const float *tq = qtab + ((METRIC == LVQ_L2 && MULTI)
                                               ? (size_t)min((int)(__float_as_uint(hdr.w) & 0xFFu), a.n_means - 1) * a.kpos
                                               : 0);
@@ -479,6 +498,7 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
                 Regs P;
                 load_pair<B1, B2, G, CH, NCH>(P, a, e, e1, slot, 0, g, npieces);
                 hdr = P.hdr;
+                ep = P.ep;
                 work = P.work;
                 const float *tq = qtab + ((METRIC == LVQ_L2 && MULTI)
                                               ? (size_t)min((int)(__float_as_uint(hdr.w) & 0xFFu), a.n_means - 1) * a.kpos
@@ -500,43 +520,47 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
             }
             if (valid && g == 0 && a.dist) a.dist[e] = score;
             if (k > 0) {
-                if (valid && g == 0) {
-                    uint64_t key = kNoKey;
-                    if (work) {
-                        const uint8_t *row = a.rows + (int64_t)slot * a.row_bytes;
-                        uint2 ep = *reinterpret_cast<const uint2 *>(row + 16);
-                        const bool live = ((__float_as_uint(hdr.w) >> 8) & 1u) && ep.x <= a.epoch &&
-                                          a.epoch < ep.y;
-                        if (live) key = make_key(score, slot, METRIC);
-                    }
-                    keys[nbuf + (int)(e - base)] = key;
+                uint64_t key = kNoKey;
+                if (work) {
+                    const bool live = ((__float_as_uint(hdr.w) >> 8) & 1u) && ep.x <= a.epoch && a.epoch < ep.y;
+                    if (live) key = make_key(score, slot, METRIC);
                 }
-                nbuf += (int)min<int64_t>(kPairsPerBlock, e1 - base);
-                // compact the buffer when the next block of pairs might not fit
-                if (nbuf + kPairsPerBlock > kCap && base + kPairsPerBlock < e1) {
-                    __syncthreads();
-                    if (wave == 0) {
-                        uint64_t *tmp = keys + kCap;   // k entries of scratch
-                        int got = wave_select_smallest(keys, nbuf, k, tmp);
-                        for (int i = lane; i < k; i += 64) keys[i] = i < got ? tmp[i] : kNoKey;
-                    }
-                    __syncthreads();
-                    nbuf = k;
+                const bool pass = valid && g == 0 && key < thr;
+                const uint64_t bal = __ballot(pass);
+                const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                if (pass) wbuf[nw + below] = key;
+                nw += __popcll(bal);
+                // compact when the next block might not fit, and after the
+                // last block (the merge takes at most k keys per wave)
+                if (nw > a.cw - kPairsPerWave || (base + kPairsPerBlock >= e1 && nw > k)) {
+                    const int got = wave_compact_lean(wbuf, nw, k, merge + (size_t)wave * k);
+                    nw = got;
+                    const uint64_t t = got == k ? wbuf[k - 1] : kNoKey;
+                    thr = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(t >> 32)) << 32) |
+                          (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t);
                 }
             }
         }
 
         if (k > 0) {
+            // each wave holds at most k keys; wave 0 merges the four
+            if (lane == 0) s_got[wave] = nw;
             __syncthreads();
             if (wave == 0) {
-                uint64_t *tmp = keys + kCap;
-                int got = wave_select_smallest(keys, nbuf, k, tmp);
+                int n = 0;
+                for (int w = 0; w < 4; ++w) {
+                    const int gw = s_got[w];
+                    for (int i = lane; i < gw; i += 64) merge[n + i] = keys[(size_t)w * a.cw + i];
+                    n += gw;
+                }
+                const int got = wave_compact_lean(merge, n, k, keys);
                 for (int i = lane; i < k; i += 64) {
                     int32_t sid = -1;
                     float sv = METRIC == LVQ_L2 ? __uint_as_float(0x7F800000u) : __uint_as_float(0xFF800000u);
                     if (i < got) {
-                        sid = (int32_t)(uint32_t)tmp[i];
-                        sv = key_score(tmp[i], METRIC);
+                        sid = (int32_t)(uint32_t)merge[i];
+                        sv = key_score(merge[i], METRIC);
                     }
                     a.topk_ids[list * k + i] = sid;
                     a.topk_dist[list * k + i] = sv;
@@ -546,12 +570,12 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
     }
 }
 
-// LDS bytes of one k_cand launch
-inline size_t cand_lds_bytes_impl(int kpos, int ntab, bool mask, int n_means_ip, int k)
+// LDS bytes of one k_cand launch with per-wave key buffers of cw entries
+inline size_t cand_lds_bytes_impl(int kpos, int ntab, bool mask, int n_means_ip, int k, int cw)
 {
     size_t b = (size_t)ntab * kpos * 4 + (mask ? (size_t)kpos * 4 : 0) + (size_t)((n_means_ip + 1) & ~1) * 4;
     b = (b + 15) & ~(size_t)15;
-    if (k > 0) b += (size_t)(2048 + k) * 8;
+    if (k > 0) b += ((size_t)4 * cw + (size_t)4 * k) * 8;
     return b;
 }
 

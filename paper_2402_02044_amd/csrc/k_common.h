@@ -61,22 +61,57 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int o)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// The wave-wide reductions below expect every lane of the wavefront active.
+// DPP row operations leave each 16-lane row with its reduction in every lane
+// (lane pairs xor 1, xor 2, then the half-row and row mirrors); the four row
+// results are read out with readlane, so the total is wave-uniform.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ uint64_t min_u64(uint64_t a, uint64_t b)
+{
+    return b < a ? b : a;
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_min_u64(uint64_t v)
+{
+    const uint64_t o = ((uint64_t)dpp_u32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp_u32<CTRL>((uint32_t)v);
+    return min_u64(v, o);
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
 {
-    for (int o = 32; o > 0; o >>= 1) {
-        uint64_t w = shfl_xor_u64(v, o);
-        v = w < v ? w : v;
-    }
-    return v;
+    v = dpp_min_u64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v = dpp_min_u64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v = dpp_min_u64<0x141>(v);   // row_half_mirror
+    v = dpp_min_u64<0x140>(v);   // row_mirror
+    return min_u64(min_u64(readlane_u64(v, 0), readlane_u64(v, 16)),
+                   min_u64(readlane_u64(v, 32), readlane_u64(v, 48)));
 }
 
 __device__ __forceinline__ int wave_sum_i32(int v)
 {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    uint32_t u = (uint32_t)v;
+    u += dpp_u32<0xB1>(u);
+    u += dpp_u32<0x4E>(u);
+    u += dpp_u32<0x141>(u);
+    u += dpp_u32<0x140>(u);
+    return (int)((uint32_t)__builtin_amdgcn_readlane((int)u, 0) + (uint32_t)__builtin_amdgcn_readlane((int)u, 16) +
+                 (uint32_t)__builtin_amdgcn_readlane((int)u, 32) + (uint32_t)__builtin_amdgcn_readlane((int)u, 48));
 }
 
-// One wavefront selects the k smallest keys of keys[0..n) (LDS) in ascending
+// One whole wavefront selects the k smallest keys of keys[0..n) (LDS) in ascending
 // order into out[0..k); entries equal to a selected key are taken together
 // (duplicates of an entry are kept as separate results, as many as fit).
 // Returns the number of keys written (< k when fewer than k are valid).
@@ -92,13 +127,18 @@ __device__ __forceinline__ int wave_select_smallest(uint64_t *keys, int n, int k
         if (best == kNoKey) break;
         int cnt = 0;
         if (mine == best) {
-            for (int i = lane; i < n; i += 64)
-                if (keys[i] == best) {
+            // one pass: take out the copies of best, keep the smallest of the rest
+            uint64_t next = kNoKey;
+            for (int i = lane; i < n; i += 64) {
+                const uint64_t x = keys[i];
+                if (x == best) {
                     keys[i] = kNoKey;
                     ++cnt;
+                } else {
+                    next = x < next ? x : next;
                 }
-            mine = kNoKey;
-            for (int i = lane; i < n; i += 64) mine = keys[i] < mine ? keys[i] : mine;
+            }
+            mine = next;
         }
         cnt = wave_sum_i32(cnt);
         for (int c = 0; c < cnt && r < k; ++c, ++r)
@@ -170,13 +210,24 @@ __device__ __forceinline__ int wave_sort_compact_e(uint64_t *buf, int n, int k)
 }
 
 // Keep the k smallest of buf[0..n) (ascending) in buf[0..k) and return how
-// many are valid keys (< k when fewer survive).  One wavefront.
+// many are valid keys (< k when fewer survive).  One whole wavefront.
 __device__ __forceinline__ int wave_compact(uint64_t *buf, int n, int k, uint64_t *scratch)
 {
     if (n <= 64 && k <= 64) return wave_sort_compact_e<1>(buf, n, k);
     if (n <= 128 && k <= 128) return wave_sort_compact_e<2>(buf, n, k);
     if (n <= 256 && k <= 256) return wave_sort_compact_e<4>(buf, n, k);
     if (n <= 512 && k <= 512) return wave_sort_compact_e<8>(buf, n, k);
+    const int lane = threadIdx.x & 63;
+    const int got = wave_select_smallest(buf, n, k, scratch);
+    for (int i = lane; i < k; i += 64) buf[i] = i < got ? scratch[i] : kNoKey;
+    return got;
+}
+
+// wave_compact with sorts of at most 128 keys and the selection loop beyond:
+// little code and few registers, for kernels that compact short buffers.
+__device__ __forceinline__ int wave_compact_lean(uint64_t *buf, int n, int k, uint64_t *scratch)
+{
+    if (n <= 64 && k <= 64) return wave_sort_compact_e<1>(buf, n, k);
     const int lane = threadIdx.x & 63;
     const int got = wave_select_smallest(buf, n, k, scratch);
     for (int i = lane; i < k; i += 64) buf[i] = i < got ? scratch[i] : kNoKey;

@@ -608,7 +608,16 @@ int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int
     void *kern = shape >= 0 ? lookup(bits2, variant, shape) : nullptr;
     if (!kern) return LVQ_ERR_UNSUPPORTED;
     const int ntab = multi ? ix->n_means : 1;
-    const size_t lds = cand_lds_bytes(f.kpos, ntab, masked, l2 ? 0 : ix->n_means, k);
+    // top-k key buffer per wave: about 2k + one block of candidates (a block
+    // holds at most 32 per wave), at least 64 and at most 2048 entries,
+    // halved while the launch does not fit the workgroup's LDS
+    int cw = 64;
+    while (cw < 2 * k + 32 && cw < 2048) cw *= 2;
+    size_t lds = cand_lds_bytes(f.kpos, ntab, masked, l2 ? 0 : ix->n_means, k, cw);
+    while (lds > ix->lds_max && cw / 2 >= k + 32) {
+        cw /= 2;
+        lds = cand_lds_bytes(f.kpos, ntab, masked, l2 ? 0 : ix->n_means, k, cw);
+    }
     if (lds > ix->lds_max) return LVQ_ERR_UNSUPPORTED;
 
     int rc = order_after_updates(ix, s);
@@ -643,6 +652,7 @@ int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int
     a.epoch = epoch;
     a.err = P<uint32_t>(ix->err);
     a.neg_empty = neg_empty ? 1 : 0;
+    a.cw = cw;
     // persistent launch: lists longest-first from a device work counter
     a.order = P<int32_t>(w.order);
     a.queue = P<int32_t>(w.queue);

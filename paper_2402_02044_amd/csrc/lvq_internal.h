@@ -93,6 +93,7 @@ struct CandArgs {
     const int32_t *order;    // list processing order (NULL: identity)
     int32_t *queue;          // persistent work counter (NULL: one list per block)
     int neg_empty;           // a negative id is an empty entry, not an error
+    int cw;                  // top-k key buffer entries per wave (>= k + 32)
 };
 
 struct ScanArgs {
@@ -144,7 +145,7 @@ void *cand_kernel_b4(int bits2, int variant, int shape);
 void *cand_kernel_b8(int bits2, int variant, int shape);
 void *scan_kernel_b4(int bits2, int variant, int shape);
 void *scan_kernel_b8(int bits2, int variant, int shape);
-size_t cand_lds_bytes(int kpos, int ntab, bool mask, int n_means_ip, int k);
+size_t cand_lds_bytes(int kpos, int ntab, bool mask, int n_means_ip, int k, int cw);
 size_t scan_lds_bytes(int kpos, int n_means_ip, int k, int capq);
 int scan_capq(int kpos, int n_means_ip, int k, int rows_per_round, size_t lds_max);
 int scan_rows_per_round(int g);

@@ -198,6 +198,78 @@ def test_every_tile_shape(L, d, b1, b2, layout, metric, M):
     ix.close()
 
 
+def _exact_selection(metric, dist, ids, live, k):
+    """The k best live entries of one list, ranked by score then slot, with
+    repeated ids kept as separate entries: the selection the fused top-k makes
+    over the same call's own values (the ranking order of the C ABI)."""
+    d = np.asarray(dist, np.float32)
+    bits = (-d if metric == oracle.IP else d).view(np.uint32).astype(np.uint64)
+    hi = np.where(bits & 0x80000000, ~bits & 0xFFFFFFFF, bits | 0x80000000)
+    hi = np.where(np.isnan(d), 0xFFFFFFFF, hi)
+    m = live[ids]
+    order = np.lexsort((ids[m].astype(np.int64), hi[m]))[:k]
+    out_i = np.full(k, -1, np.int32)
+    out_d = np.full(k, np.inf if metric == oracle.L2 else -np.inf, np.float32)
+    out_i[:len(order)] = ids[m][order]
+    out_d[:len(order)] = d[m][order]
+    return out_i, out_d
+
+
+@pytest.mark.parametrize("d,b1,b2,layout,metric", [
+    (96, 8, 0, oracle.SEQUENTIAL, oracle.L2),
+    (256, 4, 8, oracle.TURBO, oracle.IP),
+])
+def test_candidate_topk_selection(L, d, b1, b2, layout, metric):
+    """Fused per-list top-k on long lists (many times one wave's key buffer),
+    lists with repeated ids, deleted entries, and k from 1 to the maximum
+    1024: the oracle's ranking within tolerance, and exactly the selection of
+    the k best over the values the same call returns."""
+    g = synth.rng(2200 + d, b1 + b2)
+    n = 5000
+    X = g.standard_normal((n, d)).astype(np.float32)
+    Q = g.standard_normal((7, d)).astype(np.float32)
+    if metric == oracle.IP:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+        Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    means = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    fmt = oracle.Format(d, b1, b2, layout)
+    rows, resid, _ = oracle.encode_rows(fmt, X, means)
+    lens = [4096, 3000, 1030, 0, 700, 2049, 5]
+    offs = np.zeros(8, np.int64)
+    offs[1:] = np.cumsum(lens)
+    parts = []
+    for i, L_ in enumerate(lens):
+        if i == 4:   # repeated ids: 350 slots listed twice
+            base = g.choice(n, 350, replace=False)
+            parts.append(g.permutation(np.concatenate([base, base])))
+        else:
+            parts.append(g.choice(n, L_, replace=False))
+    ids = np.concatenate(parts).astype(np.int32)
+    ix = L.Index(d, b1, b2, metric, layout, capacity=n, means=means)
+    ix.insert(torch.from_numpy(X).cuda())
+    dead = np.sort(g.choice(n, 800, replace=False)).astype(np.int32)
+    ix.delete(torch.from_numpy(dead).cuda())
+    assert ix.sync() == 0
+    live = np.ones(n, bool)
+    live[dead] = False
+    qd = torch.from_numpy(Q).cuda()
+    od, idd = torch.from_numpy(offs).cuda(), torch.from_numpy(ids).cuda()
+    for level in ([oracle.PRIMARY, oracle.FULL] if b2 else [oracle.PRIMARY]):
+        ref, tol = pair_reference(fmt, metric, level, Q, rows, resid, means, offs, ids)
+        for k in (1, 10, 100, 300, 1000, 1024):
+            dist, ti, td = ix.distances(qd, od, idd, level=level, k=k)
+            assert ix.sync() == 0
+            dist, ti, td = dist.cpu().numpy(), ti.cpu().numpy(), td.cpu().numpy()
+            check_values(dist, ref, tol)
+            for i in range(7):
+                a, b = offs[i], offs[i + 1]
+                check_topk(metric, ti[i], td[i], ids[a:b], ref[a:b], tol[a:b], k, live[ids[a:b]])
+                ei, ed = _exact_selection(metric, dist[a:b], ids[a:b], live, k)
+                np.testing.assert_array_equal(ti[i], ei, err_msg="list %d k %d ids" % (i, k))
+                np.testing.assert_array_equal(td[i], ed, err_msg="list %d k %d values" % (i, k))
+    ix.close()
+
+
 def test_duplicate_ids_and_bad_slots(L):
     d, n = 96, 500
     X = synth.small_vectors(11, n, d)
