@@ -381,8 +381,13 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
 
     const int npieces = a.kchunks * 16 / CH;
     const int ntab = (METRIC == LVQ_L2 && MULTI) ? a.n_means : 1;
+    // several means (L2): the means in kernel order stay in LDS for the whole
+    // launch when a.mu_lds is set, so a list's tables q - mu_m need no reads
+    // of the means from memory
+    const bool mu_lds = METRIC == LVQ_L2 && MULTI && a.mu_lds;
     float *qtab = reinterpret_cast<float *>(smem);
-    float *mtab = qtab + (size_t)ntab * a.kpos;                 // mask (L2, MASK)
+    float *mutab = qtab + (size_t)ntab * a.kpos;
+    float *mtab = mutab + (mu_lds ? (size_t)ntab * a.kpos : 0);   // mask (L2, MASK)
     float *cmt = mtab + (MASK ? a.kpos : 0);                   // c_m (IP)
     const int cm_n = METRIC == LVQ_IP ? a.n_means : 0;
     // fused top-k: one key buffer of a.cw entries per wave, then 4k entries
@@ -393,6 +398,11 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
     __shared__ int s_item;
     __shared__ int s_got[4];
 
+    if (mu_lds)
+        for (int i = tid; i < ntab * a.kpos; i += 256) {
+            const int t = i / a.kpos, sp = i - t * a.kpos;
+            mutab[(size_t)t * a.kpos + qtab_index<B1, CH>(sp, npieces)] = a.muk[i];
+        }
     for (int iter = 0;; ++iter) {
         int item;
         if (a.queue) {
@@ -414,14 +424,18 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a)
         // ---- per-list query tables in LDS
         __syncthreads();
         const float *qk = a.qk + list * a.kpos;
-        for (int t = 0; t < ntab; ++t)
-            for (int s = tid; s < a.kpos; s += 256) {
-                float v = qk[s];
-                if (METRIC == LVQ_L2) v -= a.muk[(int64_t)t * a.kpos + s];
-                qtab[(size_t)t * a.kpos + qtab_index<B1, CH>(s, npieces)] = v;
+        for (int sp = tid; sp < a.kpos; sp += 256) {
+            const float v = qk[sp];
+            const int j = qtab_index<B1, CH>(sp, npieces);
+            for (int t = 0; t < ntab; ++t) {
+                float w = v;
+                if (METRIC == LVQ_L2)
+                    w -= mu_lds ? mutab[(size_t)t * a.kpos + j] : a.muk[(int64_t)t * a.kpos + sp];
+                qtab[(size_t)t * a.kpos + j] = w;
             }
+        }
         if (MASK)
-            for (int s = tid; s < a.kpos; s += 256) mtab[qtab_index<B1, CH>(s, npieces)] = a.kmask[s];
+            for (int sp = tid; sp < a.kpos; sp += 256) mtab[qtab_index<B1, CH>(sp, npieces)] = a.kmask[sp];
         for (int m = tid; m < cm_n; m += 256) cmt[m] = a.cm[list * a.n_means + m];
         __syncthreads();
         const float qsum = METRIC == LVQ_IP ? a.qsum[list] : 0.0f;

@@ -619,6 +619,15 @@ int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int
         lds = cand_lds_bytes(f.kpos, ntab, masked, l2 ? 0 : ix->n_means, k, cw);
     }
     if (lds > ix->lds_max) return LVQ_ERR_UNSUPPORTED;
+    // several means: a second set of tables keeps the means in LDS if it fits
+    int mu_lds = 0;
+    if (multi) {
+        const size_t with = cand_lds_bytes(f.kpos, 2 * ntab, masked, 0, k, cw);
+        if (with <= ix->lds_max) {
+            mu_lds = 1;
+            lds = with;
+        }
+    }
 
     int rc = order_after_updates(ix, s);
     if (rc) return rc;
@@ -653,6 +662,7 @@ int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int
     a.err = P<uint32_t>(ix->err);
     a.neg_empty = neg_empty ? 1 : 0;
     a.cw = cw;
+    a.mu_lds = mu_lds;
     // persistent launch: lists longest-first from a device work counter
     a.order = P<int32_t>(w.order);
     a.queue = P<int32_t>(w.queue);

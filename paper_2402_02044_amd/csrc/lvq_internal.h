@@ -94,6 +94,7 @@ struct CandArgs {
     int32_t *queue;          // persistent work counter (NULL: one list per block)
     int neg_empty;           // a negative id is an empty entry, not an error
     int cw;                  // top-k key buffer entries per wave (>= k + 32)
+    int mu_lds;              // L2 with several means: keep muk in LDS for the launch
 };
 
 struct ScanArgs {
