@@ -169,7 +169,8 @@ int lvq_set_tile(lvq_index *index, int32_t level, int32_t topk, int32_t shape);
 /* Number of tile shapes (valid shape indices are 0 .. count - 1) and the
  * parameters of one: lanes per candidate, bytes per load, loads per lane and
  * round, pipeline flags (bit 0 software-pipelined, bit 1 query in
- * registers, bit 2 two blocks ahead).  Outputs may be NULL.               */
+ * registers, bit 2 two blocks ahead, bit 3 registers allotted for at least
+ * six waves per SIMD).  Outputs may be NULL.                              */
 int lvq_num_tile_shapes(void);
 int lvq_tile_shape(int32_t shape, int32_t *lanes, int32_t *piece_bytes, int32_t *pieces, int32_t *pipe);
 

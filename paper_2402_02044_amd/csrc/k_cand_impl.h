@@ -363,8 +363,10 @@ __device__ __forceinline__ float finish_pair(const Acc &A, float l2acc, float4 h
 
 // PIPE: 0 = no software pipeline; 1 or 2 = the loads of the candidates one
 // or two blocks ahead are in flight while the current block is consumed.
-template <int B1, int B2, int METRIC, bool MULTI, bool MASK, int G, int CH, int NCH, int PIPE, bool QREG>
-__global__ __launch_bounds__(256) void k_cand(CandArgs a)
+// WAVES: the fewest waves per SIMD the register allocation must allow (1: no
+// constraint); small tiles trade a few registers for more rows in flight.
+template <int B1, int B2, int METRIC, bool MULTI, bool MASK, int G, int CH, int NCH, int PIPE, bool QREG, int WAVES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8))) void k_cand(CandArgs a)
 {
     static_assert(!QREG || (PIPE && !MULTI && !MASK), "register-resident query needs one table, one round");
     static_assert(PIPE >= 0 && PIPE <= 2, "pipeline depth");

@@ -40,6 +40,9 @@ constexpr CandShape kCandShapes[] = {
     {2, 16, 3, 5},   // 96 bytes
     {8, 8, 6, 5},    // 384 bytes
     {16, 16, 2, 5},  // 512 bytes
+    // pipelined, registers allocated for at least six waves per SIMD
+    {4, 8, 3, 9},    // 96 bytes
+    {2, 16, 3, 9},   // 96 bytes
 };
 constexpr int kNumCandShapes = sizeof(kCandShapes) / sizeof(kCandShapes[0]);
 
@@ -47,23 +50,25 @@ using CandKernel = void (*)(CandArgs);
 
 // variant: 0 = IP, 1 = L2 one mean, 2 = L2 several means, 3 = L2 masked,
 //          4 = L2 masked several means
-// pipe bits: 1 = software-pipelined, 2 = query in registers, 4 = two blocks ahead
+// pipe bits: 1 = software-pipelined, 2 = query in registers, 4 = two blocks ahead,
+//            8 = registers for at least six waves per SIMD
 template <int B1, int B2, int S>
 constexpr CandKernel cand_kernel_for(int variant)
 {
     constexpr CandShape sh = kCandShapes[S];
     constexpr int depth = (sh.pipe & 1) ? ((sh.pipe & 4) ? 2 : 1) : 0;
+    constexpr int W = (sh.pipe & 8) ? 6 : 1;
     switch (variant) {
-    case 0: return k_cand<B1, B2, LVQ_IP, false, false, sh.g, sh.ch, sh.nch, depth, (sh.pipe & 2) != 0>;
-    case 1: return k_cand<B1, B2, LVQ_L2, false, false, sh.g, sh.ch, sh.nch, depth, (sh.pipe & 2) != 0>;
+    case 0: return k_cand<B1, B2, LVQ_IP, false, false, sh.g, sh.ch, sh.nch, depth, (sh.pipe & 2) != 0, W>;
+    case 1: return k_cand<B1, B2, LVQ_L2, false, false, sh.g, sh.ch, sh.nch, depth, (sh.pipe & 2) != 0, W>;
     case 2:
-        if constexpr ((sh.pipe & 2) == 0) return k_cand<B1, B2, LVQ_L2, true, false, sh.g, sh.ch, sh.nch, depth, false>;
+        if constexpr ((sh.pipe & 2) == 0) return k_cand<B1, B2, LVQ_L2, true, false, sh.g, sh.ch, sh.nch, depth, false, W>;
         return nullptr;
     default: break;
     }
     if constexpr (S == 0) {
-        if (variant == 3) return k_cand<B1, B2, LVQ_L2, false, true, sh.g, sh.ch, sh.nch, 0, false>;
-        if (variant == 4) return k_cand<B1, B2, LVQ_L2, true, true, sh.g, sh.ch, sh.nch, 0, false>;
+        if (variant == 3) return k_cand<B1, B2, LVQ_L2, false, true, sh.g, sh.ch, sh.nch, 0, false, 1>;
+        if (variant == 4) return k_cand<B1, B2, LVQ_L2, true, true, sh.g, sh.ch, sh.nch, 0, false, 1>;
     }
     return nullptr;
 }
@@ -100,6 +105,8 @@ inline CandKernel cand_lookup(int variant, int shape)
     case 25: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 25>(variant);
     case 26: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 26>(variant);
     case 27: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 27>(variant);
+    case 28: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 28>(variant);
+    case 29: return B2 == 4 ? nullptr : cand_kernel_for<B1, B2, 29>(variant);
     default: return nullptr;
     }
 }
