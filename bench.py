@@ -329,7 +329,11 @@ def bench_c3(args):
     ti = torch.empty((nq, 10), dtype=torch.int32, device=dev)
     td = torch.empty((nq, 10), dtype=torch.float32, device=dev)
     assert ix.sync() == 0
-    tile = ix.use_tuned_tile(L.LVQ_PRIMARY, 10, qd, od, idd, retune=args.retune)
+    if args.tile >= 0:
+        ix.set_tile(L.LVQ_PRIMARY, 1, args.tile)
+        tile = args.tile
+    else:
+        tile = ix.use_tuned_tile(L.LVQ_PRIMARY, 10, qd, od, idd, retune=args.retune)
     cs = torch.cuda.Stream()
     cs.wait_stream(torch.cuda.current_stream())
 
