@@ -15,9 +15,10 @@
 //                  c2 = clamp(floor((r + Delta/2) * (1/Delta2) + 1/2), 0, 2^B2 - 1)
 //
 // Launch shape: four waves per workgroup; a vector is handled by a group of G
-// lanes (G = 16 for d <= 256, else 64), staged through LDS so the packed words
-// are written with coalesced 32-bit stores.  Code positions map to dimensions
-// arithmetically (no table lookups on the packing path).
+// lanes (G in {8, 16, 32, 64}: the fewest that leave each lane at most four
+// packing units), staged through LDS so the packed words are written with
+// coalesced 32-bit stores.  Code positions map to dimensions arithmetically
+// (no table lookups on the packing path).
 #pragma clang fp contract(off)
 
 #include <float.h>
