@@ -136,6 +136,17 @@ __device__ __forceinline__ void pack_unit(const float *ts, const Format &f, int 
     }
 }
 
+// Floats between consecutive staged vectors in LDS: d rounded up to a
+// multiple of four (float4 staging), and an odd multiple of four so that the
+// vectors of one wave start in distinct bank groups (with d a multiple of 32,
+// a stride of d would send every group's read of dimension j to one bank).
+__host__ __device__ inline int stage_stride(int d)
+{
+    int s = (d + 3) & ~3;
+    if (((s >> 2) & 1) == 0) s += 4;
+    return s;
+}
+
 template <int B1, int B2, int G>
 __global__ __launch_bounds__(256) void k_encode(EncodeArgs a)
 {
@@ -147,7 +158,8 @@ __global__ __launch_bounds__(256) void k_encode(EncodeArgs a)
     const int d = a.f.dim;
     const int64_t i = (int64_t)blockIdx.x * V + grp;
     const bool active = i < a.n;
-    float *ts = lds + (size_t)grp * d;
+    const int stride = stage_stride(d);
+    float *ts = lds + (size_t)grp * stride;
 
     // stage x, check finiteness.  Rows of a multiple of four floats are read
     // as float4, four loads per lane issued before any is used.
@@ -182,7 +194,7 @@ __global__ __launch_bounds__(256) void k_encode(EncodeArgs a)
     // means for the nearest-mean search, staged in LDS as [dim][mean] when
     // they fit (conflict-free: the lanes of a group read consecutive means)
     const int M = a.n_means;
-    float *mt = lds + (size_t)V * d;
+    float *mt = lds + (size_t)V * stride;
     if (a.means_lds) {
         for (int e = threadIdx.x; e < M * d; e += 256) {
             const int j = e / M, m = e - j * M;
@@ -197,26 +209,42 @@ __global__ __launch_bounds__(256) void k_encode(EncodeArgs a)
     if (M > 1 && active && finite) {
         float best = 0.0f;
         int bm = -1;
-        for (int m = g; m < M; m += G) {
-            float s = 0.0f;
+        // two means per pass (m0 and m0 + G), each summed in dimension order
+        for (int m0 = g; m0 < M; m0 += 2 * G) {
+            const bool two = m0 + G < M;
+            const int m1 = two ? m0 + G : m0;
+            float s0 = 0.0f, s1 = 0.0f;
             if (a.means_lds) {
 #pragma unroll 8
                 for (int j = 0; j < d; ++j) {
-                    float e = ts[j] - mt[j * M + m];
-                    float e2 = e * e;
-                    s = s + e2;
+                    const float x = ts[j];
+                    float e0 = x - mt[j * M + m0];
+                    float e1 = x - mt[j * M + m1];
+                    e0 = e0 * e0;
+                    e1 = e1 * e1;
+                    s0 = s0 + e0;
+                    s1 = s1 + e1;
                 }
             } else {
 #pragma unroll 8
                 for (int j = 0; j < d; ++j) {
-                    float e = ts[j] - a.means_t[(int64_t)j * a.means_t_stride + m];
-                    float e2 = e * e;
-                    s = s + e2;
+                    const float x = ts[j];
+                    const float *mr = a.means_t + (int64_t)j * a.means_t_stride;
+                    float e0 = x - mr[m0];
+                    float e1 = x - mr[m1];
+                    e0 = e0 * e0;
+                    e1 = e1 * e1;
+                    s0 = s0 + e0;
+                    s1 = s1 + e1;
                 }
             }
-            if (bm < 0 || s < best) {
-                best = s;
-                bm = m;
+            if (bm < 0 || s0 < best) {
+                best = s0;
+                bm = m0;
+            }
+            if (two && s1 < best) {
+                best = s1;
+                bm = m1;
             }
         }
         // group argmin over (s, m): lexicographic
@@ -406,7 +434,7 @@ hipError_t launch_encode(const EncodeArgs &a, hipStream_t s)
     int G = 8;
     while (G < 64 && units > 4 * G) G *= 2;
     const int V = 256 / G;
-    size_t lds = (size_t)V * a.f.dim * sizeof(float);
+    size_t lds = (size_t)V * stage_stride(a.f.dim) * sizeof(float);
     if (a.means_lds) lds += (size_t)a.n_means * a.f.dim * sizeof(float);
     const int64_t blocks = (a.n + V - 1) / V;
     const int b1 = a.f.bits1, b2 = a.f.bits2;
