@@ -58,6 +58,9 @@ def _L():
         lib.orc_format_init.argtypes = [ctypes.POINTER(_Fmt), i32, i32, i32, i32, i32]
         lib.orc_pos_to_dim.argtypes = [ctypes.POINTER(_Fmt), i32]
         lib.orc_assign.argtypes = [P, i32, P, i32]
+        lib.orc_mean_dists.argtypes = [P, i32, P, i32, P]
+        lib.orc_mean_dists.restype = None
+        lib.orc_probe.argtypes = [P, i32, P, i32, i32, P]
         lib.orc_encode_codes.argtypes = [P, i32, P, i32, i32, P, P, P, P, P]
         lib.orc_encode_rows.argtypes = [ctypes.POINTER(_Fmt), P, i64, P, i32, P, P]
         lib.orc_encode_rows.restype = i64
@@ -121,6 +124,41 @@ def _f32(a):
 def assign(x, means) -> int:
     x, means = _f32(x), _f32(means)
     return _L().orc_assign(_p(x), x.shape[-1], _p(means), means.shape[0])
+
+
+def mean_dists(x, means) -> np.ndarray:
+    """Def. 1 distances of one vector to every mean (binary32, dimension order)."""
+    x, means = _f32(x), _f32(means)
+    out = np.zeros(means.shape[0], np.float32)
+    _L().orc_mean_dists(_p(x), x.shape[-1], _p(means), means.shape[0], _p(out))
+    return out
+
+
+def probe_means(Q, means, nprobe) -> np.ndarray:
+    """Soft inverted index routing (Sec. 3.2): for every query the nprobe
+    means nearest it by the Def. 1 distance, nearest first, ties to the lower
+    index, NaN distances last.  Returns nq x nprobe int32."""
+    Q, means = _f32(np.atleast_2d(Q)), _f32(means)
+    out = np.zeros((Q.shape[0], nprobe), np.int32)
+    for i in range(Q.shape[0]):
+        rc = _L().orc_probe(_p(Q[i]), Q.shape[1], _p(means), means.shape[0], nprobe, _p(out[i]))
+        if rc != 0:
+            raise ValueError("orc_probe: invalid nprobe %d for %d means" % (nprobe, means.shape[0]))
+    return out
+
+
+def probe_lists(probe, row_mean, live=None):
+    """Candidate lists of the soft inverted index: for every query, the slots
+    whose row is assigned to one of its probed means (and live, if given), in
+    ascending slot order.  row_mean: the mean id of every slot (header byte
+    12).  Returns (offsets, ids) in the layout of lvq_distances."""
+    row_mean = np.asarray(row_mean)
+    ok = np.ones(row_mean.shape[0], bool) if live is None else np.asarray(live, bool)
+    lists = [np.flatnonzero(np.isin(row_mean, p) & ok).astype(np.int32) for p in np.asarray(probe)]
+    offsets = np.zeros(len(lists) + 1, np.int64)
+    offsets[1:] = np.cumsum([len(x) for x in lists])
+    ids = np.concatenate(lists) if lists and offsets[-1] else np.zeros(0, np.int32)
+    return offsets, ids
 
 
 def encode_codes(x, mean, bits1, bits2=0):

@@ -117,6 +117,59 @@ int orc_assign(const float *x, int d, const float *means, int n_means)
     return best;
 }
 
+/* Def. 1 distance of x to every mean, s_m = sum_j (x_j - mu_mj)^2, each a
+ * sequential binary32 sum in dimension order (the values orc_assign ranks). */
+void orc_mean_dists(const float *x, int d, const float *means, int n_means, float *s_out)
+{
+    for (int m = 0; m < n_means; ++m) {
+        float s = 0.0f;
+        for (int j = 0; j < d; ++j) {
+            float e = x[j] - means[(int64_t)m * d + j];
+            float sq = e * e;
+            s = s + sq;
+        }
+        s_out[m] = s;
+    }
+}
+
+/* Probe order of the soft inverted index: mean a comes before mean b when its
+ * distance is smaller, or equal with the lower index; NaN distances last. */
+static int probe_before(float sa, int ma, float sb, int mb)
+{
+    if (isnan(sa) != isnan(sb)) return isnan(sb);
+    if (!isnan(sa) && sa != sb) return sa < sb;
+    return ma < mb;
+}
+
+/* M-LVQ as a soft inverted index (the Sec. 3.2 remark that a query touches
+ * only a few centres): the nprobe means nearest x by the Def. 1 distance,
+ * nearest first.  Plain selection: nprobe passes, each taking the first
+ * remaining mean in probe order.                                            */
+int orc_probe(const float *x, int d, const float *means, int n_means, int nprobe, int32_t *out)
+{
+    if (nprobe < 1 || nprobe > n_means) return ORC_EINVAL;
+    float *s = (float *)malloc(sizeof(float) * (size_t)n_means);
+    char *taken = (char *)calloc((size_t)n_means, 1);
+    if (!s || !taken) {
+        free(s);
+        free(taken);
+        return ORC_EINVAL;
+    }
+    orc_mean_dists(x, d, means, n_means, s);
+    for (int r = 0; r < nprobe; ++r) {
+        int best = -1;
+        for (int m = 0; m < n_means; ++m) {
+            if (taken[m]) continue;
+            if (best < 0 || probe_before(s[m], m, s[best], best)) best = m;
+        }
+        taken[best] = 1;
+        out[r] = best;
+    }
+    free(s);
+    free(taken);
+    return ORC_OK;
+}
+
 /* Eq. 2 applied at one component: floor((t - lo) * inv + 1/2), clamped. */
 static unsigned quantize_one(float t, float lo, float inv, unsigned top)
 {

@@ -52,6 +52,12 @@ int orc_pos_to_dim(const orc_format *f, int p);
 /* Index of the nearest mean by squared Euclidean distance (Def. 1). */
 int orc_assign(const float *x, int d, const float *means, int n_means);
 
+/* Def. 1 distances of x to every mean (sequential binary32 sums in dimension
+ * order), and the soft-inverted-index routing: the nprobe means nearest x,
+ * nearest first, ties to the lower index, NaN distances last (Sec. 3.2). */
+void orc_mean_dists(const float *x, int d, const float *means, int n_means, float *s_out);
+int orc_probe(const float *x, int d, const float *means, int n_means, int nprobe, int32_t *out);
+
 /* First and second level codes of one vector against one mean
  * (Eq. 1, Eq. 2, Eq. 3 and the residual level of Sec. 2.3 / Def. 1).
  * c2 may be NULL when bits2 == 0.  Returns ORC_OK or ORC_NONFINITE.           */

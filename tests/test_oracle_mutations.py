@@ -8,7 +8,7 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-PINS = ["tests/test_oracle_encode.py", "tests/test_oracle_distance.py"]
+PINS = ["tests/test_oracle_encode.py", "tests/test_oracle_distance.py", "tests/test_oracle_probe.py"]
 
 MUTATIONS = {
     "round_half_even": ("float c = b + 0.5f;\n    float v = floorf(c);",
@@ -26,6 +26,9 @@ MUTATIONS = {
     "nibble_order": ("return (codes[p / 2] >> (4 * (p % 2))) & 0xFu;",
                      "return (codes[p / 2] >> (4 * (1 - p % 2))) & 0xFu;"),
     "step_off_by_one": ("delta = (u - l) / (float)top1;", "delta = (u - l) / (float)(top1 + 1u);"),
+    "probe_ties_to_higher_mean": ("return ma < mb;", "return ma > mb;"),
+    "probe_nan_first": ("if (isnan(sa) != isnan(sb)) return isnan(sb);", "if (isnan(sa) != isnan(sb)) return isnan(sa);"),
+    "probe_distance_unsquared": ("float sq = e * e;", "float sq = fabsf(e);"),
 }
 
 
