@@ -185,6 +185,23 @@ int lvq_tile_shape(int32_t shape, int32_t *lanes, int32_t *piece_bytes, int32_t 
 int lvq_topk(lvq_index *index, const void *q_dev, int32_t prec, int64_t nq, int32_t k,
              int32_t level, int32_t *ids_dev, float *dist_dev, void *stream);
 
+/* M-LVQ as a soft inverted index (the Sec. 3.2 remark that a query touches
+ * only a few centres).  For each of nq float queries q_dev (nq x dim): the
+ * nprobe means nearest the query by the Def. 1 distance (squared Euclidean,
+ * binary32, summed in dimension order, ties to the lower mean id, NaN last:
+ * the rule that assigns rows to means), and the best k rows at `level` among
+ * the rows assigned to those means and live at the call (lvq_distances'
+ * similarities and ranking).  1 <= nprobe <= number of means, 1 <= k <= 1024.
+ * probe_out_dev (nq x nprobe int32, may be NULL) receives the probed mean
+ * ids, nearest first; ids_dev / dist_dev (nq x k) are padded as for
+ * lvq_distances.  The per-mean member lists are kept per stream and rebuilt
+ * by the first call after a store update (one pass over the occupied slots).
+ * The call synchronises `stream` once, after routing, to size the candidate
+ * lists, so it cannot be captured into a HIP graph (LVQ_ERR_UNSUPPORTED).   */
+int lvq_probe_topk(lvq_index *index, const float *q_dev, int64_t nq, int32_t nprobe, int32_t k,
+                   int32_t level, int32_t *probe_out_dev, int32_t *ids_dev, float *dist_dev,
+                   void *stream);
+
 /* Copy stored rows of n slots (slots_dev int32) into rows_dev / resid_dev. */
 int lvq_read_rows(lvq_index *index, const int32_t *slots_dev, int64_t n, uint8_t *rows_dev,
                   uint8_t *resid_dev, void *stream);

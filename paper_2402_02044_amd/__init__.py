@@ -36,7 +36,7 @@ LVQ_ERR_NONFINITE = -6
 LVQ_ERR_BAD_SLOT = -7
 
 EXPORTS = ["lvq_row_format", "lvq_create", "lvq_destroy", "lvq_set_means", "lvq_encode", "lvq_insert",
-           "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_topk", "lvq_read_rows",
+           "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_topk", "lvq_probe_topk", "lvq_read_rows",
            "lvq_get_stats", "lvq_sync", "lvq_mean", "lvq_kmeans", "lvq_strerror", "lvq_set_timing",
            "lvq_kernel_time", "lvq_autotune", "lvq_set_tile", "lvq_server_create", "lvq_server_submit",
            "lvq_server_wait", "lvq_server_drain", "lvq_server_get_stats", "lvq_server_destroy",
@@ -99,6 +99,7 @@ def _load():
         "lvq_consolidate": [P, P, P],
         "lvq_distances": [P, P, i64, P, P, i64, i32, P, i32, P, P, P],
         "lvq_topk": [P, P, i32, i64, i32, i32, P, P, P],
+        "lvq_probe_topk": [P, P, i64, i32, i32, i32, P, P, P, P],
         "lvq_read_rows": [P, P, i64, P, P, P],
         "lvq_get_stats": [P, ctypes.POINTER(lvq_stats)],
         "lvq_sync": [P, P],
@@ -188,6 +189,10 @@ def lvq_distances(ix, q, nq, offsets, ids, total, level, dist, k, topk_ids, topk
 
 def lvq_topk(ix, q, prec, nq, k, level, ids, dist, stream=0):
     return _chk(_lib.lvq_topk(ix, q, prec, nq, k, level, ids, dist, stream), "lvq_topk")
+
+
+def lvq_probe_topk(ix, q, nq, nprobe, k, level, probe, ids, dist, stream=0):
+    return _chk(_lib.lvq_probe_topk(ix, q, nq, nprobe, k, level, probe, ids, dist, stream), "lvq_probe_topk")
 
 
 def lvq_read_rows(ix, slots, n, rows, resid, stream=0):
@@ -365,6 +370,17 @@ class Index:
         dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
         lvq_topk(self.handle, _ptr(q), prec, nq, k, level, _ptr(ids), _ptr(dist), _stream(stream))
         return ids, dist
+
+    def probe_topk(self, q, nprobe, k, level=LVQ_PRIMARY, stream=None):
+        """Soft inverted index: (probed means nq x nprobe, ids nq x k, values nq x k)."""
+        import torch
+        nq = q.shape[0]
+        probe = torch.empty((nq, nprobe), dtype=torch.int32, device=q.device)
+        ids = torch.empty((nq, k), dtype=torch.int32, device=q.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+        lvq_probe_topk(self.handle, _ptr(q), nq, nprobe, k, level, _ptr(probe), _ptr(ids), _ptr(dist),
+                       _stream(stream))
+        return probe, ids, dist
 
     def read_rows(self, slots, stream=None):
         import torch

@@ -172,6 +172,7 @@ int order_after_updates(lvq_index *ix, hipStream_t s)
 
 int note_update(lvq_index *ix, hipStream_t s)
 {
+    ix->version += 1;
     LVQ_HIP(hipEventRecord(ix->update_ev, s));
     ix->update_stream = s;
     ix->have_update = true;
@@ -386,7 +387,9 @@ int lvq_destroy(lvq_index *ix)
     (void)hipDeviceSynchronize();
     for (auto &kv : ix->ws) {
         Workspace &w = kv.second;
-        for (DevBuf *b : {&w.qk, &w.qsum, &w.cm, &w.order, &w.queue, &w.part, &w.q16, &w.gthr}) dev_free(ix, *b);
+        for (DevBuf *b : {&w.qk, &w.qsum, &w.cm, &w.order, &w.queue, &w.part, &w.q16, &w.gthr, &w.members, &w.moffs,
+                          &w.mcount, &w.mcursor, &w.probe, &w.qoffs, &w.qids})
+            dev_free(ix, *b);
     }
     for (DevBuf *b : {&ix->means, &ix->means_t, &ix->muk, &ix->kmask, &ix->kdim, &ix->rows,
                       &ix->resid, &ix->stack, &ix->err, &ix->scratch})
@@ -965,6 +968,70 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     LVQ_HIP(launch_topk_merge(a.part_keys, nq, (int)parts, k, LVQ_IP, ids_dev, dist_dev, s));
     return LVQ_OK;
 }
+
+// Soft inverted index: route, build the probed means' candidate lists, and
+// run the candidate kernel's fused top-k over them.
+static int probe_topk(lvq_index *ix, const float *q_dev, int64_t nq, int32_t nprobe, int32_t k, int32_t level,
+                      int32_t *probe_out_dev, int32_t *ids_dev, float *dist_dev, hipStream_t s)
+{
+    if (nq < 0 || nq > INT32_MAX || k < 1 || k > kMaxTopK) return LVQ_ERR_INVALID_ARG;
+    if (level != LVQ_PRIMARY && level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
+    if (level == LVQ_FULL && ix->f.bits2 == 0) return LVQ_ERR_INVALID_ARG;
+    const int M = ix->n_means;
+    if (nprobe < 1 || nprobe > M) return LVQ_ERR_INVALID_ARG;
+    if (ix->capturing) return LVQ_ERR_UNSUPPORTED;   // sizes the lists on the host
+    if (nq == 0) return LVQ_OK;
+    if (!q_dev || !ids_dev || !dist_dev || ix->cfg.capacity == 0) return LVQ_ERR_INVALID_ARG;
+    int rc = order_after_updates(ix, s);
+    if (rc) return rc;
+    Workspace &w = workspace(ix, s);
+    if (w.members_version != ix->version) {
+        const int64_t n = ix->list_len;
+        if ((rc = dev_alloc(ix, w.members, sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1)))) return rc;
+        if ((rc = dev_alloc(ix, w.moffs, sizeof(int64_t) * (size_t)(M + 1)))) return rc;
+        if ((rc = dev_alloc(ix, w.mcount, sizeof(uint64_t) * (size_t)M))) return rc;
+        if ((rc = dev_alloc(ix, w.mcursor, sizeof(uint64_t) * (size_t)M))) return rc;
+        if (n > 0) LVQ_HIP(launch_fill_i32(P<int32_t>(w.members), -1, n, s));
+        LVQ_HIP(launch_members(P<int32_t>(ix->lists[ix->list_active].buf), n, P<uint8_t>(ix->rows), ix->f.row_bytes,
+                               M, P<unsigned long long>(w.mcount), P<unsigned long long>(w.mcursor),
+                               P<int64_t>(w.moffs), P<int32_t>(w.members), s));
+        w.members_version = ix->version;
+    }
+    int32_t *probe = probe_out_dev;
+    if (!probe) {
+        if ((rc = dev_alloc(ix, w.probe, sizeof(int32_t) * (size_t)nq * nprobe))) return rc;
+        probe = P<int32_t>(w.probe);
+    }
+    if ((rc = dev_alloc(ix, w.qoffs, sizeof(int64_t) * (size_t)(nq + 1)))) return rc;
+    LVQ_HIP(launch_route(q_dev, nq, ix->f.dim, P<float>(ix->means_t), kMaxMeans, M, nprobe, probe, s));
+    LVQ_HIP(launch_probe_offsets(probe, nq, nprobe, P<int64_t>(w.moffs), P<int64_t>(w.qoffs), s));
+    int64_t total = 0;
+    LVQ_HIP(hipMemcpyAsync(&total, P<int64_t>(w.qoffs) + nq, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LVQ_HIP(hipStreamSynchronize(s));
+    if ((rc = dev_alloc(ix, w.qids, sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1)))) return rc;
+    LVQ_HIP(launch_probe_gather(probe, nq, nprobe, P<int64_t>(w.moffs), P<int32_t>(w.members), P<int64_t>(w.qoffs),
+                                P<int32_t>(w.qids), s));
+    return host_distances(ix, q_dev, nq, P<int64_t>(w.qoffs), P<int32_t>(w.qids), total, level, nullptr, k, ids_dev,
+                          dist_dev, s, -1, ix->epoch, true);
+}
+
+extern "C" {
+
+int lvq_probe_topk(lvq_index *ix, const float *q_dev, int64_t nq, int32_t nprobe, int32_t k, int32_t level,
+                   int32_t *probe_out_dev, int32_t *ids_dev, float *dist_dev, void *stream)
+{
+    if (!ix) return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = begin_call(ix, s);
+    if (rc) return rc;
+    rc = probe_topk(ix, q_dev, nq, nprobe, k, level, probe_out_dev, ids_dev, dist_dev, s);
+    if (rc == LVQ_OK && nq > 0) rc = note_query(ix, s, ix->epoch);
+    ix->capturing = false;
+    return rc;
+}
+
+}  // extern "C"
 
 int lvq::host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_first, int32_t prec,
                       int32_t scan_level, int32_t k_rerank, int32_t rerank_level)

@@ -23,6 +23,10 @@ struct DevBuf {
 // Per-stream scratch of the query entry points.
 struct Workspace {
     DevBuf qk, qsum, cm, order, queue, part, q16, gthr;
+    // soft inverted index: this stream's per-mean member lists (built at
+    // store version members_version) and per-call routing / candidate lists
+    DevBuf members, moffs, mcount, mcursor, probe, qoffs, qids;
+    uint64_t members_version = ~0ull;
 };
 
 // A query launch that may still be reading the store, the epoch it reads,
@@ -59,6 +63,7 @@ struct lvq_index {
     int list_active = -1;
     int64_t list_len = 0;   // entries of the active list
     uint64_t query_seq = 0; // launches recorded as in flight so far
+    uint64_t version = 0;   // store updates so far (any insert, delete, consolidation, means change)
     int64_t device_bytes = 0;
     std::map<hipStream_t, lvq::Workspace> ws;
     std::deque<lvq::InFlight> inflight;

@@ -151,6 +151,19 @@ size_t scan_lds_bytes(int kpos, int n_means_ip, int k, int capq);
 int scan_capq(int kpos, int n_means_ip, int k, int rows_per_round, size_t lds_max);
 int scan_rows_per_round(int g);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+// Soft inverted index (k_probe.hip): per-mean member lists of `list`
+// (counts, cursor: n_means entries; offsets: n_means + 1; members: n entries,
+// filled beforehand with -1), routing of queries to their nprobe nearest
+// means, and the candidate lists of the probed means (qoffs: nq + 1).
+hipError_t launch_members(const int32_t *list, int64_t n, const uint8_t *rows, int row_bytes, int n_means,
+                          unsigned long long *counts, unsigned long long *cursor, int64_t *offsets,
+                          int32_t *members, hipStream_t s);
+hipError_t launch_route(const float *q, int64_t nq, int dim, const float *means_t, int means_stride, int n_means,
+                        int nprobe, int32_t *probe, hipStream_t s);
+hipError_t launch_probe_offsets(const int32_t *probe, int64_t nq, int nprobe, const int64_t *moffs, int64_t *qoffs,
+                                hipStream_t s);
+hipError_t launch_probe_gather(const int32_t *probe, int64_t nq, int nprobe, const int64_t *moffs,
+                               const int32_t *members, const int64_t *qoffs, int32_t *qids, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_list_order(const int64_t *offsets, int64_t nq, int32_t *order, int32_t *scratch,
                              hipStream_t s);

@@ -1,0 +1,118 @@
+"""Soft inverted index (lvq_probe_topk of the C ABI) against the oracle.
+
+* The probed means equal the oracle's exactly: an integer decision both sides
+  take from the same binary32 arithmetic (Def. 1 distance, dimension order,
+  ties to the lower id).
+* The top-k is the oracle's over exactly the members of the probed means that
+  are live (values within the similarity tolerance, ranking as check_topk).
+* After inserts, deletes and a consolidation the member lists follow the
+  store (they are rebuilt by the first call after an update).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from lvq_check import check_topk, pair_reference
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2402_02044_amd as lib
+    return lib
+
+
+CASES = [
+    # d, b1, b2, layout, metric, M
+    (96, 8, 0, oracle.SEQUENTIAL, oracle.L2, 16),
+    (256, 4, 8, oracle.TURBO, oracle.IP, 12),
+    (130, 4, 8, oracle.TURBO, oracle.L2, 5),
+    (64, 8, 4, oracle.SEQUENTIAL, oracle.IP, 70),
+    (48, 8, 0, oracle.SEQUENTIAL, oracle.L2, 200),
+]
+
+
+def _check(L, ix, fmt, metric, Xs, live, means, Q, nprobe, k, level):
+    qd = torch.from_numpy(Q).cuda()
+    probe, ti, td = ix.probe_topk(qd, nprobe, k, level=level)
+    assert ix.sync() == 0
+    probe, ti, td = probe.cpu().numpy(), ti.cpu().numpy(), td.cpu().numpy()
+    want = oracle.probe_means(Q, means, nprobe)
+    np.testing.assert_array_equal(probe, want, err_msg="probed means (nprobe %d)" % nprobe)
+    rows, resid, _ = oracle.encode_rows(fmt, Xs, means)
+    offs, ids = oracle.probe_lists(want, rows[:, 12], live)
+    ref, tol = pair_reference(fmt, metric, level, Q, rows, resid, means, offs, ids)
+    for i in range(Q.shape[0]):
+        a, b = offs[i], offs[i + 1]
+        check_topk(metric, ti[i], td[i], ids[a:b], ref[a:b], tol[a:b], k)
+
+
+@pytest.mark.parametrize("d,b1,b2,layout,metric,M", CASES)
+def test_probe_topk_matches_oracle(L, d, b1, b2, layout, metric, M):
+    g = synth.rng(8200 + d, M)
+    n, cap = 3000, 4200
+    cent = g.standard_normal((M, d)).astype(np.float32)
+
+    def draw(count, shift=0.0):
+        x = cent[g.integers(0, M, count)] + shift + 0.35 * g.standard_normal((count, d)).astype(np.float32)
+        if metric == oracle.IP:
+            x /= np.linalg.norm(x, axis=1, keepdims=True)
+        return x.astype(np.float32)
+
+    means = cent.copy()
+    if metric == oracle.IP:
+        means /= np.linalg.norm(means, axis=1, keepdims=True)
+    fmt = oracle.Format(d, b1, b2, layout)
+    ix = L.Index(d, b1, b2, metric, layout, capacity=cap, means=means)
+    Xs = np.zeros((cap, d), np.float32)
+    live = np.zeros(cap, bool)
+
+    def insert(X):
+        slots = ix.insert(torch.from_numpy(X).cuda()).cpu().numpy()
+        Xs[slots] = X
+        live[slots] = True
+
+    insert(draw(n))
+    dead = np.sort(g.choice(np.flatnonzero(live), 400, replace=False)).astype(np.int32)
+    ix.delete(torch.from_numpy(dead).cuda())
+    live[dead] = False
+    assert ix.sync() == 0
+    Q = draw(37)                     # not a multiple of the four queries per workgroup
+    levels = [oracle.PRIMARY, oracle.FULL] if b2 else [oracle.PRIMARY]
+    for level in levels:
+        for nprobe, k in ((1, 10), (3, 100), (M, 10), (min(2, M), 1)):
+            _check(L, ix, fmt, metric, Xs, live, means, Q, nprobe, k, level)
+    # the store changes: member lists are rebuilt
+    more = np.sort(g.choice(np.flatnonzero(live), 300, replace=False)).astype(np.int32)
+    ix.delete(torch.from_numpy(more).cuda())
+    live[more] = False
+    ix.consolidate()
+    insert(draw(700, 0.05))
+    assert ix.sync() == 0
+    Xs[~live] = 0.0
+    for level in levels:
+        _check(L, ix, fmt, metric, Xs, live, means, Q, min(3, M), 10, level)
+    ix.close()
+
+
+def test_probe_topk_rejects_bad_arguments(L):
+    g = synth.rng(8300, 0)
+    means = g.standard_normal((4, 32)).astype(np.float32)
+    ix = L.Index(32, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=100, means=means)
+    ix.insert(torch.from_numpy(g.standard_normal((50, 32)).astype(np.float32)).cuda())
+    q = torch.from_numpy(g.standard_normal((3, 32)).astype(np.float32)).cuda()
+    for nprobe, k, level in ((0, 5, L.LVQ_PRIMARY), (5, 5, L.LVQ_PRIMARY), (2, 0, L.LVQ_PRIMARY),
+                             (2, 2000, L.LVQ_PRIMARY), (2, 5, L.LVQ_FULL)):
+        with pytest.raises(L.LVQError) as e:
+            ix.probe_topk(q, nprobe, k, level=level)
+        assert e.value.code == L.LVQ_ERR_INVALID_ARG
+    # an empty batch is a no-op
+    probe, ids, dist = ix.probe_topk(q[:0], 2, 5)
+    assert probe.shape == (0, 2)
+    assert ix.sync() == 0
+    ix.close()
