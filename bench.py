@@ -82,6 +82,40 @@ def line(value, unit, steps, warmup, ms_step, dtype, config, roofline, higher=Tr
     return out
 
 
+def exact_topk(metric, Q, X, k, live=None, chunk=1 << 20):
+    """Exact top-k over the float vectors (the ground truth of the k-recall@k
+    measure, Sec. 2.1): binary64 products on the GPU, chunk by chunk.  Returns
+    nq x k slot indices, best first."""
+    import torch
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(np.asarray(Q, np.float64)).to(dev)
+    qq = (q * q).sum(1, keepdim=True)
+    slots = np.arange(X.shape[0]) if live is None else np.flatnonzero(live)
+    bv = bi = None
+    for a in range(0, slots.shape[0], chunk):
+        sl = slots[a:a + chunk]
+        x = torch.from_numpy(np.asarray(X[sl], np.float64)).to(dev)
+        ip = q @ x.T
+        v = -ip if metric == 1 else qq - 2.0 * ip + (x * x).sum(1)[None, :]
+        v, i = torch.topk(v, min(k, v.shape[1]), dim=1, largest=False)
+        i = torch.from_numpy(sl).to(dev)[i]
+        if bv is not None:
+            v = torch.cat([bv, v], 1)
+            i = torch.cat([bi, i], 1)
+            v, o = torch.topk(v, k, dim=1, largest=False)
+            i = torch.gather(i, 1, o)
+        bv, bi = v, i
+    return bi.cpu().numpy()
+
+
+def recall_at_k(found, truth) -> float:
+    """k-recall@k: |returned ∩ true top-k| / k, averaged over queries."""
+    found, truth = np.asarray(found), np.asarray(truth)
+    k = truth.shape[1]
+    return sum(len(set(found[i].tolist()) & set(truth[i].tolist())) for i in range(truth.shape[0])) / float(
+        k * truth.shape[0])
+
+
 def timed(step, steps, warmup, ix):
     """Wall time per step (synchronised on both sides) and the average kernel
     time of the main similarity kernel (HIP events on its stream)."""
@@ -217,7 +251,6 @@ def cpu_baseline_lists(fmt, metric, level, X, Q, means, offs, ids, budget_s=12.0
 def bench_c2(args):
     import torch
 
-    import oracle
     import paper_2402_02044_amd as L
     n, nq, per = args.n or 1_000_000, args.nq or 10_000, 1000
     X, Q, mu, offs, ids = c2_inputs(n, nq, per)
@@ -264,6 +297,7 @@ def bench_c2(args):
                 "algorithmic_bytes_per_pair": per_pair},
                encode=encode_roofline(warm_encode_ms(ix, X, dev), n, 768, ix.row_bytes, ix.resid_bytes, enc_ms))
     if not args.no_cpu_baseline:
+        import oracle
         log("timing the oracle on a host-core sample")
         fmt = oracle.Format(768, 4, 8, oracle.TURBO)
         out["cpu_baseline"] = cpu_baseline_lists(fmt, oracle.IP, level, X, Q, mu, offs, ids)
@@ -278,7 +312,6 @@ def bench_c2(args):
 def bench_c1(args):
     import torch
 
-    import oracle
     import paper_2402_02044_amd as L
     import synth
     n, nq, d = 10_000, 100, 96
@@ -301,24 +334,28 @@ def bench_c1(args):
 
     ms_step, k_ms = timed(step, args.steps * 10, args.warmup, ix)
     assert ix.sync() == 0
-    gt = oracle.float_groundtruth(oracle.L2, Q, X, 10)
-    rec = oracle.recall(ids.cpu().numpy(), gt)
+    rec = recall_at_k(ids.cpu().numpy(), exact_topk(0, Q, X, 10))
     flops = 3.0 * d * n * nq          # subtract, multiply, add per (pair, dim)
     achieved = flops / (k_ms / 1000.0) / 1e12
-    fmt = oracle.Format(d, 8, 0)
-    orows, _, _ = oracle.encode_rows(fmt, X, mu)
-    t = time.perf_counter()
-    oracle.topk_exhaustive(fmt, oracle.L2, oracle.PRIMARY, Q, orows, None, mu, 10)
-    ct = time.perf_counter() - t
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        fmt = oracle.Format(d, 8, 0)
+        orows, _, _ = oracle.encode_rows(fmt, X, mu)
+        t = time.perf_counter()
+        oracle.topk_exhaustive(fmt, oracle.L2, oracle.PRIMARY, Q, orows, None, mu, 10)
+        ct = time.perf_counter() - t
+        cpu = {"value": n * nq / ct, "unit": "distances/s", "cores": 1, "kind": "oracle",
+               "sample": "all 100 queries x 10,000 rows, binary64 scalar C, %.2f s" % ct}
     out = line(n * nq / (ms_step / 1000.0), "distances/s", args.steps * 10, args.warmup, ms_step, "f32",
                {"workload": "LVQ-8 encode of 10,000 x 96 vectors (32 Gaussian clusters) + exhaustive L2 top-10 "
                             "of 100 queries", "n": n, "dim": d, "queries": nq, "k": 10},
                {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None, "kernel": "k_scan (FP32 exhaustive top-k)",
                 "kernel_ms": k_ms, "note": "store of 1.28 MB is cache resident: latency-bound, not a roofline claim"},
-               recall_at_10=rec,
-               cpu_baseline={"value": n * nq / ct, "unit": "distances/s", "cores": 1, "kind": "oracle",
-                             "sample": "all 100 queries x 10,000 rows, binary64 scalar C, %.2f s" % ct})
+               recall_at_10=rec)
+    if cpu:
+        out["cpu_baseline"] = cpu
     ix.close()
     return out
 
@@ -331,7 +368,6 @@ def bench_c1(args):
 def bench_c3(args):
     import torch
 
-    import oracle
     import paper_2402_02044_amd as L
     import synth
     n, nq, d, M = args.n or 10_000_000, args.nq or 10_000, 96, 16
@@ -378,7 +414,6 @@ def bench_c3(args):
     per_pair = 96 + 8 + 1 + 4 + 4
     achieved = per_pair * pairs / (k_ms / 1000.0) / 1e9
     log("eager step %.3f ms, graph step %.3f ms, kernel %.3f ms" % (ms_eager, ms_graph, k_ms))
-    fmt = oracle.Format(d, 8, 0)
     out = line(pairs / (ms_graph / 1000.0), "distances/s", args.steps, args.warmup, ms_graph, "f32",
                {"workload": "multi-means LVQ-8 L2, n=10,000,000, d=96 (256 clusters), 16 means (k-means on a "
                             "100k sample), 10,000 queries with log-uniform 64..4096 candidate lists, top-10, one "
@@ -391,6 +426,8 @@ def bench_c3(args):
                ms_per_step_eager=ms_eager)
     out["encode"] = encode_roofline(warm_encode_ms(ix, X, dev), n, d, ix.row_bytes, ix.resid_bytes, enc_ms)
     if not args.no_cpu_baseline:
+        import oracle
+        fmt = oracle.Format(d, 8, 0)
         out["cpu_baseline"] = cpu_baseline_lists(fmt, oracle.L2, oracle.PRIMARY, X, Q, means, offs, ids)
     ix.close()
     return out
@@ -403,7 +440,6 @@ def bench_c3(args):
 def bench_c4(args):
     import torch
 
-    import oracle
     import paper_2402_02044_amd as L
     import synth
     n, nq, d, k = args.n or 5_000_000, args.nq or 10_000, 512, 100
@@ -432,36 +468,37 @@ def bench_c4(args):
         assert ix.sync() == 0
         res[name] = (ms, k_ms, ids.cpu().numpy(), dist.cpu().numpy())
         log("%s: step %.2f ms, kernel %.2f ms" % (name, ms, k_ms))
-    # accuracy on a query sample: error of returned values against the binary64
-    # oracle with the float32 queries, recall@100 against float ground truth
+    # recall@100 of every form on a query sample against the exact float top-100
     ns = 20
     Qd = Q[:ns]
-    best = None
-    for a in range(0, n, 1 << 20):
-        sc = Qd @ X[a:a + (1 << 20)].T
-        idx = np.argsort(-sc, axis=1)[:, :k] + a
-        val = np.take_along_axis(sc, idx - a, 1)
-        if best is None:
-            best = (val, idx)
-        else:
-            v = np.concatenate([best[0], val], 1)
-            i = np.concatenate([best[1], idx], 1)
-            o = np.argsort(-v, axis=1)[:, :k]
-            best = (np.take_along_axis(v, o, 1), np.take_along_axis(i, o, 1))
-    gt = best[1]
-    fmt = oracle.Format(d, 8, 0)
+    gt = exact_topk(1, Qd, X, k)
     acc = {}
     for name, (ms, k_ms, ids, dist) in res.items():
-        rec = oracle.recall(ids[:ns], gt)
-        uniq, inv = np.unique(ids[:ns].ravel(), return_inverse=True)
-        rows, _, _ = oracle.encode_rows(fmt, X[uniq], mu)
+        acc[name] = {"recall_at_100": recall_at_k(ids[:ns], gt), "ms_per_step": ms, "kernel_ms": k_ms,
+                     "distances_per_s": n * nq / (ms / 1000.0)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on the host: returned values of every form against its
+        # binary64 similarities (float32 queries), and its own rate on a slice
+        import oracle
+        fmt = oracle.Format(d, 8, 0)
         offs = np.arange(ns + 1, dtype=np.int64) * k
-        ref = oracle.distances(fmt, oracle.IP, oracle.PRIMARY, Qd, rows, None, mu, offs, inv.astype(np.int32))
-        xh = oracle.reconstruct(fmt, rows, None, mu)[inv]
-        S = np.abs(np.repeat(Qd.astype(np.float64), k, 0) * xh).sum(1)
-        err = np.abs(dist[:ns].ravel().astype(np.float64) - ref) / S
-        acc[name] = {"recall_at_100": rec, "max_err_over_S": float(err.max()), "mean_err_over_S": float(err.mean()),
-                     "ms_per_step": ms, "kernel_ms": k_ms, "distances_per_s": n * nq / (ms / 1000.0)}
+        for name, (ms, k_ms, ids, dist) in res.items():
+            uniq, inv = np.unique(ids[:ns].ravel(), return_inverse=True)
+            rows, _, _ = oracle.encode_rows(fmt, X[uniq], mu)
+            ref = oracle.distances(fmt, oracle.IP, oracle.PRIMARY, Qd, rows, None, mu, offs, inv.astype(np.int32))
+            xh = oracle.reconstruct(fmt, rows, None, mu)[inv]
+            S = np.abs(np.repeat(Qd.astype(np.float64), k, 0) * xh).sum(1)
+            err = np.abs(dist[:ns].ravel().astype(np.float64) - ref) / S
+            acc[name]["max_err_over_S"] = float(err.max())
+            acc[name]["mean_err_over_S"] = float(err.mean())
+        m = 100_000
+        rows, _, _ = oracle.encode_rows(fmt, X[:m], mu)
+        t = time.perf_counter()
+        oracle.topk_exhaustive(fmt, oracle.IP, oracle.PRIMARY, Q[:2], rows, None, mu, k)
+        ct = time.perf_counter() - t
+        cpu = {"value": 2 * m / ct, "unit": "distances/s", "cores": 1, "kind": "oracle",
+               "sample": "exhaustive top-100 of 2 queries over the first %d rows, binary64 scalar C, %.2f s" % (m, ct)}
     ms, k_ms = res["bf16"][0], res["bf16"][1]
     flops = 2.0 * d * n * nq
     achieved = flops / (k_ms / 1000.0) / 1e12
@@ -472,9 +509,105 @@ def bench_c4(args):
                {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
                 "kernel": "k_scan_mfma (bf16, fused top-100)", "kernel_ms": k_ms},
-               precision=acc, accuracy_sample="%d queries: errors |gpu - binary64 oracle (float32 query)| / "
-                                              "sum_j |q_j x_hat_j|; recall@100 vs float ground truth" % ns)
+               precision=acc, accuracy_sample="%d queries: recall@100 vs the exact float top-100; errors "
+                                              "|gpu - binary64 oracle (float32 query)| / sum_j |q_j x_hat_j| "
+                                              "(with the CPU baseline)" % ns)
     out["encode"] = encode_roofline(warm_encode_ms(ix, X, dev), n, d, ix.row_bytes, ix.resid_bytes, enc_ms)
+    if cpu:
+        out["cpu_baseline"] = cpu
+    ix.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Soft inverted index (M-LVQ means as lists, Sec. 3.2): C3's data law with 256
+# means; each query scores the members of its nprobe nearest means
+# ---------------------------------------------------------------------------
+
+def bench_probe(args):
+    import torch
+
+    import paper_2402_02044_amd as L
+    import synth
+    n, nq, d, M, k = args.n or 10_000_000, args.nq or 10_000, 96, 256, 10
+    log("generating %d x %d base vectors (256 clusters), %d queries" % (n, d, nq))
+    X = synth.vectors("C3", synth.S_BASE, 0, n)
+    Q = synth.vectors("C3", synth.S_QUERY, 0, nq)
+    sample = X[synth.sample_indices(3, n, 100_000)]
+    log("k-means (M = %d) on a 100k sample" % M)
+    means = host_kmeans(sample, M, 10, 3)
+    dev = torch.device("cuda:0")
+    log("uploading and encoding the store")
+    ix = L.Index(d, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=n, means=means)
+    enc_ms = to_gpu_rows(ix, X, dev)
+    tile = args.tile if args.tile >= 0 else 28
+    ix.set_tile(L.LVQ_PRIMARY, 1, tile)
+    # members per mean (header byte 12 of every row), for the pairs scanned
+    sizes = torch.zeros(M, dtype=torch.int64, device=dev)
+    for a in range(0, n, 1 << 20):
+        sl = torch.arange(a, min(n, a + (1 << 20)), dtype=torch.int32, device=dev)
+        rows, _ = ix.read_rows(sl)
+        sizes += torch.bincount(rows[:, 12].long(), minlength=M)
+    sizes = sizes.cpu().numpy()
+    ns = 1000
+    log("exact float top-%d of %d queries" % (k, ns))
+    gt = exact_topk(0, Q[:ns], X, k)
+    qd = torch.from_numpy(Q).to(dev)
+    probe_buf = {}
+    ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    s = int(torch.cuda.current_stream().cuda_stream)
+    points = []
+    for nprobe in (1, 2, 4, 8):
+        probe = probe_buf.setdefault(nprobe, torch.empty((nq, nprobe), dtype=torch.int32, device=dev))
+
+        def step():
+            L.lvq_probe_topk(ix.handle, qd.data_ptr(), nq, nprobe, k, L.LVQ_PRIMARY, probe.data_ptr(),
+                             ids.data_ptr(), dist.data_ptr(), s)
+
+        ms, k_ms = timed(step, args.steps, args.warmup, ix)
+        assert ix.sync() == 0
+        pairs = int(sizes[probe.cpu().numpy()].sum())
+        rec = recall_at_k(ids[:ns].cpu().numpy(), gt)
+        points.append({"nprobe": nprobe, "ms_per_batch": ms, "kernel_ms": k_ms, "qps": nq / (ms / 1000.0),
+                       "pairs_per_query": pairs / nq, "distances_per_s": pairs / (ms / 1000.0),
+                       "recall_at_10": rec})
+        log("nprobe %2d: batch %.3f ms (k_cand %.3f ms), %.0f q/s, %.0f pairs/query, recall@10 %.3f" %
+            (nprobe, ms, k_ms, nq / (ms / 1000.0), pairs / nq, rec))
+    head = next((p for p in points if p["recall_at_10"] >= 0.9), points[-1])
+    per_pair = 96 + 8 + 1 + 4 + 4
+    pairs = head["pairs_per_query"] * nq
+    achieved = per_pair * pairs / (head["kernel_ms"] / 1000.0) / 1e9
+    out = line(head["distances_per_s"], "distances/s", args.steps, args.warmup, head["ms_per_batch"], "f32",
+               {"workload": "soft inverted index: n=10,000,000 d=96 (256 clusters) LVQ-8 L2 with 256 means "
+                            "(k-means on a 100k sample); 10,000 queries, each scoring the rows of its nprobe "
+                            "nearest means, top-10; value at the smallest nprobe reaching recall@10 >= 0.9",
+                "n": n, "dim": d, "means": M, "queries": nq, "k": k, "nprobe": head["nprobe"], "tile_shape": tile},
+               {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_cand over the probed members (fused top-10)", "kernel_ms": head["kernel_ms"],
+                "algorithmic_bytes_per_pair": per_pair},
+               qps=head["qps"], recall_at_10=head["recall_at_10"], operating_points=points,
+               recall_sample="%d queries against the exact float top-10" % ns)
+    out["encode"] = encode_roofline(warm_encode_ms(ix, X, dev), n, d, ix.row_bytes, ix.resid_bytes, enc_ms)
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the oracle on a host-core sample")
+        # a 200k-row slice of the store, encoded by the oracle; its queries
+        # routed and scored by the oracle, timed
+        m = 200_000
+        fmt = oracle.Format(d, 8, 0)
+        rows, _, _ = oracle.encode_rows(fmt, X[:m], means)
+        nqs = 200
+        t = time.perf_counter()
+        pr = oracle.probe_means(Q[:nqs], means, head["nprobe"])
+        offs, lid = oracle.probe_lists(pr, rows[:, 12])
+        dd = oracle.distances(fmt, oracle.L2, oracle.PRIMARY, Q[:nqs], rows, None, means, offs, lid)
+        oracle.topk_lists(oracle.L2, dd, offs, lid, k)
+        ct = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": int(offs[-1]) / ct, "unit": "distances/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d queries routed (nprobe %d) over a %d-row slice of the store, %d pairs, "
+                                         "binary64 scalar C, %.2f s" % (nqs, head["nprobe"], m, int(offs[-1]), ct)}
     ix.close()
     return out
 
@@ -603,9 +736,12 @@ class C5Store:
         return out
 
 
-def c5_cpu_groundtruth(store, Q, k=10):
-    import oracle
-    return oracle.float_groundtruth(oracle.IP, Q, store.Xh, k, live=store.live)
+def c5_host_groundtruth(store, Q, k=10):
+    """Exact inner-product top-k over the live float vectors on the host
+    (numpy binary64), to spot-check the GPU ground truth."""
+    live = np.flatnonzero(store.live)
+    sc = np.asarray(Q, np.float64) @ store.Xh[live].astype(np.float64).T
+    return live[np.argsort(-sc, axis=1, kind="stable")[:, :k]]
 
 
 def c5_load(sv, batches, arrivals, waiter_out):
@@ -652,7 +788,6 @@ def bench_c5(args):
 
     import torch
 
-    import oracle
     import paper_2402_02044_amd as L
     import synth
     n0 = args.n or 1_000_000
@@ -716,13 +851,13 @@ def bench_c5(args):
                 epoch = st.ix.stats().epoch
                 gt = st.groundtruth(Qr)
                 if r % 10 == 0:   # the GPU ground truth against the host definition on a few queries
-                    cpu = c5_cpu_groundtruth(st, Qr[:3])
+                    cpu = c5_host_groundtruth(st, Qr[:3])
                     assert np.array_equal(np.sort(cpu, 1), np.sort(gt[:3], 1)), "ground truth mismatch"
                     rec["gt_spot_checks"] += 1
                 for f in forms:
                     ids, _, info = res[f]
                     assert info.epoch == epoch
-                    rec["recall"][f].append(oracle.recall(ids, gt))
+                    rec["recall"][f].append(recall_at_k(ids, gt))
                 rec["epoch"].append(int(epoch))
                 log("round %d: live %d, freed %d, means %d, update %.0f ms, recall %s" %
                     (r, rec["live"][-1], freed, st.n_means, rec["update_ms"][-1],
@@ -795,6 +930,7 @@ def bench_c5(args):
     # cpu baseline: the oracle serving queries on a bounded slice of the store
     cpu = None
     if not args.no_cpu_baseline:
+        import oracle
         log("timing the oracle on a host-core sample")
         fmt = oracle.Format(768, 4, 8, oracle.TURBO)
         live = np.flatnonzero(st.live)
@@ -844,7 +980,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "layouts"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "layouts", "probe"])
     ap.add_argument("--rounds", type=int, default=30, help="c5: update rounds")
     ap.add_argument("--sat-batches", type=int, default=60, help="c5: batches of each saturation burst")
     ap.add_argument("--lat-batches", type=int, default=120, help="c5: batches of each latency phase")
@@ -878,7 +1014,7 @@ def main():
                           "launches": 5}), flush=True)
         return
     fn = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
-          "layouts": bench_layouts}[args.workload]
+          "layouts": bench_layouts, "probe": bench_probe}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

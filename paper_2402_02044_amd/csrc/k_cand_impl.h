@@ -361,6 +361,15 @@ __device__ __forceinline__ float finish_pair(const Acc &A, float l2acc, float4 h
     }
 }
 
+// Table of a row's mean: its id, or through the list's map (a stale entry of
+// a mean the list does not hold is clamped into range; such a row is never
+// visible to the list's query).
+__device__ __forceinline__ int table_of(uint32_t mid, bool sub, const uint8_t *tmap, int ntab)
+{
+    const int t = sub ? (int)tmap[mid] : (int)mid;
+    return t < ntab ? t : ntab - 1;
+}
+
 // PIPE: 0 = no software pipeline; 1 or 2 = the loads of the candidates one
 // or two blocks ahead are in flight while the current block is consumed.
 // WAVES: the fewest waves per SIMD the register allocation must allow (1: no
@@ -382,7 +391,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
     const int g = lane % G;
 
     const int npieces = a.kchunks * 16 / CH;
-    const int ntab = (METRIC == LVQ_L2 && MULTI) ? a.n_means : 1;
+    // L2 with several means: one table q - mu_m per mean, or, for lists that
+    // hold rows of a few known means only (a.list_means: list_nmeans per
+    // list), one table per listed mean and a map from mean id to table
+    const bool sub = METRIC == LVQ_L2 && MULTI && a.list_means != nullptr;
+    const int ntab = (METRIC == LVQ_L2 && MULTI) ? (sub ? a.list_nmeans : a.n_means) : 1;
     // several means (L2): the means in kernel order stay in LDS for the whole
     // launch when a.mu_lds is set, so a list's tables q - mu_m need no reads
     // of the means from memory
@@ -394,7 +407,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
     const int cm_n = METRIC == LVQ_IP ? a.n_means : 0;
     // fused top-k: one key buffer of a.cw entries per wave, then 4k entries
     // for the merge of the four waves (also each wave's selection scratch)
-    uint64_t *keys = reinterpret_cast<uint64_t *>(cmt + ((cm_n + 1) & ~1));
+    uint8_t *tmap = reinterpret_cast<uint8_t *>(cmt + ((cm_n + 1) & ~1));   // kMaxMeans bytes when sub
+    uint64_t *keys = reinterpret_cast<uint64_t *>(tmap + (sub ? kMaxMeans : 0));
     uint64_t *wbuf = keys + (size_t)wave * a.cw;
     uint64_t *merge = keys + (size_t)4 * a.cw;
     __shared__ int s_item;
@@ -431,14 +445,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
             const int j = qtab_index<B1, CH>(sp, npieces);
             for (int t = 0; t < ntab; ++t) {
                 float w = v;
+                const int64_t mt = sub ? a.list_means[list * ntab + t] : t;
                 if (METRIC == LVQ_L2)
-                    w -= mu_lds ? mutab[(size_t)t * a.kpos + j] : a.muk[(int64_t)t * a.kpos + sp];
+                    w -= mu_lds ? mutab[(size_t)t * a.kpos + j] : a.muk[mt * a.kpos + sp];
                 qtab[(size_t)t * a.kpos + j] = w;
             }
         }
         if (MASK)
             for (int sp = tid; sp < a.kpos; sp += 256) mtab[qtab_index<B1, CH>(sp, npieces)] = a.kmask[sp];
         for (int m = tid; m < cm_n; m += 256) cmt[m] = a.cm[list * a.n_means + m];
+        if (sub)
+            for (int t = tid; t < ntab; t += 256) tmap[a.list_means[list * ntab + t]] = (uint8_t)t;
         __syncthreads();
         const float qsum = METRIC == LVQ_IP ? a.qsum[list] : 0.0f;
         QRegs<B1, CH, NCH> qr;
@@ -494,7 +511,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
                 hdr = cur.hdr;
                 ep = cur.ep;
                 const float *tq = qtab + ((METRIC == LVQ_L2 && MULTI)
-                                              ? (size_t)min((int)(__float_as_uint(hdr.w) & 0xFFu), a.n_means - 1) * a.kpos
+                                              ? (size_t)table_of(__float_as_uint(hdr.w) & 0xFFu, sub, tmap, ntab) * a.kpos
                                               : 0);
                 const L2Row R = l2_row<B2>(hdr);
                 accumulate_pair<B1, B2, METRIC, MASK, G, CH, NCH, QREG>(cur, tq, qr, mtab, 0, g, npieces, R, A,
@@ -517,7 +534,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
                 ep = P.ep;
                 work = P.work;
                 const float *tq = qtab + ((METRIC == LVQ_L2 && MULTI)
-                                              ? (size_t)min((int)(__float_as_uint(hdr.w) & 0xFFu), a.n_means - 1) * a.kpos
+                                              ? (size_t)table_of(__float_as_uint(hdr.w) & 0xFFu, sub, tmap, ntab) * a.kpos
                                               : 0);
                 const L2Row R = l2_row<B2>(hdr);
                 accumulate_pair<B1, B2, METRIC, MASK, G, CH, NCH, false>(P, tq, qr, mtab, 0, g, npieces, R, A,
@@ -587,9 +604,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 }
 
 // LDS bytes of one k_cand launch with per-wave key buffers of cw entries
-inline size_t cand_lds_bytes_impl(int kpos, int ntab, bool mask, int n_means_ip, int k, int cw)
+inline size_t cand_lds_bytes_impl(int kpos, int ntab, bool mask, int n_means_ip, int k, int cw, bool map)
 {
     size_t b = (size_t)ntab * kpos * 4 + (mask ? (size_t)kpos * 4 : 0) + (size_t)((n_means_ip + 1) & ~1) * 4;
+    if (map) b += kMaxMeans;
     b = (b + 15) & ~(size_t)15;
     if (k > 0) b += ((size_t)4 * cw + (size_t)4 * k) * 8;
     return b;

@@ -585,7 +585,7 @@ int lvq_consolidate(lvq_index *ix, void *stream, int64_t *n_freed_out)
 int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev,
                         const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev, int32_t k,
                         int32_t *topk_ids_dev, float *topk_dist_dev, hipStream_t s, int force_shape,
-                        uint32_t epoch, bool neg_empty)
+                        uint32_t epoch, bool neg_empty, const int32_t *list_means, int list_nmeans)
 {
     if (!ix || nq < 0 || total < 0 || nq > INT32_MAX) return LVQ_ERR_INVALID_ARG;
     if (level != LVQ_PRIMARY && level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
@@ -610,21 +610,23 @@ int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int
     }
     void *kern = shape >= 0 ? lookup(bits2, variant, shape) : nullptr;
     if (!kern) return LVQ_ERR_UNSUPPORTED;
-    const int ntab = multi ? ix->n_means : 1;
+    const bool sub = multi && list_means != nullptr;
+    if (sub && (list_nmeans < 1 || list_nmeans > ix->n_means)) return LVQ_ERR_INVALID_ARG;
+    const int ntab = multi ? (sub ? list_nmeans : ix->n_means) : 1;
     // top-k key buffer per wave: about 2k + one block of candidates (a block
     // holds at most 32 per wave), at least 64 and at most 2048 entries,
     // halved while the launch does not fit the workgroup's LDS
     int cw = 64;
     while (cw < 2 * k + 32 && cw < 2048) cw *= 2;
-    size_t lds = cand_lds_bytes(f.kpos, ntab, masked, l2 ? 0 : ix->n_means, k, cw);
+    size_t lds = cand_lds_bytes(f.kpos, ntab, masked, l2 ? 0 : ix->n_means, k, cw, sub);
     while (lds > ix->lds_max && cw / 2 >= k + 32) {
         cw /= 2;
-        lds = cand_lds_bytes(f.kpos, ntab, masked, l2 ? 0 : ix->n_means, k, cw);
+        lds = cand_lds_bytes(f.kpos, ntab, masked, l2 ? 0 : ix->n_means, k, cw, sub);
     }
     if (lds > ix->lds_max) return LVQ_ERR_UNSUPPORTED;
     // several means: a second set of tables keeps the means in LDS if it fits
     int mu_lds = 0;
-    if (multi) {
+    if (multi && !sub) {
         const size_t with = cand_lds_bytes(f.kpos, 2 * ntab, masked, 0, k, cw);
         if (with <= ix->lds_max) {
             mu_lds = 1;
@@ -666,6 +668,8 @@ int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int
     a.neg_empty = neg_empty ? 1 : 0;
     a.cw = cw;
     a.mu_lds = mu_lds;
+    a.list_means = sub ? list_means : nullptr;
+    a.list_nmeans = sub ? list_nmeans : 0;
     // persistent launch: lists longest-first from a device work counter
     a.order = P<int32_t>(w.order);
     a.queue = P<int32_t>(w.queue);
@@ -1012,7 +1016,7 @@ static int probe_topk(lvq_index *ix, const float *q_dev, int64_t nq, int32_t npr
     LVQ_HIP(launch_probe_gather(probe, nq, nprobe, P<int64_t>(w.moffs), P<int32_t>(w.members), P<int64_t>(w.qoffs),
                                 P<int32_t>(w.qids), s));
     return host_distances(ix, q_dev, nq, P<int64_t>(w.qoffs), P<int32_t>(w.qids), total, level, nullptr, k, ids_dev,
-                          dist_dev, s, -1, ix->epoch, true);
+                          dist_dev, s, -1, ix->epoch, true, probe, nprobe);
 }
 
 extern "C" {

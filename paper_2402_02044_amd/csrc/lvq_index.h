@@ -93,11 +93,13 @@ int host_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_
 
 // Candidate-list similarities (lvq_distances' semantics) with the fused top-k
 // filtered at `epoch`.  neg_empty: a negative slot marks an empty list entry
-// (no error, left out of the top-k) instead of an invalid one.
+// (no error, left out of the top-k) instead of an invalid one.  list_means
+// (nq x list_nmeans, optional): the only means the rows of each list can
+// belong to (L2 with several means then builds a list's tables for those).
 int host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev,
                    const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev, int32_t k,
                    int32_t *topk_ids_dev, float *topk_dist_dev, hipStream_t s, int force_shape, uint32_t epoch,
-                   bool neg_empty);
+                   bool neg_empty, const int32_t *list_means = nullptr, int list_nmeans = 0);
 
 // Mark the work queued so far on `s` as a query reading the store at `epoch`
 // (consolidation keeps the slots that query may still see).

@@ -95,6 +95,8 @@ struct CandArgs {
     int neg_empty;           // a negative id is an empty entry, not an error
     int cw;                  // top-k key buffer entries per wave (>= k + 32)
     int mu_lds;              // L2 with several means: keep muk in LDS for the launch
+    const int32_t *list_means;   // L2 with several means: the means each list's rows
+    int list_nmeans;             // belong to (nq x list_nmeans), or NULL for any mean
 };
 
 struct ScanArgs {
@@ -146,7 +148,7 @@ void *cand_kernel_b4(int bits2, int variant, int shape);
 void *cand_kernel_b8(int bits2, int variant, int shape);
 void *scan_kernel_b4(int bits2, int variant, int shape);
 void *scan_kernel_b8(int bits2, int variant, int shape);
-size_t cand_lds_bytes(int kpos, int ntab, bool mask, int n_means_ip, int k, int cw);
+size_t cand_lds_bytes(int kpos, int ntab, bool mask, int n_means_ip, int k, int cw, bool map = false);
 size_t scan_lds_bytes(int kpos, int n_means_ip, int k, int capq);
 int scan_capq(int kpos, int n_means_ip, int k, int rows_per_round, size_t lds_max);
 int scan_rows_per_round(int g);
