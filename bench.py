@@ -598,7 +598,7 @@ def bench_probe(args):
         m = 200_000
         fmt = oracle.Format(d, 8, 0)
         rows, _, _ = oracle.encode_rows(fmt, X[:m], means)
-        nqs = 200
+        nqs = 2000
         t = time.perf_counter()
         pr = oracle.probe_means(Q[:nqs], means, head["nprobe"])
         offs, lid = oracle.probe_lists(pr, rows[:, 12])
