@@ -202,6 +202,35 @@ int lvq_probe_topk(lvq_index *index, const float *q_dev, int64_t nq, int32_t npr
                    int32_t level, int32_t *probe_out_dev, int32_t *ids_dev, float *dist_dev,
                    void *stream);
 
+/* Online re-estimation of M-LVQ means with selective re-encoding (Sec. 3.2;
+ * updating means needs the rows of the moved centres re-encoded).
+ *
+ * lvq_retire_means: the listed ids are no longer chosen by the nearest-mean
+ * search of later encodes and inserts; rows already assigned keep them, and
+ * routing (lvq_probe_topk) still ranks every id.  At least one mean must stay
+ * active (LVQ_ERR_INVALID_ARG otherwise).
+ *
+ * lvq_add_means: n new centres (n x dim, host memory).  Each takes the lowest
+ * retired id that no occupied slot refers to any more (its rows deleted and
+ * freed by lvq_consolidate, so no unfinished query can see them), else the
+ * next unused id (at most 256 ids over the index's life); ids_out_host (n)
+ * receives the ids.  LVQ_ERR_CAPACITY when fewer than n ids are free.
+ *
+ * lvq_mean_members: the slots of the rows live at the call whose mean is one
+ * of mean_ids_host[0 .. n): offsets_host (n + 1, host) receives the ranges
+ * and slots_dev[offsets_host[i] .. offsets_host[i + 1]) the slots of mean i,
+ * in no particular order; LVQ_ERR_CAPACITY if more than cap rows.  Re-encoding
+ * them is a delete plus an insert of their original vectors (with their
+ * external ids).
+ *
+ * All three are ordered after earlier updates, synchronise `stream`, and
+ * cannot be captured into a HIP graph (LVQ_ERR_UNSUPPORTED).              */
+int lvq_retire_means(lvq_index *index, const int32_t *ids_host, int32_t n, void *stream);
+int lvq_add_means(lvq_index *index, const float *means_host, int32_t n, int32_t *ids_out_host,
+                  void *stream);
+int lvq_mean_members(lvq_index *index, const int32_t *mean_ids_host, int32_t n, int64_t *offsets_host,
+                     int32_t *slots_dev, int64_t cap, void *stream);
+
 /* Copy stored rows of n slots (slots_dev int32) into rows_dev / resid_dev. */
 int lvq_read_rows(lvq_index *index, const int32_t *slots_dev, int64_t n, uint8_t *rows_dev,
                   uint8_t *resid_dev, void *stream);

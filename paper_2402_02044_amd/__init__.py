@@ -36,7 +36,8 @@ LVQ_ERR_NONFINITE = -6
 LVQ_ERR_BAD_SLOT = -7
 
 EXPORTS = ["lvq_row_format", "lvq_create", "lvq_destroy", "lvq_set_means", "lvq_encode", "lvq_insert",
-           "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_topk", "lvq_probe_topk", "lvq_read_rows",
+           "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_topk", "lvq_probe_topk", "lvq_retire_means",
+           "lvq_add_means", "lvq_mean_members", "lvq_read_rows",
            "lvq_get_stats", "lvq_sync", "lvq_mean", "lvq_kmeans", "lvq_strerror", "lvq_set_timing",
            "lvq_kernel_time", "lvq_autotune", "lvq_set_tile", "lvq_server_create", "lvq_server_submit",
            "lvq_server_wait", "lvq_server_drain", "lvq_server_get_stats", "lvq_server_destroy",
@@ -100,6 +101,9 @@ def _load():
         "lvq_distances": [P, P, i64, P, P, i64, i32, P, i32, P, P, P],
         "lvq_topk": [P, P, i32, i64, i32, i32, P, P, P],
         "lvq_probe_topk": [P, P, i64, i32, i32, i32, P, P, P, P],
+        "lvq_retire_means": [P, P, i32, P],
+        "lvq_add_means": [P, P, i32, P, P],
+        "lvq_mean_members": [P, P, i32, P, P, i64, P],
         "lvq_read_rows": [P, P, i64, P, P, P],
         "lvq_get_stats": [P, ctypes.POINTER(lvq_stats)],
         "lvq_sync": [P, P],
@@ -193,6 +197,18 @@ def lvq_topk(ix, q, prec, nq, k, level, ids, dist, stream=0):
 
 def lvq_probe_topk(ix, q, nq, nprobe, k, level, probe, ids, dist, stream=0):
     return _chk(_lib.lvq_probe_topk(ix, q, nq, nprobe, k, level, probe, ids, dist, stream), "lvq_probe_topk")
+
+
+def lvq_retire_means(ix, ids_host, n, stream=0):
+    return _chk(_lib.lvq_retire_means(ix, ids_host, n, stream), "lvq_retire_means")
+
+
+def lvq_add_means(ix, means_host, n, ids_out_host, stream=0):
+    return _chk(_lib.lvq_add_means(ix, means_host, n, ids_out_host, stream), "lvq_add_means")
+
+
+def lvq_mean_members(ix, ids_host, n, offsets_host, slots, cap, stream=0):
+    return _chk(_lib.lvq_mean_members(ix, ids_host, n, offsets_host, slots, cap, stream), "lvq_mean_members")
 
 
 def lvq_read_rows(ix, slots, n, rows, resid, stream=0):
@@ -381,6 +397,30 @@ class Index:
         lvq_probe_topk(self.handle, _ptr(q), nq, nprobe, k, level, _ptr(probe), _ptr(ids), _ptr(dist),
                        _stream(stream))
         return probe, ids, dist
+
+    def retire_means(self, ids, stream=None):
+        import numpy as np
+        ids = np.ascontiguousarray(ids, np.int32)
+        lvq_retire_means(self.handle, ids.ctypes.data, ids.shape[0], _stream(stream))
+
+    def add_means(self, means, stream=None):
+        """New centres; returns their ids (freed retired ids first)."""
+        import numpy as np
+        means = np.ascontiguousarray(np.atleast_2d(means), np.float32)
+        ids = np.zeros(means.shape[0], np.int32)
+        lvq_add_means(self.handle, means.ctypes.data, means.shape[0], ids.ctypes.data, _stream(stream))
+        return ids
+
+    def mean_members(self, ids, cap, device="cuda", stream=None):
+        """Live slots of the given means: (offsets n+1 host int64, slots tensor)."""
+        import numpy as np
+        import torch
+        ids = np.ascontiguousarray(ids, np.int32)
+        offs = np.zeros(ids.shape[0] + 1, np.int64)
+        slots = torch.empty(max(int(cap), 1), dtype=torch.int32, device=device)
+        lvq_mean_members(self.handle, ids.ctypes.data, ids.shape[0], offs.ctypes.data, _ptr(slots), int(cap),
+                         _stream(stream))
+        return offs, slots[:int(offs[-1])]
 
     def read_rows(self, slots, stream=None):
         import torch

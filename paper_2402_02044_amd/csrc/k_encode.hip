@@ -6,7 +6,8 @@
 // below and -ffp-contract=off on this file), IEEE division, IEEE denormals.
 // The result is bit-identical to a scalar binary32 evaluation of the same
 // operation sequence:
-//   nearest mean   s_m = sum_j (x_j - mu_mj)^2, sequential in j; ties to lower m
+//   nearest mean   s_m = sum_j (x_j - mu_mj)^2, sequential in j; ties to lower m;
+//                  means marked retired are not candidates
 //   Eq. 1          t = x - mu*, u = max t, l = min t
 //   Eq. 2/3        Delta = (u - l) / (2^B1 - 1), inv = 1 / Delta,
 //                  c1 = clamp(floor((t - l) * inv + 1/2), 0, 2^B1 - 1);
@@ -238,11 +239,14 @@ __global__ __launch_bounds__(256) void k_encode(EncodeArgs a)
                     s1 = s1 + e1;
                 }
             }
-            if (bm < 0 || s0 < best) {
+            // retired means are never chosen
+            const bool ok0 = a.mean_active[m0] != 0;
+            const bool ok1 = two && a.mean_active[m1] != 0;
+            if (ok0 && (bm < 0 || s0 < best)) {
                 best = s0;
                 bm = m0;
             }
-            if (two && s1 < best) {
+            if (ok1 && (bm < 0 || s1 < best)) {
                 best = s1;
                 bm = m1;
             }

@@ -102,6 +102,27 @@ __global__ __launch_bounds__(256) void k_member_fill(const int32_t *list, int64_
     }
 }
 
+// live members of requested means: one workgroup per requested mean
+__global__ __launch_bounds__(256) void k_members_live(const int32_t *req, int nreq, const int64_t *moffs,
+                                                      const int32_t *members, const uint8_t *rows, int row_bytes,
+                                                      uint32_t epoch, const int64_t *out_offs, int32_t *out,
+                                                      unsigned long long *counts)
+{
+    for (int i = blockIdx.x; i < nreq; i += gridDim.x) {
+        const int m = req[i];
+        for (int64_t e = moffs[m] + threadIdx.x; e < moffs[m + 1]; e += 256) {
+            const int32_t slot = members[e];
+            if (slot < 0) continue;
+            const uint8_t *row = rows + (int64_t)slot * row_bytes;
+            const uint2 ep = *reinterpret_cast<const uint2 *>(row + 16);
+            const bool live = (row[13] & 1u) && ep.x <= epoch && epoch < ep.y;
+            if (!live) continue;
+            const unsigned long long pos = atomicAdd(&counts[i], 1ull);
+            if (out_offs) out[out_offs[i] + (int64_t)pos] = slot;
+        }
+    }
+}
+
 // ---- routing ----------------------------------------------------------------
 // One wave per query; lane l scores means l, l + 64, ... (E per lane, M <=
 // 64 E), each as a sequential sum over the dimensions; the (distance, mean)
@@ -219,6 +240,30 @@ hipError_t launch_members(const int32_t *list, int64_t n, const uint8_t *rows, i
     if (blocks > 0)
         hipLaunchKernelGGL(k_member_fill, dim3((unsigned)blocks), dim3(256), 0, s, list, n, chunk, rows, row_bytes,
                            n_means, offsets, cursor, members);
+    return hipGetLastError();
+}
+
+hipError_t launch_mean_counts(const int32_t *list, int64_t n, const uint8_t *rows, int row_bytes, int n_means,
+                              unsigned long long *counts, hipStream_t s)
+{
+    if (n_means < 1 || n_means > kMaxMeans) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, counts, n_means);
+    const int64_t chunk = 8192;
+    const int64_t blocks = (n + chunk - 1) / chunk;
+    if (blocks > 0)
+        hipLaunchKernelGGL(k_member_count, dim3((unsigned)blocks), dim3(256), 0, s, list, n, chunk, rows, row_bytes,
+                           n_means, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_members_live(const int32_t *req, int nreq, const int64_t *moffs, const int32_t *members,
+                               const uint8_t *rows, int row_bytes, uint32_t epoch, const int64_t *out_offs,
+                               int32_t *out, unsigned long long *counts, hipStream_t s)
+{
+    if (nreq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, counts, nreq);
+    hipLaunchKernelGGL(k_members_live, dim3((unsigned)std::min(nreq, 4096)), dim3(256), 0, s, req, nreq, moffs,
+                       members, rows, row_bytes, epoch, out_offs, out, counts);
     return hipGetLastError();
 }
 

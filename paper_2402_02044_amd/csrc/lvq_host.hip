@@ -341,6 +341,13 @@ int lvq_create(const lvq_config *cfg, const float *means_host, int32_t n_means, 
         if ((rc = dev_alloc(ix, ix->kmask, sizeof(float) * f.kpos))) break;
         if ((rc = dev_alloc(ix, ix->err, 16))) break;
         if ((rc = dev_alloc(ix, ix->scratch, 4096))) break;
+        if ((rc = dev_alloc(ix, ix->mean_active, kMaxMeans))) break;
+        if ((rc = dev_alloc(ix, ix->mean_counts, sizeof(uint64_t) * kMaxMeans))) break;
+        ix->retired.assign(kMaxMeans, 0);
+        if (hipMemset(ix->mean_active.p, 1, kMaxMeans)) {
+            rc = LVQ_ERR_DEVICE;
+            break;
+        }
         if (hipMemcpy(ix->kdim.p, kd.data(), sizeof(int32_t) * f.kpos, hipMemcpyHostToDevice) ||
             hipMemcpy(ix->kmask.p, km.data(), sizeof(float) * f.kpos, hipMemcpyHostToDevice) ||
             hipMemset(ix->err.p, 0, 16)) {
@@ -392,7 +399,7 @@ int lvq_destroy(lvq_index *ix)
             dev_free(ix, *b);
     }
     for (DevBuf *b : {&ix->means, &ix->means_t, &ix->muk, &ix->kmask, &ix->kdim, &ix->rows,
-                      &ix->resid, &ix->stack, &ix->err, &ix->scratch})
+                      &ix->resid, &ix->stack, &ix->err, &ix->scratch, &ix->mean_active, &ix->mean_counts})
         dev_free(ix, *b);
     for (SlotList &l : ix->lists) dev_free(ix, l.buf);
     for (auto &f : ix->inflight) (void)hipEventDestroy(f.ev);
@@ -456,6 +463,7 @@ static int encode_common(lvq_index *ix, const float *x, int64_t n, uint8_t *rows
     a.means_t_stride = kMaxMeans;
     a.n_means = ix->n_means;
     a.means_lds = ix->n_means > 1 && (size_t)ix->n_means * ix->f.dim * sizeof(float) <= 32768 ? 1 : 0;
+    a.mean_active = P<uint8_t>(ix->mean_active);
     a.f = ix->f;
     a.rows = rows;
     a.resid = resid;
@@ -973,6 +981,25 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     return LVQ_OK;
 }
 
+// Per-mean member lists of stream s's workspace, rebuilt after any update.
+static int ensure_members(lvq_index *ix, Workspace &w, hipStream_t s)
+{
+    if (w.members_version == ix->version) return LVQ_OK;
+    const int M = ix->n_means;
+    const int64_t n = ix->list_len;
+    int rc;
+    if ((rc = dev_alloc(ix, w.members, sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1)))) return rc;
+    if ((rc = dev_alloc(ix, w.moffs, sizeof(int64_t) * (size_t)(kMaxMeans + 1)))) return rc;
+    if ((rc = dev_alloc(ix, w.mcount, sizeof(uint64_t) * (size_t)kMaxMeans))) return rc;
+    if ((rc = dev_alloc(ix, w.mcursor, sizeof(uint64_t) * (size_t)kMaxMeans))) return rc;
+    if (n > 0) LVQ_HIP(launch_fill_i32(P<int32_t>(w.members), -1, n, s));
+    LVQ_HIP(launch_members(n > 0 ? P<int32_t>(ix->lists[ix->list_active].buf) : nullptr, n, P<uint8_t>(ix->rows),
+                           ix->f.row_bytes, M, P<unsigned long long>(w.mcount), P<unsigned long long>(w.mcursor),
+                           P<int64_t>(w.moffs), P<int32_t>(w.members), s));
+    w.members_version = ix->version;
+    return LVQ_OK;
+}
+
 // Soft inverted index: route, build the probed means' candidate lists, and
 // run the candidate kernel's fused top-k over them.
 static int probe_topk(lvq_index *ix, const float *q_dev, int64_t nq, int32_t nprobe, int32_t k, int32_t level,
@@ -989,18 +1016,7 @@ static int probe_topk(lvq_index *ix, const float *q_dev, int64_t nq, int32_t npr
     int rc = order_after_updates(ix, s);
     if (rc) return rc;
     Workspace &w = workspace(ix, s);
-    if (w.members_version != ix->version) {
-        const int64_t n = ix->list_len;
-        if ((rc = dev_alloc(ix, w.members, sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1)))) return rc;
-        if ((rc = dev_alloc(ix, w.moffs, sizeof(int64_t) * (size_t)(M + 1)))) return rc;
-        if ((rc = dev_alloc(ix, w.mcount, sizeof(uint64_t) * (size_t)M))) return rc;
-        if ((rc = dev_alloc(ix, w.mcursor, sizeof(uint64_t) * (size_t)M))) return rc;
-        if (n > 0) LVQ_HIP(launch_fill_i32(P<int32_t>(w.members), -1, n, s));
-        LVQ_HIP(launch_members(P<int32_t>(ix->lists[ix->list_active].buf), n, P<uint8_t>(ix->rows), ix->f.row_bytes,
-                               M, P<unsigned long long>(w.mcount), P<unsigned long long>(w.mcursor),
-                               P<int64_t>(w.moffs), P<int32_t>(w.members), s));
-        w.members_version = ix->version;
-    }
+    if ((rc = ensure_members(ix, w, s))) return rc;
     int32_t *probe = probe_out_dev;
     if (!probe) {
         if ((rc = dev_alloc(ix, w.probe, sizeof(int32_t) * (size_t)nq * nprobe))) return rc;
@@ -1033,6 +1049,135 @@ int lvq_probe_topk(lvq_index *ix, const float *q_dev, int64_t nq, int32_t nprobe
     if (rc == LVQ_OK && nq > 0) rc = note_query(ix, s, ix->epoch);
     ix->capturing = false;
     return rc;
+}
+
+int lvq_retire_means(lvq_index *ix, const int32_t *ids_host, int32_t n, void *stream)
+{
+    if (!ix || n < 0 || (n > 0 && !ids_host)) return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<uint8_t> next = ix->retired;
+    for (int32_t i = 0; i < n; ++i) {
+        if (ids_host[i] < 0 || ids_host[i] >= ix->n_means) return LVQ_ERR_INVALID_ARG;
+        next[ids_host[i]] = 1;
+    }
+    int active = 0;
+    for (int m = 0; m < ix->n_means; ++m) active += !next[m];
+    if (active == 0) return LVQ_ERR_INVALID_ARG;
+    int rc = begin_call(ix, s);
+    if (rc) return rc;
+    if (ix->capturing) {
+        ix->capturing = false;
+        return LVQ_ERR_UNSUPPORTED;
+    }
+    if ((rc = order_after_updates(ix, s))) return rc;
+    ix->retired = next;
+    std::vector<uint8_t> act(kMaxMeans);
+    for (int m = 0; m < kMaxMeans; ++m) act[m] = !ix->retired[m];
+    LVQ_HIP(hipMemcpyAsync(ix->mean_active.p, act.data(), kMaxMeans, hipMemcpyHostToDevice, s));
+    LVQ_HIP(hipStreamSynchronize(s));   // the host flags must outlive the copy
+    return note_update(ix, s);
+}
+
+int lvq_add_means(lvq_index *ix, const float *means_host, int32_t n, int32_t *ids_out_host, void *stream)
+{
+    if (!ix || !means_host || !ids_out_host || n < 1 || n > kMaxMeans) return LVQ_ERR_INVALID_ARG;
+    const Format &f = ix->f;
+    const int d = f.dim;
+    if (!finite_host(means_host, (size_t)n * d)) return LVQ_ERR_NONFINITE;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = begin_call(ix, s);
+    if (rc) return rc;
+    if (ix->capturing) {
+        ix->capturing = false;
+        return LVQ_ERR_UNSUPPORTED;
+    }
+    if ((rc = order_after_updates(ix, s))) return rc;
+    // rows per id over the occupied slots: a retired id none refers to is free
+    std::vector<uint64_t> cnt(kMaxMeans, 0);
+    if (ix->list_len > 0) {
+        LVQ_HIP(launch_mean_counts(P<int32_t>(ix->lists[ix->list_active].buf), ix->list_len, P<uint8_t>(ix->rows),
+                                   f.row_bytes, ix->n_means, P<unsigned long long>(ix->mean_counts), s));
+        LVQ_HIP(hipMemcpyAsync(cnt.data(), ix->mean_counts.p, sizeof(uint64_t) * ix->n_means,
+                               hipMemcpyDeviceToHost, s));
+        LVQ_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<int32_t> ids;
+    for (int m = 0; m < ix->n_means && (int)ids.size() < n; ++m)
+        if (ix->retired[m] && cnt[m] == 0) ids.push_back(m);
+    int next_new = ix->n_means;
+    while ((int)ids.size() < n && next_new < kMaxMeans) ids.push_back(next_new++);
+    if ((int)ids.size() < n) return LVQ_ERR_CAPACITY;
+    std::vector<int32_t> kd(f.kpos);
+    kernel_order_dims(f, kd.data());
+    std::vector<float> col((size_t)d * n), mk((size_t)n * f.kpos, 0.0f);
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < d; ++j) col[(size_t)i * d + j] = means_host[(size_t)i * d + j];
+        for (int t = 0; t < f.kpos; ++t)
+            if (kd[t] >= 0) mk[(size_t)i * f.kpos + t] = means_host[(size_t)i * d + kd[t]];
+    }
+    for (int i = 0; i < n; ++i) {
+        const int m = ids[i];
+        LVQ_HIP(hipMemcpyAsync(P<float>(ix->means) + (size_t)m * d, means_host + (size_t)i * d, sizeof(float) * d,
+                               hipMemcpyHostToDevice, s));
+        // column m of the transposed table: d values with a stride of kMaxMeans
+        LVQ_HIP(hipMemcpy2DAsync(P<float>(ix->means_t) + m, sizeof(float) * kMaxMeans, col.data() + (size_t)i * d,
+                                 sizeof(float), sizeof(float), d, hipMemcpyHostToDevice, s));
+        LVQ_HIP(hipMemcpyAsync(P<float>(ix->muk) + (size_t)m * f.kpos, mk.data() + (size_t)i * f.kpos,
+                               sizeof(float) * f.kpos, hipMemcpyHostToDevice, s));
+        ix->retired[m] = 0;
+    }
+    ix->n_means = std::max(ix->n_means, next_new);
+    std::vector<uint8_t> act(kMaxMeans);
+    for (int m = 0; m < kMaxMeans; ++m) act[m] = !ix->retired[m];
+    LVQ_HIP(hipMemcpyAsync(ix->mean_active.p, act.data(), kMaxMeans, hipMemcpyHostToDevice, s));
+    if ((rc = note_update(ix, s))) return rc;
+    LVQ_HIP(hipStreamSynchronize(s));   // the host sources must outlive the copies
+    for (int i = 0; i < n; ++i) ids_out_host[i] = ids[i];
+    return LVQ_OK;
+}
+
+int lvq_mean_members(lvq_index *ix, const int32_t *mean_ids_host, int32_t n, int64_t *offsets_host,
+                     int32_t *slots_dev, int64_t cap, void *stream)
+{
+    if (!ix || n < 0 || (n > 0 && (!mean_ids_host || !offsets_host)) || cap < 0 || (cap > 0 && !slots_dev))
+        return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    for (int32_t i = 0; i < n; ++i)
+        if (mean_ids_host[i] < 0 || mean_ids_host[i] >= ix->n_means) return LVQ_ERR_INVALID_ARG;
+    if (offsets_host) offsets_host[0] = 0;
+    if (n == 0) return LVQ_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = begin_call(ix, s);
+    if (rc) return rc;
+    if (ix->capturing) {
+        ix->capturing = false;
+        return LVQ_ERR_UNSUPPORTED;
+    }
+    if ((rc = order_after_updates(ix, s))) return rc;
+    Workspace &w = workspace(ix, s);
+    if ((rc = ensure_members(ix, w, s))) return rc;
+    // requested ids and, later, the output offsets share the probe buffer
+    if ((rc = dev_alloc(ix, w.probe, sizeof(int32_t) * (size_t)n))) return rc;
+    if ((rc = dev_alloc(ix, w.qoffs, sizeof(int64_t) * (size_t)(n + 1)))) return rc;
+    if ((rc = dev_alloc(ix, w.qids, sizeof(uint64_t) * (size_t)n))) return rc;
+    LVQ_HIP(hipMemcpyAsync(w.probe.p, mean_ids_host, sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    const uint32_t epoch = ix->epoch;
+    unsigned long long *counts = P<unsigned long long>(w.qids);
+    LVQ_HIP(launch_members_live(P<int32_t>(w.probe), n, P<int64_t>(w.moffs), P<int32_t>(w.members), P<uint8_t>(ix->rows),
+                                ix->f.row_bytes, epoch, nullptr, nullptr, counts, s));
+    std::vector<uint64_t> c(n);
+    LVQ_HIP(hipMemcpyAsync(c.data(), counts, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
+    LVQ_HIP(hipStreamSynchronize(s));
+    for (int32_t i = 0; i < n; ++i) offsets_host[i + 1] = offsets_host[i] + (int64_t)c[i];
+    if (offsets_host[n] > cap) return LVQ_ERR_CAPACITY;
+    LVQ_HIP(hipMemcpyAsync(w.qoffs.p, offsets_host, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+    LVQ_HIP(launch_members_live(P<int32_t>(w.probe), n, P<int64_t>(w.moffs), P<int32_t>(w.members), P<uint8_t>(ix->rows),
+                                ix->f.row_bytes, epoch, P<int64_t>(w.qoffs), slots_dev, counts, s));
+    LVQ_HIP(hipStreamSynchronize(s));   // offsets_host is read by the copy above
+    ix->capturing = false;
+    return LVQ_OK;
 }
 
 }  // extern "C"

@@ -57,6 +57,8 @@ struct lvq_index {
     int n_means = 0;
     // device store
     lvq::DevBuf means, means_t, muk, kmask, kdim, rows, resid, stack, err, scratch;
+    lvq::DevBuf mean_active, mean_counts;   // kMaxMeans flags (0 = retired); counts per mean id
+    std::vector<uint8_t> retired;           // host copy of the retired flags
     int64_t free_top = 0;   // host view of the free-slot stack top
     uint32_t epoch = 1;
     std::vector<lvq::SlotList> lists;

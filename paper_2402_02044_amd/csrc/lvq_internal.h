@@ -47,6 +47,7 @@ struct EncodeArgs {
     int means_t_stride;
     int n_means;
     int means_lds;           // stage the transposed means in LDS (small M x dim)
+    const uint8_t *mean_active;  // n_means flags: 0 = retired (not chosen by the nearest-mean search)
     Format f;
     uint8_t *rows;           // output rows (row i at rows + slot(i) * row_bytes)
     uint8_t *resid;
@@ -164,6 +165,14 @@ hipError_t launch_route(const float *q, int64_t nq, int dim, const float *means_
                         int nprobe, int32_t *probe, hipStream_t s);
 hipError_t launch_probe_offsets(const int32_t *probe, int64_t nq, int nprobe, const int64_t *moffs, int64_t *qoffs,
                                 hipStream_t s);
+hipError_t launch_mean_counts(const int32_t *list, int64_t n, const uint8_t *rows, int row_bytes, int n_means,
+                              unsigned long long *counts, hipStream_t s);
+// Live members (flag set, insert epoch <= epoch < delete epoch) of the means
+// req[0..nreq): counts[i] (zeroed here) receives their number; with out_offs,
+// the slots of mean i are also written at out[out_offs[i] ..] in no order.
+hipError_t launch_members_live(const int32_t *req, int nreq, const int64_t *moffs, const int32_t *members,
+                               const uint8_t *rows, int row_bytes, uint32_t epoch, const int64_t *out_offs,
+                               int32_t *out, unsigned long long *counts, hipStream_t s);
 hipError_t launch_probe_gather(const int32_t *probe, int64_t nq, int nprobe, const int64_t *moffs,
                                const int32_t *members, const int64_t *qoffs, int32_t *qids, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
