@@ -520,6 +520,85 @@ def bench_c4(args):
 
 
 # ---------------------------------------------------------------------------
+# Mean re-estimation on the C5 stream (Sec. 3.2): the periodic re-fit (new
+# means appended every 10 rounds, rows never re-encoded) against online
+# updates (every round, each moved centre replaced and its rows re-encoded)
+# ---------------------------------------------------------------------------
+
+def bench_means(args):
+    import torch
+
+    import paper_2402_02044_amd as L
+    import synth
+    n0 = args.n or 1_000_000
+    rounds = args.rounds
+    ins = max(100, n0 // 100)
+    dev = torch.device("cuda:0")
+    X0 = synth.vectors("C5", synth.S_BASE, 0, n0)
+    samp = synth.sample_indices(5, n0, 100_000)
+    means = host_kmeans(X0[samp], 16, 25, 5)
+    cap = 2 * n0 + 5 * ins + 4096
+    thr = 0.05
+    res = {}
+    scan = []
+    for policy in ("periodic", "online"):
+        log("policy %s: encoding the store" % policy)
+        st = C5Store(L, X0, means, cap, dev)
+        torch.cuda.synchronize()
+        rec = {"recall_at_10": [], "update_ms": [], "reencoded": [], "means_moved": [], "ids_in_use": []}
+        for r in range(rounds):
+            t = time.perf_counter()
+            cand = np.flatnonzero(st.live)
+            dead = np.sort(synth.rng(5, synth.S_DELETE, r).choice(cand, cand.size // 10, replace=False))
+            st.delete(dead)
+            st.insert(synth.c5_points(synth.S_INSERT, r + 1, ins))
+            moved = reenc = 0
+            if policy == "periodic":
+                if (r + 1) % 10 == 0:
+                    st.refit_means(r)
+            else:
+                moved, reenc = st.online_update(thr)
+            st.consolidate()
+            st.stream.synchronize()
+            rec["update_ms"].append((time.perf_counter() - t) * 1000.0)
+            rec["reencoded"].append(reenc)
+            rec["means_moved"].append(moved)
+            rec["ids_in_use"].append(st.n_ids if policy == "online" else st.n_means)
+            Qr = synth.c5_points(synth.S_QUERY, r + 1, 200, part=0)
+            q = torch.from_numpy(Qr).to(dev).to(torch.bfloat16)
+            with torch.cuda.stream(st.stream):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ids, _ = st.ix.topk(q, 10, level=L.LVQ_FULL, stream=st.stream)
+                e1.record()
+            st.stream.synchronize()
+            scan.append(int(st.live.sum()) * Qr.shape[0] / (e0.elapsed_time(e1) / 1000.0))
+            rec["recall_at_10"].append(recall_at_k(ids.cpu().numpy(), st.groundtruth(Qr)))
+            log("%s round %d: recall %.3f, update %.0f ms, means moved %d, rows re-encoded %d" %
+                (policy, r, rec["recall_at_10"][-1], rec["update_ms"][-1], moved, reenc))
+        assert st.ix.sync() == 0
+        r_ = np.array(rec["recall_at_10"])
+        res[policy] = {"recall_at_10_mean": float(r_.mean()), "recall_at_10_min": float(r_.min()),
+                       "recall_at_10_last10_mean": float(r_[-10:].mean()),
+                       "update_ms_mean": float(np.mean(rec["update_ms"])),
+                       "update_ms_max": float(np.max(rec["update_ms"])),
+                       "rows_reencoded": int(np.sum(rec["reencoded"])), "ids_in_use_last": rec["ids_in_use"][-1],
+                       "per_round": rec}
+        st.ix.close()
+        del st
+        torch.cuda.empty_cache()
+    out = line(float(np.mean(scan)), "distances/s", rounds, 0, res["online"]["update_ms_mean"], "bf16",
+               {"workload": "C5 stream (n=1,000,000 d=768 LVQ-4x8 Turbo IP, 30 rounds of 10%% deletes, %d drifted "
+                            "inserts and consolidation) under two mean policies; per round the exhaustive bf16 "
+                            "both-level top-10 of 200 queries of the round's distribution" % ins,
+                "n": n0, "dim": 768, "rounds": rounds, "online_threshold": thr},
+               {"bound": "mfma", "achieved": None, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                "traffic": None, "kernel": "k_scan_mfma (both levels); value: scan rate during the rounds"},
+               policies=res)
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Soft inverted index (M-LVQ means as lists, Sec. 3.2): C3's data law with 256
 # means; each query scores the members of its nprobe nearest means
 # ---------------------------------------------------------------------------
@@ -679,6 +758,10 @@ class C5Store:
         self.Xh = np.zeros((cap, 768), np.float32)
         self.live = np.zeros(cap, bool)
         self.n_means = means.shape[0]
+        self.n_ids = means.shape[0]                  # ids in use (online policy)
+        self.means_by_id = np.zeros((256, 768), np.float64)
+        self.means_by_id[:self.n_ids] = means
+        self.retired = np.zeros(256, bool)
         for a in range(0, X0.shape[0], 1 << 18):
             self.insert(X0[a:a + (1 << 18)])
 
@@ -712,6 +795,42 @@ class C5Store:
         C = host_kmeans(self.Xh[pick], k, iters, 5, 200 + round_)
         self.ix.set_means(C, stream=self.stream)
         self.n_means += k
+
+    def online_update(self, thr):
+        """Online M-LVQ re-estimation: the centroid of every active mean's live
+        members (binary64, on the GPU); each mean whose centroid moved by more
+        than thr becomes a new mean at the centroid (lvq_add_means, reusing
+        freed ids), the old id is retired, and its live rows are re-encoded
+        (deleted and inserted again from their float vectors).  Returns (means
+        moved, rows re-encoded)."""
+        import torch
+        act = np.array([m for m in range(self.n_ids) if not self.retired[m]], np.int32)
+        offs, mem = self.ix.mean_members(act, cap=int(self.live.sum()), stream=self.stream)
+        with torch.cuda.stream(self.stream):
+            cnt = torch.from_numpy(np.diff(offs)).to(self.dev)
+            seg = torch.repeat_interleave(torch.arange(act.size, device=self.dev), cnt)
+            sums = torch.zeros((act.size, 768), dtype=torch.float64, device=self.dev)
+            sums.index_add_(0, seg, self.Xd[mem.long()].double())
+            cen = (sums / cnt.clamp(min=1)[:, None]).cpu().numpy()
+        self.stream.synchronize()
+        old = self.means_by_id[act].astype(np.float64)
+        shift = np.linalg.norm(cen - old, axis=1)
+        moved = np.flatnonzero((np.diff(offs) > 0) & (shift > thr))
+        if moved.size == 0:
+            return 0, 0
+        new_ids = self.ix.add_means(cen[moved].astype(np.float32), stream=self.stream)
+        self.ix.retire_means(act[moved], stream=self.stream)
+        for i, m in zip(moved, new_ids):
+            self.means_by_id[m] = cen[i]
+            self.retired[m] = False
+            self.n_ids = max(self.n_ids, int(m) + 1)
+        self.retired[act[moved]] = True
+        mem_h = mem.cpu().numpy()
+        slots = np.concatenate([mem_h[offs[i]:offs[i + 1]] for i in moved]).astype(np.int32)
+        self.delete(slots)
+        for a in range(0, slots.size, 1 << 18):
+            self.insert(self.Xh[slots[a:a + (1 << 18)]].copy())
+        return int(moved.size), int(slots.size)
 
     def groundtruth(self, Q, k=10, chunk=65536):
         """Exact top-k by inner product over the live float vectors, binary64
@@ -980,7 +1099,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "layouts", "probe"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "layouts", "probe", "means"])
     ap.add_argument("--rounds", type=int, default=30, help="c5: update rounds")
     ap.add_argument("--sat-batches", type=int, default=60, help="c5: batches of each saturation burst")
     ap.add_argument("--lat-batches", type=int, default=120, help="c5: batches of each latency phase")
@@ -1014,7 +1133,7 @@ def main():
                           "launches": 5}), flush=True)
         return
     fn = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
-          "layouts": bench_layouts, "probe": bench_probe}[args.workload]
+          "layouts": bench_layouts, "probe": bench_probe, "means": bench_means}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 
