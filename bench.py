@@ -807,11 +807,13 @@ class C5Store:
         act = np.array([m for m in range(self.n_ids) if not self.retired[m]], np.int32)
         offs, mem = self.ix.mean_members(act, cap=int(self.live.sum()), stream=self.stream)
         with torch.cuda.stream(self.stream):
-            cnt = torch.from_numpy(np.diff(offs)).to(self.dev)
-            seg = torch.repeat_interleave(torch.arange(act.size, device=self.dev), cnt)
+            # members come grouped by mean: one reduction per contiguous range
             sums = torch.zeros((act.size, 768), dtype=torch.float64, device=self.dev)
-            sums.index_add_(0, seg, self.Xd[mem.long()].double())
-            cen = (sums / cnt.clamp(min=1)[:, None]).cpu().numpy()
+            for i in range(act.size):
+                if offs[i + 1] > offs[i]:
+                    sums[i] = self.Xd[mem[offs[i]:offs[i + 1]].long()].double().sum(0)
+            cnt = torch.from_numpy(np.maximum(np.diff(offs), 1)).to(self.dev)
+            cen = (sums / cnt[:, None]).cpu().numpy()
         self.stream.synchronize()
         old = self.means_by_id[act].astype(np.float64)
         shift = np.linalg.norm(cen - old, axis=1)
