@@ -177,14 +177,26 @@ def warm_encode_ms(ix, X, dev, chunk=1 << 20):
     return best * X.shape[0] / m
 
 
-def encode_roofline(ms, n, dim, row_bytes, resid_bytes, insert_ms=None):
+# FP32 vector lane-operations per second: 256 CUs x 64 lanes x 2.4 GHz (one
+# operation per lane and cycle; FMA would count twice in the 78.6 TFLOP/s figure)
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def encode_roofline(ms, n, dim, row_bytes, resid_bytes, insert_ms=None, n_means=1):
     """k_encode against the HBM roofline: reads 4d bytes and writes a row and
     a residual row per vector.  ms: steady-state encode time of n vectors;
-    insert_ms: the store build (lvq_insert into slots never written before)."""
+    insert_ms: the store build (lvq_insert into slots never written before).
+    With several means the exact nearest-mean search (a subtraction, a
+    product and a sum per mean and dimension, in order) bounds it as well."""
     per = 4 * dim + row_bytes + resid_bytes
     gbs = per * n / (ms / 1000.0) / 1e9
     out = {"kernel": "k_encode", "ms": ms, "vectors": n, "bytes_per_vector": per,
            "achieved_GBs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+    if n_means > 1:
+        ops = 3.0 * n_means * dim
+        alu_ms = ops * n / VALU_LANE_OPS * 1000.0
+        out.update({"nearest_mean_lane_ops_per_vector": ops, "alu_bound_ms": alu_ms,
+                    "frac_of_alu_bound": alu_ms / ms})
     if insert_ms is not None:
         out["insert_ms_cold"] = insert_ms
     return out
@@ -424,7 +436,7 @@ def bench_c3(args):
                 "kernel": "k_cand (persistent, longest lists first)", "kernel_ms": k_ms,
                 "algorithmic_bytes_per_pair": per_pair},
                ms_per_step_eager=ms_eager)
-    out["encode"] = encode_roofline(warm_encode_ms(ix, X, dev), n, d, ix.row_bytes, ix.resid_bytes, enc_ms)
+    out["encode"] = encode_roofline(warm_encode_ms(ix, X, dev), n, d, ix.row_bytes, ix.resid_bytes, enc_ms, n_means=M)
     if not args.no_cpu_baseline:
         import oracle
         fmt = oracle.Format(d, 8, 0)
@@ -668,7 +680,7 @@ def bench_probe(args):
                 "algorithmic_bytes_per_pair": per_pair},
                qps=head["qps"], recall_at_10=head["recall_at_10"], operating_points=points,
                recall_sample="%d queries against the exact float top-10" % ns)
-    out["encode"] = encode_roofline(warm_encode_ms(ix, X, dev), n, d, ix.row_bytes, ix.resid_bytes, enc_ms)
+    out["encode"] = encode_roofline(warm_encode_ms(ix, X, dev), n, d, ix.row_bytes, ix.resid_bytes, enc_ms, n_means=M)
     if not args.no_cpu_baseline:
         import oracle
         log("timing the oracle on a host-core sample")
