@@ -195,9 +195,10 @@ int lvq_topk(lvq_index *index, const void *q_dev, int32_t prec, int64_t nq, int3
  * probe_out_dev (nq x nprobe int32, may be NULL) receives the probed mean
  * ids, nearest first; ids_dev / dist_dev (nq x k) are padded as for
  * lvq_distances.  The per-mean member lists are kept per stream and rebuilt
- * by the first call after a store update (one pass over the occupied slots).
- * The call synchronises `stream` once, after routing, to size the candidate
- * lists, so it cannot be captured into a HIP graph (LVQ_ERR_UNSUPPORTED).   */
+ * by the first call after a store update (one pass over the occupied slots);
+ * the candidate kernel walks the probed means' member ranges in place.  The
+ * call is asynchronous; captured into a HIP graph (after a first call on the
+ * stream has sized its buffers) it replays at the epoch of capture.        */
 int lvq_probe_topk(lvq_index *index, const float *q_dev, int64_t nq, int32_t nprobe, int32_t k,
                    int32_t level, int32_t *probe_out_dev, int32_t *ids_dev, float *dist_dev,
                    void *stream);

@@ -361,6 +361,23 @@ __device__ __forceinline__ float finish_pair(const Acc &A, float l2acc, float4 h
     }
 }
 
+// Slot of list entry e (the list starts at e0): ids[e], or for segmented
+// lists the entry of the segment holding e (the last one starting at or
+// before it, found by bisection; empty segments are never chosen).
+__device__ __forceinline__ int32_t entry_id(const CandArgs &a, int64_t e, int64_t e0, bool seg,
+                                            const int64_t *sstart, const int64_t *sbase, int nseg)
+{
+    if (!seg) return a.ids[e];
+    const int64_t loc = e - e0;
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sstart[mid] <= loc) lo = mid;
+        else hi = mid - 1;
+    }
+    return a.seg_members[sbase[lo] + (loc - sstart[lo])];
+}
+
 // Table of a row's mean: its id, or through the list's map (a stale entry of
 // a mean the list does not hold is clamped into range; such a row is never
 // visible to the list's query).
@@ -408,7 +425,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
     // fused top-k: one key buffer of a.cw entries per wave, then 4k entries
     // for the merge of the four waves (also each wave's selection scratch)
     uint8_t *tmap = reinterpret_cast<uint8_t *>(cmt + ((cm_n + 1) & ~1));   // kMaxMeans bytes when sub
-    uint64_t *keys = reinterpret_cast<uint64_t *>(tmap + (sub ? kMaxMeans : 0));
+    // segmented lists (a.seg_members): entry i of a list is entry i of the
+    // concatenation of its means' member ranges; sstart holds the segments'
+    // first entries (nseg + 1), sbase their starts in seg_members
+    const bool seg = a.seg_members != nullptr;
+    const int nseg = seg ? a.list_nmeans : 0;
+    int64_t *sstart = reinterpret_cast<int64_t *>(tmap + (sub ? kMaxMeans : 0));
+    int64_t *sbase = sstart + (seg ? nseg + 1 : 0);
+    uint64_t *keys = reinterpret_cast<uint64_t *>(sbase + (seg ? nseg + 1 : 0));
     uint64_t *wbuf = keys + (size_t)wave * a.cw;
     uint64_t *merge = keys + (size_t)4 * a.cw;
     __shared__ int s_item;
@@ -456,7 +480,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
         for (int m = tid; m < cm_n; m += 256) cmt[m] = a.cm[list * a.n_means + m];
         if (sub)
             for (int t = tid; t < ntab; t += 256) tmap[a.list_means[list * ntab + t]] = (uint8_t)t;
+        if (seg)
+            for (int p = tid; p < nseg; p += 256) {
+                const int m = a.list_means[list * nseg + p];
+                sbase[p] = a.seg_offs[m];
+                sstart[p + 1] = a.seg_offs[m + 1] - a.seg_offs[m];   // sizes, summed below
+            }
         __syncthreads();
+        if (seg) {
+            if (tid == 0) {
+                sstart[0] = 0;
+                for (int p = 0; p < nseg; ++p) sstart[p + 1] += sstart[p];
+            }
+            __syncthreads();
+        }
         const float qsum = METRIC == LVQ_IP ? a.qsum[list] : 0.0f;
         QRegs<B1, CH, NCH> qr;
         if constexpr (QREG) {
@@ -486,14 +523,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
             // and the id after them are in flight while the current one is
             // consumed
             const int64_t e = e0 + my;
-            const int32_t s0 = e < e1 ? a.ids[e] : 0;
+            const int32_t s0 = e < e1 ? entry_id(a, e, e0, seg, sstart, sbase, nseg) : 0;
             load_pair<B1, B2, G, CH, NCH>(cur, a, e, e1, s0, 0, g, npieces);
             if constexpr (PIPE == 2) {
                 const int64_t e_1 = e + kPairsPerBlock;
-                const int32_t s1 = e_1 < e1 ? a.ids[e_1] : 0;
+                const int32_t s1 = e_1 < e1 ? entry_id(a, e_1, e0, seg, sstart, sbase, nseg) : 0;
                 load_pair<B1, B2, G, CH, NCH>(nx1, a, e_1, e1, s1, 0, g, npieces);
             }
-            slot_next = e + PIPE * kPairsPerBlock < e1 ? a.ids[e + PIPE * kPairsPerBlock] : 0;
+            slot_next = e + PIPE * kPairsPerBlock < e1
+                            ? entry_id(a, e + PIPE * kPairsPerBlock, e0, seg, sstart, sbase, nseg) : 0;
         }
         for (int64_t base = e0; base < e1; base += kPairsPerBlock) {
             const int64_t e = base + my;
@@ -507,7 +545,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
                 Regs nxt;
                 const int64_t en = e + PIPE * kPairsPerBlock;
                 load_pair<B1, B2, G, CH, NCH>(nxt, a, en, e1, slot_next, 0, g, npieces);
-                slot_next = en + kPairsPerBlock < e1 ? a.ids[en + kPairsPerBlock] : 0;
+                slot_next = en + kPairsPerBlock < e1 ? entry_id(a, en + kPairsPerBlock, e0, seg, sstart, sbase, nseg) : 0;
                 hdr = cur.hdr;
                 ep = cur.ep;
                 const float *tq = qtab + ((METRIC == LVQ_L2 && MULTI)
@@ -527,7 +565,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
                 }
             } else {
                 valid = e < e1;
-                slot = valid ? a.ids[e] : 0;
+                slot = valid ? entry_id(a, e, e0, seg, sstart, sbase, nseg) : 0;
                 Regs P;
                 load_pair<B1, B2, G, CH, NCH>(P, a, e, e1, slot, 0, g, npieces);
                 hdr = P.hdr;
@@ -604,10 +642,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 }
 
 // LDS bytes of one k_cand launch with per-wave key buffers of cw entries
-inline size_t cand_lds_bytes_impl(int kpos, int ntab, bool mask, int n_means_ip, int k, int cw, bool map)
+inline size_t cand_lds_bytes_impl(int kpos, int ntab, bool mask, int n_means_ip, int k, int cw, bool map, int nseg)
 {
     size_t b = (size_t)ntab * kpos * 4 + (mask ? (size_t)kpos * 4 : 0) + (size_t)((n_means_ip + 1) & ~1) * 4;
     if (map) b += kMaxMeans;
+    if (nseg > 0) b += (size_t)2 * (nseg + 1) * 8;
     b = (b + 15) & ~(size_t)15;
     if (k > 0) b += ((size_t)4 * cw + (size_t)4 * k) * 8;
     return b;

@@ -489,9 +489,9 @@ namespace lvq {
 
 int num_tile_shapes() { return kNumCandShapes; }
 TileShape tile_shape(int i) { return kCandShapes[i]; }
-size_t cand_lds_bytes(int kpos, int ntab, bool mask, int n_means_ip, int k, int cw, bool map)
+size_t cand_lds_bytes(int kpos, int ntab, bool mask, int n_means_ip, int k, int cw, bool map, int nseg)
 {
-    return cand_lds_bytes_impl(kpos, ntab, mask, n_means_ip, k, cw, map);
+    return cand_lds_bytes_impl(kpos, ntab, mask, n_means_ip, k, cw, map, nseg);
 }
 size_t scan_lds_bytes(int kpos, int n_means_ip, int k, int capq)
 {

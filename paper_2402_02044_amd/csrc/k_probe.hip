@@ -1,8 +1,8 @@
 // k_probe.hip -- M-LVQ as a soft inverted index (the Sec. 3.2 remark that a
 // query touches only a few centres): per-mean member lists of the occupied
 // slots, the routing of each query to its nprobe nearest means, and the
-// per-query candidate lists (the members of the probed means) that the
-// candidate kernel then scores.
+// per-query list offsets over the members of the probed means, which the
+// candidate kernel walks range by range.
 //
 // Routing ranks means by the Def. 1 distance s_m = sum_j (q_j - mu_mj)^2 in
 // binary32, summed in dimension order with every operation rounded on its own
@@ -207,22 +207,6 @@ __global__ __launch_bounds__(1024) void k_scan_i64(int64_t *v, int64_t n)
     if (threadIdx.x == 0) v[n] = carry;
 }
 
-// one workgroup per query copies the member ranges of its probed means
-__global__ __launch_bounds__(256) void k_probe_gather(const int32_t *probe, int64_t nq, int nprobe,
-                                                      const int64_t *moffs, const int32_t *members,
-                                                      const int64_t *qoffs, int32_t *qids)
-{
-    for (int64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
-        int64_t out = qoffs[qi];
-        for (int p = 0; p < nprobe; ++p) {
-            const int m = probe[qi * nprobe + p];
-            const int64_t a = moffs[m], b = moffs[m + 1];
-            for (int64_t i = a + threadIdx.x; i < b; i += 256) qids[out + (i - a)] = members[i];
-            out += b - a;
-        }
-    }
-}
-
 }  // namespace
 
 hipError_t launch_members(const int32_t *list, int64_t n, const uint8_t *rows, int row_bytes, int n_means,
@@ -293,14 +277,5 @@ hipError_t launch_probe_offsets(const int32_t *probe, int64_t nq, int nprobe, co
     return hipGetLastError();
 }
 
-hipError_t launch_probe_gather(const int32_t *probe, int64_t nq, int nprobe, const int64_t *moffs,
-                               const int32_t *members, const int64_t *qoffs, int32_t *qids, hipStream_t s)
-{
-    if (nq <= 0) return hipSuccess;
-    const int64_t blocks = std::min<int64_t>(nq, 65535);
-    hipLaunchKernelGGL(k_probe_gather, dim3((unsigned)blocks), dim3(256), 0, s, probe, nq, nprobe, moffs, members,
-                       qoffs, qids);
-    return hipGetLastError();
-}
 
 }  // namespace lvq

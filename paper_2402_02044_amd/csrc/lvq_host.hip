@@ -593,13 +593,16 @@ int lvq_consolidate(lvq_index *ix, void *stream, int64_t *n_freed_out)
 int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev,
                         const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev, int32_t k,
                         int32_t *topk_ids_dev, float *topk_dist_dev, hipStream_t s, int force_shape,
-                        uint32_t epoch, bool neg_empty, const int32_t *list_means, int list_nmeans)
+                        uint32_t epoch, bool neg_empty, const int32_t *list_means, int list_nmeans,
+                        const int64_t *seg_offs, const int32_t *seg_members)
 {
     if (!ix || nq < 0 || total < 0 || nq > INT32_MAX) return LVQ_ERR_INVALID_ARG;
+    const bool segmented = seg_members != nullptr;
+    if (segmented && (!seg_offs || !list_means)) return LVQ_ERR_INVALID_ARG;
     if (level != LVQ_PRIMARY && level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
     if (k < 0 || k > kMaxTopK) return LVQ_ERR_INVALID_ARG;
     if (nq == 0) return LVQ_OK;
-    if (!q_dev || !offsets_dev || (total > 0 && !ids_dev)) return LVQ_ERR_INVALID_ARG;
+    if (!q_dev || !offsets_dev || (total > 0 && !ids_dev && !segmented)) return LVQ_ERR_INVALID_ARG;
     if (k == 0 && !dist_dev) return LVQ_ERR_INVALID_ARG;
     if (k > 0 && (!topk_ids_dev || !topk_dist_dev)) return LVQ_ERR_INVALID_ARG;
     if (ix->cfg.capacity == 0) return LVQ_ERR_INVALID_ARG;
@@ -619,23 +622,24 @@ int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int
     void *kern = shape >= 0 ? lookup(bits2, variant, shape) : nullptr;
     if (!kern) return LVQ_ERR_UNSUPPORTED;
     const bool sub = multi && list_means != nullptr;
-    if (sub && (list_nmeans < 1 || list_nmeans > ix->n_means)) return LVQ_ERR_INVALID_ARG;
+    if (list_means && (list_nmeans < 1 || list_nmeans > ix->n_means)) return LVQ_ERR_INVALID_ARG;
+    const int nseg = segmented ? list_nmeans : 0;
     const int ntab = multi ? (sub ? list_nmeans : ix->n_means) : 1;
     // top-k key buffer per wave: about 2k + one block of candidates (a block
     // holds at most 32 per wave), at least 64 and at most 2048 entries,
     // halved while the launch does not fit the workgroup's LDS
     int cw = 64;
     while (cw < 2 * k + 32 && cw < 2048) cw *= 2;
-    size_t lds = cand_lds_bytes(f.kpos, ntab, masked, l2 ? 0 : ix->n_means, k, cw, sub);
+    size_t lds = cand_lds_bytes(f.kpos, ntab, masked, l2 ? 0 : ix->n_means, k, cw, sub, nseg);
     while (lds > ix->lds_max && cw / 2 >= k + 32) {
         cw /= 2;
-        lds = cand_lds_bytes(f.kpos, ntab, masked, l2 ? 0 : ix->n_means, k, cw, sub);
+        lds = cand_lds_bytes(f.kpos, ntab, masked, l2 ? 0 : ix->n_means, k, cw, sub, nseg);
     }
     if (lds > ix->lds_max) return LVQ_ERR_UNSUPPORTED;
     // several means: a second set of tables keeps the means in LDS if it fits
     int mu_lds = 0;
     if (multi && !sub) {
-        const size_t with = cand_lds_bytes(f.kpos, 2 * ntab, masked, 0, k, cw);
+        const size_t with = cand_lds_bytes(f.kpos, 2 * ntab, masked, 0, k, cw, false, nseg);
         if (with <= ix->lds_max) {
             mu_lds = 1;
             lds = with;
@@ -676,8 +680,10 @@ int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int
     a.neg_empty = neg_empty ? 1 : 0;
     a.cw = cw;
     a.mu_lds = mu_lds;
-    a.list_means = sub ? list_means : nullptr;
-    a.list_nmeans = sub ? list_nmeans : 0;
+    a.list_means = (sub || segmented) ? list_means : nullptr;
+    a.list_nmeans = (sub || segmented) ? list_nmeans : 0;
+    a.seg_offs = segmented ? seg_offs : nullptr;
+    a.seg_members = segmented ? seg_members : nullptr;
     // persistent launch: lists longest-first from a device work counter
     a.order = P<int32_t>(w.order);
     a.queue = P<int32_t>(w.queue);
@@ -1010,7 +1016,6 @@ static int probe_topk(lvq_index *ix, const float *q_dev, int64_t nq, int32_t npr
     if (level == LVQ_FULL && ix->f.bits2 == 0) return LVQ_ERR_INVALID_ARG;
     const int M = ix->n_means;
     if (nprobe < 1 || nprobe > M) return LVQ_ERR_INVALID_ARG;
-    if (ix->capturing) return LVQ_ERR_UNSUPPORTED;   // sizes the lists on the host
     if (nq == 0) return LVQ_OK;
     if (!q_dev || !ids_dev || !dist_dev || ix->cfg.capacity == 0) return LVQ_ERR_INVALID_ARG;
     int rc = order_after_updates(ix, s);
@@ -1025,14 +1030,10 @@ static int probe_topk(lvq_index *ix, const float *q_dev, int64_t nq, int32_t npr
     if ((rc = dev_alloc(ix, w.qoffs, sizeof(int64_t) * (size_t)(nq + 1)))) return rc;
     LVQ_HIP(launch_route(q_dev, nq, ix->f.dim, P<float>(ix->means_t), kMaxMeans, M, nprobe, probe, s));
     LVQ_HIP(launch_probe_offsets(probe, nq, nprobe, P<int64_t>(w.moffs), P<int64_t>(w.qoffs), s));
-    int64_t total = 0;
-    LVQ_HIP(hipMemcpyAsync(&total, P<int64_t>(w.qoffs) + nq, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    LVQ_HIP(hipStreamSynchronize(s));
-    if ((rc = dev_alloc(ix, w.qids, sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1)))) return rc;
-    LVQ_HIP(launch_probe_gather(probe, nq, nprobe, P<int64_t>(w.moffs), P<int32_t>(w.members), P<int64_t>(w.qoffs),
-                                P<int32_t>(w.qids), s));
-    return host_distances(ix, q_dev, nq, P<int64_t>(w.qoffs), P<int32_t>(w.qids), total, level, nullptr, k, ids_dev,
-                          dist_dev, s, -1, ix->epoch, true, probe, nprobe);
+    // the lists are the probed means' member ranges, walked in place
+    return host_distances(ix, q_dev, nq, P<int64_t>(w.qoffs), nullptr, INT64_MAX, level, nullptr, k, ids_dev,
+                          dist_dev, s, -1, ix->epoch, true, probe, nprobe, P<int64_t>(w.moffs),
+                          P<int32_t>(w.members));
 }
 
 extern "C" {

@@ -98,10 +98,14 @@ int host_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_
 // (no error, left out of the top-k) instead of an invalid one.  list_means
 // (nq x list_nmeans, optional): the only means the rows of each list can
 // belong to (L2 with several means then builds a list's tables for those).
+// seg_offs / seg_members (optional, with list_means): segmented lists, entry
+// i of list q being entry i of the concatenated member ranges of q's means
+// (ids_dev unused).
 int host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *offsets_dev,
                    const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev, int32_t k,
                    int32_t *topk_ids_dev, float *topk_dist_dev, hipStream_t s, int force_shape, uint32_t epoch,
-                   bool neg_empty, const int32_t *list_means = nullptr, int list_nmeans = 0);
+                   bool neg_empty, const int32_t *list_means = nullptr, int list_nmeans = 0,
+                   const int64_t *seg_offs = nullptr, const int32_t *seg_members = nullptr);
 
 // Mark the work queued so far on `s` as a query reading the store at `epoch`
 // (consolidation keeps the slots that query may still see).

@@ -96,8 +96,10 @@ struct CandArgs {
     int neg_empty;           // a negative id is an empty entry, not an error
     int cw;                  // top-k key buffer entries per wave (>= k + 32)
     int mu_lds;              // L2 with several means: keep muk in LDS for the launch
-    const int32_t *list_means;   // L2 with several means: the means each list's rows
-    int list_nmeans;             // belong to (nq x list_nmeans), or NULL for any mean
+    const int32_t *list_means;   // the means each list's rows belong to (nq x list_nmeans),
+    int list_nmeans;             // or NULL for any mean
+    const int64_t *seg_offs;     // segmented lists: member ranges per mean (n_means + 1) and the
+    const int32_t *seg_members;  // members; a list is its means' ranges in list_means order
 };
 
 struct ScanArgs {
@@ -149,7 +151,8 @@ void *cand_kernel_b4(int bits2, int variant, int shape);
 void *cand_kernel_b8(int bits2, int variant, int shape);
 void *scan_kernel_b4(int bits2, int variant, int shape);
 void *scan_kernel_b8(int bits2, int variant, int shape);
-size_t cand_lds_bytes(int kpos, int ntab, bool mask, int n_means_ip, int k, int cw, bool map = false);
+size_t cand_lds_bytes(int kpos, int ntab, bool mask, int n_means_ip, int k, int cw, bool map = false,
+                      int nseg = 0);
 size_t scan_lds_bytes(int kpos, int n_means_ip, int k, int capq);
 int scan_capq(int kpos, int n_means_ip, int k, int rows_per_round, size_t lds_max);
 int scan_rows_per_round(int g);
@@ -157,7 +160,7 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 // Soft inverted index (k_probe.hip): per-mean member lists of `list`
 // (counts, cursor: n_means entries; offsets: n_means + 1; members: n entries,
 // filled beforehand with -1), routing of queries to their nprobe nearest
-// means, and the candidate lists of the probed means (qoffs: nq + 1).
+// means, and the list offsets of the probed means' members (qoffs: nq + 1).
 hipError_t launch_members(const int32_t *list, int64_t n, const uint8_t *rows, int row_bytes, int n_means,
                           unsigned long long *counts, unsigned long long *cursor, int64_t *offsets,
                           int32_t *members, hipStream_t s);
@@ -173,8 +176,7 @@ hipError_t launch_mean_counts(const int32_t *list, int64_t n, const uint8_t *row
 hipError_t launch_members_live(const int32_t *req, int nreq, const int64_t *moffs, const int32_t *members,
                                const uint8_t *rows, int row_bytes, uint32_t epoch, const int64_t *out_offs,
                                int32_t *out, unsigned long long *counts, hipStream_t s);
-hipError_t launch_probe_gather(const int32_t *probe, int64_t nq, int nprobe, const int64_t *moffs,
-                               const int32_t *members, const int64_t *qoffs, int32_t *qids, hipStream_t s);
+
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_list_order(const int64_t *offsets, int64_t nq, int32_t *order, int32_t *scratch,
                              hipStream_t s);

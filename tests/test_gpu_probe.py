@@ -7,6 +7,7 @@
   are live (values within the similarity tolerance, ranking as check_topk).
 * After inserts, deletes and a consolidation the member lists follow the
   store (they are rebuilt by the first call after an update).
+* A captured call replays to the eager result.
 """
 import numpy as np
 import pytest
@@ -114,5 +115,50 @@ def test_probe_topk_rejects_bad_arguments(L):
     # an empty batch is a no-op
     probe, ids, dist = ix.probe_topk(q[:0], 2, 5)
     assert probe.shape == (0, 2)
+    assert ix.sync() == 0
+    ix.close()
+
+
+def test_probe_topk_graph_replays_match_eager(L):
+    g = synth.rng(8301, 0)
+    d, M, n, nq = 96, 24, 5000, 33
+    cent = g.standard_normal((M, d)).astype(np.float32)
+    X = (cent[g.integers(0, M, n)] + 0.4 * g.standard_normal((n, d))).astype(np.float32)
+    Q = (cent[g.integers(0, M, nq)] + 0.4 * g.standard_normal((nq, d))).astype(np.float32)
+    ix = L.Index(d, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=n, means=cent)
+    ix.insert(torch.from_numpy(X).cuda())
+    assert ix.sync() == 0
+    qd = torch.from_numpy(Q).cuda()
+    probe0, ti0, td0 = ix.probe_topk(qd, 3, 10)
+    assert ix.sync() == 0
+    probe = torch.empty_like(probe0)
+    ti = torch.empty_like(ti0)
+    td = torch.empty_like(td0)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+
+    def call(stream):
+        L.lvq_probe_topk(ix.handle, qd.data_ptr(), nq, 3, 10, L.LVQ_PRIMARY, probe.data_ptr(), ti.data_ptr(),
+                         td.data_ptr(), int(stream.cuda_stream))
+
+    with torch.cuda.stream(s):
+        call(s)                               # builds this stream's member lists and buffers
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        call(s)
+    torch.cuda.synchronize()
+    for r in range(4):
+        probe.fill_(-3)
+        ti.fill_(-7)
+        td.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(probe, probe0), r
+        assert torch.equal(ti, ti0), r
+        assert torch.equal(td, td0), r
+        _ = ix.probe_topk(qd, 2, 5)           # eager work between replays
+        torch.cuda.synchronize()
     assert ix.sync() == 0
     ix.close()
