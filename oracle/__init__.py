@@ -265,6 +265,48 @@ def topk_exhaustive(fmt: Format, metric, level, Q, rows, resid, means, k, live=N
     return out_s, out_v
 
 
+def greedy_search(fmt: Format, metric, level, q, rows, resid, means, graph, entries, W, k, live=None):
+    """Greedy graph search (Alg. 1) for one query, in the paper's steps: the
+    candidate set starts as the entry nodes; while it holds an unexplored
+    node, the closest one is explored and its out-neighbours join the set,
+    which is then cut to the W closest; the result is the k closest.  Nodes
+    are ranked by similarity, ties to the lower slot (Sec. 2.1); deleted rows
+    are traversed but left out of the result (App. A, lazy deletes).
+
+    A node proposed once is never proposed again: the W-th best rank of the
+    set never worsens, so a node cut from the set could not re-enter it.
+    graph: n x R slots, -1 for no edge.  Returns (slots, values) of length
+    <= k, best first, and the number of nodes explored."""
+    q = np.asarray(q, np.float32)[None, :]
+
+    def score(slots):
+        slots = np.asarray(slots, np.int32)
+        return distances(fmt, metric, level, q, rows, resid, means, np.array([0, slots.size], np.int64), slots)
+
+    def rank(item):
+        slot, v = item
+        return (v if metric == L2 else -v, slot)
+
+    entries = sorted(set(int(e) for e in entries))
+    cand = dict(zip(entries, score(entries)))
+    seen = set(entries)
+    explored = set()
+    while True:
+        open_ = [it for it in cand.items() if it[0] not in explored]
+        if not open_:
+            break
+        x = min(open_, key=rank)[0]
+        explored.add(x)
+        new = [int(y) for y in graph[x] if y >= 0 and int(y) not in seen]
+        seen.update(new)
+        if new:
+            cand.update(zip(new, score(new)))
+        if len(cand) > W:
+            cand = dict(sorted(cand.items(), key=rank)[:W])
+    out = [it for it in sorted(cand.items(), key=rank) if live is None or live[it[0]]][:k]
+    return (np.array([s for s, _ in out], np.int32), np.array([v for _, v in out], np.float64), len(explored))
+
+
 def eps1(fmt: Format, X, rows, means) -> float:
     """Eq. 4 first-level quantisation error (sum over vectors)."""
     f = fmt._c()
