@@ -203,6 +203,24 @@ int lvq_probe_topk(lvq_index *index, const float *q_dev, int64_t nq, int32_t npr
                    int32_t level, int32_t *probe_out_dev, int32_t *ids_dev, float *dist_dev,
                    void *stream);
 
+/* Greedy graph search (Alg. 1) with first-level similarities (Sec. 2.3: the
+ * first level traverses; re-rank the result with lvq_distances at both
+ * levels).  graph_dev: capacity x degree int32 out-neighbour slots of every
+ * stored slot (-1: no edge; 1 <= degree <= 64); entries_dev: n_entries start
+ * nodes shared by all queries (1 <= n_entries <= 64).  Per query the
+ * candidate set starts at the entries; the closest unexplored node is
+ * explored, its out-neighbours not proposed before join the set, and the set
+ * is cut to the `window` closest (1 <= k <= window <= 256); ranks are
+ * lvq_distances' similarities, ties to the lower slot.  Deleted rows are
+ * traversed but left out of the result: ids_dev / dist_dev (nq x k) hold the
+ * k best live nodes of the final set, padded as for lvq_distances;
+ * explored_dev (nq, may be NULL) the number of nodes explored.  A query that
+ * proposes more than 16384 distinct nodes stops there and sets the sticky
+ * error (lvq_sync reports LVQ_ERR_INVALID_ARG).                           */
+int lvq_graph_search(lvq_index *index, const float *q_dev, int64_t nq, const int32_t *graph_dev,
+                     int32_t degree, const int32_t *entries_dev, int32_t n_entries, int32_t window,
+                     int32_t k, int32_t *ids_dev, float *dist_dev, int32_t *explored_dev, void *stream);
+
 /* Online re-estimation of M-LVQ means with selective re-encoding (Sec. 3.2;
  * updating means needs the rows of the moved centres re-encoded).
  *

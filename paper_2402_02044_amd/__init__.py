@@ -37,7 +37,7 @@ LVQ_ERR_BAD_SLOT = -7
 
 EXPORTS = ["lvq_row_format", "lvq_create", "lvq_destroy", "lvq_set_means", "lvq_encode", "lvq_insert",
            "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_topk", "lvq_probe_topk", "lvq_retire_means",
-           "lvq_add_means", "lvq_mean_members", "lvq_read_rows",
+           "lvq_add_means", "lvq_mean_members", "lvq_graph_search", "lvq_read_rows",
            "lvq_get_stats", "lvq_sync", "lvq_mean", "lvq_kmeans", "lvq_strerror", "lvq_set_timing",
            "lvq_kernel_time", "lvq_autotune", "lvq_set_tile", "lvq_server_create", "lvq_server_submit",
            "lvq_server_wait", "lvq_server_drain", "lvq_server_get_stats", "lvq_server_destroy",
@@ -104,6 +104,7 @@ def _load():
         "lvq_retire_means": [P, P, i32, P],
         "lvq_add_means": [P, P, i32, P, P],
         "lvq_mean_members": [P, P, i32, P, P, i64, P],
+        "lvq_graph_search": [P, P, i64, P, i32, P, i32, i32, i32, P, P, P, P],
         "lvq_read_rows": [P, P, i64, P, P, P],
         "lvq_get_stats": [P, ctypes.POINTER(lvq_stats)],
         "lvq_sync": [P, P],
@@ -205,6 +206,11 @@ def lvq_retire_means(ix, ids_host, n, stream=0):
 
 def lvq_add_means(ix, means_host, n, ids_out_host, stream=0):
     return _chk(_lib.lvq_add_means(ix, means_host, n, ids_out_host, stream), "lvq_add_means")
+
+
+def lvq_graph_search(ix, q, nq, graph, degree, entries, n_entries, window, k, ids, dist, explored, stream=0):
+    return _chk(_lib.lvq_graph_search(ix, q, nq, graph, degree, entries, n_entries, window, k, ids, dist, explored,
+                                      stream), "lvq_graph_search")
 
 
 def lvq_mean_members(ix, ids_host, n, offsets_host, slots, cap, stream=0):
@@ -397,6 +403,25 @@ class Index:
         lvq_probe_topk(self.handle, _ptr(q), nq, nprobe, k, level, _ptr(probe), _ptr(ids), _ptr(dist),
                        _stream(stream))
         return probe, ids, dist
+
+    def graph_search(self, q, graph, entries, window, k, stream=None):
+        """Greedy graph search: (ids nq x k, values nq x k, explored nq).
+
+        graph: (capacity x degree) contiguous int32 on the device -- the
+        kernel reads the row of every slot a walk reaches."""
+        import torch
+        if (graph.dim() != 2 or graph.dtype != torch.int32 or not graph.is_contiguous()
+                or graph.shape[0] < self.stats().capacity):
+            raise LVQError(LVQ_ERR_INVALID_ARG, "graph must be a contiguous int32 (capacity x degree) tensor")
+        if entries.dtype != torch.int32 or entries.dim() != 1 or not entries.is_contiguous():
+            raise LVQError(LVQ_ERR_INVALID_ARG, "entries must be a contiguous int32 vector")
+        nq = q.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int32, device=q.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+        explored = torch.empty(nq, dtype=torch.int32, device=q.device)
+        lvq_graph_search(self.handle, _ptr(q), nq, _ptr(graph), graph.shape[1], _ptr(entries), entries.shape[0],
+                         window, k, _ptr(ids), _ptr(dist), _ptr(explored), _stream(stream))
+        return ids, dist, explored
 
     def retire_means(self, ids, stream=None):
         import numpy as np

@@ -1052,6 +1052,62 @@ int lvq_probe_topk(lvq_index *ix, const float *q_dev, int64_t nq, int32_t nprobe
     return rc;
 }
 
+int lvq_graph_search(lvq_index *ix, const float *q_dev, int64_t nq, const int32_t *graph_dev, int32_t degree,
+                     const int32_t *entries_dev, int32_t n_entries, int32_t window, int32_t k, int32_t *ids_dev,
+                     float *dist_dev, int32_t *explored_dev, void *stream)
+{
+    if (!ix || nq < 0 || nq > INT32_MAX || degree < 1 || degree > 64 || n_entries < 1 || n_entries > 64 ||
+        k < 1 || window < k || window > 256)
+        return LVQ_ERR_INVALID_ARG;
+    if (nq > 0 && (!q_dev || !graph_dev || !entries_dev || !ids_dev || !dist_dev)) return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    if (ix->cfg.capacity == 0) return LVQ_ERR_INVALID_ARG;
+    const Format &f = ix->f;
+    if (graph_lds_bytes(f.kpos, window) > ix->lds_max) return LVQ_ERR_UNSUPPORTED;
+    if (nq == 0) return LVQ_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = begin_call(ix, s);
+    if (rc) return rc;
+    if ((rc = order_after_updates(ix, s)) == LVQ_OK) {
+        Workspace &w = workspace(ix, s);
+        if ((rc = prep_queries(ix, w, q_dev, nq, s)) == LVQ_OK) {
+            GraphLaunch l;
+            l.rows = P<uint8_t>(ix->rows);
+            l.row_bytes = f.row_bytes;
+            l.kchunks = f.kchunks;
+            l.kpos = f.kpos;
+            l.bits1 = f.bits1;
+            l.metric = ix->cfg.metric;
+            l.capacity = ix->cfg.capacity;
+            l.qk = P<float>(w.qk);
+            l.qsum = P<float>(w.qsum);
+            l.cm = P<float>(w.cm);
+            l.muk = P<float>(ix->muk);
+            l.kmask = P<float>(ix->kmask);
+            l.n_means = ix->n_means;
+            l.nq = nq;
+            l.graph = graph_dev;
+            l.degree = degree;
+            l.entries = entries_dev;
+            l.n_entries = n_entries;
+            l.window = window;
+            l.k = k;
+            l.epoch = ix->epoch;
+            l.ids = ids_dev;
+            l.dist = dist_dev;
+            l.explored = explored_dev;
+            l.err = P<uint32_t>(ix->err);
+            if ((rc = timing_begin(ix, s)) == LVQ_OK) {
+                hipError_t e = launch_graph_search(l, s);
+                rc = e == hipSuccess ? timing_end(ix, s) : map_hip(e);
+            }
+        }
+    }
+    if (rc == LVQ_OK) rc = note_query(ix, s, ix->epoch);
+    ix->capturing = false;
+    return rc;
+}
+
 int lvq_retire_means(lvq_index *ix, const int32_t *ids_host, int32_t n, void *stream)
 {
     if (!ix || n < 0 || (n > 0 && !ids_host)) return LVQ_ERR_INVALID_ARG;

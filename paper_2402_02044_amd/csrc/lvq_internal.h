@@ -168,6 +168,28 @@ hipError_t launch_route(const float *q, int64_t nq, int dim, const float *means_
                         int nprobe, int32_t *probe, hipStream_t s);
 hipError_t launch_probe_offsets(const int32_t *probe, int64_t nq, int nprobe, const int64_t *moffs, int64_t *qoffs,
                                 hipStream_t s);
+// Greedy graph search (k_graph.hip): one workgroup per query.
+struct GraphLaunch {
+    const uint8_t *rows;
+    int row_bytes, kchunks, kpos, bits1, metric;
+    int64_t capacity;
+    const float *qk, *qsum, *cm, *muk, *kmask;
+    int n_means;
+    int64_t nq;
+    const int32_t *graph;    // capacity x degree slots, -1: no edge
+    int degree;
+    const int32_t *entries;
+    int n_entries;
+    int window, k;
+    uint32_t epoch;
+    int32_t *ids;
+    float *dist;
+    int32_t *explored;       // nq, may be NULL
+    uint32_t *err;
+};
+size_t graph_lds_bytes(int kpos, int window);
+hipError_t launch_graph_search(const GraphLaunch &l, hipStream_t s);
+
 hipError_t launch_mean_counts(const int32_t *list, int64_t n, const uint8_t *rows, int row_bytes, int n_means,
                               unsigned long long *counts, hipStream_t s);
 // Live members (flag set, insert epoch <= epoch < delete epoch) of the means

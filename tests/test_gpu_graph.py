@@ -1,0 +1,134 @@
+"""Greedy graph search (lvq_graph_search of the C ABI) against the oracle's
+Alg. 1.
+
+* Complete graph and a window holding every node: the result is the
+  exhaustive top-k (oracle values within tolerance, ranking as check_topk).
+* A k-NN graph with random long edges: per query the GPU follows the
+  oracle's walk -- same result and the same number of explored nodes -- for
+  nearly every query (a near-tie decided differently in binary32 and binary64
+  may send a walk elsewhere); every returned node is live, its value matches
+  the oracle's within tolerance, and the results are ordered.
+* Deleted rows are traversed but never returned.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from lvq_check import check_topk, check_values, pair_reference
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2402_02044_amd as lib
+    return lib
+
+
+def _knn_graph(g, X, r_near, r_far):
+    """r_near exact nearest neighbours (binary64 L2) and r_far random nodes."""
+    X = X.astype(np.float64)
+    d2 = (X * X).sum(1)[:, None] - 2.0 * X @ X.T + (X * X).sum(1)[None, :]
+    np.fill_diagonal(d2, np.inf)
+    near = np.argsort(d2, axis=1, kind="stable")[:, :r_near]
+    far = g.integers(0, X.shape[0], (X.shape[0], r_far))
+    return np.concatenate([near, far], 1).astype(np.int32)
+
+
+def test_complete_graph_is_exhaustive(L):
+    g = synth.rng(8600, 0)
+    d, n = 48, 60
+    X = g.standard_normal((n, d)).astype(np.float32)
+    Q = g.standard_normal((9, d)).astype(np.float32)
+    mu = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    fmt = oracle.Format(d, 8, 0, oracle.SEQUENTIAL)
+    rows, _, _ = oracle.encode_rows(fmt, X, mu)
+    ix = L.Index(d, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=n, means=mu)
+    ix.insert(torch.from_numpy(X).cuda())
+    graph = np.array([[j for j in range(n) if j != i] for i in range(n)], np.int32)
+    ids, dist, explored = ix.graph_search(torch.from_numpy(Q).cuda(), torch.from_numpy(graph).cuda(),
+                                          torch.tensor([5], dtype=torch.int32, device="cuda"), n, 10)
+    assert ix.sync() == 0
+    ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
+    assert (explored.cpu().numpy() == n).all()
+    allids = np.arange(n, dtype=np.int32)
+    offs = np.arange(Q.shape[0] + 1, dtype=np.int64) * n
+    ref, tol = pair_reference(fmt, oracle.L2, oracle.PRIMARY, Q, rows, None, mu, offs, np.tile(allids, Q.shape[0]))
+    for i in range(Q.shape[0]):
+        a, b = offs[i], offs[i + 1]
+        check_topk(oracle.L2, ids[i], dist[i], allids, ref[a:b], tol[a:b], 10)
+    ix.close()
+
+
+CASES = [
+    # d, b1, layout, metric, M
+    (64, 8, oracle.SEQUENTIAL, oracle.L2, 1),
+    (128, 4, oracle.TURBO, oracle.IP, 3),
+    (100, 8, oracle.SEQUENTIAL, oracle.L2, 4),
+]
+
+
+@pytest.mark.parametrize("d,b1,layout,metric,M", CASES)
+def test_walks_follow_the_oracle(L, d, b1, layout, metric, M):
+    g = synth.rng(8700 + d, M)
+    n, nq, W, k = 1500, 40, 48, 10
+    cent = g.standard_normal((12, d)).astype(np.float32)
+    X = (cent[g.integers(0, 12, n)] + 0.5 * g.standard_normal((n, d))).astype(np.float32)
+    Q = (cent[g.integers(0, 12, nq)] + 0.5 * g.standard_normal((nq, d))).astype(np.float32)
+    if metric == oracle.IP:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+        Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    means = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32) if M == 1 \
+        else X[g.choice(n, M, replace=False)]
+    fmt = oracle.Format(d, b1, 0, layout)
+    rows, _, _ = oracle.encode_rows(fmt, X, means)
+    graph = _knn_graph(g, X, 12, 4)
+    entries = np.array([0, 700, 1400], np.int32)
+    ix = L.Index(d, b1, 0, metric, layout, capacity=n, means=means)
+    ix.insert(torch.from_numpy(X).cuda())
+    live = np.ones(n, bool)
+    dead = np.sort(g.choice(n, 150, replace=False)).astype(np.int32)
+    ix.delete(torch.from_numpy(dead).cuda())
+    live[dead] = False
+    assert ix.sync() == 0
+    ids, dist, explored = ix.graph_search(torch.from_numpy(Q).cuda(), torch.from_numpy(graph).cuda(),
+                                          torch.from_numpy(entries).cuda(), W, k)
+    assert ix.sync() == 0
+    ids, dist, explored = ids.cpu().numpy(), dist.cpu().numpy(), explored.cpu().numpy()
+    same = 0
+    for i in range(nq):
+        os_, ov, ne = oracle.greedy_search(fmt, metric, oracle.PRIMARY, Q[i], rows, None, means, graph, entries, W,
+                                           k, live)
+        got = ids[i][ids[i] >= 0]
+        assert live[got].all(), "a deleted row was returned"
+        assert not np.isin(got, dead).any()
+        if np.array_equal(got, os_) and explored[i] == ne:
+            same += 1
+        # every returned value is the oracle's for that node
+        offs = np.array([0, got.size], np.int64)
+        ref, tol = pair_reference(fmt, metric, oracle.PRIMARY, Q[i:i + 1], rows, None, means, offs, got)
+        check_values(dist[i][:got.size], ref, tol, "query %d" % i)
+        srt = dist[i][:got.size] if metric == oracle.L2 else -dist[i][:got.size]
+        assert np.all(np.diff(srt) >= 0), "not ordered"
+    assert same >= int(0.9 * nq), "only %d of %d walks follow the oracle" % (same, nq)
+    ix.close()
+
+
+def test_graph_search_rejects_bad_arguments(L):
+    g = synth.rng(8800, 0)
+    means = g.standard_normal((1, 32)).astype(np.float32)
+    ix = L.Index(32, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=100, means=means)
+    ix.insert(torch.from_numpy(g.standard_normal((100, 32)).astype(np.float32)).cuda())
+    q = torch.from_numpy(g.standard_normal((3, 32)).astype(np.float32)).cuda()
+    graph = torch.zeros((100, 8), dtype=torch.int32, device="cuda")
+    e = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for window, k in ((5, 10), (300, 10), (10, 0)):
+        with pytest.raises(L.LVQError):
+            ix.graph_search(q, graph, e, window, k)
+    with pytest.raises(L.LVQError):
+        ix.graph_search(q, torch.zeros((100, 65), dtype=torch.int32, device="cuda"), e, 16, 4)
+    ix.close()
