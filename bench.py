@@ -704,6 +704,125 @@ def bench_probe(args):
 
 
 # ---------------------------------------------------------------------------
+# Greedy graph search (Alg. 1) over LVQ-8 codes: queries/s against recall
+# ---------------------------------------------------------------------------
+
+def knn_random_graph(X, r_near, r_far, dev, chunk=2048):
+    """Harness input (not the method): each row's out-neighbours are its r_near
+    nearest rows (binary32 L2 on the GPU, itself excluded) and r_far uniform
+    random rows, the long edges that make the graph navigable."""
+    import torch
+
+    import synth
+    x = torch.from_numpy(X).to(dev)
+    sq = (x * x).sum(1)
+    n = x.shape[0]
+    out = torch.empty((n, r_near + r_far), dtype=torch.int32, device=dev)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        d2 = torch.addmm(sq[None, :], x[a:b], x.T, beta=1.0, alpha=-2.0)
+        d2 += sq[a:b, None]
+        d2[torch.arange(b - a, device=dev), torch.arange(a, b, device=dev)] = float("inf")
+        out[a:b, :r_near] = torch.topk(d2, r_near, dim=1, largest=False).indices.int()
+        del d2
+    g = synth.rng(6, synth.S_LISTS)
+    out[:, r_near:] = torch.from_numpy(g.integers(0, n, (n, r_far)).astype(np.int32)).to(dev)
+    torch.cuda.synchronize()
+    return out
+
+
+def bench_graph(args):
+    import torch
+
+    import paper_2402_02044_amd as L
+    import synth
+    n, nq, d, k = args.n or 1_000_000, args.nq or 10_000, 96, 10
+    r_near, r_far = 24, 8
+    R = r_near + r_far
+    log("generating %d x %d base vectors (G1), %d queries" % (n, d, nq))
+    X = synth.vectors("G1", synth.S_BASE, 0, n)
+    Q = synth.vectors("G1", synth.S_QUERY, 0, nq)
+    dev = torch.device("cuda:0")
+    mu = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    log("uploading and encoding the store")
+    ix = L.Index(d, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=n, means=mu)
+    enc_ms = to_gpu_rows(ix, X, dev)
+    log("graph: %d nearest + %d random out-neighbours per row" % (r_near, r_far))
+    t = time.perf_counter()
+    graph = knn_random_graph(X, r_near, r_far, dev)
+    graph_s = time.perf_counter() - t
+    # one entry node: the row nearest to the data mean (the medoid's stand-in)
+    xd = torch.from_numpy(X).to(dev)
+    entry = torch.argmin(((xd - torch.from_numpy(mu).to(dev)) ** 2).sum(1)).to(torch.int32).reshape(1)
+    del xd
+    ns = 1000
+    log("exact float top-%d of %d queries" % (k, ns))
+    gt = exact_topk(0, Q[:ns], X, k)
+    qd = torch.from_numpy(Q).to(dev)
+    ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    cnt = torch.empty((nq, 2), dtype=torch.int32, device=dev)
+    s = int(torch.cuda.current_stream().cuda_stream)
+    row_bytes = ix.row_bytes
+    points = []
+    for W in (16, 24, 32, 48, 64, 96, 128):
+
+        def step():
+            L.lvq_graph_search(ix.handle, qd.data_ptr(), nq, graph.data_ptr(), R, entry.data_ptr(), 1, W, k,
+                               ids.data_ptr(), dist.data_ptr(), cnt.data_ptr(), s)
+
+        ms, k_ms = timed(step, args.steps, args.warmup, ix)
+        assert ix.sync() == 0
+        c = cnt.cpu().numpy().astype(np.int64)
+        rec = recall_at_k(ids[:ns].cpu().numpy(), gt)
+        # algorithmic bytes: the query (kernel order), each explored node's
+        # graph row, each scored node's code row
+        nbytes = int(nq * d * 4 + c[:, 0].sum() * R * 4 + c[:, 1].sum() * row_bytes)
+        points.append({"window": W, "ms_per_batch": ms, "kernel_ms": k_ms, "qps": nq / (ms / 1000.0),
+                       "explored_per_query": float(c[:, 0].mean()), "scored_per_query": float(c[:, 1].mean()),
+                       "distances_per_s": float(c[:, 1].sum()) / (ms / 1000.0), "recall_at_10": rec,
+                       "bytes_per_launch": nbytes})
+        log("W %3d: batch %.3f ms (kernel %.3f ms), %.0f q/s, explored %.0f, scored %.0f, recall@10 %.3f" %
+            (W, ms, k_ms, nq / (ms / 1000.0), c[:, 0].mean(), c[:, 1].mean(), rec))
+    head = next((p for p in points if p["recall_at_10"] >= 0.9), points[-1])
+    achieved = head["bytes_per_launch"] / (head["kernel_ms"] / 1000.0) / 1e9
+    out = line(head["qps"], "queries/s", args.steps, args.warmup, head["ms_per_batch"], "f32",
+               {"workload": "greedy graph search: n=1,000,000 d=96 (anisotropic, unit norm) LVQ-8 L2, graph of "
+                            "24 nearest + 8 random out-neighbours, one entry node; 10,000 queries, top-10; value "
+                            "at the smallest window W reaching recall@10 >= 0.9",
+                "n": n, "dim": d, "degree": R, "queries": nq, "k": k, "window": head["window"]},
+               {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_graph_search (one workgroup per query; a chain of dependent steps per query)",
+                "kernel_ms": head["kernel_ms"],
+                "algorithmic_bytes": "d*4 per query + degree*4 per explored node + %d per scored node" % row_bytes},
+               distances_per_s=head["distances_per_s"], recall_at_10=head["recall_at_10"], operating_points=points,
+               recall_sample="%d queries against the exact float top-10" % ns, graph_setup_s=graph_s)
+    out["encode"] = encode_roofline(warm_encode_ms(ix, X, dev), n, d, ix.row_bytes, ix.resid_bytes, enc_ms)
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the oracle on a host-core sample")
+        fmt = oracle.Format(d, 8, 0)
+        rows, _, _ = oracle.encode_rows(fmt, X, mu)
+        g_host = graph.cpu().numpy()
+        e_host = entry.cpu().numpy()
+        # queries in order until 15 s of host time (at most 2000)
+        nqs = 0
+        t = time.perf_counter()
+        while nqs < 2000 and time.perf_counter() - t < 15.0:
+            oracle.greedy_search(fmt, oracle.L2, oracle.PRIMARY, Q[nqs], rows, None, mu, g_host, e_host,
+                                 head["window"], k)
+            nqs += 1
+        ct = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": nqs / ct, "unit": "queries/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d queries, window %d, over the whole store and graph; binary64 "
+                                         "similarities (scalar C) in a Python walk, %.2f s" %
+                                         (nqs, head["window"], ct)}
+    ix.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Turbo vs sequential 4-bit layout (the GPU analogue of the paper's Turbo
 # table, Sec. 3.1): first-level inner products over candidate lists
 # ---------------------------------------------------------------------------
@@ -1113,7 +1232,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "layouts", "probe", "means"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "layouts", "probe", "means", "graph"])
     ap.add_argument("--rounds", type=int, default=30, help="c5: update rounds")
     ap.add_argument("--sat-batches", type=int, default=60, help="c5: batches of each saturation burst")
     ap.add_argument("--lat-batches", type=int, default=120, help="c5: batches of each latency phase")
@@ -1147,7 +1266,8 @@ def main():
                           "launches": 5}), flush=True)
         return
     fn = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
-          "layouts": bench_layouts, "probe": bench_probe, "means": bench_means}[args.workload]
+          "layouts": bench_layouts, "probe": bench_probe, "means": bench_means,
+          "graph": bench_graph}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

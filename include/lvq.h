@@ -214,7 +214,8 @@ int lvq_probe_topk(lvq_index *index, const float *q_dev, int64_t nq, int32_t npr
  * lvq_distances' similarities, ties to the lower slot.  Deleted rows are
  * traversed but left out of the result: ids_dev / dist_dev (nq x k) hold the
  * k best live nodes of the final set, padded as for lvq_distances;
- * explored_dev (nq, may be NULL) the number of nodes explored.  A query that
+ * explored_dev (nq x 2 int32, may be NULL) the nodes explored and the nodes
+ * scored (entries and proposed neighbours) per query.  A query that
  * proposes more than 16384 distinct nodes stops there and sets the sticky
  * error (lvq_sync reports LVQ_ERR_INVALID_ARG).                           */
 int lvq_graph_search(lvq_index *index, const float *q_dev, int64_t nq, const int32_t *graph_dev,

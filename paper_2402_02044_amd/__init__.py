@@ -405,7 +405,8 @@ class Index:
         return probe, ids, dist
 
     def graph_search(self, q, graph, entries, window, k, stream=None):
-        """Greedy graph search: (ids nq x k, values nq x k, explored nq).
+        """Greedy graph search: (ids nq x k, values nq x k, counts nq x 2 --
+        nodes explored, nodes scored).
 
         graph: (capacity x degree) contiguous int32 on the device -- the
         kernel reads the row of every slot a walk reaches."""
@@ -418,7 +419,7 @@ class Index:
         nq = q.shape[0]
         ids = torch.empty((nq, k), dtype=torch.int32, device=q.device)
         dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
-        explored = torch.empty(nq, dtype=torch.int32, device=q.device)
+        explored = torch.empty((nq, 2), dtype=torch.int32, device=q.device)
         lvq_graph_search(self.handle, _ptr(q), nq, _ptr(graph), graph.shape[1], _ptr(entries), entries.shape[0],
                          window, k, _ptr(ids), _ptr(dist), _ptr(explored), _stream(stream))
         return ids, dist, explored

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
     uint64_t *scratch = qkey + W + kMaxDegree;                         // kMaxWindow (selection scratch)
     int32_t *hset = reinterpret_cast<int32_t *>(scratch + kMaxWindow); // kHash
     __shared__ int32_t s_new[kMaxDegree];
-    __shared__ int s_nnew, s_qn, s_pick, s_stop, s_explored;
+    __shared__ int s_nnew, s_qn, s_pick, s_stop, s_explored, s_scored;
 
     for (int p = tid; p < a.kpos; p += 256) {
         qt[p] = a.qk[qi * a.kpos + p];
@@ -129,6 +129,7 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
         s_nnew = 0;
         s_stop = 0;
         s_explored = 0;
+        s_scored = 0;
     }
     __syncthreads();
     GraphArgs b = a;
@@ -154,6 +155,7 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
     __syncthreads();
     if (wave == 0) {
         const int n0 = s_nnew;
+        if (lane == 0) s_scored = n0;
         const int got = wave_compact(qkey, n0, min(W, max(n0, 1)), scratch);
         if (lane == 0) s_qn = min(got, W);
     }
@@ -195,6 +197,7 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
         __syncthreads();
         if (wave == 0) {
             const int n = qn + s_nnew;
+            if (lane == 0) s_scored += s_nnew;
             const int got = wave_compact(qkey, n, W, scratch);
             if (lane == 0) s_qn = got;
         }
@@ -229,7 +232,10 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
             a.ids[qi * a.k + i] = -1;
             a.dist[qi * a.k + i] = METRIC == LVQ_L2 ? __uint_as_float(0x7F800000u) : __uint_as_float(0xFF800000u);
         }
-        if (lane == 0 && a.explored) a.explored[qi] = s_explored;
+        if (lane == 0 && a.explored) {
+            a.explored[2 * qi] = s_explored;
+            a.explored[2 * qi + 1] = s_scored;
+        }
     }
 }
 

@@ -19,6 +19,8 @@ Euclidean for the 96-d set):
   10^4 queries, candidate list lengths floor(exp(U(ln 64, ln 4097))).
 * ``C4``: the C2 law in 512-d; 5 * 10^6 base vectors, 10^4 queries.
 * ``C5``: 64 clusters in 768-d, unit normalised; centres drift each round.
+* ``G1``: the C2 law in 96-d (low intrinsic dimension, like the 96-d set the
+  paper searches with a graph); 10^6 base vectors, 10^4 queries, Euclidean.
 """
 from __future__ import annotations
 
@@ -40,6 +42,7 @@ WORKLOADS = {
                list_min=64, list_max=4096),
     "C4": dict(id=4, dim=512, n=5_000_000, nq=10_000, law="aniso"),
     "C5": dict(id=5, dim=768, n=1_000_000, nq=10_000, clusters=64, spread=0.3, law="mixture_unit"),
+    "G1": dict(id=6, dim=96, n=1_000_000, nq=10_000, law="aniso"),
 }
 
 

@@ -54,7 +54,8 @@ def test_complete_graph_is_exhaustive(L):
                                           torch.tensor([5], dtype=torch.int32, device="cuda"), n, 10)
     assert ix.sync() == 0
     ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
-    assert (explored.cpu().numpy() == n).all()
+    cnt = explored.cpu().numpy()
+    assert (cnt[:, 0] == n).all() and (cnt[:, 1] == n).all()   # every node explored and scored once
     allids = np.arange(n, dtype=np.int32)
     offs = np.arange(Q.shape[0] + 1, dtype=np.int64) * n
     ref, tol = pair_reference(fmt, oracle.L2, oracle.PRIMARY, Q, rows, None, mu, offs, np.tile(allids, Q.shape[0]))
@@ -106,7 +107,8 @@ def test_walks_follow_the_oracle(L, d, b1, layout, metric, M):
         got = ids[i][ids[i] >= 0]
         assert live[got].all(), "a deleted row was returned"
         assert not np.isin(got, dead).any()
-        if np.array_equal(got, os_) and explored[i] == ne:
+        assert 1 <= explored[i, 0] <= explored[i, 1]   # a node is scored before it is explored
+        if np.array_equal(got, os_) and explored[i, 0] == ne:
             same += 1
         # every returned value is the oracle's for that node
         offs = np.array([0, got.size], np.int64)
