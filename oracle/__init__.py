@@ -265,23 +265,16 @@ def topk_exhaustive(fmt: Format, metric, level, Q, rows, resid, means, k, live=N
     return out_s, out_v
 
 
-def greedy_search(fmt: Format, metric, level, q, rows, resid, means, graph, entries, W, k, live=None):
-    """Greedy graph search (Alg. 1) for one query, in the paper's steps: the
-    candidate set starts as the entry nodes; while it holds an unexplored
-    node, the closest one is explored and its out-neighbours join the set,
-    which is then cut to the W closest; the result is the k closest.  Nodes
-    are ranked by similarity, ties to the lower slot (Sec. 2.1); deleted rows
-    are traversed but left out of the result (App. A, lazy deletes).
+def _walk(score, metric, graph, entries, W, k, live=None):
+    """The steps of Alg. 1 around a scoring function (slots -> binary64
+    values): the candidate set starts as the entry nodes; while it holds an
+    unexplored node, the closest one is explored and its out-neighbours join
+    the set, which is then cut to the W closest; the result is the k closest.
+    Nodes are ranked by similarity, ties to the lower slot (Sec. 2.1); deleted
+    rows are traversed but left out of the result (App. A, lazy deletes).
 
     A node proposed once is never proposed again: the W-th best rank of the
-    set never worsens, so a node cut from the set could not re-enter it.
-    graph: n x R slots, -1 for no edge.  Returns (slots, values) of length
-    <= k, best first, and the number of nodes explored."""
-    q = np.asarray(q, np.float32)[None, :]
-
-    def score(slots):
-        slots = np.asarray(slots, np.int32)
-        return distances(fmt, metric, level, q, rows, resid, means, np.array([0, slots.size], np.int64), slots)
+    set never worsens, so a node cut from the set could not re-enter it."""
 
     def rank(item):
         slot, v = item
@@ -305,6 +298,112 @@ def greedy_search(fmt: Format, metric, level, q, rows, resid, means, graph, entr
             cand = dict(sorted(cand.items(), key=rank)[:W])
     out = [it for it in sorted(cand.items(), key=rank) if live is None or live[it[0]]][:k]
     return (np.array([s for s, _ in out], np.int32), np.array([v for _, v in out], np.float64), len(explored))
+
+
+def greedy_search(fmt: Format, metric, level, q, rows, resid, means, graph, entries, W, k, live=None):
+    """Greedy graph search (Alg. 1) for one query over LVQ rows, with the
+    similarities of ``distances`` at the given level.  graph: n x R slots, -1
+    for no edge.  Returns (slots, values) of length <= k, best first, and the
+    number of nodes explored."""
+    q = np.asarray(q, np.float32)[None, :]
+
+    def score(slots):
+        slots = np.asarray(slots, np.int32)
+        return distances(fmt, metric, level, q, rows, resid, means, np.array([0, slots.size], np.int64), slots)
+
+    return _walk(score, metric, graph, entries, W, k, live)
+
+
+def float_sim(metric, a, b) -> float:
+    """Similarity of two float vectors in binary64: the squared Euclidean
+    distance (L2, smaller is closer) or the inner product (IP)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(((a - b) ** 2).sum()) if metric == L2 else float((a * b).sum())
+
+
+def greedy_search_float(metric, q, X, graph, entries, W, k):
+    """Alg. 1 over float vectors X (binary64 similarities): the search that
+    graph construction runs for a node (App. A, initial build)."""
+
+    def score(slots):
+        return np.array([float_sim(metric, q, X[s]) for s in slots], np.float64)
+
+    return _walk(score, metric, graph, entries, W, k)
+
+
+def robust_prune(metric, X, p, cand, current, alpha, R):
+    """Neighbourhood pruning (Alg. 2) of node p over float vectors X.
+
+    The candidates are the given ones and p's current out-neighbours, without
+    p.  The closest candidate x* (ties to the lower slot) becomes an
+    out-neighbour and leaves the candidates; stop at R out-neighbours;
+    otherwise every candidate x' for which x* is at least alpha times as
+    similar as p is removed: for the inner product alpha * <x*, x'> >=
+    <p, x'>, for L2 (similarity = the squared distance, smaller is closer)
+    alpha * |x* - x'|^2 <= |p - x'|^2.  Returns the new out-neighbours in
+    selection order."""
+    C = sorted(set(int(c) for c in list(cand) + list(current) if c >= 0) - {int(p)})
+    sims = {c: float_sim(metric, X[p], X[c]) for c in C}
+    order = sorted(C, key=lambda c: (sims[c] if metric == L2 else -sims[c], c))
+    out = []
+    while order:
+        xs = order.pop(0)
+        out.append(xs)
+        if len(out) == R:
+            break
+        keep = []
+        for c in order:
+            t = float_sim(metric, X[xs], X[c])
+            removed = alpha * t <= sims[c] if metric == L2 else alpha * t >= sims[c]
+            if not removed:
+                keep.append(c)
+        order = keep
+    return out
+
+
+def vamana_insert(metric, X, graph, nodes, entry, W, alpha, R):
+    """The update routine of graph construction (App. A) for each node x of
+    `nodes` in turn, in place on graph (n x R, -1 for no edge): the W nearest
+    nodes to x found by Alg. 1 from `entry` are pruned together with x's
+    current out-neighbours (Alg. 2) into its new out-neighbours; x then joins
+    the out-neighbours of each of them, which are pruned (Alg. 2) when that
+    exceeds R."""
+    def row(y):
+        return [int(v) for v in graph[y] if v >= 0]
+
+    def put(y, ns):
+        graph[y] = -1
+        graph[y, :len(ns)] = ns
+
+    for x in nodes:
+        x = int(x)
+        found, _, _ = greedy_search_float(metric, X[x], X, graph, [entry], W, W)
+        nx = robust_prune(metric, X, x, found, row(x), alpha, R)
+        put(x, nx)
+        for y in nx:
+            ny = row(y)
+            if x in ny:
+                continue
+            if len(ny) < R:
+                put(y, ny + [x])
+            else:
+                put(y, robust_prune(metric, X, y, [x], ny, alpha, R))
+    return graph
+
+
+def vamana_build(metric, X, entry, W, alpha, R, order=None):
+    """Initial build (App. A): an empty graph, then the update routine for
+    every node twice, first with alpha = 1 and then with the given alpha.
+    The entry node goes first; the others follow `order` (default: slot
+    order)."""
+    n = X.shape[0]
+    graph = np.full((n, R), -1, np.int32)
+    rest = [int(v) for v in (range(n) if order is None else order) if int(v) != int(entry)]
+    seq = [int(entry)] + rest
+    for a in (1.0, alpha):
+        vamana_insert(metric, X, graph, seq, entry, W, a, R)
+    return graph
 
 
 def eps1(fmt: Format, X, rows, means) -> float:
