@@ -222,6 +222,46 @@ int lvq_graph_search(lvq_index *index, const float *q_dev, int64_t nq, const int
                      int32_t degree, const int32_t *entries_dev, int32_t n_entries, int32_t window,
                      int32_t k, int32_t *ids_dev, float *dist_dev, int32_t *explored_dev, void *stream);
 
+/* Neighbourhood pruning (Alg. 2) over float vectors x_dev (n x dim, row i =
+ * node i; 1 <= dim <= 4096).  For each of the m distinct nodes p =
+ * nodes_dev[i] (device int32): the candidates cand_ids_dev[cand_offsets_dev[i]
+ * .. cand_offsets_dev[i + 1]) (device int64 offsets, m + 1; -1 entries are
+ * skipped) together with p's current out-neighbours graph_dev[p * degree ..]
+ * (n x degree int32, -1 padded, 1 <= degree <= 64), without p and without
+ * repeats, are ranked by similarity to p (L2: binary32 squared distance,
+ * smaller first; IP: inner product, larger first; ties to the lower node);
+ * the best remaining candidate x* becomes an out-neighbour and leaves the
+ * candidates, and until `degree` are chosen every candidate x' is dropped for
+ * which x* is at least alpha times as similar (L2: alpha * |x* - x'|^2 <=
+ * |p - x'|^2; IP: alpha * <x*, x'> >= <p, x'>).  The row of p is rewritten
+ * with the chosen nodes in selection order, -1 padded.  Candidates are taken
+ * 256 at a time, each group pruned together with the out-neighbours chosen
+ * so far.  Synchronises `stream`; LVQ_ERR_BAD_SLOT for a node outside
+ * [0, n).                                                                  */
+int lvq_graph_prune(const float *x_dev, int64_t n, int32_t dim, int32_t metric, const int32_t *nodes_dev,
+                    int64_t m, const int64_t *cand_offsets_dev, const int32_t *cand_ids_dev, int32_t degree,
+                    float alpha, int32_t *graph_dev, void *stream);
+
+/* Graph construction (App. A) over float vectors x_dev (n x dim, row i =
+ * node i), into graph_dev (n x degree int32, -1 padded).  Nodes [0, first)
+ * already form a graph whose rows are kept; nodes [first, n) are inserted
+ * with the update routine: the `window` nodes nearest to x found by greedy
+ * search (Alg. 1, float similarities as lvq_graph_prune) from `entry` are
+ * pruned with x's out-neighbours into its new out-neighbours (lvq_graph_prune
+ * with alpha), and x is added to the out-neighbours of each of them, which are
+ * pruned when that exceeds `degree`.  first = 0 is the initial build: the
+ * entry node goes first, then the others in node order, and with passes = 2
+ * the routine runs over all of them twice, with alpha = 1 and then `alpha`
+ * (1.2 for L2, 0.95 for IP in the paper); passes = 1 runs it once with
+ * `alpha` (inserts).  Nodes are processed in batches of at most max_batch
+ * (and at most the number of nodes already in the graph): the nodes of a
+ * batch search the graph as it was before the batch, so the result depends
+ * on max_batch.  Requires degree <= window <= 256, 0 <= entry < n (entry <
+ * first when first > 0).  Synchronises `stream`.                           */
+int lvq_graph_build(const float *x_dev, int64_t n, int32_t dim, int32_t metric, int64_t first, int32_t degree,
+                    int32_t window, float alpha, int32_t passes, int32_t entry, int32_t max_batch,
+                    int32_t *graph_dev, void *stream);
+
 /* Online re-estimation of M-LVQ means with selective re-encoding (Sec. 3.2;
  * updating means needs the rows of the moved centres re-encoded).
  *

@@ -37,7 +37,8 @@ LVQ_ERR_BAD_SLOT = -7
 
 EXPORTS = ["lvq_row_format", "lvq_create", "lvq_destroy", "lvq_set_means", "lvq_encode", "lvq_insert",
            "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_topk", "lvq_probe_topk", "lvq_retire_means",
-           "lvq_add_means", "lvq_mean_members", "lvq_graph_search", "lvq_read_rows",
+           "lvq_add_means", "lvq_mean_members", "lvq_graph_search", "lvq_graph_prune", "lvq_graph_build",
+           "lvq_read_rows",
            "lvq_get_stats", "lvq_sync", "lvq_mean", "lvq_kmeans", "lvq_strerror", "lvq_set_timing",
            "lvq_kernel_time", "lvq_autotune", "lvq_set_tile", "lvq_server_create", "lvq_server_submit",
            "lvq_server_wait", "lvq_server_drain", "lvq_server_get_stats", "lvq_server_destroy",
@@ -105,6 +106,8 @@ def _load():
         "lvq_add_means": [P, P, i32, P, P],
         "lvq_mean_members": [P, P, i32, P, P, i64, P],
         "lvq_graph_search": [P, P, i64, P, i32, P, i32, i32, i32, P, P, P, P],
+        "lvq_graph_prune": [P, i64, i32, i32, P, i64, P, P, i32, ctypes.c_float, P, P],
+        "lvq_graph_build": [P, i64, i32, i32, i64, i32, i32, ctypes.c_float, i32, i32, i32, P, P],
         "lvq_read_rows": [P, P, i64, P, P, P],
         "lvq_get_stats": [P, ctypes.POINTER(lvq_stats)],
         "lvq_sync": [P, P],
@@ -211,6 +214,50 @@ def lvq_add_means(ix, means_host, n, ids_out_host, stream=0):
 def lvq_graph_search(ix, q, nq, graph, degree, entries, n_entries, window, k, ids, dist, explored, stream=0):
     return _chk(_lib.lvq_graph_search(ix, q, nq, graph, degree, entries, n_entries, window, k, ids, dist, explored,
                                       stream), "lvq_graph_search")
+
+
+def lvq_graph_prune(x, n, dim, metric, nodes, m, cand_offsets, cand_ids, degree, alpha, graph, stream=0):
+    return _chk(_lib.lvq_graph_prune(x, n, dim, metric, nodes, m, cand_offsets, cand_ids, degree, alpha, graph,
+                                     stream), "lvq_graph_prune")
+
+
+def lvq_graph_build(x, n, dim, metric, first, degree, window, alpha, passes, entry, max_batch, graph, stream=0):
+    return _chk(_lib.lvq_graph_build(x, n, dim, metric, first, degree, window, alpha, passes, entry, max_batch,
+                                     graph, stream), "lvq_graph_build")
+
+
+def graph_prune(x, nodes, cand_offsets, cand_ids, graph, alpha, metric, stream=None):
+    """Alg. 2 on torch tensors: x (n x dim float32), nodes (m int32),
+    cand_offsets (m + 1 int64), cand_ids (int32), graph (n x degree int32,
+    rewritten in place)."""
+    import torch
+    for t, dt in ((x, torch.float32), (nodes, torch.int32), (cand_offsets, torch.int64), (cand_ids, torch.int32),
+                  (graph, torch.int32)):
+        if t.dtype != dt or not t.is_contiguous():
+            raise LVQError(LVQ_ERR_INVALID_ARG, "graph_prune: contiguous tensors of the documented types")
+    if graph.shape[0] != x.shape[0] or cand_offsets.shape[0] != nodes.shape[0] + 1:
+        raise LVQError(LVQ_ERR_INVALID_ARG, "graph_prune: shapes")
+    lvq_graph_prune(_ptr(x), x.shape[0], x.shape[1], metric, _ptr(nodes), nodes.shape[0], _ptr(cand_offsets),
+                    _ptr(cand_ids) if cand_ids.numel() else _ptr(cand_offsets), graph.shape[1], alpha, _ptr(graph),
+                    _stream(stream))
+
+
+def graph_build(x, degree, window, alpha, metric, entry, passes=2, first=0, graph=None, max_batch=16384,
+                stream=None):
+    """Graph construction (App. A) over x (n x dim float32 on the device);
+    returns graph (n x degree int32).  With first > 0, graph holds the rows
+    of nodes [0, first) and nodes [first, n) are inserted."""
+    import torch
+    if x.dtype != torch.float32 or x.dim() != 2 or not x.is_contiguous():
+        raise LVQError(LVQ_ERR_INVALID_ARG, "graph_build: x must be a contiguous float32 matrix")
+    n = x.shape[0]
+    if graph is None:
+        graph = torch.empty((n, degree), dtype=torch.int32, device=x.device)
+    if graph.shape != (n, degree) or graph.dtype != torch.int32 or not graph.is_contiguous():
+        raise LVQError(LVQ_ERR_INVALID_ARG, "graph_build: graph must be a contiguous int32 (n x degree) tensor")
+    lvq_graph_build(_ptr(x), n, x.shape[1], metric, first, degree, window, alpha, passes, entry, max_batch,
+                    _ptr(graph), _stream(stream))
+    return graph
 
 
 def lvq_mean_members(ix, ids_host, n, offsets_host, slots, cap, stream=0):

@@ -1,23 +1,33 @@
-// k_graph.hip -- greedy graph search (Alg. 1) over the stored LVQ rows with
-// first-level similarities (Sec. 2.3: the first level traverses, both
-// levels re-rank).
+// k_graph.hip -- greedy graph search (Alg. 1) and the pieces of graph
+// construction (App. A): neighbourhood pruning (Alg. 2) and reverse edges.
 //
-// One workgroup per query.  LDS holds the query in kernel order (and the L2
-// padding mask), the candidate set -- at most W keys, best first -- and a
-// hash set of every node proposed so far.  A key is (score order << 32) |
-// (slot << 1) | explored: the explored flag travels with the key through the
-// sorts without changing the (score, slot) order of distinct nodes.  Each
-// step explores the best unexplored key: its out-neighbours not seen before
-// are scored (16 lanes per neighbour) and merged, and the set is cut to the
-// W best.  Deleted rows are traversed; the result is the k best live ones.
+// Search: one workgroup per query.  LDS holds the query (kernel order for
+// LVQ rows, natural order for float vectors) and the L2 padding mask, the
+// candidate set -- at most W keys, best first -- and a hash set of every node
+// proposed so far.  A key is (score order << 32) | (slot << 1) | explored: the
+// explored flag travels with the key through the sorts without changing the
+// (score, slot) order of distinct nodes.  Each step explores the best
+// unexplored key: its out-neighbours not seen before are scored (16 lanes per
+// neighbour) and merged, and the set is cut to the W best.  Deleted rows are
+// traversed; the result is the k best live ones.  Over LVQ rows the
+// similarity is the first level (Sec. 2.3: the first level traverses, both
+// levels re-rank); over float vectors (construction) it is the binary32
+// squared distance or inner product.
+//
+// Pruning: one workgroup per node.  Its candidates and current out-neighbours
+// are scored against it into LDS keys, sorted by one wave and deduplicated;
+// the best remaining candidate x* is kept and every candidate that x* is at
+// least alpha times as similar to as the node is dropped, until R are kept.
 #include "k_common.h"
 
 namespace lvq {
 namespace {
 
 constexpr int kHash = 16384;      // hash slots per query (int32 slot or -1)
-constexpr int kMaxDegree = 64;
+constexpr int kMaxDegree = kGraphMaxDegree;
 constexpr int kMaxWindow = 256;
+constexpr int kPruneCap = kPruneChunk + kMaxDegree;   // candidates of one merge
+constexpr int kFloat = 0;                             // MODE of float vectors
 
 struct GraphArgs {
     const uint8_t *rows;
@@ -36,6 +46,9 @@ struct GraphArgs {
     float *dist;
     int32_t *explored;
     uint32_t *err;
+    const float *xf;
+    int dim;
+    const int32_t *qnodes;
 };
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t s)
@@ -57,49 +70,71 @@ __device__ __forceinline__ int hash_insert(int32_t *h, int32_t s)
     return -1;
 }
 
+// Similarity of two float vectors (one in LDS, one in global memory) by the
+// 16 lanes of a group; every lane of the group returns the value.
+template <int METRIC>
+__device__ __forceinline__ float sim16_f32(const float *u, const float *x, int dim, int g)
+{
+    float s = 0.0f;
+    for (int j = g; j < dim; j += 16) {
+        const float v = x[j];
+        if constexpr (METRIC == LVQ_IP) {
+            s = fmaf(u[j], v, s);
+        } else {
+            const float t = u[j] - v;
+            s = fmaf(t, t, s);
+        }
+    }
+    return group_sum<16>(s);
+}
+
 // First-level similarity of row `slot` to the query, by the 16 lanes of a
 // group (g = 0..15); every lane of the group returns the value.
 template <int B1, int METRIC>
 __device__ __forceinline__ float score16(const GraphArgs &a, const float *qt, const float *mk, int32_t slot, int g)
 {
-    const uint8_t *row = a.rows + (int64_t)slot * a.row_bytes;
-    const float4 hdr = *reinterpret_cast<const float4 *>(row);
-    const uint32_t *codes = reinterpret_cast<const uint32_t *>(row + kHeaderBytes);
-    const int nwords = a.kchunks * 4;
-    const int mid = min((int)(__float_as_uint(hdr.w) & 0xFFu), a.n_means - 1);
-    const float l = hdr.x, dl = hdr.y;
-    constexpr int PER = B1 == 8 ? 4 : 8;   // positions per 32-bit word
-    float s_lo = 0.0f, s_hi = 0.0f;
-    for (int w = g; w < nwords; w += 16) {
-        const uint32_t c = codes[w];
-        const int p0 = w * PER;
-        float cv[PER];
-        if constexpr (B1 == 8) {
-            cv[0] = ub<0>(c); cv[1] = ub<1>(c); cv[2] = ub<2>(c); cv[3] = ub<3>(c);
-        } else {
-            // kernel order of a 4-bit word: fields 0,2,4,6 (low nibbles), then 1,3,5,7
-            const uint32_t lo = c & 0x0F0F0F0Fu, hi = (c >> 4) & 0x0F0F0F0Fu;
-            cv[0] = ub<0>(lo); cv[1] = ub<1>(lo); cv[2] = ub<2>(lo); cv[3] = ub<3>(lo);
-            cv[4] = ub<0>(hi); cv[5] = ub<1>(hi); cv[6] = ub<2>(hi); cv[7] = ub<3>(hi);
-        }
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int p = p0 + j;
-            if constexpr (METRIC == LVQ_IP) {
-                s_lo = fmaf(qt[p], cv[j], s_lo);
+    if constexpr (B1 == kFloat) {
+        return sim16_f32<METRIC>(qt, a.xf + (int64_t)slot * a.dim, a.dim, g);
+    } else {
+        const uint8_t *row = a.rows + (int64_t)slot * a.row_bytes;
+        const float4 hdr = *reinterpret_cast<const float4 *>(row);
+        const uint32_t *codes = reinterpret_cast<const uint32_t *>(row + kHeaderBytes);
+        const int nwords = a.kchunks * 4;
+        const int mid = min((int)(__float_as_uint(hdr.w) & 0xFFu), a.n_means - 1);
+        const float l = hdr.x, dl = hdr.y;
+        constexpr int PER = B1 == 8 ? 4 : 8;   // positions per 32-bit word
+        float s_lo = 0.0f, s_hi = 0.0f;
+        for (int w = g; w < nwords; w += 16) {
+            const uint32_t c = codes[w];
+            const int p0 = w * PER;
+            float cv[PER];
+            if constexpr (B1 == 8) {
+                cv[0] = ub<0>(c); cv[1] = ub<1>(c); cv[2] = ub<2>(c); cv[3] = ub<3>(c);
             } else {
-                const float qv = qt[p] - a.muk[(int64_t)mid * a.kpos + p];   // q - mu, kernel order
-                float t = qv - fmaf(dl, cv[j], l);
-                t *= mk[p];
-                s_hi = fmaf(t, t, s_hi);
+                // kernel order of a 4-bit word: fields 0,2,4,6 (low nibbles), then 1,3,5,7
+                const uint32_t lo = c & 0x0F0F0F0Fu, hi = (c >> 4) & 0x0F0F0F0Fu;
+                cv[0] = ub<0>(lo); cv[1] = ub<1>(lo); cv[2] = ub<2>(lo); cv[3] = ub<3>(lo);
+                cv[4] = ub<0>(hi); cv[5] = ub<1>(hi); cv[6] = ub<2>(hi); cv[7] = ub<3>(hi);
+            }
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int p = p0 + j;
+                if constexpr (METRIC == LVQ_IP) {
+                    s_lo = fmaf(qt[p], cv[j], s_lo);
+                } else {
+                    const float qv = qt[p] - a.muk[(int64_t)mid * a.kpos + p];   // q - mu, kernel order
+                    float t = qv - fmaf(dl, cv[j], l);
+                    t *= mk[p];
+                    s_hi = fmaf(t, t, s_hi);
+                }
             }
         }
-    }
-    if constexpr (METRIC == LVQ_IP) {
-        const float dot = group_sum<16>(s_lo);
-        return fmaf(dl, dot, fmaf(l, a.qsum[0], a.cm[mid]));   // qsum / cm already offset to the query
-    } else {
-        return group_sum<16>(s_hi);
+        if constexpr (METRIC == LVQ_IP) {
+            const float dot = group_sum<16>(s_lo);
+            return fmaf(dl, dot, fmaf(l, a.qsum[0], a.cm[mid]));   // qsum / cm already offset to the query
+        } else {
+            return group_sum<16>(s_hi);
+        }
     }
 }
 
@@ -120,9 +155,18 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
     __shared__ int32_t s_new[kMaxDegree];
     __shared__ int s_nnew, s_qn, s_pick, s_stop, s_explored, s_scored;
 
+    const float *qsrc = a.qk + qi * a.kpos;
+    bool qok = true;
+    if constexpr (B1 == kFloat) {
+        if (a.qnodes) {
+            const int32_t node = a.qnodes[qi];
+            qok = node >= 0 && node < a.capacity;
+            qsrc = a.xf + (int64_t)(qok ? node : 0) * a.dim;
+        }
+    }
     for (int p = tid; p < a.kpos; p += 256) {
-        qt[p] = a.qk[qi * a.kpos + p];
-        mk[p] = METRIC == LVQ_L2 ? a.kmask[p] : 1.0f;
+        qt[p] = qsrc[p];
+        mk[p] = METRIC == LVQ_L2 && B1 != kFloat ? a.kmask[p] : 1.0f;
     }
     for (int i = tid; i < kHash; i += 256) hset[i] = -1;
     if (tid == 0) {
@@ -130,14 +174,17 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
         s_stop = 0;
         s_explored = 0;
         s_scored = 0;
+        if (!qok) atomicOr(a.err, kErrBadSlot);
     }
     __syncthreads();
     GraphArgs b = a;
-    b.qsum = a.qsum + qi;
-    b.cm = a.cm + qi * a.n_means;
+    if constexpr (B1 != kFloat) {
+        b.qsum = a.qsum + qi;
+        b.cm = a.cm + qi * a.n_means;
+    }
 
     // entry nodes: deduplicated through the hash set, scored, sorted
-    for (int i = tid; i < a.n_entries; i += 256) {
+    for (int i = tid; i < a.n_entries && qok; i += 256) {
         const int32_t s = a.entries[i];
         if (s >= 0 && s < a.capacity && hash_insert(hset, s) == 1) s_new[atomicAdd(&s_nnew, 1)] = s;
     }
@@ -214,29 +261,258 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
             uint64_t key = kNoKey;
             if (i < qn) {
                 key = qkey[i];
-                const int32_t s = (int32_t)((uint32_t)key >> 1);
-                const uint8_t *row = a.rows + (int64_t)s * a.row_bytes;
-                const uint2 ep = *reinterpret_cast<const uint2 *>(row + 16);
-                live = (row[13] & 1u) && ep.x <= a.epoch && a.epoch < ep.y;
+                if constexpr (B1 == kFloat) {
+                    live = true;
+                } else {
+                    const int32_t s = (int32_t)((uint32_t)key >> 1);
+                    const uint8_t *row = a.rows + (int64_t)s * a.row_bytes;
+                    const uint2 ep = *reinterpret_cast<const uint2 *>(row + 16);
+                    live = (row[13] & 1u) && ep.x <= a.epoch && a.epoch < ep.y;
+                }
             }
             const uint64_t m = __ballot(live);
             const int pos = out + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
             if (live && pos < a.k) {
                 a.ids[qi * a.k + pos] = (int32_t)((uint32_t)key >> 1);
-                a.dist[qi * a.k + pos] = key_score(key, METRIC);
+                if (a.dist) a.dist[qi * a.k + pos] = key_score(key, METRIC);
             }
             out += __popcll(m);
         }
         for (int i = max(out, 0) + lane; i < a.k; i += 64) {
             a.ids[qi * a.k + i] = -1;
-            a.dist[qi * a.k + i] = METRIC == LVQ_L2 ? __uint_as_float(0x7F800000u) : __uint_as_float(0xFF800000u);
+            if (a.dist)
+                a.dist[qi * a.k + i] = METRIC == LVQ_L2 ? __uint_as_float(0x7F800000u) : __uint_as_float(0xFF800000u);
         }
         if (lane == 0 && a.explored) {
             a.explored[2 * qi] = s_explored;
             a.explored[2 * qi + 1] = s_scored;
         }
     }
+}
+
+// ---- neighbourhood pruning (Alg. 2) ----------------------------------------
+
+template <int METRIC>
+__global__ __launch_bounds__(256) void k_graph_prune(PruneLaunch a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int grp = tid >> 4, g = tid & 15;
+    const int64_t i = blockIdx.x;
+    if (i >= a.m) return;
+    float *xv = reinterpret_cast<float *>(smem);   // the node (dim)
+    float *xs = xv + a.dim;                        // x* (dim)
+    __shared__ uint64_t keys[512];
+    __shared__ int32_t cid[kPruneCap];
+    __shared__ int32_t kept[kMaxDegree];
+    __shared__ uint8_t rm[kPruneCap];
+    __shared__ int s_n, s_kept, s_pick, s_unique;
+
+    const int32_t p = a.nodes[i];
+    if (p < 0 || p >= a.n) {
+        if (tid == 0) atomicOr(a.err, kErrBadSlot);
+        return;
+    }
+    int64_t c0, c1;
+    if (a.coffs) {
+        const int64_t j = a.by_node ? (int64_t)p : i;
+        c0 = a.coffs[j];
+        c1 = a.coffs[j + 1];
+    } else {
+        c0 = i * a.cstride;
+        c1 = c0 + a.cstride;
+    }
+    if (c0 < 0 || c1 < c0) {
+        if (tid == 0) atomicOr(a.err, kErrBadOffsets);
+        return;
+    }
+    for (int j = tid; j < a.dim; j += 256) xv[j] = a.xf[(int64_t)p * a.dim + j];
+    if (tid == 0) s_kept = 0;
+    __syncthreads();
+    // the current out-neighbours (kept in LDS across chunks)
+    if (tid == 0)
+        for (int r = 0; r < a.R; ++r) {
+            const int32_t y = a.graph[(int64_t)p * a.R + r];
+            if (y >= 0 && y < a.n && y != p) kept[s_kept++] = y;
+        }
+    __syncthreads();
+
+    for (int64_t cs = c0;; cs += kPruneChunk) {
+        const int64_t ce = min(c1, cs + (int64_t)kPruneChunk);
+        if (tid == 0) s_n = s_kept;
+        for (int r = tid; r < s_kept; r += 256) cid[r] = kept[r];
+        __syncthreads();
+        for (int64_t j = cs + tid; j < ce; j += 256) {
+            const int32_t y = a.cids[j];
+            if (y >= 0 && y < a.n && y != p) cid[atomicAdd(&s_n, 1)] = y;
+        }
+        __syncthreads();
+        const int nn = s_n;
+        // similarities to the node
+        for (int c = grp; c < nn; c += 16) {
+            const int32_t y = cid[c];
+            const float v = sim16_f32<METRIC>(xv, a.xf + (int64_t)y * a.dim, a.dim, g);
+            if (g == 0) keys[c] = make_key(v, y, METRIC);
+        }
+        __syncthreads();
+        if (wave == 0 && nn > 0) wave_compact(keys, nn, nn, nullptr);   // nn <= 320: register sort
+        __syncthreads();
+        // equal keys (the same node) are adjacent
+        for (int c = tid; c < nn; c += 256) rm[c] = c > 0 && keys[c] == keys[c - 1];
+        __syncthreads();
+        if (tid == 0) {
+            int u = 0;
+            for (int c = 0; c < nn; ++c) u += !rm[c];
+            s_unique = u;
+            s_kept = 0;
+            s_pick = -1;
+        }
+        __syncthreads();
+        if (!a.always && s_unique <= a.R) {
+            if (tid == 0)
+                for (int c = 0; c < nn; ++c)
+                    if (!rm[c]) kept[s_kept++] = (int32_t)(uint32_t)keys[c];
+            __syncthreads();
+        } else {
+            int pos = 0;
+            for (;;) {
+                if (tid == 0) {
+                    int c = pos;
+                    while (c < nn && rm[c]) ++c;
+                    if (c < nn) {
+                        kept[s_kept++] = (int32_t)(uint32_t)keys[c];
+                        rm[c] = 1;
+                        s_pick = s_kept < a.R ? c : -1;
+                    } else {
+                        s_pick = -1;
+                    }
+                }
+                __syncthreads();
+                const int c = s_pick;
+                if (c < 0) break;
+                pos = c + 1;
+                const int32_t xstar = (int32_t)(uint32_t)keys[c];
+                for (int j = tid; j < a.dim; j += 256) xs[j] = a.xf[(int64_t)xstar * a.dim + j];
+                __syncthreads();
+                for (int e = pos + grp; e < nn; e += 16) {
+                    if (rm[e]) continue;   // uniform within the group
+                    const int32_t y = (int32_t)(uint32_t)keys[e];
+                    const float t = sim16_f32<METRIC>(xs, a.xf + (int64_t)y * a.dim, a.dim, g);
+                    const float sp = key_score(keys[e], METRIC);
+                    const float at = a.alpha * t;
+                    const bool drop = METRIC == LVQ_L2 ? at <= sp : at >= sp;
+                    if (g == 0 && drop) rm[e] = 1;
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+        if (ce >= c1) break;
+    }
+    for (int r = tid; r < a.R; r += 256) a.graph[(int64_t)p * a.R + r] = r < s_kept ? kept[r] : -1;
+}
+
+// ---- reverse edges ----------------------------------------------------------
+
+constexpr int kScanItems = 2048;   // per block: 256 threads x 8
+
+__global__ __launch_bounds__(256) void k_rev_count(const int32_t *graph, int R, const int32_t *nodes, int64_t m,
+                                                    int64_t n, int32_t *cnt)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < m * R; e += (int64_t)gridDim.x * 256) {
+        const int32_t x = nodes[e / R];
+        if (x < 0 || x >= n) continue;
+        const int32_t y = graph[(int64_t)x * R + e % R];
+        if (y >= 0 && y < n && y != x) atomicAdd(&cnt[y], 1);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_local(const int32_t *cnt, int64_t n, int64_t *offs, int64_t *bsum)
+{
+    __shared__ int64_t part[256];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanItems + tid * 8;
+    int64_t v[8], s = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        v[k] = base + k < n ? cnt[base + k] : 0;
+        s += v[k];
+    }
+    part[tid] = s;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {   // inclusive scan of the thread sums
+        const int64_t y = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += y;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - s;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (base + k < n) offs[base + k] = run;
+        run += v[k];
+    }
+    if (tid == 255) bsum[blockIdx.x] = part[255];
+}
+
+// exclusive scan of bsum[0..nb) in place; bsum[nb] = total
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t *bsum, int64_t nb)
+{
+    __shared__ int64_t sh[1024];
+    __shared__ int64_t carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t i = base + tid;
+        const int64_t x = i < nb ? bsum[i] : 0;
+        sh[tid] = x;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int64_t y = tid >= o ? sh[tid - o] : 0;
+            __syncthreads();
+            sh[tid] += y;
+            __syncthreads();
+        }
+        const int64_t c = carry;
+        if (i < nb) bsum[i] = c + sh[tid] - x;
+        __syncthreads();
+        if (tid == 1023) carry = c + sh[1023];
+        __syncthreads();
+    }
+    if (tid == 0) bsum[nb] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const int32_t *cnt, int64_t n, int64_t *offs, const int64_t *bsum,
+                                                     int64_t nb, int32_t *touched, int32_t *ntouched)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        offs[i] += bsum[i / kScanItems];
+        if (cnt[i] > 0) touched[atomicAdd(ntouched, 1)] = (int32_t)i;
+    }
+    if (i == 0) offs[n] = bsum[nb];
+}
+
+__global__ __launch_bounds__(256) void k_rev_fill(const int32_t *graph, int R, const int32_t *nodes, int64_t m,
+                                                   int64_t n, const int64_t *offs, int32_t *cnt, int32_t *rev)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < m * R; e += (int64_t)gridDim.x * 256) {
+        const int32_t x = nodes[e / R];
+        if (x < 0 || x >= n) continue;
+        const int32_t y = graph[(int64_t)x * R + e % R];
+        if (y >= 0 && y < n && y != x) {
+            const int32_t k = atomicSub(&cnt[y], 1) - 1;   // counts return to zero
+            rev[offs[y] + k] = x;
+        }
+    }
+}
+
+unsigned grid_for(int64_t work)
+{
+    const int64_t b = (work + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
 }
 
 }  // namespace
@@ -273,13 +549,54 @@ hipError_t launch_graph_search(const GraphLaunch &l, hipStream_t s)
     a.dist = l.dist;
     a.explored = l.explored;
     a.err = l.err;
+    a.xf = l.xf;
+    a.dim = l.dim;
+    a.qnodes = l.qnodes;
     if (l.nq <= 0) return hipSuccess;
+    if (l.window > kMaxWindow || l.degree > kMaxDegree || l.k > l.window) return hipErrorInvalidValue;
     const size_t lds = graph_lds_bytes(l.kpos, l.window);
     void (*kern)(GraphArgs) = nullptr;
-    if (l.bits1 == 8) kern = l.metric == LVQ_IP ? k_graph_search<8, LVQ_IP> : k_graph_search<8, LVQ_L2>;
-    else if (l.bits1 == 4) kern = l.metric == LVQ_IP ? k_graph_search<4, LVQ_IP> : k_graph_search<4, LVQ_L2>;
+    if (!l.rows) {
+        if (!l.xf || l.kpos != l.dim) return hipErrorInvalidValue;
+        kern = l.metric == LVQ_IP ? k_graph_search<kFloat, LVQ_IP> : k_graph_search<kFloat, LVQ_L2>;
+    } else if (l.bits1 == 8) {
+        kern = l.metric == LVQ_IP ? k_graph_search<8, LVQ_IP> : k_graph_search<8, LVQ_L2>;
+    } else if (l.bits1 == 4) {
+        kern = l.metric == LVQ_IP ? k_graph_search<4, LVQ_IP> : k_graph_search<4, LVQ_L2>;
+    }
     if (!kern) return hipErrorInvalidValue;
     hipLaunchKernelGGL(kern, dim3((unsigned)l.nq), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_graph_prune(const PruneLaunch &l, hipStream_t s)
+{
+    if (l.m <= 0) return hipSuccess;
+    if (l.R < 1 || l.R > kMaxDegree || l.dim < 1 || l.dim > kGraphMaxDim || l.m > 0x7FFFFFFF)
+        return hipErrorInvalidValue;
+    const size_t lds = (size_t)2 * l.dim * 4;
+    if (l.metric == LVQ_IP)
+        hipLaunchKernelGGL(k_graph_prune<LVQ_IP>, dim3((unsigned)l.m), dim3(256), lds, s, l);
+    else
+        hipLaunchKernelGGL(k_graph_prune<LVQ_L2>, dim3((unsigned)l.m), dim3(256), lds, s, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_reverse_edges(const int32_t *graph, int R, const int32_t *nodes, int64_t m, int64_t n,
+                                int32_t *cnt, int64_t *offs, int64_t *scratch, int32_t *rev, int32_t *touched,
+                                int32_t *ntouched, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + kScanItems - 1) / kScanItems;
+    hipError_t e = launch_fill_i32(ntouched, 0, 1, s);
+    if (e != hipSuccess) return e;
+    if (m > 0) hipLaunchKernelGGL(k_rev_count, dim3(grid_for(m * R)), dim3(256), 0, s, graph, R, nodes, m, n, cnt);
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(256), 0, s, cnt, n, offs, scratch);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, scratch, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cnt, n, offs, scratch, nb,
+                       touched, ntouched);
+    if (m > 0)
+        hipLaunchKernelGGL(k_rev_fill, dim3(grid_for(m * R)), dim3(256), 0, s, graph, R, nodes, m, n, offs, cnt, rev);
     return hipGetLastError();
 }
 

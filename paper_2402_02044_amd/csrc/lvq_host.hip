@@ -1396,3 +1396,194 @@ int lvq_kmeans(const float *x_dev, int64_t n, int32_t dim, int32_t k, const int6
 }
 
 }  // extern "C"
+
+// ---- graph construction (App. A) ---------------------------------------------
+
+namespace {
+
+int graph_device_lds(size_t *out)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    LVQ_HIP(hipGetDevice(&dev));
+    LVQ_HIP(hipGetDeviceProperties(&prop, dev));
+    *out = prop.sharedMemPerBlock;
+    return LVQ_OK;
+}
+
+int graph_kernel_error(uint32_t e)
+{
+    if (e & kErrBadSlot) return LVQ_ERR_BAD_SLOT;
+    if (e & kErrBadOffsets) return LVQ_ERR_INVALID_ARG;
+    return LVQ_OK;   // a search that stopped at the seen-set capacity still yields candidates
+}
+
+// Device buffers of one construction call, released on every exit path.
+struct GraphScratch {
+    std::vector<void *> bufs;
+    hipStream_t s;
+    explicit GraphScratch(hipStream_t st) : s(st) {}
+    template <typename T>
+    int alloc(T **p, size_t count)
+    {
+        *p = nullptr;
+        void *q = nullptr;
+        LVQ_HIP(hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)));
+        bufs.push_back(q);
+        *p = static_cast<T *>(q);
+        return LVQ_OK;
+    }
+    ~GraphScratch()
+    {
+        (void)hipStreamSynchronize(s);
+        for (void *q : bufs) (void)hipFree(q);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int lvq_graph_prune(const float *x_dev, int64_t n, int32_t dim, int32_t metric, const int32_t *nodes_dev, int64_t m,
+                    const int64_t *cand_offsets_dev, const int32_t *cand_ids_dev, int32_t degree, float alpha,
+                    int32_t *graph_dev, void *stream)
+{
+    if (n < 1 || n > INT32_MAX || dim < 1 || dim > kGraphMaxDim || (metric != LVQ_L2 && metric != LVQ_IP) || m < 0 ||
+        m > INT32_MAX || degree < 1 || degree > kGraphMaxDegree || !(alpha > 0.0f) || !std::isfinite(alpha))
+        return LVQ_ERR_INVALID_ARG;
+    if (m == 0) return LVQ_OK;
+    if (!x_dev || !nodes_dev || !cand_offsets_dev || !cand_ids_dev || !graph_dev) return LVQ_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    GraphScratch sc(s);
+    uint32_t *err = nullptr;
+    int rc = sc.alloc(&err, 1);
+    if (rc) return rc;
+    LVQ_HIP(launch_fill_u32(err, 0, 1, s));
+    PruneLaunch l{};
+    l.xf = x_dev;
+    l.dim = dim;
+    l.metric = metric;
+    l.n = n;
+    l.nodes = nodes_dev;
+    l.m = m;
+    l.coffs = cand_offsets_dev;
+    l.by_node = 0;
+    l.cids = cand_ids_dev;
+    l.always = 1;
+    l.graph = graph_dev;
+    l.R = degree;
+    l.alpha = alpha;
+    l.err = err;
+    LVQ_HIP(launch_graph_prune(l, s));
+    uint32_t herr = 0;
+    LVQ_HIP(hipMemcpyAsync(&herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
+    LVQ_HIP(hipStreamSynchronize(s));
+    return graph_kernel_error(herr);
+}
+
+int lvq_graph_build(const float *x_dev, int64_t n, int32_t dim, int32_t metric, int64_t first, int32_t degree,
+                    int32_t window, float alpha, int32_t passes, int32_t entry, int32_t max_batch, int32_t *graph_dev,
+                    void *stream)
+{
+    if (!x_dev || !graph_dev || n < 1 || n > INT32_MAX || dim < 1 || dim > kGraphMaxDim ||
+        (metric != LVQ_L2 && metric != LVQ_IP) || first < 0 || first > n || degree < 1 ||
+        degree > kGraphMaxDegree || window < degree || window > 256 || !(alpha > 0.0f) || !std::isfinite(alpha) ||
+        passes < 1 || passes > 2 || entry < 0 || entry >= n || (first > 0 && entry >= first) || max_batch < 1)
+        return LVQ_ERR_INVALID_ARG;
+    size_t lds_max = 0;
+    int rc = graph_device_lds(&lds_max);
+    if (rc) return rc;
+    if (graph_lds_bytes(dim, window) > lds_max) return LVQ_ERR_UNSUPPORTED;
+    const int64_t count = n - first;
+    if (count == 0) return LVQ_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t B = std::min<int64_t>(max_batch, count);
+    const int R = degree;
+    std::vector<int32_t> order;
+    order.reserve((size_t)count);
+    if (first == 0) {
+        order.push_back(entry);
+        for (int64_t v = 0; v < n; ++v)
+            if (v != entry) order.push_back((int32_t)v);
+    } else {
+        for (int64_t v = first; v < n; ++v) order.push_back((int32_t)v);
+    }
+    GraphScratch sc(s);
+    int32_t *order_d, *res, *cnt, *rev, *touched, *ntouched, *entry_d;
+    int64_t *offs, *scan;
+    uint32_t *err;
+    const int64_t nb = (n + 2047) / 2048;
+    if ((rc = sc.alloc(&order_d, (size_t)count)) || (rc = sc.alloc(&res, (size_t)(B * window))) ||
+        (rc = sc.alloc(&cnt, (size_t)n)) || (rc = sc.alloc(&offs, (size_t)n + 1)) ||
+        (rc = sc.alloc(&scan, (size_t)nb + 1)) || (rc = sc.alloc(&rev, (size_t)(B * R))) ||
+        (rc = sc.alloc(&touched, (size_t)(B * R))) || (rc = sc.alloc(&ntouched, 1)) ||
+        (rc = sc.alloc(&entry_d, 1)) || (rc = sc.alloc(&err, 1)))
+        return rc;
+    LVQ_HIP(hipMemcpyAsync(order_d, order.data(), sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice, s));
+    LVQ_HIP(hipMemcpyAsync(entry_d, &entry, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LVQ_HIP(launch_fill_i32(graph_dev + first * R, -1, count * R, s));
+    LVQ_HIP(launch_fill_i32(cnt, 0, n, s));
+    LVQ_HIP(launch_fill_u32(err, 0, 1, s));
+    for (int pass = 0; pass < passes; ++pass) {
+        const float a = (passes == 2 && pass == 0) ? 1.0f : alpha;
+        for (int64_t b = 0; b < count;) {
+            // a batch is at most as large as the graph it is inserted into
+            const int64_t in_graph = pass == 0 ? first + b : n;
+            const int64_t bs = std::min<int64_t>({B, std::max<int64_t>(1, in_graph), count - b});
+            const int32_t *nodes = order_d + b;
+            GraphLaunch g{};
+            g.capacity = n;
+            g.kpos = dim;
+            g.metric = metric;
+            g.n_means = 1;
+            g.nq = bs;
+            g.graph = graph_dev;
+            g.degree = R;
+            g.entries = entry_d;
+            g.n_entries = 1;
+            g.window = window;
+            g.k = window;
+            g.ids = res;
+            g.err = err;
+            g.xf = x_dev;
+            g.dim = dim;
+            g.qnodes = nodes;
+            LVQ_HIP(launch_graph_search(g, s));
+            PruneLaunch p{};
+            p.xf = x_dev;
+            p.dim = dim;
+            p.metric = metric;
+            p.n = n;
+            p.nodes = nodes;
+            p.m = bs;
+            p.cids = res;
+            p.cstride = window;
+            p.always = 1;
+            p.graph = graph_dev;
+            p.R = R;
+            p.alpha = a;
+            p.err = err;
+            LVQ_HIP(launch_graph_prune(p, s));
+            LVQ_HIP(launch_reverse_edges(graph_dev, R, nodes, bs, n, cnt, offs, scan, rev, touched, ntouched, s));
+            int32_t nt = 0;
+            LVQ_HIP(hipMemcpyAsync(&nt, ntouched, sizeof(nt), hipMemcpyDeviceToHost, s));
+            LVQ_HIP(hipStreamSynchronize(s));
+            PruneLaunch r = p;
+            r.nodes = touched;
+            r.m = nt;
+            r.coffs = offs;
+            r.by_node = 1;
+            r.cids = rev;
+            r.cstride = 0;
+            r.always = 0;
+            LVQ_HIP(launch_graph_prune(r, s));
+            b += bs;
+        }
+    }
+    uint32_t herr = 0;
+    LVQ_HIP(hipMemcpyAsync(&herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
+    LVQ_HIP(hipStreamSynchronize(s));
+    return graph_kernel_error(herr);
+}
+
+}  // extern "C"

@@ -184,11 +184,51 @@ struct GraphLaunch {
     uint32_t epoch;
     int32_t *ids;
     float *dist;
-    int32_t *explored;       // nq, may be NULL
+    int32_t *explored;       // nq x 2 (explored, scored), may be NULL
     uint32_t *err;
+    // float mode (graph construction): rows == NULL, the nodes are the float
+    // vectors xf (capacity x dim); query i is xf[qnodes[i]] (kpos = dim)
+    const float *xf;
+    int dim;
+    const int32_t *qnodes;
 };
 size_t graph_lds_bytes(int kpos, int window);
 hipError_t launch_graph_search(const GraphLaunch &l, hipStream_t s);
+
+// Neighbourhood pruning (Alg. 2) over float vectors, one workgroup per node.
+// Node i = nodes[i]; its candidates are cids[coffs[j] .. coffs[j + 1]) with
+// j = i (by_node 0) or j = the node (by_node 1), or cids[i * cstride ..
+// (i + 1) * cstride) when coffs is NULL; -1 entries are skipped.  They are
+// taken in chunks of kPruneChunk, each merged with the out-neighbours kept so
+// far; `always` 0 prunes only a merge holding more than R distinct nodes.
+constexpr int kPruneChunk = 256;
+constexpr int kGraphMaxDegree = 64;
+constexpr int kGraphMaxDim = 4096;
+struct PruneLaunch {
+    const float *xf;
+    int dim, metric;
+    int64_t n;
+    const int32_t *nodes;
+    int64_t m;
+    const int64_t *coffs;
+    int by_node;
+    const int32_t *cids;
+    int cstride;
+    int always;
+    int32_t *graph;
+    int R;
+    float alpha;
+    uint32_t *err;
+};
+hipError_t launch_graph_prune(const PruneLaunch &l, hipStream_t s);
+
+// Reverse edges of the out-neighbours of nodes[0..m): cnt (n, all zero on
+// entry and on return) counts them; offs (n + 1) receives the CSR offsets by
+// target node, rev the sources, touched[0 .. *ntouched) the targets.
+// scratch: at least (n + 2047) / 2048 + 1 int64.
+hipError_t launch_reverse_edges(const int32_t *graph, int R, const int32_t *nodes, int64_t m, int64_t n,
+                                int32_t *cnt, int64_t *offs, int64_t *scratch, int32_t *rev, int32_t *touched,
+                                int32_t *ntouched, hipStream_t s);
 
 hipError_t launch_mean_counts(const int32_t *list, int64_t n, const uint8_t *rows, int row_bytes, int n_means,
                               unsigned long long *counts, hipStream_t s);
