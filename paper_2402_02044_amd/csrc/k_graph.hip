@@ -23,7 +23,7 @@
 namespace lvq {
 namespace {
 
-constexpr int kHash = 16384;      // hash slots per query (int32 slot or -1)
+constexpr int kMaxHash = 16384;   // seen-set hash slots per query (int32 slot or -1)
 constexpr int kMaxDegree = kGraphMaxDegree;
 constexpr int kMaxWindow = 256;
 constexpr int kPruneCap = kPruneChunk + kMaxDegree;   // candidates of one merge
@@ -49,23 +49,20 @@ struct GraphArgs {
     const float *xf;
     int dim;
     const int32_t *qnodes;
+    int hash_slots;
 };
 
-__device__ __forceinline__ uint32_t hash_slot(int32_t s)
-{
-    return ((uint32_t)s * 2654435761u) >> (32 - 14);   // 14 bits: kHash slots
-}
-
-// Insert s into the hash set: 1 if it was not there, 0 if it was, -1 if the
+// Insert s into the open-addressing hash set h (mask + 1 slots, a power of
+// two; -1 marks an empty slot): 1 if it was not there, 0 if it was, -1 if the
 // set is full.
-__device__ __forceinline__ int hash_insert(int32_t *h, int32_t s)
+__device__ __forceinline__ int hash_insert(int32_t *h, int32_t s, uint32_t mask)
 {
-    uint32_t i = hash_slot(s);
-    for (int probe = 0; probe < kHash; ++probe) {
+    uint32_t i = ((uint32_t)s * 2654435761u) & mask;
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
         const int32_t old = atomicCAS(&h[i], -1, s);
         if (old == -1) return 1;
         if (old == s) return 0;
-        i = (i + 1) & (kHash - 1);
+        i = (i + 1) & mask;
     }
     return -1;
 }
@@ -149,11 +146,12 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
     const int W = a.window;
     float *qt = reinterpret_cast<float *>(smem);                       // kpos
     float *mk = qt + a.kpos;                                           // kpos
-    uint64_t *qkey = reinterpret_cast<uint64_t *>(mk + a.kpos);        // W + kMaxDegree (+ scratch)
-    uint64_t *scratch = qkey + W + kMaxDegree;                         // kMaxWindow (selection scratch)
-    int32_t *hset = reinterpret_cast<int32_t *>(scratch + kMaxWindow); // kHash
+    uint64_t *cur = reinterpret_cast<uint64_t *>(mk + a.kpos);         // W: the candidate set, ascending
+    uint64_t *nxt = cur + W;                                           // W: the merged set
+    int32_t *hset = reinterpret_cast<int32_t *>(nxt + W);              // hash_slots
+    __shared__ uint64_t s_key[kMaxDegree];                             // keys of the nodes proposed by a step
     __shared__ int32_t s_new[kMaxDegree];
-    __shared__ int s_nnew, s_qn, s_pick, s_stop, s_explored, s_scored;
+    __shared__ int s_nnew[2], s_pick[2], s_stop, s_explored, s_scored;
 
     const float *qsrc = a.qk + qi * a.kpos;
     bool qok = true;
@@ -168,9 +166,11 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
         qt[p] = qsrc[p];
         mk[p] = METRIC == LVQ_L2 && B1 != kFloat ? a.kmask[p] : 1.0f;
     }
-    for (int i = tid; i < kHash; i += 256) hset[i] = -1;
+    const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
+    for (int i = tid; i < a.hash_slots; i += 256) hset[i] = -1;
     if (tid == 0) {
-        s_nnew = 0;
+        s_nnew[0] = s_nnew[1] = 0;
+        s_pick[0] = s_pick[1] = 1 << 30;
         s_stop = 0;
         s_explored = 0;
         s_scored = 0;
@@ -183,55 +183,85 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
         b.cm = a.cm + qi * a.n_means;
     }
 
-    // entry nodes: deduplicated through the hash set, scored, sorted
-    for (int i = tid; i < a.n_entries && qok; i += 256) {
-        const int32_t s = a.entries[i];
-        if (s >= 0 && s < a.capacity && hash_insert(hset, s) == 1) s_new[atomicAdd(&s_nnew, 1)] = s;
-    }
-    __syncthreads();
-    int qn = 0;
-    auto score_new = [&](int base_n) {
-        const int nn = s_nnew;
+    // Merge the nn keys s_key[0..nn) (new, unexplored, not in cur) into the
+    // sorted set cur[0..qn): every key's merged position is its rank among the
+    // old keys plus its rank among the new ones (keys are distinct); positions
+    // below W are written to nxt, and the best unexplored one is recorded in
+    // s_pick[par].
+    auto merge = [&](int qn, int nn, int par) {
+        if (tid < qn) {
+            const uint64_t k = cur[tid];
+            int r = 0;
+            for (int c = 0; c < nn; ++c) r += s_key[c] < k;
+            const int p = tid + r;
+            if (p < W) {
+                nxt[p] = k;
+                if (!(k & 1ull)) atomicMin(&s_pick[par], p);
+            }
+        }
+        if (tid < nn) {
+            const uint64_t k = s_key[tid];
+            int r = 0;
+            for (int c = 0; c < nn; ++c) r += s_key[c] < k;
+            int lo = 0, hi = qn;   // old keys below k
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (cur[mid] < k) lo = mid + 1;
+                else hi = mid;
+            }
+            const int p = lo + r;
+            if (p < W) {
+                nxt[p] = k;
+                atomicMin(&s_pick[par], p);
+            }
+        }
+    };
+    auto score_new = [&](int nn) {
         for (int c = grp; c < nn; c += 16) {
             const int32_t s = s_new[c];
             const float v = score16<B1, METRIC>(b, qt, mk, s, g);
-            if (g == 0) qkey[base_n + c] = (make_key(v, 0, METRIC) & 0xFFFFFFFF00000000ull) | ((uint64_t)(uint32_t)s << 1);
+            if (g == 0) s_key[c] = (make_key(v, 0, METRIC) & 0xFFFFFFFF00000000ull) | ((uint64_t)(uint32_t)s << 1);
         }
     };
-    score_new(0);
-    __syncthreads();
-    if (wave == 0) {
-        const int n0 = s_nnew;
-        if (lane == 0) s_scored = n0;
-        const int got = wave_compact(qkey, n0, min(W, max(n0, 1)), scratch);
-        if (lane == 0) s_qn = min(got, W);
+
+    // entry nodes: deduplicated through the hash set, scored, merged into the
+    // empty set (parity 1: the first step reads s_pick[1])
+    for (int i = tid; i < a.n_entries && qok; i += 256) {
+        const int32_t s = a.entries[i];
+        if (s >= 0 && s < a.capacity && hash_insert(hset, s, hmask) == 1) s_new[atomicAdd(&s_nnew[1], 1)] = s;
     }
     __syncthreads();
-    qn = s_qn;
+    int nn = s_nnew[1];
+    score_new(nn);
+    __syncthreads();
+    merge(0, nn, 1);
+    __syncthreads();
+    int qn = min(W, nn);
+    {
+        uint64_t *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (tid == 0) s_scored = nn;
 
-    for (;;) {
-        // the best unexplored key (the set is sorted)
-        if (tid == 0) s_pick = 1 << 30;
-        __syncthreads();
-        for (int i = tid; i < qn; i += 256)
-            if (!(qkey[i] & 1ull)) atomicMin(&s_pick, i);
-        __syncthreads();
-        const int pick = s_pick;
+    for (int step = 0;; ++step) {
+        const int par = step & 1, prev = par ^ 1;
+        const int pick = s_pick[prev];
         if (pick >= qn || s_stop) break;
-        const int32_t x = (int32_t)((uint32_t)qkey[pick] >> 1);
-        __syncthreads();
+        const int32_t x = (int32_t)((uint32_t)cur[pick] >> 1);
+        __syncthreads();   // pick and x read by all
         if (tid == 0) {
-            qkey[pick] |= 1ull;
-            s_nnew = 0;
+            cur[pick] |= 1ull;
+            s_pick[prev] = 1 << 30;   // read above by every thread; the next step writes it
+            s_nnew[prev] = 0;
             ++s_explored;
         }
-        __syncthreads();
         // out-neighbours not seen before
         if (tid < a.degree) {
             const int32_t y = a.graph[(int64_t)x * a.degree + tid];
             if (y >= 0 && y < a.capacity) {
-                const int r = hash_insert(hset, y);
-                if (r == 1) s_new[atomicAdd(&s_nnew, 1)] = y;
+                const int r = hash_insert(hset, y, hmask);
+                if (r == 1) s_new[atomicAdd(&s_nnew[par], 1)] = y;
                 if (r < 0) {
                     s_stop = 1;
                     atomicOr(a.err, kErrOverflow);
@@ -239,17 +269,16 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
             }
         }
         __syncthreads();
-        if (s_nnew == 0) continue;
-        score_new(qn);
+        nn = s_nnew[par];
+        score_new(nn);
         __syncthreads();
-        if (wave == 0) {
-            const int n = qn + s_nnew;
-            if (lane == 0) s_scored += s_nnew;
-            const int got = wave_compact(qkey, n, W, scratch);
-            if (lane == 0) s_qn = got;
-        }
+        merge(qn, nn, par);
+        if (tid == 0) s_scored += nn;
         __syncthreads();
-        qn = s_qn;
+        qn = min(W, qn + nn);
+        uint64_t *t = cur;
+        cur = nxt;
+        nxt = t;
     }
 
     // the k best live keys, in order
@@ -260,7 +289,7 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
             bool live = false;
             uint64_t key = kNoKey;
             if (i < qn) {
-                key = qkey[i];
+                key = cur[i];
                 if constexpr (B1 == kFloat) {
                     live = true;
                 } else {
@@ -517,9 +546,19 @@ unsigned grid_for(int64_t work)
 
 }  // namespace
 
-size_t graph_lds_bytes(int kpos, int window)
+int graph_hash_slots(int window, int degree)
 {
-    return (size_t)2 * kpos * 4 + (size_t)(window + kMaxDegree + kMaxWindow) * 8 + (size_t)kHash * 4;
+    // a step proposes at most `degree` nodes and a walk explores about W
+    // nodes: room for degree * (W + 32) proposals, as a power of two
+    const int64_t want = (int64_t)degree * (window + 32);
+    int h = 1024;
+    while (h < want && h < kMaxHash) h <<= 1;
+    return h;
+}
+
+size_t graph_lds_bytes(int kpos, int window, int degree)
+{
+    return (size_t)2 * kpos * 4 + (size_t)2 * window * 8 + (size_t)graph_hash_slots(window, degree) * 4;
 }
 
 hipError_t launch_graph_search(const GraphLaunch &l, hipStream_t s)
@@ -552,9 +591,11 @@ hipError_t launch_graph_search(const GraphLaunch &l, hipStream_t s)
     a.xf = l.xf;
     a.dim = l.dim;
     a.qnodes = l.qnodes;
+    a.hash_slots = graph_hash_slots(l.window, l.degree);
     if (l.nq <= 0) return hipSuccess;
-    if (l.window > kMaxWindow || l.degree > kMaxDegree || l.k > l.window) return hipErrorInvalidValue;
-    const size_t lds = graph_lds_bytes(l.kpos, l.window);
+    if (l.window > kMaxWindow || l.degree > kMaxDegree || l.k > l.window || l.n_entries > kMaxDegree)
+        return hipErrorInvalidValue;
+    const size_t lds = graph_lds_bytes(l.kpos, l.window, l.degree);
     void (*kern)(GraphArgs) = nullptr;
     if (!l.rows) {
         if (!l.xf || l.kpos != l.dim) return hipErrorInvalidValue;

@@ -1063,7 +1063,7 @@ int lvq_graph_search(lvq_index *ix, const float *q_dev, int64_t nq, const int32_
     std::lock_guard<std::mutex> lk(ix->mu);
     if (ix->cfg.capacity == 0) return LVQ_ERR_INVALID_ARG;
     const Format &f = ix->f;
-    if (graph_lds_bytes(f.kpos, window) > ix->lds_max) return LVQ_ERR_UNSUPPORTED;
+    if (graph_lds_bytes(f.kpos, window, degree) > ix->lds_max) return LVQ_ERR_UNSUPPORTED;
     if (nq == 0) return LVQ_OK;
     hipStream_t s = (hipStream_t)stream;
     int rc = begin_call(ix, s);
@@ -1493,7 +1493,7 @@ int lvq_graph_build(const float *x_dev, int64_t n, int32_t dim, int32_t metric, 
     size_t lds_max = 0;
     int rc = graph_device_lds(&lds_max);
     if (rc) return rc;
-    if (graph_lds_bytes(dim, window) > lds_max) return LVQ_ERR_UNSUPPORTED;
+    if (graph_lds_bytes(dim, window, degree) > lds_max) return LVQ_ERR_UNSUPPORTED;
     const int64_t count = n - first;
     if (count == 0) return LVQ_OK;
     hipStream_t s = (hipStream_t)stream;

@@ -192,7 +192,10 @@ struct GraphLaunch {
     int dim;
     const int32_t *qnodes;
 };
-size_t graph_lds_bytes(int kpos, int window);
+// Seen-set hash slots of a walk (a power of two, at most 16384) and the
+// search kernel's LDS bytes.
+int graph_hash_slots(int window, int degree);
+size_t graph_lds_bytes(int kpos, int window, int degree);
 hipError_t launch_graph_search(const GraphLaunch &l, hipStream_t s);
 
 // Neighbourhood pruning (Alg. 2) over float vectors, one workgroup per node.
