@@ -707,6 +707,34 @@ def bench_probe(args):
 # Greedy graph search (Alg. 1) over LVQ-8 codes: queries/s against recall
 # ---------------------------------------------------------------------------
 
+GRAPH_TRAFFIC = os.path.join(ROOT, "profiles", "k_graph_search_g1_stats.md")
+GRAPH_SOURCES = ["paper_2402_02044_amd/csrc/k_graph.hip", "paper_2402_02044_amd/csrc/k_common.h"]
+
+
+def read_graph_traffic(nq: int, window: int):
+    """HBM bytes per search launch from the committed counter summary, if it
+    was taken on the current kernel source, batch and window (else None)."""
+    if not os.path.exists(GRAPH_TRAFFIC):
+        return None
+    vals = {}
+    for ln in open(GRAPH_TRAFFIC):
+        if ":" in ln and ln.strip().startswith("- "):
+            k, v = ln.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for p in GRAPH_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    try:
+        if vals.get("kernel_source_sha") != h.hexdigest()[:16]:
+            return None
+        if int(vals["queries_per_launch"]) != nq or int(vals["window"]) != window:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def bench_graph(args):
     import torch
 
@@ -746,7 +774,7 @@ def bench_graph(args):
     s = int(torch.cuda.current_stream().cuda_stream)
     row_bytes = ix.row_bytes
     points = []
-    for W in (16, 24, 32, 48, 64, 96, 128):
+    for W in ((args.window,) if args.window else (16, 24, 32, 48, 64, 96, 128)):
 
         def step():
             L.lvq_graph_search(ix.handle, qd.data_ptr(), nq, graph.data_ptr(), R, entry.data_ptr(), 1, W, k,
@@ -773,7 +801,7 @@ def bench_graph(args):
                             "node; 10,000 queries, top-10; value at the smallest window W reaching recall@10 >= 0.9",
                 "n": n, "dim": d, "degree": R, "queries": nq, "k": k, "window": head["window"]},
                {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": read_graph_traffic(nq, head["window"]),
                 "kernel": "k_graph_search (one workgroup per query; a chain of dependent steps per query)",
                 "kernel_ms": head["kernel_ms"],
                 "algorithmic_bytes": "d*4 per query + degree*4 per explored node + %d per scored node" % row_bytes},
@@ -1224,6 +1252,7 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override the store size (testing)")
     ap.add_argument("--nq", type=int, default=0, help="override the query count (testing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--window", type=int, default=0, help="graph: one search window instead of the sweep")
     ap.add_argument("--tile", type=int, default=-1, help="fixed tile shape (default: tuning cache, else autotune)")
     ap.add_argument("--retune", action="store_true", help="run the autotuner even when the cache has a shape")
     ap.add_argument("--calibrate-copy", action="store_true",
