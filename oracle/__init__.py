@@ -392,6 +392,35 @@ def vamana_insert(metric, X, graph, nodes, entry, W, alpha, R):
     return graph
 
 
+def vamana_delete(metric, X, graph, deleted, alpha, R):
+    """Delete consolidation (App. A) of the nodes flagged in `deleted`, on a
+    copy of graph: every kept node x' with deleted out-neighbours gets as
+    candidates its kept out-neighbours and the kept out-neighbours of each
+    deleted one (x' -> x -> x'' becomes x' -> x''), without x' itself; more
+    than R distinct candidates are pruned (Alg. 2).  All rows are read from
+    the graph before the consolidation; rows of deleted nodes are cleared."""
+    deleted = np.asarray(deleted, bool)
+    out = graph.copy()
+    for p in range(graph.shape[0]):
+        if deleted[p]:
+            continue
+        row = [int(v) for v in graph[p] if v >= 0]
+        if not any(deleted[v] for v in row):
+            continue
+        cand = set()
+        for v in row:
+            if deleted[v]:
+                cand.update(int(u) for u in graph[v] if u >= 0 and not deleted[u] and u != p)
+            else:
+                cand.add(v)
+        cand = sorted(cand)
+        keep = robust_prune(metric, X, p, cand, [], alpha, R) if len(cand) > R else cand
+        out[p] = -1
+        out[p, :len(keep)] = keep
+    out[deleted] = -1
+    return out
+
+
 def vamana_build(metric, X, entry, W, alpha, R, order=None):
     """Initial build (App. A): an empty graph, then the update routine for
     every node twice, first with alpha = 1 and then with the given alpha.

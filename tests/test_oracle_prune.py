@@ -116,3 +116,47 @@ def test_insert_adds_reachable_nodes():
     oracle.vamana_insert(oracle.L2, X, graph, range(250, 300), entry, 20, 1.2, 10)
     for i in range(250, 300):
         assert oracle.greedy_search_float(oracle.L2, X[i], X, graph, [entry], 20, 1)[0][0] == i
+
+
+def test_delete_consolidation_by_hand():
+    # points on a line 0..5 (slot = position), path graph; delete 2 and 3.
+    # Node 1 had {0, 2}: 2 is deleted, its kept neighbour is 1 itself (dropped)
+    # and 3 is deleted too, so node 1 keeps {0} -- only one hop is bridged.
+    # Node 4 had {3, 5}: 3's kept neighbours are none (2 deleted, 4 itself),
+    # so 4 keeps {5}.  With R = 1, node 1's candidates {0} fit; nothing pruned.
+    X = _line([0, 1, 2, 3, 4, 5])
+    g = np.full((6, 2), -1, np.int32)
+    for i in range(6):
+        nb = [j for j in (i - 1, i + 1) if 0 <= j < 6]
+        g[i, :len(nb)] = nb
+    deleted = np.zeros(6, bool)
+    deleted[[2, 3]] = True
+    out = oracle.vamana_delete(oracle.L2, X, g, deleted, 1.2, 2)
+    assert [set(int(v) for v in out[i] if v >= 0) for i in range(6)] == [{1}, {0}, set(), set(), {5}, {4}]
+    # delete only 2: node 1 bridges to 3, node 3 bridges to 1
+    deleted[3] = False
+    out = oracle.vamana_delete(oracle.L2, X, g, deleted, 1.2, 2)
+    assert set(int(v) for v in out[1] if v >= 0) == {0, 3}
+    assert set(int(v) for v in out[3] if v >= 0) == {1, 4}
+    # R = 1 forces a prune: node 1's candidates {0, 3} -> the nearer, 0
+    g1 = g.copy()
+    out = oracle.vamana_delete(oracle.L2, X, g1, deleted, 1.2, 1)
+    assert set(int(v) for v in out[1] if v >= 0) == {0}
+
+
+def test_delete_consolidation_keeps_search_working():
+    g = synth.rng(8905, 0)
+    n, R = 400, 10
+    X = g.standard_normal((n, 2)).astype(np.float32)
+    entry = int(np.argmin(((X - X.mean(0)) ** 2).sum(1)))
+    graph = oracle.vamana_build(oracle.L2, X, entry, 20, 1.2, R)
+    deleted = np.zeros(n, bool)
+    deleted[g.choice([i for i in range(n) if i != entry], 80, replace=False)] = True
+    out = oracle.vamana_delete(oracle.L2, X, graph, deleted, 1.2, R)
+    assert (out[deleted] == -1).all()
+    for i in np.flatnonzero(~deleted):
+        row = [int(v) for v in out[i] if v >= 0]
+        assert len(row) <= R and not deleted[row].any() and i not in row
+    hit = sum(int(oracle.greedy_search_float(oracle.L2, X[i], X, out, [entry], 20, 1)[0][0] == i)
+              for i in np.flatnonzero(~deleted))
+    assert hit >= int(0.98 * (~deleted).sum())
