@@ -263,6 +263,27 @@ int lvq_graph_build(const float *x_dev, int64_t n, int32_t dim, int32_t metric, 
                     int32_t window, float alpha, int32_t passes, int32_t entry, int32_t max_batch,
                     int32_t *graph_dev, void *stream);
 
+/* Insertions (App. A): the update routine of lvq_graph_build, once with
+ * `alpha`, for the m distinct nodes nodes_host[0 .. m) (host int32, in that
+ * order; their rows are cleared first; none of them the entry), into the
+ * graph formed by the other nodes -- e.g. slots freed by a consolidation and
+ * filled again.  Batches as lvq_graph_build.  Synchronises `stream`.        */
+int lvq_graph_insert(const float *x_dev, int64_t n, int32_t dim, int32_t metric, const int32_t *nodes_host,
+                     int64_t m, int32_t degree, int32_t window, float alpha, int32_t entry, int32_t max_batch,
+                     int32_t *graph_dev, void *stream);
+
+/* Delete consolidation (App. A) of the nodes flagged in deleted_dev (n bytes,
+ * nonzero = deleted): every kept node x' with deleted out-neighbours takes as
+ * candidates its kept out-neighbours and the kept out-neighbours of each
+ * deleted one (x' -> x -> x'' becomes x' -> x''); more than `degree` distinct
+ * candidates are pruned as in lvq_graph_prune (in groups of 256 positions of
+ * the degree x degree neighbour table, a single group for degree <= 16).
+ * Every row is read as it was before the call; rows of deleted nodes become
+ * -1.  A deleted node must no longer serve as an entry.  Synchronises
+ * `stream`.                                                                */
+int lvq_graph_delete(const float *x_dev, int64_t n, int32_t dim, int32_t metric, const uint8_t *deleted_dev,
+                     int32_t degree, float alpha, int32_t *graph_dev, void *stream);
+
 /* Online re-estimation of M-LVQ means with selective re-encoding (Sec. 3.2;
  * updating means needs the rows of the moved centres re-encoded).
  *

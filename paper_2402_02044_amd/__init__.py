@@ -38,7 +38,7 @@ LVQ_ERR_BAD_SLOT = -7
 EXPORTS = ["lvq_row_format", "lvq_create", "lvq_destroy", "lvq_set_means", "lvq_encode", "lvq_insert",
            "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_topk", "lvq_probe_topk", "lvq_retire_means",
            "lvq_add_means", "lvq_mean_members", "lvq_graph_search", "lvq_graph_prune", "lvq_graph_build",
-           "lvq_read_rows",
+           "lvq_graph_insert", "lvq_graph_delete", "lvq_read_rows",
            "lvq_get_stats", "lvq_sync", "lvq_mean", "lvq_kmeans", "lvq_strerror", "lvq_set_timing",
            "lvq_kernel_time", "lvq_autotune", "lvq_set_tile", "lvq_server_create", "lvq_server_submit",
            "lvq_server_wait", "lvq_server_drain", "lvq_server_get_stats", "lvq_server_destroy",
@@ -108,6 +108,8 @@ def _load():
         "lvq_graph_search": [P, P, i64, P, i32, P, i32, i32, i32, P, P, P, P],
         "lvq_graph_prune": [P, i64, i32, i32, P, i64, P, P, i32, ctypes.c_float, P, P],
         "lvq_graph_build": [P, i64, i32, i32, i64, i32, i32, ctypes.c_float, i32, i32, i32, P, P],
+        "lvq_graph_insert": [P, i64, i32, i32, P, i64, i32, i32, ctypes.c_float, i32, i32, P, P],
+        "lvq_graph_delete": [P, i64, i32, i32, P, i32, ctypes.c_float, P, P],
         "lvq_read_rows": [P, P, i64, P, P, P],
         "lvq_get_stats": [P, ctypes.POINTER(lvq_stats)],
         "lvq_sync": [P, P],
@@ -224,6 +226,45 @@ def lvq_graph_prune(x, n, dim, metric, nodes, m, cand_offsets, cand_ids, degree,
 def lvq_graph_build(x, n, dim, metric, first, degree, window, alpha, passes, entry, max_batch, graph, stream=0):
     return _chk(_lib.lvq_graph_build(x, n, dim, metric, first, degree, window, alpha, passes, entry, max_batch,
                                      graph, stream), "lvq_graph_build")
+
+
+def lvq_graph_insert(x, n, dim, metric, nodes_host, m, degree, window, alpha, entry, max_batch, graph, stream=0):
+    return _chk(_lib.lvq_graph_insert(x, n, dim, metric, nodes_host, m, degree, window, alpha, entry, max_batch,
+                                      graph, stream), "lvq_graph_insert")
+
+
+def lvq_graph_delete(x, n, dim, metric, deleted, degree, alpha, graph, stream=0):
+    return _chk(_lib.lvq_graph_delete(x, n, dim, metric, deleted, degree, alpha, graph, stream), "lvq_graph_delete")
+
+
+def _graph_args(x, graph):
+    import torch
+    if x.dtype != torch.float32 or x.dim() != 2 or not x.is_contiguous():
+        raise LVQError(LVQ_ERR_INVALID_ARG, "x must be a contiguous float32 matrix")
+    if graph.dim() != 2 or graph.shape[0] != x.shape[0] or graph.dtype != torch.int32 or not graph.is_contiguous():
+        raise LVQError(LVQ_ERR_INVALID_ARG, "graph must be a contiguous int32 (n x degree) tensor")
+
+
+def graph_insert(x, graph, nodes, window, alpha, metric, entry, max_batch=16384, stream=None):
+    """Insert the listed nodes (host sequence) into graph (App. A, one pass)."""
+    import numpy as np
+    _graph_args(x, graph)
+    nodes = np.ascontiguousarray(nodes, np.int32)
+    lvq_graph_insert(_ptr(x), x.shape[0], x.shape[1], metric, nodes.ctypes.data, nodes.shape[0], graph.shape[1],
+                     window, alpha, entry, max_batch, _ptr(graph), _stream(stream))
+    return graph
+
+
+def graph_delete(x, graph, deleted, alpha, metric, stream=None):
+    """Delete consolidation (App. A); deleted: n uint8/bool device flags."""
+    import torch
+    _graph_args(x, graph)
+    deleted = deleted.to(torch.uint8).contiguous()
+    if deleted.shape != (x.shape[0],):
+        raise LVQError(LVQ_ERR_INVALID_ARG, "deleted must hold one flag per node")
+    lvq_graph_delete(_ptr(x), x.shape[0], x.shape[1], metric, _ptr(deleted), graph.shape[1], alpha, _ptr(graph),
+                     _stream(stream))
+    return graph
 
 
 def graph_prune(x, nodes, cand_offsets, cand_ids, graph, alpha, metric, stream=None):

@@ -343,8 +343,14 @@ __global__ __launch_bounds__(256) void k_graph_prune(PruneLaunch a)
         if (tid == 0) atomicOr(a.err, kErrBadSlot);
         return;
     }
+    const uint8_t *del = a.deleted;
     int64_t c0, c1;
-    if (a.coffs) {
+    if (del) {
+        // delete consolidation: position j names out-neighbour j / R of p
+        // and, when that one is deleted, its out-neighbour j % R
+        c0 = 0;
+        c1 = (int64_t)a.R * a.R;
+    } else if (a.coffs) {
         const int64_t j = a.by_node ? (int64_t)p : i;
         c0 = a.coffs[j];
         c1 = a.coffs[j + 1];
@@ -363,7 +369,7 @@ __global__ __launch_bounds__(256) void k_graph_prune(PruneLaunch a)
     if (tid == 0)
         for (int r = 0; r < a.R; ++r) {
             const int32_t y = a.graph[(int64_t)p * a.R + r];
-            if (y >= 0 && y < a.n && y != p) kept[s_kept++] = y;
+            if (y >= 0 && y < a.n && y != p && !(del && del[y])) kept[s_kept++] = y;
         }
     __syncthreads();
 
@@ -373,7 +379,14 @@ __global__ __launch_bounds__(256) void k_graph_prune(PruneLaunch a)
         for (int r = tid; r < s_kept; r += 256) cid[r] = kept[r];
         __syncthreads();
         for (int64_t j = cs + tid; j < ce; j += 256) {
-            const int32_t y = a.cids[j];
+            int32_t y;
+            if (del) {
+                const int32_t v = a.graph[(int64_t)p * a.R + j / a.R];
+                y = v >= 0 && v < a.n && del[v] ? a.graph[(int64_t)v * a.R + j % a.R] : -1;
+                if (y >= 0 && y < a.n && del[y]) y = -1;
+            } else {
+                y = a.cids[j];
+            }
             if (y >= 0 && y < a.n && y != p) cid[atomicAdd(&s_n, 1)] = y;
         }
         __syncthreads();
@@ -538,6 +551,37 @@ __global__ __launch_bounds__(256) void k_rev_fill(const int32_t *graph, int R, c
     }
 }
 
+// Kept nodes with a deleted out-neighbour: out[0 .. *count).
+__global__ __launch_bounds__(256) void k_graph_affected(const int32_t *graph, int R, int64_t n, const uint8_t *deleted,
+                                                         int32_t *out, int32_t *count)
+{
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        if (deleted[p]) continue;
+        bool hit = false;
+        for (int r = 0; r < R && !hit; ++r) {
+            const int32_t y = graph[p * R + r];
+            hit = y >= 0 && y < n && deleted[y];
+        }
+        if (hit) out[atomicAdd(count, 1)] = (int32_t)p;
+    }
+}
+
+// Rows of the flagged nodes (deleted != NULL) or of the listed nodes to -1.
+__global__ __launch_bounds__(256) void k_graph_clear_rows(int32_t *graph, int R, int64_t n, const uint8_t *deleted,
+                                                           const int32_t *nodes, int64_t m)
+{
+    const int64_t total = (deleted ? n : m) * R;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e / R;
+        if (deleted) {
+            if (deleted[i]) graph[e] = -1;
+        } else {
+            const int32_t p = nodes[i];
+            if (p >= 0 && p < n) graph[(int64_t)p * R + e % R] = -1;
+        }
+    }
+}
+
 unsigned grid_for(int64_t work)
 {
     const int64_t b = (work + 255) / 256;
@@ -620,6 +664,25 @@ hipError_t launch_graph_prune(const PruneLaunch &l, hipStream_t s)
         hipLaunchKernelGGL(k_graph_prune<LVQ_IP>, dim3((unsigned)l.m), dim3(256), lds, s, l);
     else
         hipLaunchKernelGGL(k_graph_prune<LVQ_L2>, dim3((unsigned)l.m), dim3(256), lds, s, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_graph_affected(const int32_t *graph, int R, int64_t n, const uint8_t *deleted, int32_t *out,
+                                 int32_t *count, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipError_t e = launch_fill_i32(count, 0, 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_graph_affected, dim3(grid_for(n)), dim3(256), 0, s, graph, R, n, deleted, out, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_graph_clear_rows(int32_t *graph, int R, int64_t n, const uint8_t *deleted, const int32_t *nodes,
+                                   int64_t m, hipStream_t s)
+{
+    const int64_t rows = deleted ? n : m;
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_graph_clear_rows, dim3(grid_for(rows * R)), dim3(256), 0, s, graph, R, n, deleted, nodes, m);
     return hipGetLastError();
 }
 

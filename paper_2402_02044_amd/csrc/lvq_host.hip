@@ -1440,74 +1440,27 @@ struct GraphScratch {
     }
 };
 
-}  // namespace
-
-extern "C" {
-
-int lvq_graph_prune(const float *x_dev, int64_t n, int32_t dim, int32_t metric, const int32_t *nodes_dev, int64_t m,
-                    const int64_t *cand_offsets_dev, const int32_t *cand_ids_dev, int32_t degree, float alpha,
-                    int32_t *graph_dev, void *stream)
+// The update routine of graph construction (App. A) for the nodes of
+// `order`, `passes` times (alpha = 1 first when there are two passes):
+// their rows are cleared, then batch by batch each node's window nearest
+// nodes found from `entry` are pruned into its out-neighbours and it joins
+// their out-neighbours (pruned on overflow).  A batch is at most max_batch
+// nodes and, in the first pass, at most the number already in the graph
+// (in_graph before the first node, plus the nodes inserted so far).
+int graph_update(const float *x_dev, int64_t n, int dim, int metric, const std::vector<int32_t> &order,
+                 int64_t in_graph, int R, int window, float alpha, int passes, int32_t entry, int32_t max_batch,
+                 int32_t *graph_dev, hipStream_t s)
 {
-    if (n < 1 || n > INT32_MAX || dim < 1 || dim > kGraphMaxDim || (metric != LVQ_L2 && metric != LVQ_IP) || m < 0 ||
-        m > INT32_MAX || degree < 1 || degree > kGraphMaxDegree || !(alpha > 0.0f) || !std::isfinite(alpha))
-        return LVQ_ERR_INVALID_ARG;
-    if (m == 0) return LVQ_OK;
-    if (!x_dev || !nodes_dev || !cand_offsets_dev || !cand_ids_dev || !graph_dev) return LVQ_ERR_INVALID_ARG;
-    hipStream_t s = (hipStream_t)stream;
-    GraphScratch sc(s);
-    uint32_t *err = nullptr;
-    int rc = sc.alloc(&err, 1);
-    if (rc) return rc;
-    LVQ_HIP(launch_fill_u32(err, 0, 1, s));
-    PruneLaunch l{};
-    l.xf = x_dev;
-    l.dim = dim;
-    l.metric = metric;
-    l.n = n;
-    l.nodes = nodes_dev;
-    l.m = m;
-    l.coffs = cand_offsets_dev;
-    l.by_node = 0;
-    l.cids = cand_ids_dev;
-    l.always = 1;
-    l.graph = graph_dev;
-    l.R = degree;
-    l.alpha = alpha;
-    l.err = err;
-    LVQ_HIP(launch_graph_prune(l, s));
-    uint32_t herr = 0;
-    LVQ_HIP(hipMemcpyAsync(&herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
-    LVQ_HIP(hipStreamSynchronize(s));
-    return graph_kernel_error(herr);
-}
-
-int lvq_graph_build(const float *x_dev, int64_t n, int32_t dim, int32_t metric, int64_t first, int32_t degree,
-                    int32_t window, float alpha, int32_t passes, int32_t entry, int32_t max_batch, int32_t *graph_dev,
-                    void *stream)
-{
-    if (!x_dev || !graph_dev || n < 1 || n > INT32_MAX || dim < 1 || dim > kGraphMaxDim ||
-        (metric != LVQ_L2 && metric != LVQ_IP) || first < 0 || first > n || degree < 1 ||
-        degree > kGraphMaxDegree || window < degree || window > 256 || !(alpha > 0.0f) || !std::isfinite(alpha) ||
-        passes < 1 || passes > 2 || entry < 0 || entry >= n || (first > 0 && entry >= first) || max_batch < 1)
+    if (dim < 1 || dim > kGraphMaxDim || (metric != LVQ_L2 && metric != LVQ_IP) || R < 1 || R > kGraphMaxDegree ||
+        window < R || window > 256 || !(alpha > 0.0f) || !std::isfinite(alpha) || max_batch < 1)
         return LVQ_ERR_INVALID_ARG;
     size_t lds_max = 0;
     int rc = graph_device_lds(&lds_max);
     if (rc) return rc;
-    if (graph_lds_bytes(dim, window, degree) > lds_max) return LVQ_ERR_UNSUPPORTED;
-    const int64_t count = n - first;
+    if (graph_lds_bytes(dim, window, R) > lds_max) return LVQ_ERR_UNSUPPORTED;
+    const int64_t count = (int64_t)order.size();
     if (count == 0) return LVQ_OK;
-    hipStream_t s = (hipStream_t)stream;
     const int64_t B = std::min<int64_t>(max_batch, count);
-    const int R = degree;
-    std::vector<int32_t> order;
-    order.reserve((size_t)count);
-    if (first == 0) {
-        order.push_back(entry);
-        for (int64_t v = 0; v < n; ++v)
-            if (v != entry) order.push_back((int32_t)v);
-    } else {
-        for (int64_t v = first; v < n; ++v) order.push_back((int32_t)v);
-    }
     GraphScratch sc(s);
     int32_t *order_d, *res, *cnt, *rev, *touched, *ntouched, *entry_d;
     int64_t *offs, *scan;
@@ -1521,15 +1474,14 @@ int lvq_graph_build(const float *x_dev, int64_t n, int32_t dim, int32_t metric, 
         return rc;
     LVQ_HIP(hipMemcpyAsync(order_d, order.data(), sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice, s));
     LVQ_HIP(hipMemcpyAsync(entry_d, &entry, sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LVQ_HIP(launch_fill_i32(graph_dev + first * R, -1, count * R, s));
+    LVQ_HIP(launch_graph_clear_rows(graph_dev, R, n, nullptr, order_d, count, s));
     LVQ_HIP(launch_fill_i32(cnt, 0, n, s));
     LVQ_HIP(launch_fill_u32(err, 0, 1, s));
     for (int pass = 0; pass < passes; ++pass) {
         const float a = (passes == 2 && pass == 0) ? 1.0f : alpha;
         for (int64_t b = 0; b < count;) {
-            // a batch is at most as large as the graph it is inserted into
-            const int64_t in_graph = pass == 0 ? first + b : n;
-            const int64_t bs = std::min<int64_t>({B, std::max<int64_t>(1, in_graph), count - b});
+            const int64_t now = pass == 0 ? in_graph + b : n;
+            const int64_t bs = std::min<int64_t>({B, std::max<int64_t>(1, now), count - b});
             const int32_t *nodes = order_d + b;
             GraphLaunch g{};
             g.capacity = n;
@@ -1580,6 +1532,123 @@ int lvq_graph_build(const float *x_dev, int64_t n, int32_t dim, int32_t metric, 
             b += bs;
         }
     }
+    uint32_t herr = 0;
+    LVQ_HIP(hipMemcpyAsync(&herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
+    LVQ_HIP(hipStreamSynchronize(s));
+    return graph_kernel_error(herr);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lvq_graph_prune(const float *x_dev, int64_t n, int32_t dim, int32_t metric, const int32_t *nodes_dev, int64_t m,
+                    const int64_t *cand_offsets_dev, const int32_t *cand_ids_dev, int32_t degree, float alpha,
+                    int32_t *graph_dev, void *stream)
+{
+    if (n < 1 || n > INT32_MAX || dim < 1 || dim > kGraphMaxDim || (metric != LVQ_L2 && metric != LVQ_IP) || m < 0 ||
+        m > INT32_MAX || degree < 1 || degree > kGraphMaxDegree || !(alpha > 0.0f) || !std::isfinite(alpha))
+        return LVQ_ERR_INVALID_ARG;
+    if (m == 0) return LVQ_OK;
+    if (!x_dev || !nodes_dev || !cand_offsets_dev || !cand_ids_dev || !graph_dev) return LVQ_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    GraphScratch sc(s);
+    uint32_t *err = nullptr;
+    int rc = sc.alloc(&err, 1);
+    if (rc) return rc;
+    LVQ_HIP(launch_fill_u32(err, 0, 1, s));
+    PruneLaunch l{};
+    l.xf = x_dev;
+    l.dim = dim;
+    l.metric = metric;
+    l.n = n;
+    l.nodes = nodes_dev;
+    l.m = m;
+    l.coffs = cand_offsets_dev;
+    l.by_node = 0;
+    l.cids = cand_ids_dev;
+    l.always = 1;
+    l.graph = graph_dev;
+    l.R = degree;
+    l.alpha = alpha;
+    l.err = err;
+    LVQ_HIP(launch_graph_prune(l, s));
+    uint32_t herr = 0;
+    LVQ_HIP(hipMemcpyAsync(&herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
+    LVQ_HIP(hipStreamSynchronize(s));
+    return graph_kernel_error(herr);
+}
+
+int lvq_graph_build(const float *x_dev, int64_t n, int32_t dim, int32_t metric, int64_t first, int32_t degree,
+                    int32_t window, float alpha, int32_t passes, int32_t entry, int32_t max_batch, int32_t *graph_dev,
+                    void *stream)
+{
+    if (!x_dev || !graph_dev || n < 1 || n > INT32_MAX || first < 0 || first > n || passes < 1 || passes > 2 ||
+        entry < 0 || entry >= n || (first > 0 && entry >= first))
+        return LVQ_ERR_INVALID_ARG;
+    std::vector<int32_t> order;
+    order.reserve((size_t)(n - first));
+    if (first == 0) {
+        order.push_back(entry);
+        for (int64_t v = 0; v < n; ++v)
+            if (v != entry) order.push_back((int32_t)v);
+    } else {
+        for (int64_t v = first; v < n; ++v) order.push_back((int32_t)v);
+    }
+    return graph_update(x_dev, n, dim, metric, order, first, degree, window, alpha, passes, entry, max_batch,
+                        graph_dev, (hipStream_t)stream);
+}
+
+int lvq_graph_insert(const float *x_dev, int64_t n, int32_t dim, int32_t metric, const int32_t *nodes_host,
+                     int64_t m, int32_t degree, int32_t window, float alpha, int32_t entry, int32_t max_batch,
+                     int32_t *graph_dev, void *stream)
+{
+    if (!x_dev || !graph_dev || n < 1 || n > INT32_MAX || m < 0 || m > n || (m > 0 && !nodes_host) || entry < 0 ||
+        entry >= n)
+        return LVQ_ERR_INVALID_ARG;
+    std::vector<int32_t> order(nodes_host, nodes_host + m);
+    std::vector<int32_t> sorted = order;
+    std::sort(sorted.begin(), sorted.end());
+    for (size_t i = 0; i < sorted.size(); ++i)
+        if (sorted[i] < 0 || sorted[i] >= n || sorted[i] == entry || (i > 0 && sorted[i] == sorted[i - 1]))
+            return LVQ_ERR_INVALID_ARG;
+    return graph_update(x_dev, n, dim, metric, order, n - m, degree, window, alpha, 1, entry, max_batch, graph_dev,
+                        (hipStream_t)stream);
+}
+
+int lvq_graph_delete(const float *x_dev, int64_t n, int32_t dim, int32_t metric, const uint8_t *deleted_dev,
+                     int32_t degree, float alpha, int32_t *graph_dev, void *stream)
+{
+    if (!x_dev || !deleted_dev || !graph_dev || n < 1 || n > INT32_MAX || dim < 1 || dim > kGraphMaxDim ||
+        (metric != LVQ_L2 && metric != LVQ_IP) || degree < 1 || degree > kGraphMaxDegree || !(alpha > 0.0f) ||
+        !std::isfinite(alpha))
+        return LVQ_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    GraphScratch sc(s);
+    int32_t *affected, *count;
+    uint32_t *err;
+    int rc;
+    if ((rc = sc.alloc(&affected, (size_t)n)) || (rc = sc.alloc(&count, 1)) || (rc = sc.alloc(&err, 1))) return rc;
+    LVQ_HIP(launch_fill_u32(err, 0, 1, s));
+    LVQ_HIP(launch_graph_affected(graph_dev, degree, n, deleted_dev, affected, count, s));
+    int32_t na = 0;
+    LVQ_HIP(hipMemcpyAsync(&na, count, sizeof(na), hipMemcpyDeviceToHost, s));
+    LVQ_HIP(hipStreamSynchronize(s));
+    PruneLaunch p{};
+    p.xf = x_dev;
+    p.dim = dim;
+    p.metric = metric;
+    p.n = n;
+    p.nodes = affected;
+    p.m = na;
+    p.always = 0;
+    p.graph = graph_dev;
+    p.R = degree;
+    p.alpha = alpha;
+    p.err = err;
+    p.deleted = deleted_dev;
+    LVQ_HIP(launch_graph_prune(p, s));
+    LVQ_HIP(launch_graph_clear_rows(graph_dev, degree, n, deleted_dev, nullptr, 0, s));
     uint32_t herr = 0;
     LVQ_HIP(hipMemcpyAsync(&herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
     LVQ_HIP(hipStreamSynchronize(s));

@@ -204,6 +204,9 @@ hipError_t launch_graph_search(const GraphLaunch &l, hipStream_t s);
 // (i + 1) * cstride) when coffs is NULL; -1 entries are skipped.  They are
 // taken in chunks of kPruneChunk, each merged with the out-neighbours kept so
 // far; `always` 0 prunes only a merge holding more than R distinct nodes.
+// With `deleted` (n flags) the candidates of p are instead the kept
+// out-neighbours of its deleted out-neighbours, and its own deleted
+// out-neighbours are dropped (delete consolidation).
 constexpr int kPruneChunk = 256;
 constexpr int kGraphMaxDegree = 64;
 constexpr int kGraphMaxDim = 4096;
@@ -222,8 +225,15 @@ struct PruneLaunch {
     int R;
     float alpha;
     uint32_t *err;
+    const uint8_t *deleted;
 };
 hipError_t launch_graph_prune(const PruneLaunch &l, hipStream_t s);
+// Kept nodes with a deleted out-neighbour into out[0 .. *count); rows of the
+// flagged (deleted) or listed (nodes, m) nodes set to -1.
+hipError_t launch_graph_affected(const int32_t *graph, int R, int64_t n, const uint8_t *deleted, int32_t *out,
+                                 int32_t *count, hipStream_t s);
+hipError_t launch_graph_clear_rows(int32_t *graph, int R, int64_t n, const uint8_t *deleted, const int32_t *nodes,
+                                   int64_t m, hipStream_t s);
 
 // Reverse edges of the out-neighbours of nodes[0..m): cnt (n, all zero on
 // entry and on return) counts them; offs (n + 1) receives the CSR offsets by

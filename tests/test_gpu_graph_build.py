@@ -153,3 +153,59 @@ def test_graph_build_rejects_bad_arguments(L):
             L.graph_build(X, degree, window, alpha, 0, entry, passes=passes)
     with pytest.raises(L.LVQError):
         L.graph_build(torch.zeros((100, 5000), dtype=torch.float32, device="cuda"), 8, 16, 1.2, 0, 0)
+
+
+@pytest.mark.parametrize("metric,alpha", [(0, 1.2), (1, 0.95)])
+def test_delete_consolidation_matches_oracle(L, metric, alpha):
+    # degree 16: the 16 x 16 neighbour table is one group of candidates, so
+    # the GPU prunes each affected row in one step as the oracle does
+    g = synth.rng(9400, metric)
+    n, d, R, W = 3000, 16, 16, 32
+    X = g.standard_normal((n, d)).astype(np.float32)
+    if metric == oracle.IP:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+    entry = int(np.argmin(((X - X.mean(0)) ** 2).sum(1)))
+    xd = torch.from_numpy(X).cuda()
+    graph = L.graph_build(xd, R, W, alpha, metric, entry, passes=2, max_batch=512)
+    before = graph.cpu().numpy()
+    deleted = np.zeros(n, bool)
+    deleted[g.choice([i for i in range(n) if i != entry], 450, replace=False)] = True
+    L.graph_delete(xd, graph, torch.from_numpy(deleted).cuda(), alpha, metric)
+    got = graph.cpu().numpy()
+    want = oracle.vamana_delete(metric, X, before, deleted, alpha, R)
+    assert (got[deleted] == -1).all()
+    kept = np.flatnonzero(~deleted)
+    _rows_ok(got, n, kept)
+    for i in kept:
+        assert not deleted[got[i][got[i] >= 0]].any()
+    same = sum(set(got[i][got[i] >= 0].tolist()) == set(want[i][want[i] >= 0].tolist()) for i in kept)
+    assert same >= len(kept) - 5, "%d of %d rows equal the oracle's consolidation" % (same, len(kept))
+    # rows without deleted out-neighbours are untouched
+    clean = [i for i in kept if not deleted[before[i][before[i] >= 0]].any()]
+    np.testing.assert_array_equal(got[clean], before[clean])
+
+
+def test_insert_listed_nodes_matches_oracle(L):
+    # one node at a time: the paper's sequential insert of scattered nodes
+    g = synth.rng(9500, 0)
+    n, d, R, W = 800, 8, 10, 24
+    X = g.standard_normal((n, d)).astype(np.float32)
+    xd = torch.from_numpy(X).cuda()
+    new = np.sort(g.choice(np.arange(1, n), 120, replace=False)).astype(np.int32)
+    old = np.setdiff1d(np.arange(n), new)
+    entry = int(old[np.argmin(((X[old] - X[old].mean(0)) ** 2).sum(1))])
+    base = np.full((n, R), -1, np.int32)
+    oracle.vamana_insert(0, X, base, [entry] + [int(v) for v in old if v != entry], entry, W, 1.2, R)
+    graph = torch.from_numpy(base.copy()).cuda()
+    order = g.permutation(new).astype(np.int32)
+    L.graph_insert(xd, graph, order, W, 1.2, 0, entry, max_batch=1)
+    got = graph.cpu().numpy()
+    want = base.copy()
+    oracle.vamana_insert(0, X, want, order, entry, W, 1.2, R)
+    _rows_ok(got, n)
+    same = sum(set(got[i][got[i] >= 0].tolist()) == set(want[i][want[i] >= 0].tolist()) for i in range(n))
+    assert same >= int(0.98 * n), "%d of %d rows equal the oracle's inserts" % (same, n)
+    with pytest.raises(L.LVQError):   # the entry cannot be inserted
+        L.graph_insert(xd, graph, [entry], W, 1.2, 0, entry)
+    with pytest.raises(L.LVQError):   # repeated node
+        L.graph_insert(xd, graph, [new[0], new[0]], W, 1.2, 0, entry)
