@@ -80,3 +80,15 @@ def test_complete_graph_and_full_window_is_exhaustive():
             assert ne == n
             np.testing.assert_array_equal(s, es[i])
             np.testing.assert_array_equal(v, ev[i])
+
+
+def test_the_closest_unexplored_node_is_explored_first():
+    # positions 0, 5, -5, 9 (slots 0..3); edges 0 -> {1, 2}, 1 -> {3}; query 10,
+    # W = 3.  Exploring 0 adds 1 (25) and 2 (225); the closest unexplored, 1,
+    # adds 3 (1), and the cut to W = 3 drops 2 before it is ever explored:
+    # explored {0, 1, 3}.  (Taking 2 first would explore four nodes.)
+    fmt, rows, mu = _line([0, 5, -5, 9])
+    graph = np.array([[1, 2], [3, -1], [-1, -1], [-1, -1]], np.int32)
+    s, v, ne = _search(fmt, rows, mu, graph, 10.0, W=3, k=3)
+    assert ne == 3
+    assert s.tolist() == [3, 1, 0] and v.tolist() == [1.0, 25.0, 100.0]

@@ -8,7 +8,8 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-PINS = ["tests/test_oracle_encode.py", "tests/test_oracle_distance.py", "tests/test_oracle_probe.py"]
+PINS = ["tests/test_oracle_encode.py", "tests/test_oracle_distance.py", "tests/test_oracle_probe.py",
+        "tests/test_oracle_graph.py", "tests/test_oracle_prune.py"]
 
 MUTATIONS = {
     "round_half_even": ("float c = b + 0.5f;\n    float v = floorf(c);",
@@ -31,10 +32,33 @@ MUTATIONS = {
     "probe_distance_unsquared": ("float sq = e * e;", "float sq = fabsf(e);"),
 }
 
+# mistakes in the graph functions of oracle/__init__.py (Alg. 1, Alg. 2, App. A)
+PY_MUTATIONS = {
+    "prune_rule_reversed_l2": ("removed = alpha * t <= sims[c] if metric == L2",
+                               "removed = alpha * t >= sims[c] if metric == L2"),
+    "prune_alpha_on_node_side": ("removed = alpha * t <= sims[c] if metric == L2",
+                                 "removed = t <= alpha * sims[c] if metric == L2"),
+    "prune_rule_reversed_ip": ("else alpha * t >= sims[c]", "else alpha * t <= sims[c]"),
+    "prune_keeps_node": ("for c in list(cand) + list(current) if c >= 0) - {int(p)})",
+                         "for c in list(cand) + list(current) if c >= 0))"),
+    "prune_ignores_current": ("for c in list(cand) + list(current) if c >= 0)",
+                              "for c in list(cand) if c >= 0)"),
+    "prune_ties_to_higher": ("key=lambda c: (sims[c] if metric == L2 else -sims[c], c))",
+                             "key=lambda c: (sims[c] if metric == L2 else -sims[c], -c))"),
+    "walk_cut_off_by_one": ("if len(cand) > W:\n            cand = dict(sorted(cand.items(), key=rank)[:W])",
+                            "if len(cand) > W + 1:\n            cand = dict(sorted(cand.items(), key=rank)[:W + 1])"),
+    "walk_explores_worst": ("x = min(open_, key=rank)[0]", "x = max(open_, key=rank)[0]"),
+    "walk_returns_deleted": ("if live is None or live[it[0]]][:k]", "][:k]"),
+    "insert_no_reverse_edges": ("        for y in nx:\n", "        for y in []:\n"),
+    "delete_rows_kept": ("    out[deleted] = -1\n    return out", "    return out"),
+    "delete_never_prunes": ("if len(cand) > R else cand", "if False else cand"),
+}
 
-@pytest.mark.parametrize("name", sorted(MUTATIONS))
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS) + sorted(PY_MUTATIONS))
 def test_planted_mistake_is_caught(name, tmp_path):
-    old, new = MUTATIONS[name]
+    target = "lvq_oracle.c" if name in MUTATIONS else "__init__.py"
+    old, new = MUTATIONS[name] if name in MUTATIONS else PY_MUTATIONS[name]
     work = tmp_path / "repo"
     (work / "tests").mkdir(parents=True)
     shutil.copytree(os.path.join(ROOT, "oracle"), work / "oracle",
@@ -44,7 +68,7 @@ def test_planted_mistake_is_caught(name, tmp_path):
     shutil.copytree(os.path.join(ROOT, "tests", "golden"), work / "tests" / "golden")
     for f in PINS + ["tests/conftest.py"]:
         shutil.copy(os.path.join(ROOT, f), work / f)
-    src = work / "oracle" / "lvq_oracle.c"
+    src = work / "oracle" / target
     text = src.read_text()
     assert text.count(old) == 1, "mutation anchor not found: " + name
     src.write_text(text.replace(old, new))
