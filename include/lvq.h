@@ -215,10 +215,12 @@ int lvq_probe_topk(lvq_index *index, const float *q_dev, int64_t nq, int32_t npr
  * traversed but left out of the result: ids_dev / dist_dev (nq x k) hold the
  * k best live nodes of the final set, padded as for lvq_distances;
  * explored_dev (nq x 2 int32, may be NULL) the nodes explored and the nodes
- * scored (entries and proposed neighbours) per query.  The nodes a query has
- * proposed are kept in a set of degree * (window + 32) entries rounded up to
- * a power of two (1024 to 16384); a query that proposes more stops there and
- * sets the sticky error (lvq_sync reports LVQ_ERR_INVALID_ARG).             */
+ * scored (entries and proposed neighbours; a neighbour rejected once is
+ * scored again when proposed again) per query.  The nodes that enter a
+ * query's candidate set are kept in a table of 8 * (window + 64) entries
+ * rounded up to a power of two (1024 to 16384); a query in which more enter
+ * stops there and sets the sticky error (lvq_sync reports
+ * LVQ_ERR_INVALID_ARG).                                                    */
 int lvq_graph_search(lvq_index *index, const float *q_dev, int64_t nq, const int32_t *graph_dev,
                      int32_t degree, const int32_t *entries_dev, int32_t n_entries, int32_t window,
                      int32_t k, int32_t *ids_dev, float *dist_dev, int32_t *explored_dev, void *stream);

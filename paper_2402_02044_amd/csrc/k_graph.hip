@@ -7,7 +7,7 @@
 // proposed so far.  A key is (score order << 32) | (slot << 1) | explored: the
 // explored flag travels with the key through the sorts without changing the
 // (score, slot) order of distinct nodes.  Each step explores the best
-// unexplored key: its out-neighbours not seen before are scored (16 lanes per
+// unexplored key: its out-neighbours not seen before are scored (4 or 16 lanes per
 // neighbour) and merged, and the set is cut to the W best.  Deleted rows are
 // traversed; the result is the k best live ones.  Over LVQ rows the
 // similarity is the first level (Sec. 2.3: the first level traverses, both
@@ -52,9 +52,9 @@ struct GraphArgs {
     int hash_slots;
 };
 
-// Insert s into the open-addressing hash set h (mask + 1 slots, a power of
-// two; -1 marks an empty slot): 1 if it was not there, 0 if it was, -1 if the
-// set is full.
+// Open-addressing hash set h (mask + 1 slots, a power of two; -1 marks an
+// empty slot).  Insert: 1 if s was not there, 0 if it was, -1 if the set is
+// full.
 __device__ __forceinline__ int hash_insert(int32_t *h, int32_t s, uint32_t mask)
 {
     uint32_t i = ((uint32_t)s * 2654435761u) & mask;
@@ -67,13 +67,25 @@ __device__ __forceinline__ int hash_insert(int32_t *h, int32_t s, uint32_t mask)
     return -1;
 }
 
+__device__ __forceinline__ bool hash_contains(const int32_t *h, int32_t s, uint32_t mask)
+{
+    uint32_t i = ((uint32_t)s * 2654435761u) & mask;
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        const int32_t v = h[i];
+        if (v == s) return true;
+        if (v == -1) return false;
+        i = (i + 1) & mask;
+    }
+    return false;
+}
+
 // Similarity of two float vectors (one in LDS, one in global memory) by the
-// 16 lanes of a group; every lane of the group returns the value.
-template <int METRIC>
-__device__ __forceinline__ float sim16_f32(const float *u, const float *x, int dim, int g)
+// G lanes of a group (G = 4 or 16); every lane of the group returns the value.
+template <int METRIC, int G>
+__device__ __forceinline__ float sim_f32(const float *u, const float *x, int dim, int g)
 {
     float s = 0.0f;
-    for (int j = g; j < dim; j += 16) {
+    for (int j = g; j < dim; j += G) {
         const float v = x[j];
         if constexpr (METRIC == LVQ_IP) {
             s = fmaf(u[j], v, s);
@@ -82,16 +94,17 @@ __device__ __forceinline__ float sim16_f32(const float *u, const float *x, int d
             s = fmaf(t, t, s);
         }
     }
-    return group_sum<16>(s);
+    return group_sum<G>(s);
 }
 
-// First-level similarity of row `slot` to the query, by the 16 lanes of a
-// group (g = 0..15); every lane of the group returns the value.
-template <int B1, int METRIC>
-__device__ __forceinline__ float score16(const GraphArgs &a, const float *qt, const float *mk, int32_t slot, int g)
+// First-level similarity of row `slot` to the query, by the G lanes of a
+// group (g = 0..G-1); every lane of the group returns the value.  qt holds
+// the query in kernel order, less the mean when there is one mean (L2).
+template <int B1, int METRIC, int G>
+__device__ __forceinline__ float score_g(const GraphArgs &a, const float *qt, const float *mk, int32_t slot, int g)
 {
     if constexpr (B1 == kFloat) {
-        return sim16_f32<METRIC>(qt, a.xf + (int64_t)slot * a.dim, a.dim, g);
+        return sim_f32<METRIC, G>(qt, a.xf + (int64_t)slot * a.dim, a.dim, g);
     } else {
         const uint8_t *row = a.rows + (int64_t)slot * a.row_bytes;
         const float4 hdr = *reinterpret_cast<const float4 *>(row);
@@ -101,7 +114,8 @@ __device__ __forceinline__ float score16(const GraphArgs &a, const float *qt, co
         const float l = hdr.x, dl = hdr.y;
         constexpr int PER = B1 == 8 ? 4 : 8;   // positions per 32-bit word
         float s_lo = 0.0f, s_hi = 0.0f;
-        for (int w = g; w < nwords; w += 16) {
+        const bool one_mean = a.n_means == 1;
+        for (int w = g; w < nwords; w += G) {
             const uint32_t c = codes[w];
             const int p0 = w * PER;
             float cv[PER];
@@ -119,7 +133,7 @@ __device__ __forceinline__ float score16(const GraphArgs &a, const float *qt, co
                 if constexpr (METRIC == LVQ_IP) {
                     s_lo = fmaf(qt[p], cv[j], s_lo);
                 } else {
-                    const float qv = qt[p] - a.muk[(int64_t)mid * a.kpos + p];   // q - mu, kernel order
+                    const float qv = one_mean ? qt[p] : qt[p] - a.muk[(int64_t)mid * a.kpos + p];
                     float t = qv - fmaf(dl, cv[j], l);
                     t *= mk[p];
                     s_hi = fmaf(t, t, s_hi);
@@ -127,20 +141,33 @@ __device__ __forceinline__ float score16(const GraphArgs &a, const float *qt, co
             }
         }
         if constexpr (METRIC == LVQ_IP) {
-            const float dot = group_sum<16>(s_lo);
+            const float dot = group_sum<G>(s_lo);
             return fmaf(dl, dot, fmaf(l, a.qsum[0], a.cm[mid]));   // qsum / cm already offset to the query
         } else {
-            return group_sum<16>(s_hi);
+            return group_sum<G>(s_hi);
         }
     }
 }
 
-template <int B1, int METRIC>
+// True unless a lower lane of the wave holds the same value.  Called by all
+// 64 lanes of the wave.
+__device__ __forceinline__ bool first_copy(int32_t v, int lane)
+{
+    bool first = true;
+    for (int t = 0; t < 64; ++t) {
+        const int32_t o = __shfl(v, t, 64);
+        first = first && !(t < lane && o == v);
+    }
+    return first;
+}
+
+template <int B1, int METRIC, int G>
 __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NG = 256 / G;   // groups of G lanes, one neighbour each
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int grp = tid >> 4, g = tid & 15;   // 16 groups of 16 lanes
+    const int grp = tid / G, g = tid % G;
     const int64_t qi = blockIdx.x;
     if (qi >= a.nq) return;
     const int W = a.window;
@@ -163,7 +190,9 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
         }
     }
     for (int p = tid; p < a.kpos; p += 256) {
-        qt[p] = qsrc[p];
+        float v = qsrc[p];
+        if (B1 != kFloat && METRIC == LVQ_L2 && a.n_means == 1) v -= a.muk[p];   // q - mu once per query
+        qt[p] = v;
         mk[p] = METRIC == LVQ_L2 && B1 != kFloat ? a.kmask[p] : 1.0f;
     }
     const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
@@ -213,22 +242,31 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
             if (p < W) {
                 nxt[p] = k;
                 atomicMin(&s_pick[par], p);
+                // remember the node: it may not be proposed again while in the
+                // set, and once cut it could not re-enter
+                if (hash_insert(hset, (int32_t)((uint32_t)k >> 1), hmask) < 0) {
+                    s_stop = 1;
+                    atomicOr(a.err, kErrOverflow);
+                }
             }
         }
     };
     auto score_new = [&](int nn) {
-        for (int c = grp; c < nn; c += 16) {
+        for (int c = grp; c < nn; c += NG) {
             const int32_t s = s_new[c];
-            const float v = score16<B1, METRIC>(b, qt, mk, s, g);
+            const float v = score_g<B1, METRIC, G>(b, qt, mk, s, g);
             if (g == 0) s_key[c] = (make_key(v, 0, METRIC) & 0xFFFFFFFF00000000ull) | ((uint64_t)(uint32_t)s << 1);
         }
     };
 
-    // entry nodes: deduplicated through the hash set, scored, merged into the
-    // empty set (parity 1: the first step reads s_pick[1])
-    for (int i = tid; i < a.n_entries && qok; i += 256) {
-        const int32_t s = a.entries[i];
-        if (s >= 0 && s < a.capacity && hash_insert(hset, s, hmask) == 1) s_new[atomicAdd(&s_nnew[1], 1)] = s;
+    // entry nodes (at most 64, wave 0), repeats dropped, scored, merged into
+    // the empty set (parity 1: the first step reads s_pick[1])
+    if (wave == 0) {
+        int32_t s = lane < a.n_entries && qok ? a.entries[lane] : -1;
+        if (s >= a.capacity) s = -1;
+        const bool fc = first_copy(s, lane);   // whole wave: the shuffles read every lane
+        if (!fc) s = -1;
+        if (s >= 0) s_new[atomicAdd(&s_nnew[1], 1)] = s;
     }
     __syncthreads();
     int nn = s_nnew[1];
@@ -256,17 +294,15 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
             s_nnew[prev] = 0;
             ++s_explored;
         }
-        // out-neighbours not seen before
-        if (tid < a.degree) {
-            const int32_t y = a.graph[(int64_t)x * a.degree + tid];
-            if (y >= 0 && y < a.capacity) {
-                const int r = hash_insert(hset, y, hmask);
-                if (r == 1) s_new[atomicAdd(&s_nnew[par], 1)] = y;
-                if (r < 0) {
-                    s_stop = 1;
-                    atomicOr(a.err, kErrOverflow);
-                }
-            }
+        // out-neighbours that never entered the set (wave 0: degree <= 64);
+        // one that was rejected before is scored again and rejected again,
+        // since the set's W-th best only improves
+        if (wave == 0) {
+            int32_t y = lane < a.degree ? a.graph[(int64_t)x * a.degree + lane] : -1;
+            if (y >= a.capacity) y = -1;
+            const bool fc = first_copy(y, lane);   // whole wave
+            if (!fc) y = -1;
+            if (y >= 0 && !hash_contains(hset, y, hmask)) s_new[atomicAdd(&s_nnew[par], 1)] = y;
         }
         __syncthreads();
         nn = s_nnew[par];
@@ -322,12 +358,13 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
 
 // ---- neighbourhood pruning (Alg. 2) ----------------------------------------
 
-template <int METRIC>
+template <int METRIC, int G>
 __global__ __launch_bounds__(256) void k_graph_prune(PruneLaunch a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NG = 256 / G;
     const int tid = threadIdx.x, wave = tid >> 6;
-    const int grp = tid >> 4, g = tid & 15;
+    const int grp = tid / G, g = tid % G;
     const int64_t i = blockIdx.x;
     if (i >= a.m) return;
     float *xv = reinterpret_cast<float *>(smem);   // the node (dim)
@@ -392,9 +429,9 @@ __global__ __launch_bounds__(256) void k_graph_prune(PruneLaunch a)
         __syncthreads();
         const int nn = s_n;
         // similarities to the node
-        for (int c = grp; c < nn; c += 16) {
+        for (int c = grp; c < nn; c += NG) {
             const int32_t y = cid[c];
-            const float v = sim16_f32<METRIC>(xv, a.xf + (int64_t)y * a.dim, a.dim, g);
+            const float v = sim_f32<METRIC, G>(xv, a.xf + (int64_t)y * a.dim, a.dim, g);
             if (g == 0) keys[c] = make_key(v, y, METRIC);
         }
         __syncthreads();
@@ -437,10 +474,10 @@ __global__ __launch_bounds__(256) void k_graph_prune(PruneLaunch a)
                 const int32_t xstar = (int32_t)(uint32_t)keys[c];
                 for (int j = tid; j < a.dim; j += 256) xs[j] = a.xf[(int64_t)xstar * a.dim + j];
                 __syncthreads();
-                for (int e = pos + grp; e < nn; e += 16) {
+                for (int e = pos + grp; e < nn; e += NG) {
                     if (rm[e]) continue;   // uniform within the group
                     const int32_t y = (int32_t)(uint32_t)keys[e];
-                    const float t = sim16_f32<METRIC>(xs, a.xf + (int64_t)y * a.dim, a.dim, g);
+                    const float t = sim_f32<METRIC, G>(xs, a.xf + (int64_t)y * a.dim, a.dim, g);
                     const float sp = key_score(keys[e], METRIC);
                     const float at = a.alpha * t;
                     const bool drop = METRIC == LVQ_L2 ? at <= sp : at >= sp;
@@ -592,9 +629,11 @@ unsigned grid_for(int64_t work)
 
 int graph_hash_slots(int window, int degree)
 {
-    // a step proposes at most `degree` nodes and a walk explores about W
-    // nodes: room for degree * (W + 32) proposals, as a power of two
-    const int64_t want = (int64_t)degree * (window + 32);
+    // the nodes that enter a walk's candidate set: about 5.5 W on average and
+    // under 8.5 W at most on 10^6-node graphs of out-degree 64; 8 (W + 64)
+    // slots, as a power of two, keep the table under half full
+    (void)degree;
+    const int64_t want = (int64_t)8 * (window + 64);
     int h = 1024;
     while (h < want && h < kMaxHash) h <<= 1;
     return h;
@@ -640,14 +679,24 @@ hipError_t launch_graph_search(const GraphLaunch &l, hipStream_t s)
     if (l.window > kMaxWindow || l.degree > kMaxDegree || l.k > l.window || l.n_entries > kMaxDegree)
         return hipErrorInvalidValue;
     const size_t lds = graph_lds_bytes(l.kpos, l.window, l.degree);
+    // short rows: 4 lanes per neighbour (a step's neighbours in one round of
+    // loads); longer rows: 16
     void (*kern)(GraphArgs) = nullptr;
+    const bool ip = l.metric == LVQ_IP;
     if (!l.rows) {
         if (!l.xf || l.kpos != l.dim) return hipErrorInvalidValue;
-        kern = l.metric == LVQ_IP ? k_graph_search<kFloat, LVQ_IP> : k_graph_search<kFloat, LVQ_L2>;
-    } else if (l.bits1 == 8) {
-        kern = l.metric == LVQ_IP ? k_graph_search<8, LVQ_IP> : k_graph_search<8, LVQ_L2>;
-    } else if (l.bits1 == 4) {
-        kern = l.metric == LVQ_IP ? k_graph_search<4, LVQ_IP> : k_graph_search<4, LVQ_L2>;
+        if (l.dim <= 128)
+            kern = ip ? k_graph_search<kFloat, LVQ_IP, 4> : k_graph_search<kFloat, LVQ_L2, 4>;
+        else
+            kern = ip ? k_graph_search<kFloat, LVQ_IP, 16> : k_graph_search<kFloat, LVQ_L2, 16>;
+    } else {
+        const bool narrow = l.kchunks * 4 <= 32;   // code words per row
+        if (l.bits1 == 8)
+            kern = narrow ? (ip ? k_graph_search<8, LVQ_IP, 4> : k_graph_search<8, LVQ_L2, 4>)
+                          : (ip ? k_graph_search<8, LVQ_IP, 16> : k_graph_search<8, LVQ_L2, 16>);
+        else if (l.bits1 == 4)
+            kern = narrow ? (ip ? k_graph_search<4, LVQ_IP, 4> : k_graph_search<4, LVQ_L2, 4>)
+                          : (ip ? k_graph_search<4, LVQ_IP, 16> : k_graph_search<4, LVQ_L2, 16>);
     }
     if (!kern) return hipErrorInvalidValue;
     hipLaunchKernelGGL(kern, dim3((unsigned)l.nq), dim3(256), lds, s, a);
@@ -660,10 +709,10 @@ hipError_t launch_graph_prune(const PruneLaunch &l, hipStream_t s)
     if (l.R < 1 || l.R > kMaxDegree || l.dim < 1 || l.dim > kGraphMaxDim || l.m > 0x7FFFFFFF)
         return hipErrorInvalidValue;
     const size_t lds = (size_t)2 * l.dim * 4;
-    if (l.metric == LVQ_IP)
-        hipLaunchKernelGGL(k_graph_prune<LVQ_IP>, dim3((unsigned)l.m), dim3(256), lds, s, l);
-    else
-        hipLaunchKernelGGL(k_graph_prune<LVQ_L2>, dim3((unsigned)l.m), dim3(256), lds, s, l);
+    void (*kern)(PruneLaunch) = l.dim <= 128
+        ? (l.metric == LVQ_IP ? k_graph_prune<LVQ_IP, 4> : k_graph_prune<LVQ_L2, 4>)
+        : (l.metric == LVQ_IP ? k_graph_prune<LVQ_IP, 16> : k_graph_prune<LVQ_L2, 16>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)l.m), dim3(256), lds, s, l);
     return hipGetLastError();
 }
 

@@ -70,6 +70,8 @@ CASES = [
     (64, 8, oracle.SEQUENTIAL, oracle.L2, 1),
     (128, 4, oracle.TURBO, oracle.IP, 3),
     (100, 8, oracle.SEQUENTIAL, oracle.L2, 4),
+    (256, 8, oracle.SEQUENTIAL, oracle.IP, 1),      # 64 code words per row: 16 lanes per neighbour
+    (384, 4, oracle.TURBO, oracle.L2, 2),
 ]
 
 

@@ -40,10 +40,10 @@ def _rows_ok(graph, n, nodes=None):
         assert (v < n).all() and i not in v.tolist() and len(set(v.tolist())) == k, i
 
 
-@pytest.mark.parametrize("metric,alpha", [(0, 1.2), (1, 0.95), (0, 1.0)])
-def test_prune_matches_oracle(L, metric, alpha):
-    g = synth.rng(9000, metric)
-    n, d, R, m = 2000, 48, 16, 300
+@pytest.mark.parametrize("metric,alpha,d", [(0, 1.2, 48), (1, 0.95, 48), (0, 1.0, 48), (0, 1.2, 160)])
+def test_prune_matches_oracle(L, metric, alpha, d):
+    g = synth.rng(9000 + d, metric)
+    n, R, m = 2000, 16, 300
     X = g.standard_normal((n, d)).astype(np.float32)
     if metric == oracle.IP:
         X /= np.linalg.norm(X, axis=1, keepdims=True)
