@@ -97,55 +97,88 @@ __device__ __forceinline__ float sim_f32(const float *u, const float *x, int dim
     return group_sum<G>(s);
 }
 
-// First-level similarity of row `slot` to the query, by the G lanes of a
-// group (g = 0..G-1); every lane of the group returns the value.  qt holds
-// the query in kernel order, less the mean when there is one mean (L2).
-template <int B1, int METRIC, int G>
-__device__ __forceinline__ float score_g(const GraphArgs &a, const float *qt, const float *mk, int32_t slot, int g)
+// Similarity of one stored node to the query, by one lane.  LVQ rows: the
+// first level in kernel order (qt less the mean when there is one mean, L2;
+// IP adds l * sum(q) + <q, mu_m> from qsum / cm); float rows: binary32
+// squared distance or inner product.
+template <int B1, int METRIC>
+__device__ __forceinline__ float score_lane(const GraphArgs &a, const float *qt, const float *mk, int32_t slot,
+                                            float qsum, const float *cm)
 {
     if constexpr (B1 == kFloat) {
-        return sim_f32<METRIC, G>(qt, a.xf + (int64_t)slot * a.dim, a.dim, g);
-    } else {
-        const uint8_t *row = a.rows + (int64_t)slot * a.row_bytes;
-        const float4 hdr = *reinterpret_cast<const float4 *>(row);
-        const uint32_t *codes = reinterpret_cast<const uint32_t *>(row + kHeaderBytes);
-        const int nwords = a.kchunks * 4;
-        const int mid = min((int)(__float_as_uint(hdr.w) & 0xFFu), a.n_means - 1);
-        const float l = hdr.x, dl = hdr.y;
-        constexpr int PER = B1 == 8 ? 4 : 8;   // positions per 32-bit word
-        float s_lo = 0.0f, s_hi = 0.0f;
-        const bool one_mean = a.n_means == 1;
-        for (int w = g; w < nwords; w += G) {
-            const uint32_t c = codes[w];
-            const int p0 = w * PER;
-            float cv[PER];
-            if constexpr (B1 == 8) {
-                cv[0] = ub<0>(c); cv[1] = ub<1>(c); cv[2] = ub<2>(c); cv[3] = ub<3>(c);
-            } else {
-                // kernel order of a 4-bit word: fields 0,2,4,6 (low nibbles), then 1,3,5,7
-                const uint32_t lo = c & 0x0F0F0F0Fu, hi = (c >> 4) & 0x0F0F0F0Fu;
-                cv[0] = ub<0>(lo); cv[1] = ub<1>(lo); cv[2] = ub<2>(lo); cv[3] = ub<3>(lo);
-                cv[4] = ub<0>(hi); cv[5] = ub<1>(hi); cv[6] = ub<2>(hi); cv[7] = ub<3>(hi);
-            }
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                const int p = p0 + j;
+        const float *x = a.xf + (int64_t)slot * a.dim;
+        float s = 0.0f;
+        if ((a.dim & 3) == 0) {
+            const float4 *x4 = reinterpret_cast<const float4 *>(x);
+            const float4 *q4 = reinterpret_cast<const float4 *>(qt);
+            for (int c = 0; c < (a.dim >> 2); ++c) {
+                const float4 v = x4[c], q = q4[c];
                 if constexpr (METRIC == LVQ_IP) {
-                    s_lo = fmaf(qt[p], cv[j], s_lo);
+                    s = fmaf(q.x, v.x, s);
+                    s = fmaf(q.y, v.y, s);
+                    s = fmaf(q.z, v.z, s);
+                    s = fmaf(q.w, v.w, s);
                 } else {
-                    const float qv = one_mean ? qt[p] : qt[p] - a.muk[(int64_t)mid * a.kpos + p];
-                    float t = qv - fmaf(dl, cv[j], l);
-                    t *= mk[p];
-                    s_hi = fmaf(t, t, s_hi);
+                    const float t0 = q.x - v.x, t1 = q.y - v.y, t2 = q.z - v.z, t3 = q.w - v.w;
+                    s = fmaf(t0, t0, s);
+                    s = fmaf(t1, t1, s);
+                    s = fmaf(t2, t2, s);
+                    s = fmaf(t3, t3, s);
+                }
+            }
+        } else {
+            for (int j = 0; j < a.dim; ++j) {
+                if constexpr (METRIC == LVQ_IP) {
+                    s = fmaf(qt[j], x[j], s);
+                } else {
+                    const float t = qt[j] - x[j];
+                    s = fmaf(t, t, s);
                 }
             }
         }
-        if constexpr (METRIC == LVQ_IP) {
-            const float dot = group_sum<G>(s_lo);
-            return fmaf(dl, dot, fmaf(l, a.qsum[0], a.cm[mid]));   // qsum / cm already offset to the query
-        } else {
-            return group_sum<G>(s_hi);
+        return s;
+    } else {
+        const uint8_t *row = a.rows + (int64_t)slot * a.row_bytes;
+        const float4 hdr = *reinterpret_cast<const float4 *>(row);
+        const uint4 *code = reinterpret_cast<const uint4 *>(row + kHeaderBytes);
+        const int mid = min((int)(__float_as_uint(hdr.w) & 0xFFu), a.n_means - 1);
+        const float l = hdr.x, dl = hdr.y;
+        const bool one_mean = a.n_means == 1;
+        const float *mu = a.muk + (int64_t)mid * a.kpos;
+        constexpr int PER = B1 == 8 ? 4 : 8;   // positions per 32-bit word
+        float s = 0.0f;
+        for (int c = 0; c < a.kchunks; ++c) {
+            const uint4 v = code[c];
+            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t w = wv[i];
+                const int p0 = (4 * c + i) * PER;
+                float cv[PER];
+                if constexpr (B1 == 8) {
+                    cv[0] = ub<0>(w); cv[1] = ub<1>(w); cv[2] = ub<2>(w); cv[3] = ub<3>(w);
+                } else {
+                    // kernel order of a 4-bit word: fields 0,2,4,6 (low nibbles), then 1,3,5,7
+                    const uint32_t lo = w & 0x0F0F0F0Fu, hi = (w >> 4) & 0x0F0F0F0Fu;
+                    cv[0] = ub<0>(lo); cv[1] = ub<1>(lo); cv[2] = ub<2>(lo); cv[3] = ub<3>(lo);
+                    cv[4] = ub<0>(hi); cv[5] = ub<1>(hi); cv[6] = ub<2>(hi); cv[7] = ub<3>(hi);
+                }
+#pragma unroll
+                for (int j = 0; j < PER; ++j) {
+                    const int p = p0 + j;
+                    if constexpr (METRIC == LVQ_IP) {
+                        s = fmaf(qt[p], cv[j], s);
+                    } else {
+                        const float qv = one_mean ? qt[p] : qt[p] - mu[p];
+                        float t = qv - fmaf(dl, cv[j], l);
+                        t *= mk[p];
+                        s = fmaf(t, t, s);
+                    }
+                }
+            }
         }
+        if constexpr (METRIC == LVQ_IP) return fmaf(dl, s, fmaf(l, qsum, cm[mid]));
+        return s;
     }
 }
 
@@ -161,24 +194,34 @@ __device__ __forceinline__ bool first_copy(int32_t v, int lane)
     return first;
 }
 
-template <int B1, int METRIC, int G>
-__global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
+__device__ __forceinline__ int32_t key_node(uint64_t k)
+{
+    return (int32_t)((uint32_t)k >> 1);
+}
+
+// One wavefront (one 64-lane workgroup) per query.  Each step explores the
+// best unexplored node x: lane t takes x's out-neighbour t, drops repeats and
+// nodes that entered the set before, and scores the rest, one neighbour per
+// lane.  The new keys are sorted across the wave (register bitonic sort) and
+// merged into the sorted set by binary searches: a new key lands at its index
+// among the new keys plus the number of set keys below it, a set key moves
+// down by the number of new keys below it.  Keys landing below W form the new
+// set; the smallest position of an unexplored key is the next node.
+template <int B1, int METRIC>
+__global__ __launch_bounds__(64) void k_graph_search(GraphArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int NG = 256 / G;   // groups of G lanes, one neighbour each
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int grp = tid / G, g = tid % G;
+    const int lane = threadIdx.x;
     const int64_t qi = blockIdx.x;
     if (qi >= a.nq) return;
     const int W = a.window;
-    float *qt = reinterpret_cast<float *>(smem);                       // kpos
-    float *mk = qt + a.kpos;                                           // kpos
-    uint64_t *cur = reinterpret_cast<uint64_t *>(mk + a.kpos);         // W: the candidate set, ascending
-    uint64_t *nxt = cur + W;                                           // W: the merged set
-    int32_t *hset = reinterpret_cast<int32_t *>(nxt + W);              // hash_slots
-    __shared__ uint64_t s_key[kMaxDegree];                             // keys of the nodes proposed by a step
-    __shared__ int32_t s_new[kMaxDegree];
-    __shared__ int s_nnew[2], s_pick[2], s_stop, s_explored, s_scored;
+    const int kq = (a.kpos + 3) & ~3;
+    float *qt = reinterpret_cast<float *>(smem);                     // kq
+    float *mk = qt + kq;                                             // kq
+    uint64_t *cur = reinterpret_cast<uint64_t *>(mk + kq);           // W: the candidate set, ascending
+    uint64_t *nxt = cur + W;                                         // W: the merged set
+    uint64_t *skey = nxt + W;                                        // 64: a step's keys, ascending
+    int32_t *hset = reinterpret_cast<int32_t *>(skey + 64);          // hash_slots: nodes that entered
 
     const float *qsrc = a.qk + qi * a.kpos;
     bool qok = true;
@@ -189,170 +232,144 @@ __global__ __launch_bounds__(256) void k_graph_search(GraphArgs a)
             qsrc = a.xf + (int64_t)(qok ? node : 0) * a.dim;
         }
     }
-    for (int p = tid; p < a.kpos; p += 256) {
-        float v = qsrc[p];
-        if (B1 != kFloat && METRIC == LVQ_L2 && a.n_means == 1) v -= a.muk[p];   // q - mu once per query
+    for (int p = lane; p < kq; p += 64) {
+        float v = p < a.kpos ? qsrc[p] : 0.0f;
+        if (B1 != kFloat && METRIC == LVQ_L2 && a.n_means == 1 && p < a.kpos) v -= a.muk[p];   // q - mu once
         qt[p] = v;
-        mk[p] = METRIC == LVQ_L2 && B1 != kFloat ? a.kmask[p] : 1.0f;
+        mk[p] = METRIC == LVQ_L2 && B1 != kFloat && p < a.kpos ? a.kmask[p] : 1.0f;
     }
     const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
-    for (int i = tid; i < a.hash_slots; i += 256) hset[i] = -1;
-    if (tid == 0) {
-        s_nnew[0] = s_nnew[1] = 0;
-        s_pick[0] = s_pick[1] = 1 << 30;
-        s_stop = 0;
-        s_explored = 0;
-        s_scored = 0;
-        if (!qok) atomicOr(a.err, kErrBadSlot);
-    }
+    for (int i = lane; i < a.hash_slots; i += 64) hset[i] = -1;
+    if (lane == 0 && !qok) atomicOr(a.err, kErrBadSlot);
+    const float qsum = B1 != kFloat && METRIC == LVQ_IP ? a.qsum[qi] : 0.0f;
+    const float *cm = B1 != kFloat && METRIC == LVQ_IP ? a.cm + qi * a.n_means : nullptr;
     __syncthreads();
-    GraphArgs b = a;
-    if constexpr (B1 != kFloat) {
-        b.qsum = a.qsum + qi;
-        b.cm = a.cm + qi * a.n_means;
-    }
 
-    // Merge the nn keys s_key[0..nn) (new, unexplored, not in cur) into the
-    // sorted set cur[0..qn): every key's merged position is its rank among the
-    // old keys plus its rank among the new ones (keys are distinct); positions
-    // below W are written to nxt, and the best unexplored one is recorded in
-    // s_pick[par].
-    auto merge = [&](int qn, int nn, int par) {
-        if (tid < qn) {
-            const uint64_t k = cur[tid];
-            int r = 0;
-            for (int c = 0; c < nn; ++c) r += s_key[c] < k;
-            const int p = tid + r;
-            if (p < W) {
-                nxt[p] = k;
-                if (!(k & 1ull)) atomicMin(&s_pick[par], p);
-            }
-        }
-        if (tid < nn) {
-            const uint64_t k = s_key[tid];
-            int r = 0;
-            for (int c = 0; c < nn; ++c) r += s_key[c] < k;
-            int lo = 0, hi = qn;   // old keys below k
+    int qn = 0, pick = 1 << 30, explored = 0, scored = 0;
+    bool stop = false;
+    // Merge this lane's key (kNoKey if none; nn valid keys in the wave).
+    auto merge = [&](uint64_t key, int nn) {
+        uint64_t v[1] = {key};
+        wave_bitonic_sort<1>(v);
+        key = v[0];
+        skey[lane] = key;
+        __syncthreads();
+        int best = 1 << 30;
+        bool full = false;
+        if (lane < nn) {
+            int lo = 0, hi = qn;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
-                if (cur[mid] < k) lo = mid + 1;
+                if (cur[mid] < key) lo = mid + 1;
                 else hi = mid;
             }
-            const int p = lo + r;
+            const int p = lane + lo;
             if (p < W) {
-                nxt[p] = k;
-                atomicMin(&s_pick[par], p);
-                // remember the node: it may not be proposed again while in the
-                // set, and once cut it could not re-enter
-                if (hash_insert(hset, (int32_t)((uint32_t)k >> 1), hmask) < 0) {
-                    s_stop = 1;
-                    atomicOr(a.err, kErrOverflow);
-                }
+                nxt[p] = key;
+                best = p;
+                // remembered: not proposed again while in the set, and once
+                // cut it could not re-enter (the W-th best only improves)
+                full = hash_insert(hset, key_node(key), hmask) < 0;
             }
         }
-    };
-    auto score_new = [&](int nn) {
-        for (int c = grp; c < nn; c += NG) {
-            const int32_t s = s_new[c];
-            const float v = score_g<B1, METRIC, G>(b, qt, mk, s, g);
-            if (g == 0) s_key[c] = (make_key(v, 0, METRIC) & 0xFFFFFFFF00000000ull) | ((uint64_t)(uint32_t)s << 1);
+        for (int i = lane; i < qn; i += 64) {
+            const uint64_t k = cur[i];
+            int lo = 0, hi = nn;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (skey[mid] < k) lo = mid + 1;
+                else hi = mid;
+            }
+            const int p = i + lo;
+            if (p < W) {
+                nxt[p] = k;
+                if (!(k & 1ull) && p < best) best = p;
+            }
         }
-    };
-
-    // entry nodes (at most 64, wave 0), repeats dropped, scored, merged into
-    // the empty set (parity 1: the first step reads s_pick[1])
-    if (wave == 0) {
-        int32_t s = lane < a.n_entries && qok ? a.entries[lane] : -1;
-        if (s >= a.capacity) s = -1;
-        const bool fc = first_copy(s, lane);   // whole wave: the shuffles read every lane
-        if (!fc) s = -1;
-        if (s >= 0) s_new[atomicAdd(&s_nnew[1], 1)] = s;
-    }
-    __syncthreads();
-    int nn = s_nnew[1];
-    score_new(nn);
-    __syncthreads();
-    merge(0, nn, 1);
-    __syncthreads();
-    int qn = min(W, nn);
-    {
-        uint64_t *t = cur;
-        cur = nxt;
-        nxt = t;
-    }
-    if (tid == 0) s_scored = nn;
-
-    for (int step = 0;; ++step) {
-        const int par = step & 1, prev = par ^ 1;
-        const int pick = s_pick[prev];
-        if (pick >= qn || s_stop) break;
-        const int32_t x = (int32_t)((uint32_t)cur[pick] >> 1);
-        __syncthreads();   // pick and x read by all
-        if (tid == 0) {
-            cur[pick] |= 1ull;
-            s_pick[prev] = 1 << 30;   // read above by every thread; the next step writes it
-            s_nnew[prev] = 0;
-            ++s_explored;
-        }
-        // out-neighbours that never entered the set (wave 0: degree <= 64);
-        // one that was rejected before is scored again and rejected again,
-        // since the set's W-th best only improves
-        if (wave == 0) {
-            int32_t y = lane < a.degree ? a.graph[(int64_t)x * a.degree + lane] : -1;
-            if (y >= a.capacity) y = -1;
-            const bool fc = first_copy(y, lane);   // whole wave
-            if (!fc) y = -1;
-            if (y >= 0 && !hash_contains(hset, y, hmask)) s_new[atomicAdd(&s_nnew[par], 1)] = y;
+        if (__ballot(full)) {
+            if (lane == 0) atomicOr(a.err, kErrOverflow);
+            stop = true;
         }
         __syncthreads();
-        nn = s_nnew[par];
-        score_new(nn);
-        __syncthreads();
-        merge(qn, nn, par);
-        if (tid == 0) s_scored += nn;
-        __syncthreads();
+        pick = (int)wave_min_u64((uint64_t)(uint32_t)best);
         qn = min(W, qn + nn);
         uint64_t *t = cur;
         cur = nxt;
         nxt = t;
+    };
+
+    // entry nodes (at most 64), repeats dropped
+    {
+        int32_t s = lane < a.n_entries && qok ? a.entries[lane] : -1;
+        if (s >= a.capacity) s = -1;
+        const bool fc = first_copy(s, lane);
+        if (!fc) s = -1;
+        uint64_t key = kNoKey;
+        if (s >= 0) {
+            const float v = score_lane<B1, METRIC>(a, qt, mk, s, qsum, cm);
+            key = (make_key(v, 0, METRIC) & 0xFFFFFFFF00000000ull) | ((uint64_t)(uint32_t)s << 1);
+        }
+        const int nn = __popcll(__ballot(s >= 0));
+        scored = nn;
+        merge(key, nn);
+    }
+
+    while (pick < qn && !stop) {
+        const uint64_t kx = cur[pick];
+        const int32_t x = key_node(kx);
+        if (lane == 0) cur[pick] = kx | 1ull;   // explored; read by the merge after its barrier
+        ++explored;
+        // out-neighbours that never entered the set; one rejected before is
+        // scored again and rejected again, since the set's W-th best only
+        // improves
+        int32_t y = lane < a.degree ? a.graph[(int64_t)x * a.degree + lane] : -1;
+        if (y >= a.capacity) y = -1;
+        const bool fc = first_copy(y, lane);
+        if (!fc) y = -1;
+        if (y >= 0 && hash_contains(hset, y, hmask)) y = -1;
+        uint64_t key = kNoKey;
+        if (y >= 0) {
+            const float v = score_lane<B1, METRIC>(a, qt, mk, y, qsum, cm);
+            key = (make_key(v, 0, METRIC) & 0xFFFFFFFF00000000ull) | ((uint64_t)(uint32_t)y << 1);
+        }
+        const int nn = __popcll(__ballot(y >= 0));
+        scored += nn;
+        merge(key, nn);
     }
 
     // the k best live keys, in order
-    if (wave == 0) {
-        int out = 0;
-        for (int base = 0; base < qn && out < a.k; base += 64) {
-            const int i = base + lane;
-            bool live = false;
-            uint64_t key = kNoKey;
-            if (i < qn) {
-                key = cur[i];
-                if constexpr (B1 == kFloat) {
-                    live = true;
-                } else {
-                    const int32_t s = (int32_t)((uint32_t)key >> 1);
-                    const uint8_t *row = a.rows + (int64_t)s * a.row_bytes;
-                    const uint2 ep = *reinterpret_cast<const uint2 *>(row + 16);
-                    live = (row[13] & 1u) && ep.x <= a.epoch && a.epoch < ep.y;
-                }
+    int out = 0;
+    for (int base = 0; base < qn && out < a.k; base += 64) {
+        const int i = base + lane;
+        bool live = false;
+        uint64_t key = kNoKey;
+        if (i < qn) {
+            key = cur[i];
+            if constexpr (B1 == kFloat) {
+                live = true;
+            } else {
+                const uint8_t *row = a.rows + (int64_t)key_node(key) * a.row_bytes;
+                const uint2 ep = *reinterpret_cast<const uint2 *>(row + 16);
+                live = (row[13] & 1u) && ep.x <= a.epoch && a.epoch < ep.y;
             }
-            const uint64_t m = __ballot(live);
-            const int pos = out + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            if (live && pos < a.k) {
-                a.ids[qi * a.k + pos] = (int32_t)((uint32_t)key >> 1);
-                if (a.dist) a.dist[qi * a.k + pos] = key_score(key, METRIC);
-            }
-            out += __popcll(m);
         }
-        for (int i = max(out, 0) + lane; i < a.k; i += 64) {
-            a.ids[qi * a.k + i] = -1;
-            if (a.dist)
-                a.dist[qi * a.k + i] = METRIC == LVQ_L2 ? __uint_as_float(0x7F800000u) : __uint_as_float(0xFF800000u);
+        const uint64_t m = __ballot(live);
+        const int pos = out + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (live && pos < a.k) {
+            a.ids[qi * a.k + pos] = key_node(key);
+            if (a.dist) a.dist[qi * a.k + pos] = key_score(key, METRIC);
         }
-        if (lane == 0 && a.explored) {
-            a.explored[2 * qi] = s_explored;
-            a.explored[2 * qi + 1] = s_scored;
-        }
+        out += __popcll(m);
+    }
+    for (int i = max(out, 0) + lane; i < a.k; i += 64) {
+        a.ids[qi * a.k + i] = -1;
+        if (a.dist)
+            a.dist[qi * a.k + i] = METRIC == LVQ_L2 ? __uint_as_float(0x7F800000u) : __uint_as_float(0xFF800000u);
+    }
+    if (lane == 0 && a.explored) {
+        a.explored[2 * qi] = explored;
+        a.explored[2 * qi + 1] = scored;
     }
 }
 
@@ -641,7 +658,8 @@ int graph_hash_slots(int window, int degree)
 
 size_t graph_lds_bytes(int kpos, int window, int degree)
 {
-    return (size_t)2 * kpos * 4 + (size_t)2 * window * 8 + (size_t)graph_hash_slots(window, degree) * 4;
+    const size_t kq = (size_t)((kpos + 3) & ~3);
+    return 2 * kq * 4 + (size_t)(2 * window + 64) * 8 + (size_t)graph_hash_slots(window, degree) * 4;
 }
 
 hipError_t launch_graph_search(const GraphLaunch &l, hipStream_t s)
@@ -679,27 +697,18 @@ hipError_t launch_graph_search(const GraphLaunch &l, hipStream_t s)
     if (l.window > kMaxWindow || l.degree > kMaxDegree || l.k > l.window || l.n_entries > kMaxDegree)
         return hipErrorInvalidValue;
     const size_t lds = graph_lds_bytes(l.kpos, l.window, l.degree);
-    // short rows: 4 lanes per neighbour (a step's neighbours in one round of
-    // loads); longer rows: 16
     void (*kern)(GraphArgs) = nullptr;
     const bool ip = l.metric == LVQ_IP;
     if (!l.rows) {
         if (!l.xf || l.kpos != l.dim) return hipErrorInvalidValue;
-        if (l.dim <= 128)
-            kern = ip ? k_graph_search<kFloat, LVQ_IP, 4> : k_graph_search<kFloat, LVQ_L2, 4>;
-        else
-            kern = ip ? k_graph_search<kFloat, LVQ_IP, 16> : k_graph_search<kFloat, LVQ_L2, 16>;
-    } else {
-        const bool narrow = l.kchunks * 4 <= 32;   // code words per row
-        if (l.bits1 == 8)
-            kern = narrow ? (ip ? k_graph_search<8, LVQ_IP, 4> : k_graph_search<8, LVQ_L2, 4>)
-                          : (ip ? k_graph_search<8, LVQ_IP, 16> : k_graph_search<8, LVQ_L2, 16>);
-        else if (l.bits1 == 4)
-            kern = narrow ? (ip ? k_graph_search<4, LVQ_IP, 4> : k_graph_search<4, LVQ_L2, 4>)
-                          : (ip ? k_graph_search<4, LVQ_IP, 16> : k_graph_search<4, LVQ_L2, 16>);
+        kern = ip ? k_graph_search<kFloat, LVQ_IP> : k_graph_search<kFloat, LVQ_L2>;
+    } else if (l.bits1 == 8) {
+        kern = ip ? k_graph_search<8, LVQ_IP> : k_graph_search<8, LVQ_L2>;
+    } else if (l.bits1 == 4) {
+        kern = ip ? k_graph_search<4, LVQ_IP> : k_graph_search<4, LVQ_L2>;
     }
     if (!kern) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kern, dim3((unsigned)l.nq), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)l.nq), dim3(64), lds, s, a);
     return hipGetLastError();
 }
 
