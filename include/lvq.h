@@ -218,7 +218,7 @@ int lvq_probe_topk(lvq_index *index, const float *q_dev, int64_t nq, int32_t npr
  * scored (entries and proposed neighbours; a neighbour rejected once is
  * scored again when proposed again) per query.  The nodes that enter a
  * query's candidate set are kept in a table of 8 * (window + 64) entries
- * rounded up to a power of two (1024 to 16384); a query in which more enter
+ * (at most 16384); a query in which more enter
  * stops there and sets the sticky error (lvq_sync reports
  * LVQ_ERR_INVALID_ARG).                                                    */
 int lvq_graph_search(lvq_index *index, const float *q_dev, int64_t nq, const int32_t *graph_dev,

@@ -18,6 +18,8 @@
 // are scored against it into LDS keys, sorted by one wave and deduplicated;
 // the best remaining candidate x* is kept and every candidate that x* is at
 // least alpha times as similar to as the node is dropped, until R are kept.
+#include <algorithm>
+
 #include "k_common.h"
 
 namespace lvq {
@@ -52,29 +54,34 @@ struct GraphArgs {
     int hash_slots;
 };
 
-// Open-addressing hash set h (mask + 1 slots, a power of two; -1 marks an
-// empty slot).  Insert: 1 if s was not there, 0 if it was, -1 if the set is
-// full.
-__device__ __forceinline__ int hash_insert(int32_t *h, int32_t s, uint32_t mask)
+// Open-addressing hash set h of n slots (-1 marks an empty slot), linear
+// probing from a multiplicative hash scaled to [0, n).  Insert: 1 if s was
+// not there, 0 if it was, -1 if the set is full.
+__device__ __forceinline__ uint32_t hash_home(int32_t s, uint32_t n)
 {
-    uint32_t i = ((uint32_t)s * 2654435761u) & mask;
-    for (uint32_t probe = 0; probe <= mask; ++probe) {
+    return (uint32_t)(((uint64_t)((uint32_t)s * 2654435761u) * n) >> 32);
+}
+
+__device__ __forceinline__ int hash_insert(int32_t *h, int32_t s, uint32_t n)
+{
+    uint32_t i = hash_home(s, n);
+    for (uint32_t probe = 0; probe < n; ++probe) {
         const int32_t old = atomicCAS(&h[i], -1, s);
         if (old == -1) return 1;
         if (old == s) return 0;
-        i = (i + 1) & mask;
+        i = i + 1 == n ? 0 : i + 1;
     }
     return -1;
 }
 
-__device__ __forceinline__ bool hash_contains(const int32_t *h, int32_t s, uint32_t mask)
+__device__ __forceinline__ bool hash_contains(const int32_t *h, int32_t s, uint32_t n)
 {
-    uint32_t i = ((uint32_t)s * 2654435761u) & mask;
-    for (uint32_t probe = 0; probe <= mask; ++probe) {
+    uint32_t i = hash_home(s, n);
+    for (uint32_t probe = 0; probe < n; ++probe) {
         const int32_t v = h[i];
         if (v == s) return true;
         if (v == -1) return false;
-        i = (i + 1) & mask;
+        i = i + 1 == n ? 0 : i + 1;
     }
     return false;
 }
@@ -99,11 +106,69 @@ __device__ __forceinline__ float sim_f32(const float *u, const float *x, int dim
 
 // Similarity of one stored node to the query, by one lane.  LVQ rows: the
 // first level in kernel order (qt less the mean when there is one mean, L2;
-// IP adds l * sum(q) + <q, mu_m> from qsum / cm); float rows: binary32
-// squared distance or inner product.
+// IP adds l * sum(q) + <q, mu_m> from qsum / cm); the L2 padding mask is
+// applied from chunk cpad on (the first 16-byte chunk of codes holding a
+// padding position).  Float rows: binary32 squared distance or inner product.
+template <int B1, int METRIC, bool ONE_MEAN>
+__device__ __forceinline__ float score_rows(const GraphArgs &a, const float *qt, const float *mk, int32_t slot,
+                                            float qsum, const float *cm, int cpad)
+{
+    const uint8_t *row = a.rows + (int64_t)slot * a.row_bytes;
+    const float4 hdr = *reinterpret_cast<const float4 *>(row);
+    const uint4 *code = reinterpret_cast<const uint4 *>(row + kHeaderBytes);
+    const int mid = min((int)(__float_as_uint(hdr.w) & 0xFFu), a.n_means - 1);
+    const float l = hdr.x, dl = hdr.y;
+    const float *mu = a.muk + (int64_t)mid * a.kpos;
+    constexpr int PER = B1 == 8 ? 4 : 8;   // positions per 32-bit word
+    const float4 *q4 = reinterpret_cast<const float4 *>(qt);
+    const float4 *m4 = reinterpret_cast<const float4 *>(mk);
+    float s = 0.0f;
+    for (int c = 0; c < a.kchunks; ++c) {
+        const uint4 v = code[c];
+        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+        const bool masked = METRIC == LVQ_L2 && c >= cpad;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t w = wv[i];
+            const int p0 = (4 * c + i) * PER;
+            float cv[PER], qv[PER], mv[PER];
+            if constexpr (B1 == 8) {
+                cv[0] = ub<0>(w); cv[1] = ub<1>(w); cv[2] = ub<2>(w); cv[3] = ub<3>(w);
+            } else {
+                // kernel order of a 4-bit word: fields 0,2,4,6 (low nibbles), then 1,3,5,7
+                const uint32_t lo = w & 0x0F0F0F0Fu, hi = (w >> 4) & 0x0F0F0F0Fu;
+                cv[0] = ub<0>(lo); cv[1] = ub<1>(lo); cv[2] = ub<2>(lo); cv[3] = ub<3>(lo);
+                cv[4] = ub<0>(hi); cv[5] = ub<1>(hi); cv[6] = ub<2>(hi); cv[7] = ub<3>(hi);
+            }
+#pragma unroll
+            for (int h = 0; h < PER / 4; ++h) {
+                const float4 q = q4[p0 / 4 + h];
+                qv[4 * h] = q.x; qv[4 * h + 1] = q.y; qv[4 * h + 2] = q.z; qv[4 * h + 3] = q.w;
+                if (masked) {
+                    const float4 m = m4[p0 / 4 + h];
+                    mv[4 * h] = m.x; mv[4 * h + 1] = m.y; mv[4 * h + 2] = m.z; mv[4 * h + 3] = m.w;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                if constexpr (METRIC == LVQ_IP) {
+                    s = fmaf(qv[j], cv[j], s);
+                } else {
+                    const float qj = ONE_MEAN ? qv[j] : qv[j] - mu[p0 + j];
+                    float t = qj - fmaf(dl, cv[j], l);
+                    if (masked) t *= mv[j];
+                    s = fmaf(t, t, s);
+                }
+            }
+        }
+    }
+    if constexpr (METRIC == LVQ_IP) return fmaf(dl, s, fmaf(l, qsum, cm[mid]));
+    return s;
+}
+
 template <int B1, int METRIC>
 __device__ __forceinline__ float score_lane(const GraphArgs &a, const float *qt, const float *mk, int32_t slot,
-                                            float qsum, const float *cm)
+                                            float qsum, const float *cm, int cpad)
 {
     if constexpr (B1 == kFloat) {
         const float *x = a.xf + (int64_t)slot * a.dim;
@@ -137,61 +202,11 @@ __device__ __forceinline__ float score_lane(const GraphArgs &a, const float *qt,
             }
         }
         return s;
+    } else if (METRIC == LVQ_IP || a.n_means != 1) {
+        return score_rows<B1, METRIC, false>(a, qt, mk, slot, qsum, cm, cpad);
     } else {
-        const uint8_t *row = a.rows + (int64_t)slot * a.row_bytes;
-        const float4 hdr = *reinterpret_cast<const float4 *>(row);
-        const uint4 *code = reinterpret_cast<const uint4 *>(row + kHeaderBytes);
-        const int mid = min((int)(__float_as_uint(hdr.w) & 0xFFu), a.n_means - 1);
-        const float l = hdr.x, dl = hdr.y;
-        const bool one_mean = a.n_means == 1;
-        const float *mu = a.muk + (int64_t)mid * a.kpos;
-        constexpr int PER = B1 == 8 ? 4 : 8;   // positions per 32-bit word
-        float s = 0.0f;
-        for (int c = 0; c < a.kchunks; ++c) {
-            const uint4 v = code[c];
-            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t w = wv[i];
-                const int p0 = (4 * c + i) * PER;
-                float cv[PER];
-                if constexpr (B1 == 8) {
-                    cv[0] = ub<0>(w); cv[1] = ub<1>(w); cv[2] = ub<2>(w); cv[3] = ub<3>(w);
-                } else {
-                    // kernel order of a 4-bit word: fields 0,2,4,6 (low nibbles), then 1,3,5,7
-                    const uint32_t lo = w & 0x0F0F0F0Fu, hi = (w >> 4) & 0x0F0F0F0Fu;
-                    cv[0] = ub<0>(lo); cv[1] = ub<1>(lo); cv[2] = ub<2>(lo); cv[3] = ub<3>(lo);
-                    cv[4] = ub<0>(hi); cv[5] = ub<1>(hi); cv[6] = ub<2>(hi); cv[7] = ub<3>(hi);
-                }
-#pragma unroll
-                for (int j = 0; j < PER; ++j) {
-                    const int p = p0 + j;
-                    if constexpr (METRIC == LVQ_IP) {
-                        s = fmaf(qt[p], cv[j], s);
-                    } else {
-                        const float qv = one_mean ? qt[p] : qt[p] - mu[p];
-                        float t = qv - fmaf(dl, cv[j], l);
-                        t *= mk[p];
-                        s = fmaf(t, t, s);
-                    }
-                }
-            }
-        }
-        if constexpr (METRIC == LVQ_IP) return fmaf(dl, s, fmaf(l, qsum, cm[mid]));
-        return s;
+        return score_rows<B1, METRIC, true>(a, qt, mk, slot, qsum, cm, cpad);
     }
-}
-
-// True unless a lower lane of the wave holds the same value.  Called by all
-// 64 lanes of the wave.
-__device__ __forceinline__ bool first_copy(int32_t v, int lane)
-{
-    bool first = true;
-    for (int t = 0; t < 64; ++t) {
-        const int32_t o = __shfl(v, t, 64);
-        first = first && !(t < lane && o == v);
-    }
-    return first;
 }
 
 __device__ __forceinline__ int32_t key_node(uint64_t k)
@@ -200,10 +215,11 @@ __device__ __forceinline__ int32_t key_node(uint64_t k)
 }
 
 // One wavefront (one 64-lane workgroup) per query.  Each step explores the
-// best unexplored node x: lane t takes x's out-neighbour t, drops repeats and
-// nodes that entered the set before, and scores the rest, one neighbour per
-// lane.  The new keys are sorted across the wave (register bitonic sort) and
-// merged into the sorted set by binary searches: a new key lands at its index
+// best unexplored node x: lane t takes x's out-neighbour t, drops nodes that
+// entered the set before, and scores the rest, one neighbour per lane.  The
+// new keys are sorted across the wave (register bitonic sort), repeats of a
+// node (equal keys, now adjacent) are dropped, and the keys are merged into
+// the sorted set by binary searches: a new key lands at its index
 // among the new keys plus the number of set keys below it, a set key moves
 // down by the number of new keys below it.  Keys landing below W form the new
 // set; the smallest position of an unexplored key is the next node.
@@ -238,38 +254,53 @@ __global__ __launch_bounds__(64) void k_graph_search(GraphArgs a)
         qt[p] = v;
         mk[p] = METRIC == LVQ_L2 && B1 != kFloat && p < a.kpos ? a.kmask[p] : 1.0f;
     }
-    const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
+    const uint32_t hn = (uint32_t)a.hash_slots;
     for (int i = lane; i < a.hash_slots; i += 64) hset[i] = -1;
     if (lane == 0 && !qok) atomicOr(a.err, kErrBadSlot);
+    // first 16-byte code chunk holding a padding position (L2 mask)
+    int cpad = 1 << 30;
+    if constexpr (B1 != kFloat && METRIC == LVQ_L2) {
+        int first = 1 << 30;
+        for (int p = lane; p < a.kpos; p += 64)
+            if (a.kmask[p] == 0.0f) first = min(first, p);
+        first = (int)wave_min_u64((uint64_t)(uint32_t)first);
+        cpad = first == (1 << 30) ? first : first / (B1 == 8 ? 16 : 32);
+    }
     const float qsum = B1 != kFloat && METRIC == LVQ_IP ? a.qsum[qi] : 0.0f;
     const float *cm = B1 != kFloat && METRIC == LVQ_IP ? a.cm + qi * a.n_means : nullptr;
     __syncthreads();
 
     int qn = 0, pick = 1 << 30, explored = 0, scored = 0;
     bool stop = false;
-    // Merge this lane's key (kNoKey if none; nn valid keys in the wave).
-    auto merge = [&](uint64_t key, int nn) {
+    // Merge the lanes' keys (kNoKey where none) into the set; returns the
+    // number of distinct new nodes.
+    auto merge = [&](uint64_t key) -> int {
         uint64_t v[1] = {key};
         wave_bitonic_sort<1>(v);
         key = v[0];
-        skey[lane] = key;
+        const uint32_t plo = __shfl_up((uint32_t)key, 1, 64), phi = __shfl_up((uint32_t)(key >> 32), 1, 64);
+        const bool valid = key != kNoKey && !(lane > 0 && key == (((uint64_t)phi << 32) | plo));
+        const uint64_t vm = __ballot(valid);
+        const int nn = __popcll(vm);
+        const int j = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(vm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)vm, 0u));
+        if (valid) skey[j] = key;
         __syncthreads();
         int best = 1 << 30;
         bool full = false;
-        if (lane < nn) {
+        if (valid) {
             int lo = 0, hi = qn;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 if (cur[mid] < key) lo = mid + 1;
                 else hi = mid;
             }
-            const int p = lane + lo;
+            const int p = j + lo;
             if (p < W) {
                 nxt[p] = key;
                 best = p;
                 // remembered: not proposed again while in the set, and once
                 // cut it could not re-enter (the W-th best only improves)
-                full = hash_insert(hset, key_node(key), hmask) < 0;
+                full = hash_insert(hset, key_node(key), hn) < 0;
             }
         }
         for (int i = lane; i < qn; i += 64) {
@@ -296,22 +327,19 @@ __global__ __launch_bounds__(64) void k_graph_search(GraphArgs a)
         uint64_t *t = cur;
         cur = nxt;
         nxt = t;
+        return nn;
     };
 
     // entry nodes (at most 64), repeats dropped
     {
         int32_t s = lane < a.n_entries && qok ? a.entries[lane] : -1;
         if (s >= a.capacity) s = -1;
-        const bool fc = first_copy(s, lane);
-        if (!fc) s = -1;
         uint64_t key = kNoKey;
         if (s >= 0) {
-            const float v = score_lane<B1, METRIC>(a, qt, mk, s, qsum, cm);
+            const float v = score_lane<B1, METRIC>(a, qt, mk, s, qsum, cm, cpad);
             key = (make_key(v, 0, METRIC) & 0xFFFFFFFF00000000ull) | ((uint64_t)(uint32_t)s << 1);
         }
-        const int nn = __popcll(__ballot(s >= 0));
-        scored = nn;
-        merge(key, nn);
+        scored = merge(key);
     }
 
     while (pick < qn && !stop) {
@@ -324,17 +352,13 @@ __global__ __launch_bounds__(64) void k_graph_search(GraphArgs a)
         // improves
         int32_t y = lane < a.degree ? a.graph[(int64_t)x * a.degree + lane] : -1;
         if (y >= a.capacity) y = -1;
-        const bool fc = first_copy(y, lane);
-        if (!fc) y = -1;
-        if (y >= 0 && hash_contains(hset, y, hmask)) y = -1;
+        if (y >= 0 && hash_contains(hset, y, hn)) y = -1;
         uint64_t key = kNoKey;
         if (y >= 0) {
-            const float v = score_lane<B1, METRIC>(a, qt, mk, y, qsum, cm);
+            const float v = score_lane<B1, METRIC>(a, qt, mk, y, qsum, cm, cpad);
             key = (make_key(v, 0, METRIC) & 0xFFFFFFFF00000000ull) | ((uint64_t)(uint32_t)y << 1);
         }
-        const int nn = __popcll(__ballot(y >= 0));
-        scored += nn;
-        merge(key, nn);
+        scored += merge(key);
     }
 
     // the k best live keys, in order
@@ -648,12 +672,9 @@ int graph_hash_slots(int window, int degree)
 {
     // the nodes that enter a walk's candidate set: about 5.5 W on average and
     // under 8.5 W at most on 10^6-node graphs of out-degree 64; 8 (W + 64)
-    // slots, as a power of two, keep the table under half full
+    // slots keep the table at most two-thirds full
     (void)degree;
-    const int64_t want = (int64_t)8 * (window + 64);
-    int h = 1024;
-    while (h < want && h < kMaxHash) h <<= 1;
-    return h;
+    return std::min(kMaxHash, 8 * (window + 64));
 }
 
 size_t graph_lds_bytes(int kpos, int window, int degree)
