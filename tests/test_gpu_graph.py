@@ -136,3 +136,45 @@ def test_graph_search_rejects_bad_arguments(L):
     with pytest.raises(L.LVQError):
         ix.graph_search(q, torch.zeros((100, 65), dtype=torch.int32, device="cuda"), e, 16, 4)
     ix.close()
+
+
+def test_graph_search_edge_cases(L):
+    g = synth.rng(8850, 0)
+    d, n = 40, 50
+    X = g.standard_normal((n, d)).astype(np.float32)
+    mu = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    fmt = oracle.Format(d, 8, 0, oracle.SEQUENTIAL)
+    rows, _, _ = oracle.encode_rows(fmt, X, mu)
+    ix = L.Index(d, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=n, means=mu)
+    ix.insert(torch.from_numpy(X).cuda())
+    Q = g.standard_normal((5, d)).astype(np.float32)
+    qd = torch.from_numpy(Q).cuda()
+    # no edges at all: the result is the entries themselves, repeats and
+    # out-of-range entries dropped, padded to k
+    empty = torch.full((n, 8), -1, dtype=torch.int32, device="cuda")
+    ent = torch.tensor([7, 3, 7, -4, 900, 12], dtype=torch.int32, device="cuda")
+    ids, dist, cnt = ix.graph_search(qd, empty, ent, 8, 6)
+    assert ix.sync() == 0
+    ids, dist, cnt = ids.cpu().numpy(), dist.cpu().numpy(), cnt.cpu().numpy()
+    offs = np.arange(Q.shape[0] + 1, dtype=np.int64) * 3
+    ref, tol = pair_reference(fmt, oracle.L2, oracle.PRIMARY, Q, rows, None, mu, offs,
+                              np.tile(np.int32([3, 7, 12]), Q.shape[0]))
+    for i in range(Q.shape[0]):
+        order = np.lexsort((np.int32([3, 7, 12]), ref[3 * i:3 * i + 3]))
+        assert sorted(ids[i][:3].tolist()) == [3, 7, 12] and (ids[i][3:] == -1).all()
+        assert np.isinf(dist[i][3:]).all()
+        check_values(dist[i][:3], ref[3 * i:3 * i + 3][order], tol[3 * i:3 * i + 3][order], "entries only")
+        assert cnt[i, 0] == 3 and cnt[i, 1] == 3
+    # W = k = 1 on a complete graph: a greedy descent to a local best
+    full = np.array([[j for j in range(n) if j != i][:32] for i in range(n)], np.int32)
+    ids1, dist1, _ = ix.graph_search(qd, torch.from_numpy(full).cuda(),
+                                     torch.tensor([0], dtype=torch.int32, device="cuda"), 1, 1)
+    assert ix.sync() == 0
+    for i in range(Q.shape[0]):
+        s, v, _ = oracle.greedy_search(fmt, oracle.L2, oracle.PRIMARY, Q[i], rows, None, mu, full, [0], 1, 1)
+        assert ids1.cpu().numpy()[i, 0] == s[0]
+    # an empty batch is a no-op
+    z = ix.graph_search(qd[:0], empty, ent, 8, 6)
+    assert z[0].shape == (0, 6)
+    assert ix.sync() == 0
+    ix.close()
