@@ -793,6 +793,33 @@ def bench_graph(args):
                        "bytes_per_launch": nbytes})
         log("W %3d: batch %.3f ms (kernel %.3f ms), %.0f q/s, explored %.0f, scored %.0f, recall@10 %.3f" %
             (W, ms, k_ms, nq / (ms / 1000.0), c[:, 0].mean(), c[:, 1].mean(), rec))
+    # two levels (Sec. 2.3): an LVQ-4x8 store of the same vectors; the 4-bit
+    # first level traverses, both levels re-rank the walk's final set
+    two = []
+    if not args.window:
+        log("LVQ-4x8 store: walk on the first level, re-rank the final set at both levels")
+        ix2 = L.Index(d, 4, 8, L.LVQ_L2, L.LVQ_TURBO, capacity=n, means=mu)
+        to_gpu_rows(ix2, X, dev)
+        for W in (32, 48, 64, 96):
+            wid = torch.empty((nq, W), dtype=torch.int32, device=dev)
+            wd = torch.empty((nq, W), dtype=torch.float32, device=dev)
+            offs = torch.arange(nq + 1, dtype=torch.int64, device=dev) * W
+
+            def step2():
+                L.lvq_graph_search(ix2.handle, qd.data_ptr(), nq, graph.data_ptr(), R, entry.data_ptr(), 1, W, W,
+                                   wid.data_ptr(), wd.data_ptr(), 0, s)
+                L.lvq_distances(ix2.handle, qd.data_ptr(), nq, offs.data_ptr(), wid.data_ptr(), nq * W, L.LVQ_FULL,
+                                0, k, ids.data_ptr(), dist.data_ptr(), s)
+
+            ms2, _ = timed(step2, args.steps, args.warmup, ix2)
+            assert ix2.sync() == 0
+            rec2 = recall_at_k(ids[:ns].cpu().numpy(), gt)
+            rec1 = recall_at_k(wid[:ns, :k].cpu().numpy(), gt)
+            two.append({"window": W, "ms_per_batch": ms2, "qps": nq / (ms2 / 1000.0), "recall_at_10": rec2,
+                        "recall_at_10_first_level_only": rec1})
+            log("4x8 W %3d: walk + re-rank %.3f ms, %.0f q/s, recall@10 %.3f (first level alone %.3f)" %
+                (W, ms2, nq / (ms2 / 1000.0), rec2, rec1))
+        ix2.close()
     head = next((p for p in points if p["recall_at_10"] >= 0.9), points[-1])
     achieved = head["bytes_per_launch"] / (head["kernel_ms"] / 1000.0) / 1e9
     out = line(head["qps"], "queries/s", args.steps, args.warmup, head["ms_per_batch"], "f32",
@@ -806,7 +833,7 @@ def bench_graph(args):
                 "kernel_ms": head["kernel_ms"],
                 "algorithmic_bytes": "d*4 per query + degree*4 per explored node + %d per scored node" % row_bytes},
                distances_per_s=head["distances_per_s"], recall_at_10=head["recall_at_10"], operating_points=points,
-               recall_sample="%d queries against the exact float top-10" % ns,
+               recall_sample="%d queries against the exact float top-10" % ns, two_level_lvq4x8=two,
                graph_build={"seconds": graph_s, "nodes_per_s": n / graph_s, "degree": R, "window": build_w,
                             "alpha": alpha, "passes": 2, "mean_out_degree": deg.mean().item()})
     out["encode"] = encode_roofline(warm_encode_ms(ix, X, dev), n, d, ix.row_bytes, ix.resid_bytes, enc_ms)

@@ -178,3 +178,32 @@ def test_graph_search_edge_cases(L):
     assert z[0].shape == (0, 6)
     assert ix.sync() == 0
     ix.close()
+
+
+def test_rerank_final_set_at_both_levels(L):
+    # Sec. 2.3: the first level traverses (k = W returns the whole final set),
+    # both levels re-rank it through lvq_distances' fused top-k
+    g = synth.rng(8870, 0)
+    d, n, nq, W, k = 96, 2000, 24, 48, 10
+    cent = g.standard_normal((10, d)).astype(np.float32)
+    X = (cent[g.integers(0, 10, n)] + 0.5 * g.standard_normal((n, d))).astype(np.float32)
+    Q = (cent[g.integers(0, 10, nq)] + 0.5 * g.standard_normal((nq, d))).astype(np.float32)
+    mu = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    fmt = oracle.Format(d, 4, 8, oracle.TURBO)
+    rows, resid, _ = oracle.encode_rows(fmt, X, mu)
+    ix = L.Index(d, 4, 8, L.LVQ_L2, L.LVQ_TURBO, capacity=n, means=mu)
+    ix.insert(torch.from_numpy(X).cuda())
+    graph = torch.from_numpy(_knn_graph(g, X, 16, 4)).cuda()
+    qd = torch.from_numpy(Q).cuda()
+    wid, wd, _ = ix.graph_search(qd, graph, torch.tensor([0], dtype=torch.int32, device="cuda"), W, W)
+    assert ix.sync() == 0
+    assert (wid.cpu().numpy() >= 0).all()          # the final set is full
+    offs = torch.arange(nq + 1, dtype=torch.int64, device="cuda") * W
+    _, ti, td = ix.distances(qd, offs, wid.reshape(-1).contiguous(), level=L.LVQ_FULL, k=k, want_dist=False)
+    assert ix.sync() == 0
+    wid, ti, td = wid.cpu().numpy(), ti.cpu().numpy(), td.cpu().numpy()
+    for i in range(nq):
+        ref, tol = pair_reference(fmt, oracle.L2, oracle.FULL, Q[i:i + 1], rows, resid, mu,
+                                  np.array([0, W], np.int64), wid[i])
+        check_topk(oracle.L2, ti[i], td[i], wid[i], ref, tol, k)
+    ix.close()
