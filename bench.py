@@ -116,6 +116,43 @@ def recall_at_k(found, truth) -> float:
         k * truth.shape[0])
 
 
+def read_ceilings(ix, ids_dev, n_ids, level, per_pair, kernel_ms, reps=10):
+    """The library's bandwidth probes beside a candidate-kernel measurement:
+    a coalesced streaming read of 4 GiB, and the kernel's own gather (the same
+    slots in the same order, the same bytes per slot, no arithmetic); median
+    of `reps` launches timed with HIP events on the current stream."""
+    import torch
+
+    import paper_2402_02044_amd as L
+    dev = ids_dev.device
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    s = int(torch.cuda.current_stream().cuda_stream)
+
+    def med(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    nbytes = 1 << 32
+    buf = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    st_ms = med(lambda: L.lvq_bw_stream(buf.data_ptr(), nbytes, sink.data_ptr(), s))
+    del buf
+    g_ms = med(lambda: L.lvq_bw_gather(ix.handle, ids_dev.data_ptr(), n_ids, level, sink.data_ptr(), s))
+    assert ix.sync() == 0
+    return {"stream_read_GBs": nbytes / (st_ms / 1000.0) / 1e9,
+            "gather_ms": g_ms, "gather_GBs_algorithmic": per_pair * n_ids / (g_ms / 1000.0) / 1e9,
+            "kernel_frac_of_gather": g_ms / kernel_ms,
+            "probes": "lvq_bw_stream over 4 GiB; lvq_bw_gather over the kernel's candidate slots"}
+
+
 def timed(step, steps, warmup, ix):
     """Wall time per step (synchronised on both sides) and the average kernel
     time of the main similarity kernel (HIP events on its stream)."""
@@ -298,6 +335,9 @@ def bench_c2(args):
     achieved = per_pair * pairs / (k_ms / 1000.0) / 1e9
     traffic = read_traffic(pairs, tile) if level == L.LVQ_FULL and args.align == 32 else None
     log("step %.3f ms, kernel %.3f ms, %.1f GB/s algorithmic" % (ms_step, k_ms, achieved))
+    ceil = read_ceilings(ix, idd, pairs, level, per_pair, k_ms)
+    log("streaming read %.0f GB/s; the same gather without arithmetic %.3f ms (kernel at %.0f%% of it)" %
+        (ceil["stream_read_GBs"], ceil["gather_ms"], 100.0 * ceil["kernel_frac_of_gather"]))
     out = line(pairs / (ms_step / 1000.0), "distances/s", args.steps, args.warmup, ms_step, "f32",
                {"workload": "LVQ-4x8 Turbo inner product, n=1,000,000, d=768, 10,000 queries x 1,000 "
                             "candidates, %s level, distances + per-list top-10" % args.level,
@@ -306,7 +346,7 @@ def bench_c2(args):
                {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "k_cand (candidate-list similarity + fused top-k)", "kernel_ms": k_ms,
-                "algorithmic_bytes_per_pair": per_pair},
+                "algorithmic_bytes_per_pair": per_pair, "ceilings": ceil},
                encode=encode_roofline(warm_encode_ms(ix, X, dev), n, 768, ix.row_bytes, ix.resid_bytes, enc_ms))
     if not args.no_cpu_baseline:
         import oracle
@@ -426,6 +466,9 @@ def bench_c3(args):
     per_pair = 96 + 8 + 1 + 4 + 4
     achieved = per_pair * pairs / (k_ms / 1000.0) / 1e9
     log("eager step %.3f ms, graph step %.3f ms, kernel %.3f ms" % (ms_eager, ms_graph, k_ms))
+    ceil = read_ceilings(ix, idd, pairs, L.LVQ_PRIMARY, per_pair, k_ms)
+    log("streaming read %.0f GB/s; the same gather without arithmetic %.3f ms (kernel at %.0f%% of it)" %
+        (ceil["stream_read_GBs"], ceil["gather_ms"], 100.0 * ceil["kernel_frac_of_gather"]))
     out = line(pairs / (ms_graph / 1000.0), "distances/s", args.steps, args.warmup, ms_graph, "f32",
                {"workload": "multi-means LVQ-8 L2, n=10,000,000, d=96 (256 clusters), 16 means (k-means on a "
                             "100k sample), 10,000 queries with log-uniform 64..4096 candidate lists, top-10, one "
@@ -434,7 +477,7 @@ def bench_c3(args):
                {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                 "kernel": "k_cand (persistent, longest lists first)", "kernel_ms": k_ms,
-                "algorithmic_bytes_per_pair": per_pair},
+                "algorithmic_bytes_per_pair": per_pair, "ceilings": ceil},
                ms_per_step_eager=ms_eager)
     out["encode"] = encode_roofline(warm_encode_ms(ix, X, dev), n, d, ix.row_bytes, ix.resid_bytes, enc_ms, n_means=M)
     if not args.no_cpu_baseline:

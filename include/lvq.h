@@ -319,6 +319,23 @@ int lvq_mean_members(lvq_index *index, const int32_t *mean_ids_host, int32_t n, 
 int lvq_read_rows(lvq_index *index, const int32_t *slots_dev, int64_t n, uint8_t *rows_dev,
                   uint8_t *resid_dev, void *stream);
 
+/* Bandwidth probes, for measurement: the loads of an access pattern without
+ * the arithmetic, giving the ceiling a kernel with that pattern can reach.
+ * Both write to *sink_dev (device uint32, zeroed first) the XOR of every
+ * 32-bit word they read, so no load can be elided and the result can be
+ * checked.  Asynchronous on `stream`.
+ *
+ * lvq_bw_stream: a coalesced streaming read of `bytes` (a multiple of 16) at
+ * src_dev.
+ * lvq_bw_gather: for each of the n slots ids_dev[i] (device int32; out of
+ * range ones skipped), the bytes the similarity kernels fetch: the 32-byte
+ * header and the first-level code chunks and, at LVQ_FULL, the residual row
+ * (4, 8 or 16 lanes per slot, whichever covers a row in one round of
+ * 16-byte loads), in list order.                                           */
+int lvq_bw_stream(const void *src_dev, int64_t bytes, uint32_t *sink_dev, void *stream);
+int lvq_bw_gather(lvq_index *index, const int32_t *ids_dev, int64_t n, int32_t level, uint32_t *sink_dev,
+                  void *stream);
+
 /* Store statistics (host values). */
 typedef struct {
     int64_t capacity, free_slots, live_estimate, device_bytes;

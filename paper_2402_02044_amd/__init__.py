@@ -38,7 +38,7 @@ LVQ_ERR_BAD_SLOT = -7
 EXPORTS = ["lvq_row_format", "lvq_create", "lvq_destroy", "lvq_set_means", "lvq_encode", "lvq_insert",
            "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_topk", "lvq_probe_topk", "lvq_retire_means",
            "lvq_add_means", "lvq_mean_members", "lvq_graph_search", "lvq_graph_prune", "lvq_graph_build",
-           "lvq_graph_insert", "lvq_graph_delete", "lvq_read_rows",
+           "lvq_graph_insert", "lvq_graph_delete", "lvq_bw_stream", "lvq_bw_gather", "lvq_read_rows",
            "lvq_get_stats", "lvq_sync", "lvq_mean", "lvq_kmeans", "lvq_strerror", "lvq_set_timing",
            "lvq_kernel_time", "lvq_autotune", "lvq_set_tile", "lvq_server_create", "lvq_server_submit",
            "lvq_server_wait", "lvq_server_drain", "lvq_server_get_stats", "lvq_server_destroy",
@@ -111,6 +111,8 @@ def _load():
         "lvq_graph_insert": [P, i64, i32, i32, P, i64, i32, i32, ctypes.c_float, i32, i32, P, P],
         "lvq_graph_delete": [P, i64, i32, i32, P, i32, ctypes.c_float, P, P],
         "lvq_read_rows": [P, P, i64, P, P, P],
+        "lvq_bw_stream": [P, i64, P, P],
+        "lvq_bw_gather": [P, P, i64, i32, P, P],
         "lvq_get_stats": [P, ctypes.POINTER(lvq_stats)],
         "lvq_sync": [P, P],
         "lvq_mean": [P, i64, i32, P, P],
@@ -226,6 +228,14 @@ def lvq_graph_prune(x, n, dim, metric, nodes, m, cand_offsets, cand_ids, degree,
 def lvq_graph_build(x, n, dim, metric, first, degree, window, alpha, passes, entry, max_batch, graph, stream=0):
     return _chk(_lib.lvq_graph_build(x, n, dim, metric, first, degree, window, alpha, passes, entry, max_batch,
                                      graph, stream), "lvq_graph_build")
+
+
+def lvq_bw_stream(src, nbytes, sink, stream=0):
+    return _chk(_lib.lvq_bw_stream(src, nbytes, sink, stream), "lvq_bw_stream")
+
+
+def lvq_bw_gather(ix, ids, n, level, sink, stream=0):
+    return _chk(_lib.lvq_bw_gather(ix, ids, n, level, sink, stream), "lvq_bw_gather")
 
 
 def lvq_graph_insert(x, n, dim, metric, nodes_host, m, degree, window, alpha, entry, max_batch, graph, stream=0):

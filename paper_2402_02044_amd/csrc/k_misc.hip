@@ -3,6 +3,8 @@
 // (Sec. 2.3) and k-means for the M-LVQ centres (Sec. 3.2).
 #include <float.h>
 
+#include <algorithm>
+
 #include "k_common.h"
 
 namespace lvq {
@@ -367,6 +369,71 @@ __global__ __launch_bounds__(256) void k_km_update(const float *x, int64_t n, in
     if (cnt > 0) c[(int64_t)m * dim + j] = (float)(s / (double)cnt);
 }
 
+// ---- bandwidth probes (measurement): the loads of an access pattern with
+// no arithmetic; each lane folds the words it read into one, and each block
+// XORs its lanes' words into *sink, so no load can be dropped and the result
+// is the XOR of every 32-bit word read.
+__device__ __forceinline__ void block_xor_into(uint32_t acc, uint32_t *sink)
+{
+    __shared__ uint32_t part[4];
+    for (int o = 32; o > 0; o >>= 1) acc ^= (uint32_t)__shfl_xor((int)acc, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicXor(sink, part[0] ^ part[1] ^ part[2] ^ part[3]);
+}
+
+__global__ __launch_bounds__(256) void k_bw_stream(const uint4 *src, int64_t n, uint32_t *sink)
+{
+    uint32_t acc = 0;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i + 7 * stride < n; i += 8 * stride) {   // eight 16-byte loads in flight per lane
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 *p4 = reinterpret_cast<const u32x4 *>(src);
+        u32x4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(p4 + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    }
+    for (; i < n; i += stride) {
+        const uint4 a = src[i];
+        acc ^= a.x ^ a.y ^ a.z ^ a.w;
+    }
+    block_xor_into(acc, sink);
+}
+
+// GL lanes per listed slot (GL in {4, 8, 16}, the smallest covering the
+// pieces): the header and first-level code bytes the similarity kernels read
+// (code16 pieces of 16 bytes) and, when resid is set, the residual row
+// (res16 pieces).
+template <int GL>
+__global__ __launch_bounds__(256) void k_bw_gather(const uint8_t *rows, int row_bytes, int code16, const uint8_t *resid,
+                                                    int resid_bytes, int res16, const int32_t *ids, int64_t n,
+                                                    int64_t capacity, uint32_t *sink)
+{
+    const int g = threadIdx.x % GL;
+    const int64_t stride = (int64_t)gridDim.x * (256 / GL);
+    uint32_t acc = 0;
+    for (int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) / GL; i < n; i += stride) {
+        const int32_t s = ids[i];
+        if (s < 0 || s >= capacity) continue;
+        const uint4 *r = reinterpret_cast<const uint4 *>(rows + (int64_t)s * row_bytes);
+        for (int p = g; p < code16; p += GL) {
+            const uint4 v = r[p];
+            acc ^= v.x ^ v.y ^ v.z ^ v.w;
+        }
+        if (resid) {
+            const uint4 *q = reinterpret_cast<const uint4 *>(resid + (int64_t)s * resid_bytes);
+            for (int p = g; p < res16; p += GL) {
+                const uint4 v = q[p];
+                acc ^= v.x ^ v.y ^ v.z ^ v.w;
+            }
+        }
+    }
+    block_xor_into(acc, sink);
+}
+
 }  // namespace
 
 hipError_t launch_prep(const PrepArgs &a, hipStream_t s)
@@ -393,6 +460,28 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_bw_stream(const void *src, int64_t n16, uint32_t *sink, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32(sink, 0u, 1, s);
+    if (e != hipSuccess || n16 <= 0) return e;
+    hipLaunchKernelGGL(k_bw_stream, dim3(4096), dim3(256), 0, s, reinterpret_cast<const uint4 *>(src), n16, sink);
+    return hipGetLastError();
+}
+
+hipError_t launch_bw_gather(const uint8_t *rows, int row_bytes, int code16, const uint8_t *resid, int resid_bytes,
+                            int res16, const int32_t *ids, int64_t n, int64_t capacity, uint32_t *sink, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32(sink, 0u, 1, s);
+    if (e != hipSuccess || n <= 0) return e;
+    const int pieces = std::max(code16, resid ? res16 : 0);
+    const int gl = pieces > 8 ? 16 : (pieces > 4 ? 8 : 4);
+    const int64_t blocks = std::min<int64_t>((n * gl + 255) / 256, 16384);
+    auto kern = gl == 16 ? k_bw_gather<16> : (gl == 8 ? k_bw_gather<8> : k_bw_gather<4>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, rows, row_bytes, code16, resid, resid_bytes,
+                       res16, ids, n, capacity, sink);
     return hipGetLastError();
 }
 

@@ -1297,6 +1297,30 @@ int lvq_read_rows(lvq_index *ix, const int32_t *slots_dev, int64_t n, uint8_t *r
     return LVQ_OK;
 }
 
+int lvq_bw_stream(const void *src_dev, int64_t bytes, uint32_t *sink_dev, void *stream)
+{
+    if (!sink_dev || bytes < 0 || (bytes & 15) || (bytes > 0 && !src_dev)) return LVQ_ERR_INVALID_ARG;
+    LVQ_HIP(launch_bw_stream(src_dev, bytes / 16, sink_dev, (hipStream_t)stream));
+    return LVQ_OK;
+}
+
+int lvq_bw_gather(lvq_index *ix, const int32_t *ids_dev, int64_t n, int32_t level, uint32_t *sink_dev, void *stream)
+{
+    if (!ix || !sink_dev || n < 0 || (n > 0 && !ids_dev) || (level != LVQ_PRIMARY && level != LVQ_FULL))
+        return LVQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ix->mu);
+    const Format &f = ix->f;
+    if (level == LVQ_FULL && !f.bits2) return LVQ_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = order_after_updates(ix, s);
+    if (rc) return rc;
+    const bool full = level == LVQ_FULL;
+    LVQ_HIP(launch_bw_gather(P<uint8_t>(ix->rows), f.row_bytes, (kHeaderBytes + 16 * f.kchunks) / 16,
+                             full ? P<uint8_t>(ix->resid) : nullptr, f.resid_bytes, f.resid_bytes / 16, ids_dev, n,
+                             ix->cfg.capacity, sink_dev, s));
+    return LVQ_OK;
+}
+
 int lvq_get_stats(lvq_index *ix, lvq_stats *out)
 {
     if (!ix || !out) return LVQ_ERR_INVALID_ARG;

@@ -253,6 +253,10 @@ hipError_t launch_members_live(const int32_t *req, int nreq, const int64_t *moff
                                int32_t *out, unsigned long long *counts, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+// Bandwidth probes (measurement): *sink = XOR of every 32-bit word read.
+hipError_t launch_bw_stream(const void *src, int64_t n16, uint32_t *sink, hipStream_t s);
+hipError_t launch_bw_gather(const uint8_t *rows, int row_bytes, int code16, const uint8_t *resid, int resid_bytes,
+                            int res16, const int32_t *ids, int64_t n, int64_t capacity, uint32_t *sink, hipStream_t s);
 hipError_t launch_list_order(const int64_t *offsets, int64_t nq, int32_t *order, int32_t *scratch,
                              hipStream_t s);
 // bits2: 0 scans the first level, 8 both levels (8-bit residual codes).
