@@ -384,21 +384,23 @@ __device__ __forceinline__ void block_xor_into(uint32_t acc, uint32_t *sink)
 
 __global__ __launch_bounds__(256) void k_bw_stream(const uint4 *src, int64_t n, uint32_t *sink)
 {
+    // workgroup b streams the contiguous range [b * chunk, (b + 1) * chunk),
+    // eight coalesced 16-byte loads in flight per lane
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = min(n, lo + chunk);
     uint32_t acc = 0;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    for (; i + 7 * stride < n; i += 8 * stride) {   // eight 16-byte loads in flight per lane
-        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-        const u32x4 *p4 = reinterpret_cast<const u32x4 *>(src);
-        u32x4 v[8];
+    int64_t i = lo + threadIdx.x;
+    for (; i + 7 * 256 < hi; i += 8 * 256) {
+        uint4 v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(p4 + i + u * stride);
+        for (int u = 0; u < 8; ++u) v[u] = src[i + u * 256];
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
     }
-    for (; i < n; i += stride) {
-        const uint4 a = src[i];
-        acc ^= a.x ^ a.y ^ a.z ^ a.w;
+    for (; i < hi; i += 256) {
+        const uint4 v = src[i];
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
     }
     block_xor_into(acc, sink);
 }
@@ -467,7 +469,7 @@ hipError_t launch_bw_stream(const void *src, int64_t n16, uint32_t *sink, hipStr
 {
     hipError_t e = launch_fill_u32(sink, 0u, 1, s);
     if (e != hipSuccess || n16 <= 0) return e;
-    hipLaunchKernelGGL(k_bw_stream, dim3(4096), dim3(256), 0, s, reinterpret_cast<const uint4 *>(src), n16, sink);
+    hipLaunchKernelGGL(k_bw_stream, dim3(8192), dim3(256), 0, s, reinterpret_cast<const uint4 *>(src), n16, sink);
     return hipGetLastError();
 }
 
