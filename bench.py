@@ -19,6 +19,7 @@ Prints one JSON line per workload.  Progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import glob
 import hashlib
 import json
 import os
@@ -53,12 +54,21 @@ def kernel_source_hash() -> str:
 
 
 def read_traffic(launch_pairs: int, tile: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source and tile shape (else None)."""
-    if not os.path.exists(PROFILE_TRAFFIC):
+    """HBM bytes per launch from a committed rocprofv3 counter summary taken
+    on the current kernel source and this tile shape (else None)."""
+    stem = PROFILE_TRAFFIC[:-3]
+    for path in [PROFILE_TRAFFIC] + sorted(glob.glob(stem + "_tile*.md")):
+        got = read_traffic_file(path, launch_pairs, tile)
+        if got is not None:
+            return got
+    return None
+
+
+def read_traffic_file(path, launch_pairs: int, tile: int):
+    if not os.path.exists(path):
         return None
     vals = {}
-    for ln in open(PROFILE_TRAFFIC):
+    for ln in open(path):
         if ":" in ln and ln.strip().startswith("- "):
             k, v = ln.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip()
@@ -1324,7 +1334,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--window", type=int, default=0, help="graph: one search window instead of the sweep")
     ap.add_argument("--tile", type=int, default=-1, help="fixed tile shape (default: tuning cache, else autotune)")
-    ap.add_argument("--retune", action="store_true", help="run the autotuner even when the cache has a shape")
+    ap.add_argument("--retune", action=argparse.BooleanOptionalAction, default=True,
+                    help="c2, c3: run the library's autotuner on this box before timing (default); --no-retune "
+                         "takes the shape recorded in the tuning cache")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
