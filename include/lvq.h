@@ -326,7 +326,7 @@ int lvq_read_rows(lvq_index *index, const int32_t *slots_dev, int64_t n, uint8_t
  * checked.  Asynchronous on `stream`.
  *
  * lvq_bw_stream: a coalesced streaming read of `bytes` (a multiple of 16) at
- * src_dev.
+ * src_dev (16-byte aligned); LVQ_ERR_INVALID_ARG otherwise.
  * lvq_bw_gather: for each of the n slots ids_dev[i] (device int32; out of
  * range ones skipped), the bytes the similarity kernels fetch: the 32-byte
  * header and the first-level code chunks and, at LVQ_FULL, the residual row

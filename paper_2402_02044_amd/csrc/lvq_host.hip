@@ -1299,7 +1299,8 @@ int lvq_read_rows(lvq_index *ix, const int32_t *slots_dev, int64_t n, uint8_t *r
 
 int lvq_bw_stream(const void *src_dev, int64_t bytes, uint32_t *sink_dev, void *stream)
 {
-    if (!sink_dev || bytes < 0 || (bytes & 15) || (bytes > 0 && !src_dev)) return LVQ_ERR_INVALID_ARG;
+    if (!sink_dev || bytes < 0 || (bytes & 15) || (bytes > 0 && (!src_dev || ((uintptr_t)src_dev & 15))))
+        return LVQ_ERR_INVALID_ARG;
     LVQ_HIP(launch_bw_stream(src_dev, bytes / 16, sink_dev, (hipStream_t)stream));
     return LVQ_OK;
 }

@@ -32,7 +32,9 @@ def test_stream_reads_every_word(L):
         torch.cuda.synchronize()
         assert int(sink.cpu().numpy().view(np.uint32)[0]) == _xor(buf), nbytes
     with pytest.raises(L.LVQError):
-        L.lvq_bw_stream(src.data_ptr(), 20, sink.data_ptr(), 0)
+        L.lvq_bw_stream(src.data_ptr(), 20, sink.data_ptr(), 0)        # not a multiple of 16 bytes
+    with pytest.raises(L.LVQError):
+        L.lvq_bw_stream(src.data_ptr() + 4, 16, sink.data_ptr(), 0)    # not 16-byte aligned
 
 
 @pytest.mark.parametrize("d,b1,b2,layout", [(130, 4, 8, 1), (96, 8, 0, 0), (768, 4, 8, 1)])
