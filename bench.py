@@ -873,6 +873,44 @@ def bench_graph(args):
             log("4x8 W %3d: walk + re-rank %.3f ms, %.0f q/s, recall@10 %.3f (first level alone %.3f)" %
                 (W, ms2, nq / (ms2 / 1000.0), rec2, rec1))
         ix2.close()
+    # graph updates (App. A): consolidate the deletion of 1% of the nodes out of
+    # the graph, then insert their vectors again into the freed slots
+    updates = None
+    if not args.window:
+        g = synth.rng(6, synth.S_DELETE)
+        cand = np.setdiff1d(np.arange(n), [int(entry.item())])
+        dead = np.sort(g.choice(cand, n // 100, replace=False)).astype(np.int32)
+        ix.delete(torch.from_numpy(dead).to(dev))
+        flags = torch.zeros(n, dtype=torch.uint8, device=dev)
+        flags[torch.from_numpy(dead).long().to(dev)] = 1
+        xg = torch.from_numpy(X).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.graph_delete(xg, graph, flags, alpha, L.LVQ_L2)
+        torch.cuda.synchronize()
+        del_s = time.perf_counter() - t0
+        ix.consolidate()
+        slots = ix.insert(torch.from_numpy(X[dead]).to(dev))
+        assert ix.sync() == 0
+        xg[slots.long()] = torch.from_numpy(X[dead]).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.graph_insert(xg, graph, slots.cpu().numpy(), build_w, alpha, L.LVQ_L2, int(entry.item()))
+        torch.cuda.synchronize()
+        ins_s = time.perf_counter() - t0
+        Xnow = xg.cpu().numpy()
+        gt2 = exact_topk(0, Q[:ns], Xnow, k)
+        W = head_w = next((p["window"] for p in points if p["recall_at_10"] >= 0.9), points[-1]["window"])
+        L.lvq_graph_search(ix.handle, qd.data_ptr(), nq, graph.data_ptr(), R, entry.data_ptr(), 1, W, k,
+                           ids.data_ptr(), dist.data_ptr(), cnt.data_ptr(), s)
+        assert ix.sync() == 0
+        rec_after = recall_at_k(ids[:ns].cpu().numpy(), gt2)
+        updates = {"deleted": int(dead.size), "delete_consolidation_s": del_s, "reinserted": int(dead.size),
+                   "insert_s": ins_s, "insert_nodes_per_s": dead.size / ins_s, "window": head_w,
+                   "recall_at_10_after": rec_after}
+        log("graph updates: delete consolidation of %d nodes %.3f s; insert of %d nodes %.3f s; recall@10 at "
+            "W %d afterwards %.3f" % (dead.size, del_s, dead.size, ins_s, head_w, rec_after))
+        del xg
     head = next((p for p in points if p["recall_at_10"] >= 0.9), points[-1])
     achieved = head["bytes_per_launch"] / (head["kernel_ms"] / 1000.0) / 1e9
     out = line(head["qps"], "queries/s", args.steps, args.warmup, head["ms_per_batch"], "f32",
@@ -887,6 +925,7 @@ def bench_graph(args):
                 "algorithmic_bytes": "d*4 per query + degree*4 per explored node + %d per scored node" % row_bytes},
                distances_per_s=head["distances_per_s"], recall_at_10=head["recall_at_10"], operating_points=points,
                recall_sample="%d queries against the exact float top-10" % ns, two_level_lvq4x8=two,
+               graph_updates=updates,
                graph_build={"seconds": graph_s, "nodes_per_s": n / graph_s, "degree": R, "window": build_w,
                             "alpha": alpha, "passes": 2, "mean_out_degree": deg.mean().item()})
     out["encode"] = encode_roofline(warm_encode_ms(ix, X, dev), n, d, ix.row_bytes, ix.resid_bytes, enc_ms)

@@ -237,9 +237,10 @@ int lvq_graph_search(lvq_index *index, const float *q_dev, int64_t nq, const int
  * candidates, and until `degree` are chosen every candidate x' is dropped for
  * which x* is at least alpha times as similar (L2: alpha * |x* - x'|^2 <=
  * |p - x'|^2; IP: alpha * <x*, x'> >= <p, x'>).  The row of p is rewritten
- * with the chosen nodes in selection order, -1 padded.  Candidates are taken
- * 256 at a time, each group pruned together with the out-neighbours chosen
- * so far.  Synchronises `stream`; LVQ_ERR_BAD_SLOT for a node outside
+ * with the chosen nodes in selection order, -1 padded.  Long candidate
+ * lists are taken in groups -- whole blocks of 256 entries, in order, as many
+ * as fit in 256 + degree candidates beside the out-neighbours chosen so far
+ * -- each group pruned together with them.  Synchronises `stream`; LVQ_ERR_BAD_SLOT for a node outside
  * [0, n).                                                                  */
 int lvq_graph_prune(const float *x_dev, int64_t n, int32_t dim, int32_t metric, const int32_t *nodes_dev,
                     int64_t m, const int64_t *cand_offsets_dev, const int32_t *cand_ids_dev, int32_t degree,
@@ -278,8 +279,9 @@ int lvq_graph_insert(const float *x_dev, int64_t n, int32_t dim, int32_t metric,
  * nonzero = deleted): every kept node x' with deleted out-neighbours takes as
  * candidates its kept out-neighbours and the kept out-neighbours of each
  * deleted one (x' -> x -> x'' becomes x' -> x''); more than `degree` distinct
- * candidates are pruned as in lvq_graph_prune (in groups of 256 positions of
- * the degree x degree neighbour table, a single group for degree <= 16).
+ * candidates are pruned as in lvq_graph_prune (the degree x degree table of
+ * neighbours' neighbours read in blocks of 256 positions, grouped as
+ * lvq_graph_prune groups its candidates; a single group for degree <= 16).
  * Every row is read as it was before the call; rows of deleted nodes become
  * -1.  A deleted node must no longer serve as an entry.  Synchronises
  * `stream`.                                                                */

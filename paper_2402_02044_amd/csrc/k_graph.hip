@@ -451,23 +451,34 @@ __global__ __launch_bounds__(256) void k_graph_prune(PruneLaunch a)
         }
     __syncthreads();
 
-    for (int64_t cs = c0;; cs += kPruneChunk) {
-        const int64_t ce = min(c1, cs + (int64_t)kPruneChunk);
+    int64_t cs = c0;   // next position block (kPruneChunk positions) to read
+    for (;;) {
         if (tid == 0) s_n = s_kept;
         for (int r = tid; r < s_kept; r += 256) cid[r] = kept[r];
         __syncthreads();
-        for (int64_t j = cs + tid; j < ce; j += 256) {
-            int32_t y;
-            if (del) {
-                const int32_t v = a.graph[(int64_t)p * a.R + j / a.R];
-                y = v >= 0 && v < a.n && del[v] ? a.graph[(int64_t)v * a.R + j % a.R] : -1;
-                if (y >= 0 && y < a.n && del[y]) y = -1;
-            } else {
-                y = a.cids[j];
+        // append whole position blocks, in order, while their candidates fit
+        // beside the out-neighbours kept so far (the first block always fits:
+        // R + kPruneChunk <= kPruneCap)
+        for (;;) {
+            const int have = s_n;   // last written before the preceding barrier
+            const int64_t j = cs + tid;
+            int32_t y = -1;
+            if (j < c1) {
+                if (del) {
+                    const int32_t v = a.graph[(int64_t)p * a.R + j / a.R];
+                    y = v >= 0 && v < a.n && del[v] ? a.graph[(int64_t)v * a.R + j % a.R] : -1;
+                    if (y >= 0 && y < a.n && del[y]) y = -1;
+                } else {
+                    y = a.cids[j];
+                }
+                if (!(y >= 0 && y < a.n && y != p)) y = -1;
             }
-            if (y >= 0 && y < a.n && y != p) cid[atomicAdd(&s_n, 1)] = y;
+            const int cnt = __syncthreads_count(y >= 0);
+            if (cs >= c1 || have + cnt > kPruneCap) break;
+            if (y >= 0) cid[atomicAdd(&s_n, 1)] = y;
+            cs += kPruneChunk;
+            __syncthreads();
         }
-        __syncthreads();
         const int nn = s_n;
         // similarities to the node
         for (int c = grp; c < nn; c += NG) {
@@ -528,7 +539,7 @@ __global__ __launch_bounds__(256) void k_graph_prune(PruneLaunch a)
             }
         }
         __syncthreads();
-        if (ce >= c1) break;
+        if (cs >= c1) break;
     }
     for (int r = tid; r < a.R; r += 256) a.graph[(int64_t)p * a.R + r] = r < s_kept ? kept[r] : -1;
 }

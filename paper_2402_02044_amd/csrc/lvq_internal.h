@@ -202,11 +202,14 @@ hipError_t launch_graph_search(const GraphLaunch &l, hipStream_t s);
 // Node i = nodes[i]; its candidates are cids[coffs[j] .. coffs[j + 1]) with
 // j = i (by_node 0) or j = the node (by_node 1), or cids[i * cstride ..
 // (i + 1) * cstride) when coffs is NULL; -1 entries are skipped.  They are
-// taken in chunks of kPruneChunk, each merged with the out-neighbours kept so
-// far; `always` 0 prunes only a merge holding more than R distinct nodes.
-// With `deleted` (n flags) the candidates of p are instead the kept
-// out-neighbours of its deleted out-neighbours, and its own deleted
-// out-neighbours are dropped (delete consolidation).
+// taken in groups of whole blocks of kPruneChunk positions, as many blocks
+// as fit (at most kPruneChunk + R candidates) beside the out-neighbours kept
+// so far, each group merged with those; `always` 0 prunes only a merge
+// holding more than R distinct nodes.  With `deleted` (n flags) the
+// candidate positions are instead the R x R table of p's out-neighbours'
+// out-neighbours, of which only the kept out-neighbours of deleted ones
+// count, and p's own deleted out-neighbours are dropped (delete
+// consolidation).
 constexpr int kPruneChunk = 256;
 constexpr int kGraphMaxDegree = 64;
 constexpr int kGraphMaxDim = 4096;

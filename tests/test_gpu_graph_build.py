@@ -4,8 +4,9 @@ ABI) against the oracle's Alg. 2 and App. A update routine.
 * Pruning: every pruned row equals the oracle's robust_prune of the same
   candidates and current out-neighbours (binary32 against binary64 may decide
   a near-tie of the pruning rule differently: nearly every row, not all).
-  Candidates are taken 256 at a time: a long list equals the oracle's pruning
-  folded over the same groups.
+  Long candidate lists are pruned in groups (whole blocks of 256 positions,
+  as many as fit beside the kept out-neighbours): the result equals the
+  oracle's pruning folded over the same groups.
 * Build with batches of one node is the paper's sequential routine: the rows
   equal the oracle's vamana_build (as sets; again nearly all rows).
 * Batched build: rows are valid (distinct, no self edge, -1 padded at the
@@ -65,10 +66,22 @@ def test_prune_matches_oracle(L, metric, alpha, d):
     got = gd.cpu().numpy()
     same = 0
     for i, p in enumerate(nodes):
-        cur = [int(v) for v in before[p] if v >= 0]
         c = cand[offs[i]:offs[i + 1]]
-        for a in range(0, max(len(c), 1), 256):         # the kernel's groups of 256
-            cur = oracle.robust_prune(metric, X, int(p), c[a:a + 256], cur, alpha, R)
+        cur = [int(v) for v in before[p] if 0 <= v < n and v != p]   # repeats included, as the kernel reads the row
+        pos = 0
+        while True:
+            # the kernel's groups: whole blocks of 256 candidate positions, in
+            # order, while their valid entries fit beside the kept ones (320)
+            group = []
+            while pos < len(c):
+                valid = [int(y) for y in c[pos:pos + 256] if 0 <= y < n and y != p]
+                if len(cur) + len(group) + len(valid) > 320:
+                    break
+                group += valid
+                pos += 256
+            cur = oracle.robust_prune(metric, X, int(p), group, cur, alpha, R)
+            if pos >= len(c):
+                break
         row = got[p][got[p] >= 0].tolist()
         same += row == cur
     assert same >= m - 3, "%d of %d pruned rows equal the oracle's" % (same, m)
