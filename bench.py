@@ -952,6 +952,101 @@ def bench_graph(args):
     return out
 
 
+def bench_graph_stream(args):
+    """Streaming graph search (App. A): the G1 store and its graph, then
+    rounds of: tombstone 5% of the live nodes, consolidate them out of the
+    graph (lvq_graph_delete) and the store, insert 50,000 fresh vectors into
+    the freed slots (store, then lvq_graph_insert); after each round the
+    search (W = 96, top-10) over the live set: queries/s and recall@10."""
+    import torch
+
+    import paper_2402_02044_amd as L
+    import synth
+    n, nq, d, k, W = args.n or 1_000_000, args.nq or 10_000, 96, 10, 96
+    R, build_w, alpha = 64, 200, 1.2
+    rounds = min(args.rounds, 10)
+    per_round_new, frac_del = n // 20, 0.05
+    dev = torch.device("cuda:0")
+    log("generating %d x %d base vectors (G1), %d queries" % (n, d, nq))
+    X = synth.vectors("G1", synth.S_BASE, 0, n)
+    Q = synth.vectors("G1", synth.S_QUERY, 0, nq)
+    mu = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    ix = L.Index(d, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=n, means=mu)
+    to_gpu_rows(ix, X, dev)
+    xg = torch.from_numpy(X).to(dev)
+    entry = int(torch.argmin(((xg - torch.from_numpy(mu).to(dev)) ** 2).sum(1)).item())
+    t = time.perf_counter()
+    graph = L.graph_build(xg, R, build_w, alpha, L.LVQ_L2, entry, passes=2, max_batch=16384)
+    torch.cuda.synchronize()
+    log("graph built in %.1f s" % (time.perf_counter() - t))
+    live = np.ones(n, bool)
+    qd = torch.from_numpy(Q).to(dev)
+    ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    ed = torch.tensor([entry], dtype=torch.int32, device=dev)
+    s = int(torch.cuda.current_stream().cuda_stream)
+    ns = 1000
+
+    def search_round(r, upd):
+        def step():
+            L.lvq_graph_search(ix.handle, qd.data_ptr(), nq, graph.data_ptr(), R, ed.data_ptr(), 1, W, k,
+                               ids.data_ptr(), dist.data_ptr(), 0, s)
+        ms, _ = timed(step, args.steps, args.warmup, ix)
+        assert ix.sync() == 0
+        xs = xg.cpu().numpy()
+        gt = exact_topk(0, Q[:ns], xs, k, live=live)
+        rec = recall_at_k(ids[:ns].cpu().numpy(), gt)
+        row = {"round": r, "live": int(live.sum()), "ms_per_batch": ms, "qps": nq / (ms / 1000.0),
+               "recall_at_10": rec}
+        row.update(upd)
+        log("round %2d: live %d, %.0f q/s, recall@10 %.3f %s" %
+            (r, live.sum(), nq / (ms / 1000.0), rec,
+             " ".join(("%s %d" if isinstance(v, (int, np.integer)) else "%s %.3f") % (kk, v) for kk, v in upd.items())))
+        return row
+
+    hist = [search_round(0, {})]
+    for r in range(1, rounds + 1):
+        g = synth.rng(6, synth.S_DELETE, r)
+        cand = np.flatnonzero(live & (np.arange(n) != entry))
+        dead = np.sort(g.choice(cand, int(frac_del * live.sum()), replace=False)).astype(np.int32)
+        ix.delete(torch.from_numpy(dead).to(dev))
+        flags = torch.zeros(n, dtype=torch.uint8, device=dev)
+        flags[torch.from_numpy(dead).long().to(dev)] = 1
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.graph_delete(xg, graph, flags, alpha, L.LVQ_L2)
+        torch.cuda.synchronize()
+        del_s = time.perf_counter() - t0
+        ix.consolidate()
+        live[dead] = False
+        Xn = synth.vectors("G1", synth.S_INSERT, (r - 1) * per_round_new, min(per_round_new, dead.size))
+        slots = ix.insert(torch.from_numpy(Xn).to(dev))
+        assert ix.sync() == 0
+        sl = slots.cpu().numpy()
+        xg[slots.long()] = torch.from_numpy(Xn).to(dev)
+        live[sl] = True
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.graph_insert(xg, graph, sl, build_w, alpha, L.LVQ_L2, entry)
+        torch.cuda.synchronize()
+        ins_s = time.perf_counter() - t0
+        hist.append(search_round(r, {"deleted": int(dead.size), "delete_s": del_s, "inserted": int(sl.size),
+                                     "insert_s": ins_s}))
+    last = hist[-1]
+    out = line(last["qps"], "queries/s", args.steps, args.warmup, last["ms_per_batch"], "f32",
+               {"workload": "streaming graph search: G1 n=1,000,000 d=96 LVQ-8 L2, graph out-degree 64 (build "
+                            "window 200, alpha 1.2); %d rounds of 5%% deletes consolidated out of the graph and "
+                            "50,000 inserts into the freed slots; search W=96, top-10, 10,000 queries; value "
+                            "after the last round" % rounds,
+                "n": n, "dim": d, "degree": R, "window": W, "rounds": rounds, "queries": nq, "k": k},
+               {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                "traffic": None, "kernel": "k_graph_search",
+                "note": "per-round search measurement; the roofline of the search kernel is the graph line's"},
+               rounds=hist, recall_sample="%d queries against the exact float top-10 of the live set" % ns)
+    ix.close()
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Turbo vs sequential 4-bit layout (the GPU analogue of the paper's Turbo
 # table, Sec. 3.1): first-level inner products over candidate lists
@@ -1362,7 +1457,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "layouts", "probe", "means", "graph"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "layouts", "probe", "means", "graph", "graph_stream"])
     ap.add_argument("--rounds", type=int, default=30, help="c5: update rounds")
     ap.add_argument("--sat-batches", type=int, default=60, help="c5: batches of each saturation burst")
     ap.add_argument("--lat-batches", type=int, default=120, help="c5: batches of each latency phase")
@@ -1400,7 +1495,7 @@ def main():
         return
     fn = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
           "layouts": bench_layouts, "probe": bench_probe, "means": bench_means,
-          "graph": bench_graph}[args.workload]
+          "graph": bench_graph, "graph_stream": bench_graph_stream}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 
