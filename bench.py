@@ -920,7 +920,7 @@ def bench_graph(args):
                 "n": n, "dim": d, "degree": R, "queries": nq, "k": k, "window": head["window"]},
                {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": read_graph_traffic(nq, head["window"]),
-                "kernel": "k_graph_search (one workgroup per query; a chain of dependent steps per query)",
+                "kernel": "k_graph_search (one 64-lane workgroup per query; a chain of dependent steps per query)",
                 "kernel_ms": head["kernel_ms"],
                 "algorithmic_bytes": "d*4 per query + degree*4 per explored node + %d per scored node" % row_bytes},
                distances_per_s=head["distances_per_s"], recall_at_10=head["recall_at_10"], operating_points=points,
