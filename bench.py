@@ -983,6 +983,7 @@ def bench_graph_stream(args):
     qd = torch.from_numpy(Q).to(dev)
     ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
     dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    cnt = torch.empty((nq, 2), dtype=torch.int32, device=dev)
     ed = torch.tensor([entry], dtype=torch.int32, device=dev)
     s = int(torch.cuda.current_stream().cuda_stream)
     ns = 1000
@@ -990,14 +991,16 @@ def bench_graph_stream(args):
     def search_round(r, upd):
         def step():
             L.lvq_graph_search(ix.handle, qd.data_ptr(), nq, graph.data_ptr(), R, ed.data_ptr(), 1, W, k,
-                               ids.data_ptr(), dist.data_ptr(), 0, s)
-        ms, _ = timed(step, args.steps, args.warmup, ix)
+                               ids.data_ptr(), dist.data_ptr(), cnt.data_ptr(), s)
+        ms, k_ms = timed(step, args.steps, args.warmup, ix)
         assert ix.sync() == 0
+        c = cnt.cpu().numpy().astype(np.int64)
         xs = xg.cpu().numpy()
         gt = exact_topk(0, Q[:ns], xs, k, live=live)
         rec = recall_at_k(ids[:ns].cpu().numpy(), gt)
-        row = {"round": r, "live": int(live.sum()), "ms_per_batch": ms, "qps": nq / (ms / 1000.0),
-               "recall_at_10": rec}
+        row = {"round": r, "live": int(live.sum()), "ms_per_batch": ms, "kernel_ms": k_ms, "qps": nq / (ms / 1000.0),
+               "recall_at_10": rec,
+               "bytes_per_launch": int(nq * d * 4 + c[:, 0].sum() * R * 4 + c[:, 1].sum() * ix.row_bytes)}
         row.update(upd)
         log("round %2d: live %d, %.0f q/s, recall@10 %.3f %s" %
             (r, live.sum(), nq / (ms / 1000.0), rec,
@@ -1033,16 +1036,35 @@ def bench_graph_stream(args):
         hist.append(search_round(r, {"deleted": int(dead.size), "delete_s": del_s, "inserted": int(sl.size),
                                      "insert_s": ins_s}))
     last = hist[-1]
+    achieved = last["bytes_per_launch"] / (last["kernel_ms"] / 1000.0) / 1e9
     out = line(last["qps"], "queries/s", args.steps, args.warmup, last["ms_per_batch"], "f32",
                {"workload": "streaming graph search: G1 n=1,000,000 d=96 LVQ-8 L2, graph out-degree 64 (build "
                             "window 200, alpha 1.2); %d rounds of 5%% deletes consolidated out of the graph and "
                             "50,000 inserts into the freed slots; search W=96, top-10, 10,000 queries; value "
                             "after the last round" % rounds,
                 "n": n, "dim": d, "degree": R, "window": W, "rounds": rounds, "queries": nq, "k": k},
-               {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
-                "traffic": None, "kernel": "k_graph_search",
-                "note": "per-round search measurement; the roofline of the search kernel is the graph line's"},
+               {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_graph_search after the last round (one 64-lane workgroup per query)",
+                "kernel_ms": last["kernel_ms"],
+                "algorithmic_bytes": "d*4 per query + degree*4 per explored node + %d per scored node" % ix.row_bytes},
                rounds=hist, recall_sample="%d queries against the exact float top-10 of the live set" % ns)
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the oracle on a host-core sample")
+        fmt = oracle.Format(d, 8, 0)
+        xs = xg.cpu().numpy()
+        rows, _, _ = oracle.encode_rows(fmt, xs, mu)
+        g_host = graph.cpu().numpy()
+        nqs = 0
+        t = time.perf_counter()
+        while nqs < 2000 and time.perf_counter() - t < 15.0:
+            oracle.greedy_search(fmt, oracle.L2, oracle.PRIMARY, Q[nqs], rows, None, mu, g_host, [entry], W, k, live)
+            nqs += 1
+        ct = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": nqs / ct, "unit": "queries/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d queries, window %d, over the store and graph after the last round; "
+                                         "binary64 similarities (scalar C) in a Python walk, %.2f s" % (nqs, W, ct)}
     ix.close()
     return out
 
