@@ -293,19 +293,19 @@ def cpu_baseline_lists(fmt, metric, level, X, Q, means, offs, ids, budget_s=12.0
         e = int(offs[nq_s])
         uniq, inv = np.unique(ids[:e], return_inverse=True)
         rows, resid, _ = oracle.encode_rows(fmt, X[uniq], means)
+        inv = inv.astype(np.int32)
         t = time.perf_counter()
-        oracle.distances(fmt, metric, level, Q[:nq_s], rows, resid, means, offs[:nq_s + 1],
-                         inv.astype(np.int32))
-        return time.perf_counter() - t, e
+        oracle.distances(fmt, metric, level, Q[:nq_s], rows, resid, means, offs[:nq_s + 1], inv)
+        return time.perf_counter() - t, e, (rows, resid, inv)
 
-    dt, e = run(4)
+    dt, e, _ = run(4)
     nq_s = int(min(len(offs) - 1, max(4, 4 * budget_s / max(dt, 1e-6))))
-    dt, e = run(nq_s)
+    dt, e, enc = run(nq_s)
     out = {"value": e / dt, "unit": "distances/s", "cores": 1, "kind": "oracle",
            "sample": "first %d queries' candidate lists (%d pairs) of the same workload, %s level, "
                      "binary64 scalar C on one host core, %.1f s" %
                      (nq_s, e, "full" if level == 2 else "primary", dt)}
-    out["all_cores"] = cpu_baseline_threads(fmt, metric, level, X, Q, means, offs, ids, nq_s)
+    out["all_cores"] = cpu_baseline_threads(fmt, metric, level, Q, means, offs, nq_s, enc)
     return out
 
 
@@ -319,17 +319,16 @@ def host_cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline_threads(fmt, metric, level, X, Q, means, offs, ids, nq_s):
-    """The same oracle sample split over host threads (one query range per
-    thread; the C calls run without the interpreter lock)."""
+def cpu_baseline_threads(fmt, metric, level, Q, means, offs, nq_s, enc):
+    """The same oracle sample (its encoded rows in `enc`) split over host
+    threads: one query range per thread; the C calls run without the
+    interpreter lock."""
     import threading
 
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
     e = int(offs[nq_s])
-    uniq, inv = np.unique(ids[:e], return_inverse=True)
-    rows, resid, _ = oracle.encode_rows(fmt, X[uniq], means)
-    inv = inv.astype(np.int32)
+    rows, resid, inv = enc
     bounds = np.linspace(0, nq_s, threads + 1).astype(int)
 
     def work(a, b):
