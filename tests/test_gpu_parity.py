@@ -31,7 +31,10 @@ def _special_rows(d, g):
 ENC_FORMATS = [(96, 8, 0, oracle.SEQUENTIAL), (96, 4, 8, oracle.TURBO), (768, 4, 8, oracle.TURBO),
                (130, 4, 8, oracle.TURBO), (7, 8, 4, oracle.SEQUENTIAL), (200, 4, 4, oracle.SEQUENTIAL),
                (64, 8, 8, oracle.TURBO), (1, 4, 0, oracle.SEQUENTIAL), (512, 8, 0, oracle.SEQUENTIAL),
-               (300, 8, 8, oracle.SEQUENTIAL)]
+               (300, 8, 8, oracle.SEQUENTIAL),
+               # the largest row whose packing units fit four per lane, and a
+               # longer one encoded through the staged (LDS) path
+               (2048, 4, 8, oracle.TURBO), (1100, 8, 0, oracle.SEQUENTIAL)]
 
 
 @pytest.mark.parametrize("d,b1,b2,layout", ENC_FORMATS)
