@@ -215,8 +215,9 @@ int lvq_probe_topk(lvq_index *index, const float *q_dev, int64_t nq, int32_t npr
  * traversed but left out of the result: ids_dev / dist_dev (nq x k) hold the
  * k best live nodes of the final set, padded as for lvq_distances;
  * explored_dev (nq x 2 int32, may be NULL) the nodes explored and the nodes
- * scored (entries and proposed neighbours; a neighbour rejected once is
- * scored again when proposed again) per query.  The nodes that enter a
+ * scored (distinct entries, then one per out-neighbour entry scored: a
+ * neighbour rejected once is scored again when proposed again, and a node
+ * listed twice in one row counts twice) per query.  The nodes that enter a
  * query's candidate set are kept in a table of 8 * (window + 64) entries
  * (at most 16384); a query in which more enter
  * stops there and sets the sticky error (lvq_sync reports

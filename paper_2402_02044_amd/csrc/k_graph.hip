@@ -19,6 +19,7 @@
 // the best remaining candidate x* is kept and every candidate that x* is at
 // least alpha times as similar to as the node is dropped, until R are kept.
 #include <algorithm>
+#include <type_traits>
 
 #include "k_common.h"
 
@@ -123,10 +124,12 @@ __device__ __forceinline__ float score_rows(const GraphArgs &a, const float *qt,
     const float4 *q4 = reinterpret_cast<const float4 *>(qt);
     const float4 *m4 = reinterpret_cast<const float4 *>(mk);
     float s = 0.0f;
-    for (int c = 0; c < a.kchunks; ++c) {
+    // one 16-byte chunk; the mask is applied only in the chunks from cpad on,
+    // which run in a loop of their own (same order of accumulation)
+    auto chunk = [&](int c, auto masked_tag) {
+        constexpr bool masked = decltype(masked_tag)::value;
         const uint4 v = code[c];
         const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-        const bool masked = METRIC == LVQ_L2 && c >= cpad;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint32_t w = wv[i];
@@ -144,7 +147,7 @@ __device__ __forceinline__ float score_rows(const GraphArgs &a, const float *qt,
             for (int h = 0; h < PER / 4; ++h) {
                 const float4 q = q4[p0 / 4 + h];
                 qv[4 * h] = q.x; qv[4 * h + 1] = q.y; qv[4 * h + 2] = q.z; qv[4 * h + 3] = q.w;
-                if (masked) {
+                if constexpr (masked) {
                     const float4 m = m4[p0 / 4 + h];
                     mv[4 * h] = m.x; mv[4 * h + 1] = m.y; mv[4 * h + 2] = m.z; mv[4 * h + 3] = m.w;
                 }
@@ -156,12 +159,15 @@ __device__ __forceinline__ float score_rows(const GraphArgs &a, const float *qt,
                 } else {
                     const float qj = ONE_MEAN ? qv[j] : qv[j] - mu[p0 + j];
                     float t = qj - fmaf(dl, cv[j], l);
-                    if (masked) t *= mv[j];
+                    if constexpr (masked) t *= mv[j];
                     s = fmaf(t, t, s);
                 }
             }
         }
-    }
+    };
+    const int split = METRIC == LVQ_L2 ? min(cpad, a.kchunks) : a.kchunks;
+    for (int c = 0; c < split; ++c) chunk(c, std::false_type{});
+    for (int c = split; c < a.kchunks; ++c) chunk(c, std::true_type{});
     if constexpr (METRIC == LVQ_IP) return fmaf(dl, s, fmaf(l, qsum, cm[mid]));
     return s;
 }
@@ -212,6 +218,38 @@ __device__ __forceinline__ float score_lane(const GraphArgs &a, const float *qt,
 __device__ __forceinline__ int32_t key_node(uint64_t k)
 {
     return (int32_t)((uint32_t)k >> 1);
+}
+
+// Ascending sort of the wave's 64 keys (one per lane, all lanes active),
+// the bitonic network of wave_bitonic_sort with each exchange distance's own
+// data movement: DPP quad permutations for lanes 1 and 2 apart (11 of the 21
+// stages), ds_swizzle's bit mode for 4 to 16 (within 32-lane halves) and
+// ds_bpermute only for 32.
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v)
+{
+    if constexpr (J == 1) return dpp_u32<0xB1>(v);   // quad_perm [1,0,3,2]
+    else if constexpr (J == 2) return dpp_u32<0x4E>(v);   // quad_perm [2,3,0,1]
+    else if constexpr (J < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (J << 10) | 0x1F);
+    else return __shfl_xor(v, J, 64);
+}
+
+template <int SIZE, int J>
+__device__ __forceinline__ void sort64_stages(uint64_t &v, int lane)
+{
+    const uint64_t o = ((uint64_t)xor_lane_u32<J>((uint32_t)(v >> 32)) << 32) | xor_lane_u32<J>((uint32_t)v);
+    const bool asc = (lane & SIZE) == 0;
+    const bool lower = (lane & J) == 0;
+    const uint64_t mn = o < v ? o : v, mx = o < v ? v : o;
+    v = lower == asc ? mn : mx;
+    if constexpr (J > 1) sort64_stages<SIZE, J / 2>(v, lane);
+}
+
+template <int SIZE = 2>
+__device__ __forceinline__ void wave_sort64(uint64_t &v, int lane)
+{
+    sort64_stages<SIZE, SIZE / 2>(v, lane);
+    if constexpr (SIZE < 64) wave_sort64<SIZE * 2>(v, lane);
 }
 
 // One wavefront (one 64-lane workgroup) per query.  Each step explores the
@@ -275,9 +313,7 @@ __global__ __launch_bounds__(64) void k_graph_search(GraphArgs a)
     // Merge the lanes' keys (kNoKey where none) into the set; returns the
     // number of distinct new nodes.
     auto merge = [&](uint64_t key) -> int {
-        uint64_t v[1] = {key};
-        wave_bitonic_sort<1>(v);
-        key = v[0];
+        wave_sort64(key, lane);
         const uint32_t plo = __shfl_up((uint32_t)key, 1, 64), phi = __shfl_up((uint32_t)(key >> 32), 1, 64);
         const bool valid = key != kNoKey && !(lane > 0 && key == (((uint64_t)phi << 32) | plo));
         const uint64_t vm = __ballot(valid);
@@ -345,6 +381,9 @@ __global__ __launch_bounds__(64) void k_graph_search(GraphArgs a)
     while (pick < qn && !stop) {
         const uint64_t kx = cur[pick];
         const int32_t x = key_node(kx);
+        // the set's W-th key (its explored bit, which the mark below may
+        // change, plays no part in comparisons with new keys)
+        const uint64_t worst = qn == W ? cur[W - 1] : kNoKey;
         if (lane == 0) cur[pick] = kx | 1ull;   // explored; read by the merge after its barrier
         ++explored;
         // out-neighbours that never entered the set; one rejected before is
@@ -358,7 +397,24 @@ __global__ __launch_bounds__(64) void k_graph_search(GraphArgs a)
             const float v = score_lane<B1, METRIC>(a, qt, mk, y, qsum, cm, cpad);
             key = (make_key(v, 0, METRIC) & 0xFFFFFFFF00000000ull) | ((uint64_t)(uint32_t)y << 1);
         }
-        scored += merge(key);
+        scored += __popcll(__ballot(y >= 0));
+        // A full set keeps only keys below its W-th: when no lane has one, the
+        // merge would change nothing but the explored mark, and the next node
+        // is the first unexplored key of the set as it stands.
+        if (!__ballot(key < worst)) {
+            __syncthreads();   // the explored mark
+            pick = 1 << 30;
+            for (int base = 0; base < qn; base += 64) {
+                const int i = base + lane;
+                const uint64_t m = __ballot(i < qn && !(cur[i] & 1ull));
+                if (m) {
+                    pick = base + __builtin_ctzll(m);
+                    break;
+                }
+            }
+            continue;
+        }
+        merge(key);
     }
 
     // the k best live keys, in order
