@@ -75,10 +75,12 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("W", [48, 12])
 @pytest.mark.parametrize("d,b1,layout,metric,M", CASES)
-def test_walks_follow_the_oracle(L, d, b1, layout, metric, M):
+def test_walks_follow_the_oracle(L, d, b1, layout, metric, M, W):
+    # W = 12 fills the set at the first step, so most steps end without a merge
     g = synth.rng(8700 + d, M)
-    n, nq, W, k = 1500, 40, 48, 10
+    n, nq, k = 1500, 40, 10
     cent = g.standard_normal((12, d)).astype(np.float32)
     X = (cent[g.integers(0, 12, n)] + 0.5 * g.standard_normal((n, d))).astype(np.float32)
     Q = (cent[g.integers(0, 12, nq)] + 0.5 * g.standard_normal((nq, d))).astype(np.float32)
@@ -206,4 +208,26 @@ def test_rerank_final_set_at_both_levels(L):
         ref, tol = pair_reference(fmt, oracle.L2, oracle.FULL, Q[i:i + 1], rows, resid, mu,
                                   np.array([0, W], np.int64), wid[i])
         check_topk(oracle.L2, ti[i], td[i], wid[i], ref, tol, k)
+    ix.close()
+
+
+def test_scored_counts_every_row_entry(L):
+    # Three nodes; node 0's row lists node 1 twice.  Step 1 explores the
+    # entry 0 and scores the three row entries (1 twice; the merge keeps one
+    # copy); every later row holds only nodes already in the set.  So the
+    # walk explores 3 nodes and scores 1 (the entry) + 3 = 4, and returns all
+    # three nodes once each.
+    d = 8
+    g = synth.rng(8710, 0)
+    X = g.standard_normal((3, d)).astype(np.float32)
+    mu = np.zeros((1, d), np.float32)
+    graph = np.array([[1, 1, 2, -1], [2, 0, -1, -1], [0, 1, -1, -1]], np.int32)
+    ix = L.Index(d, 8, 0, L.LVQ_L2, L.LVQ_SEQUENTIAL, capacity=3, means=mu)
+    ix.insert(torch.from_numpy(X).cuda())
+    q = torch.from_numpy(X[2:3] + 0.1).cuda()
+    ids, dist, explored = ix.graph_search(q, torch.from_numpy(graph).cuda(),
+                                          torch.from_numpy(np.array([0], np.int32)).cuda(), 8, 3)
+    assert ix.sync() == 0
+    assert sorted(ids.cpu().numpy()[0].tolist()) == [0, 1, 2]
+    assert explored.cpu().numpy()[0].tolist() == [3, 4]
     ix.close()
