@@ -166,7 +166,9 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
         const bool in = t < nqt;
         qsum[t] = in ? a.qsum[q0 + t] : 0.0f;
         thr[t] = kNoKey;
-        thr_f[t] = -__builtin_inff();
+        // query slots past the batch admit nothing (+inf): the append test
+        // needs no per-query range check
+        thr_f[t] = in ? -__builtin_inff() : __builtin_inff();
         cnt[t] = 0;
     }
     for (int t = tid; t < TQ * nm; t += 256) {
@@ -312,7 +314,6 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
                 uint32_t passm = 0u;   // bit i: score i reaches its query's bound
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
-                    const int q4 = 32 * b + 8 * g + 4 * half;
                     const float qsv[4] = {qsA[g].x, qsA[g].y, qsA[g].z, qsA[g].w};
                     const float tfv[4] = {tfA[g].x, tfA[g].y, tfA[g].z, tfA[g].w};
                     const float cmv[4] = {cmA[g].x, cmA[g].y, cmA[g].z, cmA[g].w};
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(ScanArgs a)
                         if constexpr (B2 != 0) v = fmaf(hcur.z, acc2[b][i], v);
                         sc[i] = v;
                         // tfv never rejects a score that can enter the top k
-                        passm |= (live && (q4 + r) < nqt && v >= tfv[r]) ? 1u << i : 0u;
+                        passm |= (live && v >= tfv[r]) ? 1u << i : 0u;
                     }
                 }
                 if (__ballot(passm != 0u)) {
