@@ -339,11 +339,20 @@ int lvq_bw_stream(const void *src_dev, int64_t bytes, uint32_t *sink_dev, void *
 int lvq_bw_gather(lvq_index *index, const int32_t *ids_dev, int64_t n, int32_t level, uint32_t *sink_dev,
                   void *stream);
 
-/* Store statistics (host values). */
+/* Store statistics (host values).  The last_* fields describe the most
+ * recent lvq_distances, lvq_topk or lvq_probe_topk call on the index (zero
+ * before the first): last_workgroups is the grid of its main similarity
+ * launch, last_lists the lists it scored (lvq_distances, lvq_probe_topk:
+ * the persistent workgroups pop lists from a device counter, so a grid
+ * smaller than the list count makes workgroups take several lists), and
+ * last_parts the row parts an exhaustive scan split the occupied slots
+ * into (lvq_topk; each part keeps its own top-k, merged afterwards).      */
 typedef struct {
     int64_t capacity, free_slots, live_estimate, device_bytes;
     int32_t n_means, row_bytes, resid_bytes, code_positions;
     uint32_t epoch;
+    int64_t last_workgroups, last_lists;
+    int32_t last_parts;
 } lvq_stats;
 int lvq_get_stats(lvq_index *index, lvq_stats *out);
 

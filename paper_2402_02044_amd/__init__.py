@@ -56,7 +56,8 @@ class lvq_stats(ctypes.Structure):
                 ("live_estimate", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("n_means", ctypes.c_int32), ("row_bytes", ctypes.c_int32),
                 ("resid_bytes", ctypes.c_int32), ("code_positions", ctypes.c_int32),
-                ("epoch", ctypes.c_uint32)]
+                ("epoch", ctypes.c_uint32), ("last_workgroups", ctypes.c_int64),
+                ("last_lists", ctypes.c_int64), ("last_parts", ctypes.c_int32)]
 
 
 class lvq_server_config(ctypes.Structure):

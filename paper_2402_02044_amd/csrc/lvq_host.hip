@@ -692,6 +692,9 @@ int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds) != hipSuccess || per_cu < 1) per_cu = 1;
     const int64_t grid = std::min<int64_t>(nq, (int64_t)ix->n_cu * per_cu);
+    ix->last_wg = grid;
+    ix->last_lists = nq;
+    ix->last_parts = 0;
     if ((rc = timing_begin(ix, s))) return rc;
     hipLaunchKernelGGL(reinterpret_cast<void (*)(CandArgs)>(kern), dim3((unsigned)grid), dim3(256), lds, s, a);
     LVQ_HIP(hipGetLastError());
@@ -900,6 +903,9 @@ int lvq::host_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, i
     a.gthr = nullptr;
     a.part_keys = P<uint64_t>(w.part);
     a.err = P<uint32_t>(ix->err);
+    ix->last_wg = qtiles * parts;
+    ix->last_lists = 0;
+    ix->last_parts = (int32_t)parts;
     if ((rc = timing_begin(ix, s))) return rc;
     hipLaunchKernelGGL(reinterpret_cast<void (*)(ScanArgs)>(kern), dim3((unsigned)qtiles, (unsigned)parts), dim3(256),
                        lds, s, a);
@@ -980,6 +986,9 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     a.gthr = P<uint32_t>(w.gthr);
     a.part_keys = P<uint64_t>(w.part);
     a.err = P<uint32_t>(ix->err);
+    ix->last_wg = (qtiles * parts + 7) / 8 * 8;
+    ix->last_lists = 0;
+    ix->last_parts = (int32_t)parts;
     if ((rc = timing_begin(ix, s))) return rc;
     LVQ_HIP(launch_scan_mfma(a, f.bits1, bits2, prec, s));
     if ((rc = timing_end(ix, s))) return rc;
@@ -1335,6 +1344,9 @@ int lvq_get_stats(lvq_index *ix, lvq_stats *out)
     out->resid_bytes = ix->f.resid_bytes;
     out->code_positions = ix->f.npos;
     out->epoch = ix->epoch;
+    out->last_workgroups = ix->last_wg;
+    out->last_lists = ix->last_lists;
+    out->last_parts = ix->last_parts;
     return LVQ_OK;
 }
 

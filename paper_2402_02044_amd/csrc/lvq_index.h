@@ -77,6 +77,8 @@ struct lvq_index {
     int cand_shape[2][2] = {{-1, -1}, {-1, -1}};   // tuned [level][topk]
     bool capturing = false;   // the current call's stream is capturing a HIP graph
     bool timing = false;
+    int64_t last_wg = 0, last_lists = 0;   // shape of the latest similarity launch (lvq_stats)
+    int32_t last_parts = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
 };
 

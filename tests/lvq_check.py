@@ -25,8 +25,9 @@ def pair_tolerance(metric, Q, xhat, mean_rows, q_index):
     return 1e-4 * r + 1e-7 * scale
 
 
-def pair_reference(fmt, metric, level, Q, rows, resid, means, offsets, ids):
-    """Oracle values and tolerances for every listed pair."""
+def pair_reference(fmt, metric, level, Q, rows, resid, means, offsets, ids, chunk=1 << 15):
+    """Oracle values and tolerances for every listed pair (the tolerances are
+    evaluated in chunks of pairs, so long lists need no pairs x d array)."""
     ref = oracle.distances(fmt, metric, level, Q, rows, resid, means, offsets, ids)
     ids = np.asarray(ids)
     uniq, inv = np.unique(ids, return_inverse=True)
@@ -34,8 +35,53 @@ def pair_reference(fmt, metric, level, Q, rows, resid, means, offsets, ids):
     mid_u = oracle.unpack(fmt, rows[uniq])[3]
     mrow_u = np.asarray(means, np.float64)[mid_u]
     q_index = np.repeat(np.arange(len(offsets) - 1), np.diff(offsets))
-    tol = pair_tolerance(metric, Q, xh_u[inv], mrow_u[inv], q_index)
+    tol = np.empty(len(ids), np.float64)
+    for a in range(0, len(ids), chunk):
+        c = slice(a, a + chunk)
+        tol[c] = pair_tolerance(metric, Q, xh_u[inv[c]], mrow_u[inv[c]], q_index[c])
     return ref, tol
+
+
+class ExhaustiveReference:
+    """Oracle values and tolerances of a few queries against every row of a
+    store (for checking exhaustive top-k lists on a query sample).  The
+    reconstructions are computed once per level; each query's values come
+    from its own oracle call, run on host threads (the calls release the
+    interpreter lock)."""
+
+    def __init__(self, fmt, rows, resid, means):
+        self.fmt, self.rows, self.resid = fmt, rows, resid
+        self.means = np.asarray(means, np.float32)
+        self.mid = oracle.unpack(fmt, rows)[3]
+        self._xh = {}
+
+    def xhat(self, level):
+        if level not in self._xh:
+            self._xh[level] = oracle.reconstruct(self.fmt, self.rows, self.resid, self.means, level)
+        return self._xh[level]
+
+    def __call__(self, metric, level, Qs):
+        from concurrent.futures import ThreadPoolExecutor
+        n = self.rows.shape[0]
+        Qs = np.ascontiguousarray(Qs, np.float32)
+        ids = np.arange(n, dtype=np.int32)
+        offs = np.array([0, n], np.int64)
+
+        def one(i):
+            return oracle.distances(self.fmt, metric, level, Qs[i:i + 1], self.rows, self.resid, self.means,
+                                    offs, ids)
+
+        with ThreadPoolExecutor(min(16, max(1, Qs.shape[0]))) as ex:
+            ref = np.stack(list(ex.map(one, range(Qs.shape[0]))))
+        # pair_tolerance's formulas, as products over the whole store
+        xh = self.xhat(level)
+        q = np.asarray(Qs, np.float64)
+        if metric == oracle.IP:
+            return ref, 1e-4 * (np.abs(q) @ np.abs(xh).T)
+        m = np.asarray(self.means, np.float64)
+        qm = ((q[:, None, :] - m[None, :, :]) ** 2).sum(2)[:, self.mid]
+        xm = ((xh - m[self.mid]) ** 2).sum(1)
+        return ref, 1e-4 * ref + 1e-7 * (qm + xm[None, :])
 
 
 def check_values(got, ref, tol, what="distances"):
