@@ -57,7 +57,8 @@ enum {
     LVQ_ERR_CAPACITY = -4,     /* not enough free slots */
     LVQ_ERR_DEVICE = -5,       /* HIP runtime error */
     LVQ_ERR_NONFINITE = -6,    /* an input vector had a non-finite component */
-    LVQ_ERR_BAD_SLOT = -7      /* a slot id out of range (or not live for lvq_delete) */
+    LVQ_ERR_BAD_SLOT = -7,     /* a slot id out of range (or not live for lvq_delete) */
+    LVQ_ERR_SCRATCH = -8       /* lvq_distances_noalloc: the call needs more than its fixed scratch */
 };
 
 /* Index configuration.
@@ -152,6 +153,30 @@ int lvq_consolidate(lvq_index *index, void *stream, int64_t *n_freed_out);
 int lvq_distances(lvq_index *index, const float *q_dev, int64_t nq, const int64_t *offsets_dev,
                   const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev,
                   int32_t k, int32_t *topk_ids_dev, float *topk_dist_dev, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that forbid
+ * allocation): lvq_distances with the same arguments, semantics, kernels and
+ * results, except that its scratch -- the queries in kernel order
+ * (nq x kpos floats, kpos = code positions rounded up to 16-byte chunks),
+ * the sums of q (nq floats), the per-mean terms (nq x n_means floats), the
+ * list order (nq int32) and a work counter, each rounded up to 256 bytes --
+ * lives in one fixed array of LVQ_NOALLOC_SCRATCH_BYTES per device instead of
+ * the stream's workspace.  The call allocates nothing and creates no event
+ * (with no spare in-flight record it waits for the oldest query launch of
+ * the index), and lvq_set_timing does not time it.  The array is set up by
+ * lvq_create on each device an index is created on and is held until the
+ * process ends.  Every call on a device shares that device's array, and it
+ * keeps the last call's contents: calls that overlap on one device (on
+ * different streams, or from different indices) race and must be ordered by
+ * the caller.  A call needing more scratch than the array returns
+ * LVQ_ERR_SCRATCH before enqueuing anything (at d = 768, 4-bit codes: up to
+ * about 10,900 queries); LVQ_ERR_INVALID_ARG if the current device is not
+ * the index's.                                                             */
+#define LVQ_NOALLOC_SCRATCH_BYTES (32u << 20)
+int lvq_distances_noalloc(lvq_index *index, const float *q_dev, int64_t nq, const int64_t *offsets_dev,
+                          const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev,
+                          int32_t k, int32_t *topk_ids_dev, float *topk_dist_dev, void *stream);
 
 /* Tile shapes of the candidate-list kernel (lanes per candidate, bytes per
  * load, loads per lane, software pipelining; see the library source for the

@@ -34,9 +34,12 @@ LVQ_ERR_CAPACITY = -4
 LVQ_ERR_DEVICE = -5
 LVQ_ERR_NONFINITE = -6
 LVQ_ERR_BAD_SLOT = -7
+LVQ_ERR_SCRATCH = -8
+LVQ_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 EXPORTS = ["lvq_row_format", "lvq_create", "lvq_destroy", "lvq_set_means", "lvq_encode", "lvq_insert",
-           "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_topk", "lvq_probe_topk", "lvq_retire_means",
+           "lvq_delete", "lvq_consolidate", "lvq_distances", "lvq_distances_noalloc", "lvq_topk",
+           "lvq_probe_topk", "lvq_retire_means",
            "lvq_add_means", "lvq_mean_members", "lvq_graph_search", "lvq_graph_prune", "lvq_graph_build",
            "lvq_graph_insert", "lvq_graph_delete", "lvq_bw_stream", "lvq_bw_gather", "lvq_read_rows",
            "lvq_get_stats", "lvq_sync", "lvq_mean", "lvq_kmeans", "lvq_strerror", "lvq_set_timing",
@@ -101,6 +104,7 @@ def _load():
         "lvq_delete": [P, P, i64, P],
         "lvq_consolidate": [P, P, P],
         "lvq_distances": [P, P, i64, P, P, i64, i32, P, i32, P, P, P],
+        "lvq_distances_noalloc": [P, P, i64, P, P, i64, i32, P, i32, P, P, P],
         "lvq_topk": [P, P, i32, i64, i32, i32, P, P, P],
         "lvq_probe_topk": [P, P, i64, i32, i32, i32, P, P, P, P],
         "lvq_retire_means": [P, P, i32, P],
@@ -198,6 +202,11 @@ def lvq_consolidate(ix, stream=0) -> int:
 def lvq_distances(ix, q, nq, offsets, ids, total, level, dist, k, topk_ids, topk_dist, stream=0):
     return _chk(_lib.lvq_distances(ix, q, nq, offsets, ids, total, level, dist, k, topk_ids, topk_dist,
                                    stream), "lvq_distances")
+
+
+def lvq_distances_noalloc(ix, q, nq, offsets, ids, total, level, dist, k, topk_ids, topk_dist, stream=0):
+    return _chk(_lib.lvq_distances_noalloc(ix, q, nq, offsets, ids, total, level, dist, k, topk_ids, topk_dist,
+                                           stream), "lvq_distances_noalloc")
 
 
 def lvq_topk(ix, q, prec, nq, k, level, ids, dist, stream=0):

@@ -179,10 +179,19 @@ int note_update(lvq_index *ix, hipStream_t s)
     return LVQ_OK;
 }
 
-int note_query(lvq_index *ix, hipStream_t s, uint32_t epoch)
+// may_create = false (the allocation-free entry point): with no spare event,
+// wait for the oldest in-flight launch and take its event (lvq_create makes
+// a few spare events, so one of the two lists is never empty).
+int note_query(lvq_index *ix, hipStream_t s, uint32_t epoch, bool may_create = true)
 {
     if (ix->capturing) return LVQ_OK;
     hipEvent_t ev;
+    if (ix->spare_events.empty() && !may_create) {
+        if (ix->inflight.empty()) return LVQ_ERR_DEVICE;
+        LVQ_HIP(hipEventSynchronize(ix->inflight.front().ev));
+        ix->spare_events.push_back(ix->inflight.front().ev);
+        ix->inflight.pop_front();
+    }
     if (!ix->spare_events.empty()) {
         ev = ix->spare_events.back();
         ix->spare_events.pop_back();
@@ -218,13 +227,10 @@ int timing_end(lvq_index *ix, hipStream_t s)
     return LVQ_OK;
 }
 
-int prep_queries(lvq_index *ix, Workspace &w, const float *q, int64_t nq, hipStream_t s)
+// Query prep into the given buffers (nq x kpos, nq, nq x n_means floats).
+int prep_into(lvq_index *ix, const float *q, int64_t nq, float *qk, float *qsum, float *cm, hipStream_t s)
 {
     const Format &f = ix->f;
-    int rc;
-    if ((rc = dev_alloc(ix, w.qk, sizeof(float) * (size_t)std::max<int64_t>(nq, 1) * f.kpos))) return rc;
-    if ((rc = dev_alloc(ix, w.qsum, sizeof(float) * (size_t)std::max<int64_t>(nq, 1)))) return rc;
-    if ((rc = dev_alloc(ix, w.cm, sizeof(float) * (size_t)std::max<int64_t>(nq, 1) * ix->n_means))) return rc;
     PrepArgs pa;
     pa.q = q;
     pa.nq = nq;
@@ -234,11 +240,21 @@ int prep_queries(lvq_index *ix, Workspace &w, const float *q, int64_t nq, hipStr
     pa.metric = ix->cfg.metric;
     pa.kdim = P<int32_t>(ix->kdim);
     pa.means = P<float>(ix->means);
-    pa.qk = P<float>(w.qk);
-    pa.qsum = P<float>(w.qsum);
-    pa.cm = P<float>(w.cm);
+    pa.qk = qk;
+    pa.qsum = qsum;
+    pa.cm = cm;
     LVQ_HIP(launch_prep(pa, s));
     return LVQ_OK;
+}
+
+int prep_queries(lvq_index *ix, Workspace &w, const float *q, int64_t nq, hipStream_t s)
+{
+    const Format &f = ix->f;
+    int rc;
+    if ((rc = dev_alloc(ix, w.qk, sizeof(float) * (size_t)std::max<int64_t>(nq, 1) * f.kpos))) return rc;
+    if ((rc = dev_alloc(ix, w.qsum, sizeof(float) * (size_t)std::max<int64_t>(nq, 1)))) return rc;
+    if ((rc = dev_alloc(ix, w.cm, sizeof(float) * (size_t)std::max<int64_t>(nq, 1) * ix->n_means))) return rc;
+    return prep_into(ix, q, nq, P<float>(w.qk), P<float>(w.qsum), P<float>(w.cm), s);
 }
 
 // Default tile shape: the instantiated shape whose round covers the code
@@ -276,7 +292,10 @@ bool shape_fits(const Format &f, void *(*lookup)(int, int, int), int bits2, int 
 namespace lvq {
 
 int host_begin_call(lvq_index *ix, hipStream_t s) { return begin_call(ix, s); }
-int host_note_query(lvq_index *ix, hipStream_t s, uint32_t epoch) { return note_query(ix, s, epoch); }
+int host_note_query(lvq_index *ix, hipStream_t s, uint32_t epoch, bool may_create)
+{
+    return note_query(ix, s, epoch, may_create);
+}
 int host_alloc(lvq_index *ix, DevBuf &b, size_t bytes) { return dev_alloc(ix, b, bytes); }
 void host_free(lvq_index *ix, DevBuf &b) { dev_free(ix, b); }
 
@@ -295,6 +314,7 @@ const char *lvq_strerror(int code)
     case LVQ_ERR_DEVICE: return "HIP runtime error";
     case LVQ_ERR_NONFINITE: return "non-finite input vector";
     case LVQ_ERR_BAD_SLOT: return "slot out of range or not live";
+    case LVQ_ERR_SCRATCH: return "request exceeds the fixed scratch of the allocation-free entry point";
     default: return "unknown error";
     }
 }
@@ -379,6 +399,13 @@ int lvq_create(const lvq_config *cfg, const float *means_host, int32_t n_means, 
             ix->list_len = 0;
         }
         if (hipEventCreateWithFlags(&ix->update_ev, hipEventDisableTiming)) { rc = LVQ_ERR_DEVICE; break; }
+        for (int i = 0; i < 8 && rc == LVQ_OK; ++i) {
+            hipEvent_t ev;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming)) rc = LVQ_ERR_DEVICE;
+            else ix->spare_events.push_back(ev);
+        }
+        if (rc) break;
+        if ((rc = noalloc_setup(ix->device))) break;
     } while (0);
     if (rc) {
         lvq_destroy(ix);
@@ -594,7 +621,7 @@ int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int
                         const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev, int32_t k,
                         int32_t *topk_ids_dev, float *topk_dist_dev, hipStream_t s, int force_shape,
                         uint32_t epoch, bool neg_empty, const int32_t *list_means, int list_nmeans,
-                        const int64_t *seg_offs, const int32_t *seg_members)
+                        const int64_t *seg_offs, const int32_t *seg_members, const DistScratch *fixed)
 {
     if (!ix || nq < 0 || total < 0 || nq > INT32_MAX) return LVQ_ERR_INVALID_ARG;
     const bool segmented = seg_members != nullptr;
@@ -648,10 +675,17 @@ int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int
 
     int rc = order_after_updates(ix, s);
     if (rc) return rc;
-    Workspace &w = workspace(ix, s);
-    if ((rc = prep_queries(ix, w, q_dev, nq, s))) return rc;
-    if ((rc = dev_alloc(ix, w.order, sizeof(int32_t) * (size_t)nq))) return rc;
-    if ((rc = dev_alloc(ix, w.queue, 64))) return rc;
+    DistScratch sc;
+    if (fixed) {
+        sc = *fixed;
+        if ((rc = prep_into(ix, q_dev, nq, sc.qk, sc.qsum, sc.cm, s))) return rc;
+    } else {
+        Workspace &w = workspace(ix, s);
+        if ((rc = prep_queries(ix, w, q_dev, nq, s))) return rc;
+        if ((rc = dev_alloc(ix, w.order, sizeof(int32_t) * (size_t)nq))) return rc;
+        if ((rc = dev_alloc(ix, w.queue, 64))) return rc;
+        sc = {P<float>(w.qk), P<float>(w.qsum), P<float>(w.cm), P<int32_t>(w.order), P<int32_t>(w.queue)};
+    }
 
     CandArgs a;
     a.rows = P<uint8_t>(ix->rows);
@@ -661,9 +695,9 @@ int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int
     a.kchunks = f.kchunks;
     a.kpos = f.kpos;
     a.capacity = ix->cfg.capacity;
-    a.qk = P<float>(w.qk);
-    a.qsum = P<float>(w.qsum);
-    a.cm = P<float>(w.cm);
+    a.qk = sc.qk;
+    a.qsum = sc.qsum;
+    a.cm = sc.cm;
     a.muk = P<float>(ix->muk);
     a.kmask = P<float>(ix->kmask);
     a.n_means = ix->n_means;
@@ -685,20 +719,20 @@ int lvq::host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int
     a.seg_offs = segmented ? seg_offs : nullptr;
     a.seg_members = segmented ? seg_members : nullptr;
     // persistent launch: lists longest-first from a device work counter
-    a.order = P<int32_t>(w.order);
-    a.queue = P<int32_t>(w.queue);
+    a.order = sc.order;
+    a.queue = sc.queue;
     LVQ_HIP(launch_fill_i32(a.queue, 0, 1, s));
-    LVQ_HIP(launch_list_order(offsets_dev, nq, P<int32_t>(w.order), nullptr, s));
+    LVQ_HIP(launch_list_order(offsets_dev, nq, sc.order, nullptr, s));
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds) != hipSuccess || per_cu < 1) per_cu = 1;
     const int64_t grid = std::min<int64_t>(nq, (int64_t)ix->n_cu * per_cu);
     ix->last_wg = grid;
     ix->last_lists = nq;
     ix->last_parts = 0;
-    if ((rc = timing_begin(ix, s))) return rc;
+    if (!fixed && (rc = timing_begin(ix, s))) return rc;
     hipLaunchKernelGGL(reinterpret_cast<void (*)(CandArgs)>(kern), dim3((unsigned)grid), dim3(256), lds, s, a);
     LVQ_HIP(hipGetLastError());
-    return timing_end(ix, s);
+    return fixed ? LVQ_OK : timing_end(ix, s);
 }
 
 extern "C" {

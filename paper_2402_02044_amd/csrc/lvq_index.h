@@ -20,6 +20,14 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Scratch of one host_distances call given by the caller (the allocation-free
+// entry point): query tables (nq x kpos), sums of q (nq), mean terms
+// (nq x n_means), list order (nq) and the persistent launch's work counter.
+struct DistScratch {
+    float *qk, *qsum, *cm;
+    int32_t *order, *queue;
+};
+
 // Per-stream scratch of the query entry points.
 struct Workspace {
     DevBuf qk, qsum, cm, order, queue, part, q16, gthr;
@@ -107,11 +115,18 @@ int host_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t 
                    const int32_t *ids_dev, int64_t total, int32_t level, float *dist_dev, int32_t k,
                    int32_t *topk_ids_dev, float *topk_dist_dev, hipStream_t s, int force_shape, uint32_t epoch,
                    bool neg_empty, const int32_t *list_means = nullptr, int list_nmeans = 0,
-                   const int64_t *seg_offs = nullptr, const int32_t *seg_members = nullptr);
+                   const int64_t *seg_offs = nullptr, const int32_t *seg_members = nullptr,
+                   const DistScratch *fixed = nullptr);
 
 // Mark the work queued so far on `s` as a query reading the store at `epoch`
-// (consolidation keeps the slots that query may still see).
-int host_note_query(lvq_index *ix, hipStream_t s, uint32_t epoch);
+// (consolidation keeps the slots that query may still see).  may_create =
+// false never creates an event: without a spare one it waits for the oldest
+// in-flight launch and reuses its event.
+int host_note_query(lvq_index *ix, hipStream_t s, uint32_t epoch, bool may_create = true);
+
+// Per-device set-up of the allocation-free entry point's fixed scratch
+// (called by lvq_create with the index's device current).
+int noalloc_setup(int device);
 
 // Size the workspace of stream `s` for every query batch of up to max_nq
 // queries through host_topk (k_first, prec, scan_level) followed by
