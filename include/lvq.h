@@ -21,12 +21,23 @@
  *  - The library owns the store (rows, residual rows, means, free-slot list)
  *    and its workspace, all in device memory it allocates itself, counted
  *    against lvq_config.mem_budget_bytes.
- *  - HIP graphs: lvq_distances and lvq_topk may be captured into a graph on
- *    `stream` once an uncaptured call of the same size has sized the
- *    workspace (a captured call allocates nothing and otherwise fails with
- *    LVQ_ERR_INVALID_ARG).  A captured call replays at the store epoch of
- *    capture and does not order itself after store updates on other
- *    streams; no other entry point may be captured.
+ *  - HIP graphs: lvq_distances, lvq_topk, lvq_probe_topk and
+ *    lvq_graph_search may be captured into a graph on `stream` once an
+ *    uncaptured call of the same size has sized the stream's workspace (a
+ *    captured call allocates nothing and otherwise fails with
+ *    LVQ_ERR_INVALID_ARG); lvq_distances_noalloc needs no such call.  A
+ *    captured call replays at the store epoch of capture and does not order
+ *    itself after store updates on other streams; no other entry point may
+ *    be captured.  After a capture the stream's workspace is fixed for the
+ *    index's life, so that no replay reads or writes freed memory: a later
+ *    call on that stream that would need a larger workspace fails with
+ *    LVQ_ERR_INVALID_ARG (use another stream).  The occupied-slot list a
+ *    captured lvq_topk or lvq_probe_topk scans is never recycled by
+ *    lvq_consolidate (each later consolidation writes a new list buffer), so
+ *    replays keep scanning the slots listed at capture; a row deleted after
+ *    the capture and then freed by a consolidation is no longer seen by
+ *    them (its slot is cleared or holds a row inserted after the capture).
+ *    Re-capture after consolidations to replay the current store.
  *  - Matrices are row-major and dense: x_dev is n x dim float32, q_dev is
  *    nq x dim (float32, or bfloat16 / float16 for lvq_topk's MFMA forms).
  *  - Similarity: LVQ_L2 returns the squared Euclidean distance to the

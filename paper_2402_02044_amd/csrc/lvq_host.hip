@@ -89,6 +89,7 @@ int dev_alloc(lvq_index *ix, DevBuf &b, size_t bytes)
 {
     if (b.bytes >= bytes && b.p) return LVQ_OK;
     if (ix->capturing) return LVQ_ERR_INVALID_ARG;   // no allocation inside graph capture
+    if (b.pinned) return LVQ_ERR_INVALID_ARG;        // a captured graph still reads it
     if (bytes == 0) bytes = 16;
     const int64_t grow = (int64_t)bytes - (int64_t)b.bytes;
     if (ix->cfg.mem_budget_bytes > 0 && ix->device_bytes + grow > ix->cfg.mem_budget_bytes)
@@ -150,6 +151,19 @@ int upload_means(lvq_index *ix, const std::vector<float> &all)
 }
 
 Workspace &workspace(lvq_index *ix, hipStream_t s) { return ix->ws[s]; }
+
+// After a captured call on `s`: its workspace buffers (which the graph's
+// kernels read and write) are never freed or grown again, and the occupied-
+// slot list a captured scan walks is never recycled by consolidation.
+void pin_after_capture(lvq_index *ix, hipStream_t s, bool reads_list)
+{
+    if (!ix->capturing) return;
+    Workspace &w = ix->ws[s];
+    for (DevBuf *b : {&w.qk, &w.qsum, &w.cm, &w.order, &w.queue, &w.part, &w.q16, &w.gthr, &w.members, &w.moffs,
+                      &w.mcount, &w.mcursor, &w.probe, &w.qoffs, &w.qids})
+        if (b->p) b->pinned = true;
+    if (reads_list && ix->list_active >= 0) ix->lists[ix->list_active].captured = true;
+}
 
 // Record whether `s` is capturing a HIP graph: captured calls allocate
 // nothing, skip cross-stream ordering and in-flight bookkeeping, and replay
@@ -587,7 +601,7 @@ int lvq_consolidate(lvq_index *ix, void *stream, int64_t *n_freed_out)
     // reads, else a new one
     int next = -1;
     for (int i = 0; i < (int)ix->lists.size(); ++i)
-        if (i != ix->list_active && ix->lists[i].retire_seq < oldest) {
+        if (i != ix->list_active && ix->lists[i].retire_seq < oldest && !ix->lists[i].captured) {
             next = i;
             break;
         }
@@ -748,6 +762,7 @@ int lvq_distances(lvq_index *ix, const float *q_dev, int64_t nq, const int64_t *
     rc = host_distances(ix, q_dev, nq, offsets_dev, ids_dev, total, level, dist_dev, k, topk_ids_dev,
                         topk_dist_dev, (hipStream_t)stream, -1, ix->epoch, false);
     if (rc == LVQ_OK) rc = note_query(ix, (hipStream_t)stream, ix->epoch);
+    if (rc == LVQ_OK) pin_after_capture(ix, (hipStream_t)stream, false);
     ix->capturing = false;
     return rc;
 }
@@ -961,6 +976,7 @@ int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t
     if (rc) return rc;
     rc = host_topk(ix, q_dev, prec, nq, k, level, ids_dev, dist_dev, s, ix->epoch);
     if (rc == LVQ_OK && nq > 0) rc = note_query(ix, s, ix->epoch);
+    if (rc == LVQ_OK) pin_after_capture(ix, s, true);
     ix->capturing = false;
     return rc;
 }
@@ -1091,6 +1107,7 @@ int lvq_probe_topk(lvq_index *ix, const float *q_dev, int64_t nq, int32_t nprobe
     if (rc) return rc;
     rc = probe_topk(ix, q_dev, nq, nprobe, k, level, probe_out_dev, ids_dev, dist_dev, s);
     if (rc == LVQ_OK && nq > 0) rc = note_query(ix, s, ix->epoch);
+    if (rc == LVQ_OK) pin_after_capture(ix, s, true);
     ix->capturing = false;
     return rc;
 }
@@ -1147,6 +1164,7 @@ int lvq_graph_search(lvq_index *ix, const float *q_dev, int64_t nq, const int32_
         }
     }
     if (rc == LVQ_OK) rc = note_query(ix, s, ix->epoch);
+    if (rc == LVQ_OK) pin_after_capture(ix, s, false);
     ix->capturing = false;
     return rc;
 }

@@ -18,6 +18,7 @@ namespace lvq {
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool pinned = false;   // read by a captured HIP graph: never freed or grown while the index lives
 };
 
 // Scratch of one host_distances call given by the caller (the allocation-free
@@ -52,6 +53,7 @@ struct InFlight {
 struct SlotList {
     DevBuf buf;
     uint64_t retire_seq = 0;
+    bool captured = false;   // a captured scan reads it: never reused for another list
 };
 
 }  // namespace lvq

@@ -538,5 +538,32 @@ def test_graph_capture_replays_match_eager(L):
         torch.cuda.synchronize()
         assert torch.equal(dist, dist0), r
         assert torch.equal(ti, ti0) and torch.equal(td, td0), r
+    # the captured stream's workspace is fixed now: a larger batch on that
+    # stream is refused (the graph still reads the buffers it would grow), a
+    # smaller one runs in them, and replays still match
+    q3 = torch.cat([qd, qd, qd])
+    o3 = torch.from_numpy(np.concatenate([offs[:-1], offs[:-1] + offs[-1], offs + 2 * offs[-1]])).cuda()
+    i3 = torch.cat([idd, idd, idd])
+    d3 = torch.empty(3 * ids.shape[0], device="cuda")
+    t3 = torch.empty((3 * nq, 10), dtype=torch.int32, device="cuda")
+    v3 = torch.empty((3 * nq, 10), device="cuda")
+    torch.cuda.synchronize()
+    with pytest.raises(L.LVQError) as e:
+        L.lvq_distances(ix.handle, q3.data_ptr(), 3 * nq, o3.data_ptr(), i3.data_ptr(), 3 * ids.shape[0],
+                        L.LVQ_PRIMARY, d3.data_ptr(), 10, t3.data_ptr(), v3.data_ptr(), int(s.cuda_stream))
+    assert e.value.code == L.LVQ_ERR_INVALID_ARG
+    L.lvq_distances(ix.handle, q3.data_ptr(), 3 * nq, o3.data_ptr(), i3.data_ptr(), 3 * ids.shape[0],
+                    L.LVQ_PRIMARY, d3.data_ptr(), 10, t3.data_ptr(), v3.data_ptr(), 0)   # another stream
+    h = nq // 2
+    tot = int(offs[h])
+    L.lvq_distances(ix.handle, qd.data_ptr(), h, od.data_ptr(), idd.data_ptr(), tot, L.LVQ_PRIMARY,
+                    d3.data_ptr(), 10, t3.data_ptr(), v3.data_ptr(), int(s.cuda_stream))
+    torch.cuda.synchronize()
+    assert torch.equal(d3[:tot], dist0[:tot]) and torch.equal(t3[:h], ti0[:h]) and torch.equal(v3[:h], td0[:h])
+    dist.fill_(-1.0)
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(dist, dist0) and torch.equal(ti, ti0) and torch.equal(td, td0)
     assert ix.sync() == 0
     ix.close()
