@@ -9,7 +9,10 @@ their admission epoch.
   top-k over those candidates).
 * The alone results hold oracle values: every returned distance matches the
   oracle's two-level value of that slot, every slot is live at the epoch.
-* Admission by memory: a pool that fits one largest batch runs one at a time.
+* Admission by memory: a pool that fits one largest batch runs one at a time,
+  while small batches share it.
+* Batches overlap on the device: a burst is admitted into several slots and
+  their admission-to-completion intervals overlap.
 * Consolidation during serving never hands a batch a slot that was not live
   at the batch's epoch.
 """
@@ -173,7 +176,7 @@ def test_mix_equals_alone(L, form):
     prec = {"fp32": L.LVQ_FP32, "bf16": L.LVQ_BF16}[form.split("-")[0]]
     scan_level = L.LVQ_FULL if form.endswith("full") else L.LVQ_PRIMARY
     ops, mixed, stats = _run_mix(L, prec, scan_level, slots=5, pool_batches=2.5)
-    assert stats.completed == len(mixed) and stats.peak_in_flight >= 1
+    assert stats.completed == len(mixed) and stats.peak_in_flight >= 2
     assert stats.pool_peak <= stats.pool_bytes
     epochs = [info.epoch for _, _, info in mixed]
     assert len(set(epochs)) > 1, "updates should interleave with the batches"
@@ -204,12 +207,49 @@ def test_admission_by_memory(L):
         sv.wait(t, 1)
     s2 = sv.stats()
     assert s2.pool_peak <= one and s2.completed == 30
+    assert s2.peak_in_flight >= 2, "small batches should share the pool of one large batch"
     with pytest.raises(L.LVQError):
         sv.submit(np.zeros((MAXB + 1, D), np.float32))
     with pytest.raises(L.LVQError):
         sv.wait(10 ** 9, 1)
     sv.close()
     st.ix.close()
+
+
+def _overlapping_pairs(infos):
+    iv = sorted((i.t_admit, i.t_done) for i in infos)
+    return sum(1 for a in range(len(iv)) for b in range(a + 1, len(iv)) if iv[b][0] < iv[a][1])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batches_overlap_on_the_device(L, prec):
+    """Continuous batching: a burst of batches over a 200,000-row store is
+    admitted into several slots at once, so batches run on the device at the
+    same time (overlapping admission-to-completion intervals), and each
+    result equals the direct exhaustive call on the same store."""
+    g = synth.rng(7003, 0)
+    n, nb = 200_000, 16
+    cent = g.standard_normal((16, D)).astype(np.float32)
+    X = cent[g.integers(0, 16, n)] + 0.5 * g.standard_normal((n, D)).astype(np.float32)
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    ix = L.Index(D, 4, 8, L.LVQ_IP, L.LVQ_TURBO, capacity=n, means=X[:4])
+    ix.insert(torch.from_numpy(X).cuda())
+    assert ix.sync() == 0
+    p = {"fp32": L.LVQ_FP32, "bf16": L.LVQ_BF16}[prec]
+    sv = L.Server(ix, slots=6, max_batch=MAXB, k=K, k_first=KF, precision=p, scan_level=L.LVQ_FULL)
+    qs = [(X[g.integers(0, n, MAXB)] + 0.1 * g.standard_normal((MAXB, D))).astype(np.float32) for _ in range(nb)]
+    tickets = [sv.submit(q) for q in qs]
+    res = [sv.wait(t, MAXB) for t in tickets]
+    st = sv.stats()
+    sv.close()
+    assert st.completed == nb and st.peak_in_flight >= 2
+    assert _overlapping_pairs([info for _, _, info in res]) >= 1
+    tdt = torch.float32 if prec == "fp32" else torch.bfloat16
+    for q, (ids, dist, info) in zip(qs, res):
+        ti, td = ix.topk(torch.from_numpy(q).cuda().to(tdt), K, level=L.LVQ_FULL)
+        assert np.array_equal(ti.cpu().numpy(), ids) and np.array_equal(td.cpu().numpy(), dist)
+    assert ix.sync() == 0
+    ix.close()
 
 
 def test_consolidation_while_serving(L):
