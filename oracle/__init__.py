@@ -66,6 +66,10 @@ def _L():
         lib.orc_encode_rows.restype = i64
         lib.orc_unpack.argtypes = [ctypes.POINTER(_Fmt), P, P, P, P, P, P, P, P]
         lib.orc_reconstruct.argtypes = [ctypes.POINTER(_Fmt), P, P, P, i32, P]
+        lib.orc_unpack_rows.argtypes = [ctypes.POINTER(_Fmt), P, P, i64, P, P, P, P, P, P]
+        lib.orc_unpack_rows.restype = None
+        lib.orc_reconstruct_rows.argtypes = [ctypes.POINTER(_Fmt), P, P, i64, P, i32, P]
+        lib.orc_reconstruct_rows.restype = None
         lib.orc_distances.argtypes = [ctypes.POINTER(_Fmt), i32, i32, P, i64, P, P, P, P, P, P]
         lib.orc_select_topk.argtypes = [i32, P, P, P, i64, i32, P, P]
         lib.orc_eps1.argtypes = [ctypes.POINTER(_Fmt), P, i64, P, P]
@@ -190,17 +194,14 @@ def unpack(fmt: Format, rows, resid=None):
     f = fmt._c()
     rows = np.ascontiguousarray(rows, np.uint8).reshape(-1, f.row_bytes)
     n = rows.shape[0]
-    hdr = np.zeros((n, 3), np.float32)
+    hdr = np.zeros((3, n), np.float32)
     mid = np.zeros(n, np.int32)
     c1 = np.zeros((n, fmt.dim), np.uint8)
     c2 = np.zeros((n, fmt.dim), np.uint8)
-    m = np.zeros(1, np.int32)
-    for i in range(n):
-        res = None if resid is None else np.ascontiguousarray(resid[i], np.uint8)
-        _L().orc_unpack(ctypes.byref(f), _p(rows[i]), _p(res), _p(hdr[i, 0:1]), _p(hdr[i, 1:2]),
-                        _p(hdr[i, 2:3]), _p(m), _p(c1[i]), _p(c2[i]))
-        mid[i] = m[0]
-    return hdr[:, 0], hdr[:, 1], hdr[:, 2], mid, c1, c2
+    res = None if resid is None else np.ascontiguousarray(resid, np.uint8).reshape(n, f.resid_bytes)
+    _L().orc_unpack_rows(ctypes.byref(f), _p(rows), _p(res), n, _p(hdr[0]), _p(hdr[1]), _p(hdr[2]), _p(mid),
+                         _p(c1), _p(c2))
+    return hdr[0], hdr[1], hdr[2], mid, c1, c2
 
 
 def reconstruct(fmt: Format, rows, resid, means, level=PRIMARY) -> np.ndarray:
@@ -208,10 +209,8 @@ def reconstruct(fmt: Format, rows, resid, means, level=PRIMARY) -> np.ndarray:
     rows = np.ascontiguousarray(rows, np.uint8).reshape(-1, f.row_bytes)
     means = _f32(means)
     out = np.zeros((rows.shape[0], fmt.dim), np.float64)
-    for i in range(rows.shape[0]):
-        res = None if resid is None else np.ascontiguousarray(resid[i], np.uint8)
-        _L().orc_reconstruct(ctypes.byref(f), _p(rows[i]), _p(res), _p(means), level,
-                             _p(out[i]))
+    res = None if resid is None else np.ascontiguousarray(resid, np.uint8).reshape(rows.shape[0], f.resid_bytes)
+    _L().orc_reconstruct_rows(ctypes.byref(f), _p(rows), _p(res), rows.shape[0], _p(means), level, _p(out))
     return out
 
 

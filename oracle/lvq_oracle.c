@@ -323,6 +323,26 @@ void orc_reconstruct(const orc_format *f, const uint8_t *row, const uint8_t *res
     free(c2);
 }
 
+/* The two routines above over n consecutive rows (test bookkeeping). */
+void orc_unpack_rows(const orc_format *f, const uint8_t *rows, const uint8_t *resid, int64_t n,
+                     float *l, float *delta, float *delta2, int32_t *mean_id, uint8_t *c1, uint8_t *c2)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        int m;
+        orc_unpack(f, rows + i * f->row_bytes, resid ? resid + i * f->resid_bytes : NULL, l + i, delta + i,
+                   delta2 + i, &m, c1 + i * f->dim, c2 ? c2 + i * f->dim : NULL);
+        mean_id[i] = m;
+    }
+}
+
+void orc_reconstruct_rows(const orc_format *f, const uint8_t *rows, const uint8_t *resid, int64_t n,
+                          const float *means, int level, double *xhat)
+{
+    for (int64_t i = 0; i < n; ++i)
+        orc_reconstruct(f, rows + i * f->row_bytes, resid ? resid + i * f->resid_bytes : NULL, means, level,
+                        xhat + i * f->dim);
+}
+
 void orc_distances(const orc_format *f, int metric, int level, const float *Q, int64_t nq,
                    const uint8_t *rows, const uint8_t *resid, const float *means,
                    const int64_t *offsets, const int32_t *ids, double *out)

@@ -78,6 +78,11 @@ void orc_unpack(const orc_format *f, const uint8_t *row, const uint8_t *resid,
 /* Reconstruction x_hat (binary64) of one stored row at the given level. */
 void orc_reconstruct(const orc_format *f, const uint8_t *row, const uint8_t *resid,
                      const float *means, int level, double *xhat);
+/* orc_unpack / orc_reconstruct over n consecutive rows (and residual rows). */
+void orc_unpack_rows(const orc_format *f, const uint8_t *rows, const uint8_t *resid, int64_t n,
+                     float *l, float *delta, float *delta2, int32_t *mean_id, uint8_t *c1, uint8_t *c2);
+void orc_reconstruct_rows(const orc_format *f, const uint8_t *rows, const uint8_t *resid, int64_t n,
+                          const float *means, int level, double *xhat);
 
 /* Similarity of queries to listed slots: L2 = squared Euclidean distance to
  * the reconstruction, IP = inner product with it (Sec. 3.2).  offsets has
