@@ -35,7 +35,7 @@ METRIC = "LVQ distances/s + HBM GB/s vs peak; QPS and p99 at 10-recall@10≥0.9"
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 FP32_PEAK_TFLOPS = 157.3
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_cand_c2_full_traffic.md")
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["paper_2402_02044_amd/csrc/k_cand_impl.h", "paper_2402_02044_amd/csrc/k_common.h",
                   "paper_2402_02044_amd/csrc/k_cand_inst.h"]
 T0 = time.time()
@@ -53,11 +53,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(launch_pairs: int, tile: int):
-    """HBM bytes per launch from a committed rocprofv3 counter summary taken
-    on the current kernel source and this tile shape (else None)."""
-    stem = PROFILE_TRAFFIC[:-3]
-    for path in [PROFILE_TRAFFIC] + sorted(glob.glob(stem + "_tile*.md")):
+def read_traffic(stem: str, launch_pairs: int, tile: int):
+    """HBM bytes per launch from a committed rocprofv3 counter summary
+    (profiles/<stem>*.md) taken on the current kernel source, this many pairs
+    per launch and this tile shape (else None)."""
+    for path in sorted(glob.glob(os.path.join(PROFILES, stem + "*.md"))):
         got = read_traffic_file(path, launch_pairs, tile)
         if got is not None:
             return got
@@ -295,18 +295,53 @@ def cpu_baseline_lists(fmt, metric, level, X, Q, means, offs, ids, budget_s=12.0
         rows, resid, _ = oracle.encode_rows(fmt, X[uniq], means)
         inv = inv.astype(np.int32)
         t = time.perf_counter()
-        oracle.distances(fmt, metric, level, Q[:nq_s], rows, resid, means, offs[:nq_s + 1], inv)
-        return time.perf_counter() - t, e, (rows, resid, inv)
+        ref = oracle.distances(fmt, metric, level, Q[:nq_s], rows, resid, means, offs[:nq_s + 1], inv)
+        return time.perf_counter() - t, e, (rows, resid, inv), ref
 
-    dt, e, _ = run(4)
-    nq_s = int(min(len(offs) - 1, max(4, 4 * budget_s / max(dt, 1e-6))))
-    dt, e, enc = run(nq_s)
+    dt, e, _, _ = run(4)
+    # as many leading lists as fit the time budget at the measured rate per pair
+    want = budget_s * max(e, 1) / max(dt, 1e-6)
+    nq_s = int(min(len(offs) - 1, max(4, np.searchsorted(offs, want) - 1)))
+    dt, e, enc, ref = run(nq_s)
     out = {"value": e / dt, "unit": "distances/s", "cores": 1, "kind": "oracle",
            "sample": "first %d queries' candidate lists (%d pairs) of the same workload, %s level, "
                      "binary64 scalar C on one host core, %.1f s" %
                      (nq_s, e, "full" if level == 2 else "primary", dt)}
     out["all_cores"] = cpu_baseline_threads(fmt, metric, level, Q, means, offs, nq_s, enc)
-    return out
+    return out, (nq_s, enc, ref)
+
+
+def sample_parity(fmt, metric, level, Q, means, offs, ids, sample, dist, topk_ids, topk_dist, k):
+    """The timed launch's outputs on the oracle's sample (the first queries'
+    lists, values the CPU baseline computed): every value within the test
+    suite's tolerance of the oracle's, every top-k list equal to the oracle's
+    up to near-ties."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import oracle
+    from lvq_check import check_topk, pair_tolerance
+    nq_s, (rows, resid, inv), ref = sample
+    e = int(offs[nq_s])
+    xh = oracle.reconstruct(fmt, rows, resid, means, level)
+    mrow = np.asarray(means, np.float64)[oracle.unpack(fmt, rows)[3]]
+    qi = np.repeat(np.arange(nq_s), np.diff(offs[:nq_s + 1]))
+    tol = np.empty(e)
+    for a in range(0, e, 1 << 16):
+        c = slice(a, a + (1 << 16))
+        tol[c] = pair_tolerance(metric, Q, xh[inv[c]], mrow[inv[c]], qi[c])
+    got = np.asarray(dist[:e], np.float64)
+    ratio = np.abs(got - ref) / np.maximum(tol, 1e-300)
+    bad_topk = 0
+    for i in range(nq_s):
+        a, b = int(offs[i]), int(offs[i + 1])
+        try:
+            check_topk(metric, topk_ids[i], topk_dist[i], ids[a:b], ref[a:b], tol[a:b], k)
+        except AssertionError:
+            bad_topk += 1
+    ok = bool(np.all(np.abs(got - ref) <= tol)) and bad_topk == 0
+    return {"pairs_checked": e, "lists_checked": nq_s, "max_err_over_tolerance": float(ratio.max()),
+            "topk_lists_failed": bad_topk, "ok": ok,
+            "note": "the timed launch's values and top-%d lists on the oracle's sample, tolerance of "
+                    "tests/lvq_check.py" % k}
 
 
 def host_cpu_model() -> str:
@@ -381,9 +416,10 @@ def bench_c2(args):
     ms_step, k_ms = timed(step, args.steps, args.warmup, ix)
     assert ix.sync() == 0
     pairs = int(ids.shape[0])
-    per_pair = (384 + 768 + 12 + 4 + 4) if level == L.LVQ_FULL else (384 + 8 + 4 + 4)
+    # codes (+ residual codes) + l, Delta + slot id read + value written
+    per_pair = (384 + 768 + 8 + 4 + 4) if level == L.LVQ_FULL else (384 + 8 + 4 + 4)
     achieved = per_pair * pairs / (k_ms / 1000.0) / 1e9
-    traffic = read_traffic(pairs, tile) if level == L.LVQ_FULL and args.align == 32 else None
+    traffic = read_traffic("k_cand_c2_%s_traffic" % args.level, pairs, tile) if args.align == 32 else None
     log("step %.3f ms, kernel %.3f ms, %.1f GB/s algorithmic" % (ms_step, k_ms, achieved))
     ceil = read_ceilings(ix, idd, pairs, level, per_pair, k_ms)
     log("streaming read %.0f GB/s; the same gather without arithmetic %.3f ms (kernel at %.0f%% of it)" %
@@ -398,12 +434,19 @@ def bench_c2(args):
                 "kernel": "k_cand (candidate-list similarity + fused top-k)", "kernel_ms": k_ms,
                 "algorithmic_bytes_per_pair": per_pair, "ceilings": ceil},
                encode=encode_roofline(warm_encode_ms(ix, X, dev), n, 768, ix.row_bytes, ix.resid_bytes, enc_ms))
+    dist_h, ti_h, td_h = dist.cpu().numpy(), ti.cpu().numpy(), td.cpu().numpy()
+    ix.close()
+    del qd, od, idd, dist, ti, td
     if not args.no_cpu_baseline:
         import oracle
         log("timing the oracle on a host-core sample")
         fmt = oracle.Format(768, 4, 8, oracle.TURBO)
-        out["cpu_baseline"] = cpu_baseline_lists(fmt, oracle.IP, level, X, Q, mu, offs, ids)
-    ix.close()
+        out["cpu_baseline"], sample = cpu_baseline_lists(fmt, oracle.IP, level, X, Q, mu, offs, ids)
+        out["parity"] = sample_parity(fmt, oracle.IP, level, Q, mu, offs, ids, sample, dist_h, ti_h, td_h, 10)
+        log("parity on the oracle sample: %s" % json.dumps(out["parity"]))
+    del X
+    if args.serving:
+        out["serving"] = serving_summary(args)
     return out
 
 
@@ -530,10 +573,25 @@ def bench_c3(args):
                 "algorithmic_bytes_per_pair": per_pair, "ceilings": ceil},
                ms_per_step_eager=ms_eager)
     out["encode"] = encode_roofline(warm_encode_ms(ix, X, dev), n, d, ix.row_bytes, ix.resid_bytes, enc_ms, n_means=M)
+    out["roofline"]["traffic"] = read_traffic("k_cand_c3_traffic", pairs, tile)
+    # load balance inside a list: a workgroup scores blocks of 256 / lanes
+    # candidates (lanes per candidate of the tile shape); the last block of a
+    # list leaves the lanes past its end idle
+    lanes = L.lvq_tile_shape(tile)[0]
+    blk = 256 // lanes
+    lens = np.diff(offs)
+    out["load_balance"] = {"busy_lane_fraction": pairs / float((np.ceil(lens / blk) * blk).sum()),
+                           "candidates_per_block": blk, "lists": nq,
+                           "note": "listed pairs / lane slots of the blocks the lists occupy; lists are taken "
+                                   "longest first from one work counter by the persistent workgroups"}
+    dist_h, ti_h, td_h = dist.cpu().numpy(), ti.cpu().numpy(), td.cpu().numpy()
     if not args.no_cpu_baseline:
         import oracle
         fmt = oracle.Format(d, 8, 0)
-        out["cpu_baseline"] = cpu_baseline_lists(fmt, oracle.L2, oracle.PRIMARY, X, Q, means, offs, ids)
+        out["cpu_baseline"], sample = cpu_baseline_lists(fmt, oracle.L2, oracle.PRIMARY, X, Q, means, offs, ids)
+        out["parity"] = sample_parity(fmt, oracle.L2, oracle.PRIMARY, Q, means, offs, ids, sample, dist_h, ti_h,
+                                      td_h, 10)
+        log("parity on the oracle sample: %s" % json.dumps(out["parity"]))
     ix.close()
     return out
 
@@ -559,7 +617,10 @@ def bench_c4(args):
     assert ix.sync() == 0
     qf = torch.from_numpy(Q).to(dev)
     res = {}
-    for name, q in (("bf16", qf.to(torch.bfloat16)), ("fp16", qf.to(torch.float16)), ("fp32", qf)):
+    forms = [f for f in (("bf16", torch.bfloat16), ("fp16", torch.float16), ("fp32", torch.float32))
+             if f[0] in args.forms.split(",")]
+    for name, tdt in forms:
+        q = qf.to(tdt)
         ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
         dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
         prec = {"bf16": L.LVQ_BF16, "fp16": L.LVQ_FP16, "fp32": L.LVQ_FP32}[name]
@@ -574,7 +635,7 @@ def bench_c4(args):
         res[name] = (ms, k_ms, ids.cpu().numpy(), dist.cpu().numpy())
         log("%s: step %.2f ms, kernel %.2f ms" % (name, ms, k_ms))
     # recall@100 of every form on a query sample against the exact float top-100
-    ns = 20
+    ns = 100
     Qd = Q[:ns]
     gt = exact_topk(1, Qd, X, k)
     acc = {}
@@ -1322,6 +1383,129 @@ def c5_load(sv, batches, arrivals, waiter_out):
     return float(np.mean(lag)) if lag else 0.0
 
 
+def serving_summary(args, n0=1_000_000, load=0.8, n_sat=60, n_lat=120):
+    """A bounded run of the serving workload for the default line: the C5
+    store (10^6 LVQ-4x8 Turbo vectors of d = 768 from 64 unit clusters, 16
+    means from k-means on a 100k sample) served in batches of U{1..512}
+    queries by the request server in two forms -- exhaustive two-level top-10
+    on the FP32 vector path and on the matrix cores (bf16) -- while a thread
+    runs update rounds at a constant store size (delete 10^4 live vectors,
+    insert 10^4 drifted ones, consolidate; the paper's constant-size streaming
+    protocol, so that both forms are measured over the same row count).  Per form: the saturation rate of a burst
+    of batches, p50 / p99 latency under Poisson arrivals at `load` times that
+    rate, and recall@10 of 200 queries against the exact float top-10 of the
+    live vectors; beside them the two-stage form (first-level bf16 top-K'
+    re-ranked with both levels) for K' in {64, 256, 1024}."""
+    import threading
+
+    import torch
+
+    import paper_2402_02044_amd as L
+    import synth
+    K, MAXB, SLOTS, ins = 10, 512, 8, 10_000
+    dev = torch.device("cuda:0")
+    t_start = time.perf_counter()
+    log("serving: generating %d x 768 C5 vectors, 16 means" % n0)
+    X0 = synth.vectors("C5", synth.S_BASE, 0, n0)
+    means = host_kmeans(X0[synth.sample_indices(5, n0, 100_000)], 16, 25, 5)
+    st = C5Store(L, X0, means, n0 + 8 * ins + 4096, dev)
+    del X0
+    torch.cuda.synchronize()
+    forms = {"fp32": L.LVQ_FP32, "bf16": L.LVQ_BF16}
+    servers = {f: L.Server(st.ix, slots=SLOTS, max_batch=MAXB, k=K, k_first=64, precision=p,
+                           scan_level=L.LVQ_FULL) for f, p in forms.items()}
+    qpool = synth.c5_points(synth.S_QUERY, 1, 4096, part=1)
+    g = synth.rng(5, synth.S_ARRIVAL, 1)
+
+    def make_batches(nb):
+        sizes = g.integers(1, MAXB + 1, nb)
+        starts = g.integers(0, qpool.shape[0] - MAXB, nb)
+        return [qpool[a:a + s] for a, s in zip(starts, sizes)]
+
+    stop = threading.Event()
+    rounds = []
+
+    def updates():
+        r = 0
+        while not stop.is_set() and r < 20:
+            t = time.perf_counter()
+            cand = np.flatnonzero(st.live)
+            st.delete(np.sort(synth.rng(5, synth.S_DELETE, 1000 + r).choice(cand, ins, replace=False)))
+            st.insert(synth.c5_points(synth.S_INSERT, r + 1, ins))
+            freed = st.consolidate()
+            rounds.append({"round": r, "live": int(st.live.sum()), "freed": int(freed),
+                           "update_ms": (time.perf_counter() - t) * 1000.0})
+            r += 1
+            stop.wait(0.3)
+
+    for f in forms:   # warm-up
+        c5_load(servers[f], make_batches(8), None, [])
+    upd = threading.Thread(target=updates)
+    upd.start()
+    out = {}
+    try:
+        for f in forms:
+            sv = servers[f]
+            rows0 = st.ix.stats().live_estimate
+            got = []
+            c5_load(sv, make_batches(n_sat), None, got)
+            qps = sum(nq for nq, _ in got) / (max(i.t_done for _, i in got) - min(i.t_submit for _, i in got))
+            arr = np.cumsum(g.exponential((MAXB + 1) / 2.0 / (load * qps), n_lat))
+            got = []
+            c5_load(sv, make_batches(n_lat), arr, got)
+            lat = np.array([(i.t_done - i.t_submit) * 1000.0 for _, i in got])
+            span = max(i.t_done for _, i in got) - min(i.t_submit for _, i in got)
+            out[f] = {"qps_saturation": qps, "rows_at_saturation": int(rows0),
+                      "load": load, "achieved_qps": sum(nq for nq, _ in got) / span,
+                      "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                      "peak_in_flight": sv.stats().peak_in_flight}
+            log("serving %s: saturation %.0f q/s over %d rows; at %d%% load p50 %.2f ms, p99 %.2f ms" %
+                (f, qps, rows0, load * 100, out[f]["p50_ms"], out[f]["p99_ms"]))
+    finally:
+        stop.set()
+        upd.join()
+    # recall at the final state
+    Qr = synth.c5_points(synth.S_QUERY, 1, 200, part=0)
+    gt = st.groundtruth(Qr)
+    for f in forms:
+        t = servers[f].submit(Qr)
+        ids, _, _ = servers[f].wait(t, Qr.shape[0])
+        out[f]["recall_at_10"] = recall_at_k(ids, gt)
+    for sv in servers.values():
+        sv.close()
+    qd = torch.from_numpy(Qr).to(dev)
+    rerank = {}
+    for kf in (64, 256, 1024):
+        # the matrix-core scan's per-query buffers hold up to a few hundred
+        # keys; larger K' take the first-level FP32 scan
+        cid = None
+        for prec, tdt in (("bf16", torch.bfloat16), ("fp32", torch.float32)):
+            try:
+                cid, _ = st.ix.topk(qd.to(tdt), kf, level=L.LVQ_PRIMARY)
+                break
+            except L.LVQError as e:
+                if e.code != L.LVQ_ERR_UNSUPPORTED:
+                    raise
+        if cid is None:
+            rerank[str(kf)] = None
+            continue
+        offs = torch.arange(0, (Qr.shape[0] + 1) * kf, kf, dtype=torch.int64, device=dev)
+        _, ti, _ = st.ix.distances(qd, offs, cid.reshape(-1), level=L.LVQ_FULL, k=K, want_dist=False)
+        rerank[str(kf)] = {"first_level_scan": prec, "recall_at_10": recall_at_k(ti.cpu().numpy(), gt)}
+    assert st.ix.sync() == 0
+    st.ix.close()
+    log("serving: recall@10 fp32 %.3f, bf16 %.3f; first-level top-K' re-ranked: %s" %
+        (out["fp32"]["recall_at_10"], out["bf16"]["recall_at_10"], rerank))
+    out["rerank_first_level_top_kprime"] = rerank
+    out["update_rounds"] = rounds
+    out["workload"] = ("C5 store: LVQ-4x8 Turbo inner product, d=768, %d vectors from 64 unit clusters, 16 means; "
+                       "request server, %d slots, batches of U{1..%d} queries, exhaustive two-level top-%d; "
+                       "update rounds (delete %d live, insert as many, consolidate) beside the load; recall@10 of "
+                       "200 queries against the exact float top-10 of the live vectors" % (n0, SLOTS, MAXB, K, ins))
+    out["seconds"] = time.perf_counter() - t_start
+    return out
+
+
 def bench_c5(args):
     import threading
 
@@ -1524,6 +1708,7 @@ def main():
     ap.add_argument("--sat-batches", type=int, default=60, help="c5: batches of each saturation burst")
     ap.add_argument("--lat-batches", type=int, default=120, help="c5: batches of each latency phase")
     ap.add_argument("--level", default="full", choices=["full", "primary"])
+    ap.add_argument("--forms", default="bf16,fp16,fp32", help="c4: query precisions to run (comma list)")
     ap.add_argument("--align", type=int, default=32)
     ap.add_argument("--n", type=int, default=0, help="override the store size (testing)")
     ap.add_argument("--nq", type=int, default=0, help="override the query count (testing)")
@@ -1533,6 +1718,8 @@ def main():
     ap.add_argument("--retune", action=argparse.BooleanOptionalAction, default=True,
                     help="c2, c3: run the library's autotuner on this box before timing (default); --no-retune "
                          "takes the shape recorded in the tuning cache")
+    ap.add_argument("--serving", action=argparse.BooleanOptionalAction, default=True,
+                    help="c2: add a bounded serving run (the C5 store, fp32 and bf16 two-level forms) to the line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -1558,7 +1745,11 @@ def main():
     fn = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
           "layouts": bench_layouts, "probe": bench_probe, "means": bench_means,
           "graph": bench_graph, "graph_stream": bench_graph_stream}[args.workload]
-    print(json.dumps(fn(args)), flush=True)
+    out = fn(args)
+    print(json.dumps(out), flush=True)
+    if not out.get("parity", {}).get("ok", True):
+        log("the timed launch's outputs disagree with the oracle on its sample")
+        sys.exit(3)
 
 
 if __name__ == "__main__":
