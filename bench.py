@@ -300,7 +300,7 @@ def cpu_baseline_lists(fmt, metric, level, X, Q, means, offs, ids, budget_s=12.0
 
     dt, e, _, _ = run(4)
     # as many leading lists as fit the time budget at the measured rate per pair
-    want = budget_s * max(e, 1) / max(dt, 1e-6)
+    want = min(budget_s * max(e, 1) / max(dt, 1e-6), 4e6)
     nq_s = int(min(len(offs) - 1, max(4, np.searchsorted(offs, want) - 1)))
     dt, e, enc, ref = run(nq_s)
     out = {"value": e / dt, "unit": "distances/s", "cores": 1, "kind": "oracle",
