@@ -264,7 +264,7 @@ def topk_exhaustive(fmt: Format, metric, level, Q, rows, resid, means, k, live=N
     return out_s, out_v
 
 
-def _walk(score, metric, graph, entries, W, k, live=None):
+def _walk(score, metric, graph, entries, W, k, live=None, tol=None, margins=None):
     """The steps of Alg. 1 around a scoring function (slots -> binary64
     values): the candidate set starts as the entry nodes; while it holds an
     unexplored node, the closest one is explored and its out-neighbours join
@@ -273,44 +273,64 @@ def _walk(score, metric, graph, entries, W, k, live=None):
     rows are traversed but left out of the result (App. A, lazy deletes).
 
     A node proposed once is never proposed again: the W-th best rank of the
-    set never worsens, so a node cut from the set could not re-enter it."""
+    set never worsens, so a node cut from the set could not re-enter it.
+
+    With `tol` (slot -> error bound of an approximate score) and a list
+    `margins`, every decision that compares two scores appends its margin,
+    |a - b| - (tol(a) + tol(b)): the choice of the next node (the closest
+    unexplored one against the runner-up), each cut of the set (its W-th
+    against the (W+1)-th) and the result (its k-th against the next live one).
+    A walk all of whose margins are positive is taken by any evaluation of
+    the scores within those bounds."""
 
     def rank(item):
         slot, v = item
         return (v if metric == L2 else -v, slot)
+
+    def note(a, b):
+        if margins is not None:
+            margins.append(abs(a[1] - b[1]) - (tol(a[0]) + tol(b[0])))
 
     entries = sorted(set(int(e) for e in entries))
     cand = dict(zip(entries, score(entries)))
     seen = set(entries)
     explored = set()
     while True:
-        open_ = [it for it in cand.items() if it[0] not in explored]
+        open_ = sorted((it for it in cand.items() if it[0] not in explored), key=rank)
         if not open_:
             break
-        x = min(open_, key=rank)[0]
+        if len(open_) > 1:
+            note(open_[0], open_[1])
+        x = open_[0][0]
         explored.add(x)
         new = [int(y) for y in graph[x] if y >= 0 and int(y) not in seen]
         seen.update(new)
         if new:
             cand.update(zip(new, score(new)))
         if len(cand) > W:
-            cand = dict(sorted(cand.items(), key=rank)[:W])
-    out = [it for it in sorted(cand.items(), key=rank) if live is None or live[it[0]]][:k]
+            ranked = sorted(cand.items(), key=rank)
+            note(ranked[W - 1], ranked[W])
+            cand = dict(ranked[:W])
+    ranked = [it for it in sorted(cand.items(), key=rank) if live is None or live[it[0]]]
+    if len(ranked) > k:
+        note(ranked[k - 1], ranked[k])
+    out = ranked[:k]
     return (np.array([s for s, _ in out], np.int32), np.array([v for _, v in out], np.float64), len(explored))
 
 
-def greedy_search(fmt: Format, metric, level, q, rows, resid, means, graph, entries, W, k, live=None):
+def greedy_search(fmt: Format, metric, level, q, rows, resid, means, graph, entries, W, k, live=None, tol=None,
+                  margins=None):
     """Greedy graph search (Alg. 1) for one query over LVQ rows, with the
     similarities of ``distances`` at the given level.  graph: n x R slots, -1
     for no edge.  Returns (slots, values) of length <= k, best first, and the
-    number of nodes explored."""
+    number of nodes explored.  tol / margins: as ``_walk``."""
     q = np.asarray(q, np.float32)[None, :]
 
     def score(slots):
         slots = np.asarray(slots, np.int32)
         return distances(fmt, metric, level, q, rows, resid, means, np.array([0, slots.size], np.int64), slots)
 
-    return _walk(score, metric, graph, entries, W, k, live)
+    return _walk(score, metric, graph, entries, W, k, live, tol, margins)
 
 
 def float_sim(metric, a, b) -> float:
@@ -331,7 +351,7 @@ def greedy_search_float(metric, q, X, graph, entries, W, k):
     return _walk(score, metric, graph, entries, W, k)
 
 
-def robust_prune(metric, X, p, cand, current, alpha, R):
+def robust_prune(metric, X, p, cand, current, alpha, R, tol=None, margins=None):
     """Neighbourhood pruning (Alg. 2) of node p over float vectors X.
 
     The candidates are the given ones and p's current out-neighbours, without
@@ -341,10 +361,20 @@ def robust_prune(metric, X, p, cand, current, alpha, R):
     similar as p is removed: for the inner product alpha * <x*, x'> >=
     <p, x'>, for L2 (similarity = the squared distance, smaller is closer)
     alpha * |x* - x'|^2 <= |p - x'|^2.  Returns the new out-neighbours in
-    selection order."""
+    selection order.
+
+    With `tol` ((a, b, similarity) -> error bound of an approximate
+    similarity of vectors a and b) and a list `margins`, the decisions append
+    their margins: the ranking of the candidates by similarity to p (each
+    adjacent pair, |s - s'| - (tol + tol')) and every test of the rule
+    (|alpha t - s| - (alpha tol_t + tol_s)).  A pruning all of whose margins
+    are positive is reproduced by any evaluation within those bounds."""
     C = sorted(set(int(c) for c in list(cand) + list(current) if c >= 0) - {int(p)})
     sims = {c: float_sim(metric, X[p], X[c]) for c in C}
     order = sorted(C, key=lambda c: (sims[c] if metric == L2 else -sims[c], c))
+    if margins is not None:
+        for a, b in zip(order, order[1:]):
+            margins.append(abs(sims[a] - sims[b]) - (tol(p, a, sims[a]) + tol(p, b, sims[b])))
     out = []
     while order:
         xs = order.pop(0)
@@ -355,6 +385,8 @@ def robust_prune(metric, X, p, cand, current, alpha, R):
         for c in order:
             t = float_sim(metric, X[xs], X[c])
             removed = alpha * t <= sims[c] if metric == L2 else alpha * t >= sims[c]
+            if margins is not None:
+                margins.append(abs(alpha * t - sims[c]) - (alpha * tol(xs, c, t) + tol(p, c, sims[c])))
             if not removed:
                 keep.append(c)
         order = keep
@@ -388,6 +420,62 @@ def vamana_insert(metric, X, graph, nodes, entry, W, alpha, R):
                 put(y, ny + [x])
             else:
                 put(y, robust_prune(metric, X, y, [x], ny, alpha, R))
+    return graph
+
+
+def vamana_update(metric, X, graph, order, in_graph, entry, W, alpha, R, passes, max_batch):
+    """The update routine of App. A run in batches, as the batched reading of
+    the construction takes it: the rows of the nodes of `order` are cleared;
+    then, `passes` times (alpha = 1 first when there are two passes), the
+    nodes are taken in batches of at most max_batch (and, in the first pass,
+    at most the number of nodes already in the graph: in_graph plus the
+    nodes processed so far, at least one).  Every node of a batch finds its
+    W nearest by Alg. 1 from `entry` in the graph as it was before the batch
+    and prunes them with its current out-neighbours (Alg. 2) into its new
+    out-neighbours; then each node y named by the batch's new rows takes all
+    of its new sources at once: their union with N(y) if it holds at most R
+    nodes, else Alg. 2 over the sources and N(y).  With max_batch = 1 this is
+    vamana_insert / vamana_build.  In place on graph (n x R, -1 padded)."""
+    n = X.shape[0]
+    order = [int(v) for v in order]
+
+    def row(y):
+        return [int(v) for v in graph[y] if v >= 0]
+
+    def put(y, ns):
+        graph[y] = -1
+        graph[y, :len(ns)] = ns
+
+    for v in order:
+        graph[v] = -1
+    count = len(order)
+    B = min(max_batch, count)
+    for pass_ in range(passes):
+        a = 1.0 if (passes == 2 and pass_ == 0) else alpha
+        b = 0
+        while b < count:
+            now = in_graph + b if pass_ == 0 else n
+            bs = min(B, max(1, now), count - b)
+            batch = order[b:b + bs]
+            before = graph.copy()
+            new_rows = []
+            for x in batch:
+                found, _, _ = greedy_search_float(metric, X[x], X, before, [entry], W, W)
+                new_rows.append(robust_prune(metric, X, x, found, [int(v) for v in before[x] if v >= 0], a, R))
+            for x, nx in zip(batch, new_rows):
+                put(x, nx)
+            sources = {}
+            for x, nx in zip(batch, new_rows):
+                for y in nx:
+                    sources.setdefault(y, []).append(x)
+            for y, S in sources.items():
+                ny = row(y)
+                union = ny + [v for v in dict.fromkeys(S) if v not in ny and v != y]
+                if len(union) <= R:
+                    put(y, union)
+                else:
+                    put(y, robust_prune(metric, X, y, S, ny, a, R))
+            b += bs
     return graph
 
 

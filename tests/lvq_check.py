@@ -25,6 +25,30 @@ def pair_tolerance(metric, Q, xhat, mean_rows, q_index):
     return 1e-4 * r + 1e-7 * scale
 
 
+def rounding_bound(fmt, metric, level, q, rows, resid, means):
+    """A realistic bound on the binary32 rounding error of the similarity of
+    query q to every row, for deciding whether two oracle scores are too
+    close for a binary32 evaluation to be sure to order them alike: 4 sqrt(d)
+    unit roundoffs (2^-24) of the magnitudes summed, sum_j (|q_j - mu_j| +
+    |x_hat_j - mu_j|)^2 for L2 (the direct form's terms) and
+    sum_j |q_j| (|mu_j| + |x_hat_j - mu_j|) for IP (the terms of the
+    identity).  Rounding errors of d terms grow like sqrt(d) in practice; the
+    worst case, d, is what the acceptance tolerance covers."""
+    q = np.asarray(q, np.float64)
+    xh = reconstruct_all(fmt, rows, resid, means, level)
+    mu = np.asarray(means, np.float64)[oracle.unpack(fmt, rows)[3]]
+    xr = np.abs(xh - mu)
+    if metric == oracle.IP:
+        T = (np.abs(q)[None, :] * (np.abs(mu) + xr)).sum(1)
+    else:
+        T = ((np.abs(q[None, :] - mu) + xr) ** 2).sum(1)
+    return 4.0 * np.sqrt(fmt.dim) * 2.0 ** -24 * T
+
+
+def reconstruct_all(fmt, rows, resid, means, level):
+    return oracle.reconstruct(fmt, rows, resid, means, level)
+
+
 def pair_reference(fmt, metric, level, Q, rows, resid, means, offsets, ids, chunk=1 << 15):
     """Oracle values and tolerances for every listed pair (the tolerances are
     evaluated in chunks of pairs, so long lists need no pairs x d array)."""

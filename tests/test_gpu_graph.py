@@ -3,11 +3,14 @@ Alg. 1.
 
 * Complete graph and a window holding every node: the result is the
   exhaustive top-k (oracle values within tolerance, ranking as check_topk).
-* A k-NN graph with random long edges: per query the GPU follows the
-  oracle's walk -- same result and the same number of explored nodes -- for
-  nearly every query (a near-tie decided differently in binary32 and binary64
-  may send a walk elsewhere); every returned node is live, its value matches
-  the oracle's within tolerance, and the results are ordered.
+* A k-NN graph with random long edges: the oracle's walk records the margin
+  of each of its decisions (the next node, each cut of the set, the result)
+  against the similarity tolerance of the two scores compared; every query
+  whose decisions all clear their tolerances must follow the oracle's walk
+  exactly on the GPU (same result, same number of explored nodes).  Only a
+  walk through a near-tie may go elsewhere; for every query each returned
+  node is live, its value matches the oracle's within tolerance, and the
+  results are ordered.
 * Deleted rows are traversed but never returned.
 """
 import numpy as np
@@ -15,7 +18,7 @@ import pytest
 
 import oracle
 import synth
-from lvq_check import check_topk, check_values, pair_reference
+from lvq_check import check_topk, check_values, pair_reference, rounding_bound
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -104,23 +107,71 @@ def test_walks_follow_the_oracle(L, d, b1, layout, metric, M, W):
                                           torch.from_numpy(entries).cuda(), W, k)
     assert ix.sync() == 0
     ids, dist, explored = ids.cpu().numpy(), dist.cpu().numpy(), explored.cpu().numpy()
-    same = 0
+    decisive = 0
     for i in range(nq):
+        tol_i = rounding_bound(fmt, metric, oracle.PRIMARY, Q[i], rows, None, means)
+        margins = []
         os_, ov, ne = oracle.greedy_search(fmt, metric, oracle.PRIMARY, Q[i], rows, None, means, graph, entries, W,
-                                           k, live)
+                                           k, live, tol=lambda s_: tol_i[s_], margins=margins)
         got = ids[i][ids[i] >= 0]
         assert live[got].all(), "a deleted row was returned"
         assert not np.isin(got, dead).any()
         assert 1 <= explored[i, 0] <= explored[i, 1]   # a node is scored before it is explored
-        if np.array_equal(got, os_) and explored[i, 0] == ne:
-            same += 1
+        if min(margins, default=1.0) > 0:
+            decisive += 1
+            np.testing.assert_array_equal(got, os_, err_msg="query %d: a decisive walk went elsewhere" % i)
+            assert explored[i, 0] == ne, "query %d explored %d nodes, the oracle %d" % (i, explored[i, 0], ne)
         # every returned value is the oracle's for that node
         offs = np.array([0, got.size], np.int64)
         ref, tol = pair_reference(fmt, metric, oracle.PRIMARY, Q[i:i + 1], rows, None, means, offs, got)
         check_values(dist[i][:got.size], ref, tol, "query %d" % i)
         srt = dist[i][:got.size] if metric == oracle.L2 else -dist[i][:got.size]
         assert np.all(np.diff(srt) >= 0), "not ordered"
-    assert same >= int(0.9 * nq), "only %d of %d walks follow the oracle" % (same, nq)
+    # the decisive walks are a good share of them (else this test would check little)
+    assert decisive >= nq // 8, "only %d of %d walks clear every bound" % (decisive, nq)
+    ix.close()
+
+
+@pytest.mark.parametrize("d,b1,layout,metric", [(64, 8, oracle.SEQUENTIAL, oracle.L2),
+                                                 (64, 8, oracle.SEQUENTIAL, oracle.IP),
+                                                 (128, 4, oracle.TURBO, oracle.L2)])
+def test_walks_equal_the_oracle_on_exact_rows(L, d, b1, layout, metric):
+    """Integer vectors spanning exactly 0 .. 2^B - 1 in every row (mean 0):
+    Delta = 1, l = 0, the codes are the coordinates, so every similarity is
+    an integer that binary32 computes exactly.  Every walk must then be the
+    oracle's: same nodes, same values, same explored count, with the many
+    exact ties ordered by the lower node on both sides."""
+    g = synth.rng(8750 + d, b1 + metric)
+    n, nq, k, W = 1500, 40, 10, 24
+    top = (1 << b1) - 1
+    X = g.integers(0, top + 1, (n, d)).astype(np.float32)
+    X[:, 0], X[:, 1] = 0, top
+    Q = g.integers(0, top + 1, (nq, d)).astype(np.float32)
+    means = np.zeros((1, d), np.float32)
+    fmt = oracle.Format(d, b1, 0, layout)
+    rows, _, _ = oracle.encode_rows(fmt, X, means)
+    hdr = oracle.unpack(fmt, rows)
+    assert (hdr[0] == 0).all() and (hdr[1] == 1).all() and (hdr[4] == X.astype(np.uint8)).all()
+    graph = _knn_graph(g, X, 12, 4)
+    entries = np.array([0, 700, 1400], np.int32)
+    ix = L.Index(d, b1, 0, metric, layout, capacity=n, means=means)
+    ix.insert(torch.from_numpy(X).cuda())
+    live = np.ones(n, bool)
+    dead = np.sort(g.choice(n, 150, replace=False)).astype(np.int32)
+    ix.delete(torch.from_numpy(dead).cuda())
+    live[dead] = False
+    assert ix.sync() == 0
+    ids, dist, explored = ix.graph_search(torch.from_numpy(Q).cuda(), torch.from_numpy(graph).cuda(),
+                                          torch.from_numpy(entries).cuda(), W, k)
+    assert ix.sync() == 0
+    ids, dist, explored = ids.cpu().numpy(), dist.cpu().numpy(), explored.cpu().numpy()
+    for i in range(nq):
+        os_, ov, ne = oracle.greedy_search(fmt, metric, oracle.PRIMARY, Q[i], rows, None, means, graph, entries, W,
+                                           k, live)
+        got = ids[i][ids[i] >= 0]
+        np.testing.assert_array_equal(got, os_, err_msg="query %d" % i)
+        np.testing.assert_array_equal(dist[i][:got.size].astype(np.float64), ov, err_msg="query %d values" % i)
+        assert explored[i, 0] == ne, "query %d explored %d nodes, the oracle %d" % (i, explored[i, 0], ne)
     ix.close()
 
 

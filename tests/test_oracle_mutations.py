@@ -45,11 +45,14 @@ PY_MUTATIONS = {
                               "for c in list(cand) if c >= 0)"),
     "prune_ties_to_higher": ("key=lambda c: (sims[c] if metric == L2 else -sims[c], c))",
                              "key=lambda c: (sims[c] if metric == L2 else -sims[c], -c))"),
-    "walk_cut_off_by_one": ("if len(cand) > W:\n            cand = dict(sorted(cand.items(), key=rank)[:W])",
-                            "if len(cand) > W + 1:\n            cand = dict(sorted(cand.items(), key=rank)[:W + 1])"),
-    "walk_explores_worst": ("x = min(open_, key=rank)[0]", "x = max(open_, key=rank)[0]"),
-    "walk_returns_deleted": ("if live is None or live[it[0]]][:k]", "][:k]"),
-    "insert_no_reverse_edges": ("        for y in nx:\n", "        for y in []:\n"),
+    "walk_cut_off_by_one": ("cand = dict(ranked[:W])", "cand = dict(ranked[:W + 1])"),
+    "walk_explores_worst": ("x = open_[0][0]", "x = open_[-1][0]"),
+    "walk_returns_deleted": ("if live is None or live[it[0]]]", "]"),
+    "insert_no_reverse_edges": ("        for y in nx:\n            ny = row(y)\n", "        for y in []:\n            ny = row(y)\n"),
+    "batched_first_pass_unbounded": ("bs = min(B, max(1, now), count - b)", "bs = min(B, count - b)"),
+    "batched_overflow_truncated": ("                    put(y, robust_prune(metric, X, y, S, ny, a, R))",
+                                   "                    put(y, union[:R])"),
+    "batched_second_pass_alpha_one": ("a = 1.0 if (passes == 2 and pass_ == 0) else alpha", "a = 1.0"),
     "delete_rows_kept": ("    out[deleted] = -1\n    return out", "    return out"),
     "delete_never_prunes": ("if len(cand) > R else cand", "if False else cand"),
 }

@@ -160,3 +160,96 @@ def test_delete_consolidation_keeps_search_working():
     hit = sum(int(oracle.greedy_search_float(oracle.L2, X[i], X, out, [entry], 20, 1)[0][0] == i)
               for i in np.flatnonzero(~deleted))
     assert hit >= int(0.98 * (~deleted).sum())
+
+
+def test_batched_update_with_batches_of_one_is_the_sequential_routine():
+    # the batched reading of App. A's construction: with max_batch = 1 every
+    # batch is one node, which searches the graph left by the node before it
+    g = synth.rng(8906, 0)
+    n, R, W = 150, 6, 12
+    X = g.standard_normal((n, 3)).astype(np.float32)
+    entry = int(np.argmin(((X - X.mean(0)) ** 2).sum(1)))
+    want = oracle.vamana_build(oracle.L2, X, entry, W, 1.2, R)
+    got = np.full((n, R), -1, np.int32)
+    order = [entry] + [i for i in range(n) if i != entry]
+    oracle.vamana_update(oracle.L2, X, got, order, 0, entry, W, 1.2, R, 2, 1)
+    np.testing.assert_array_equal(got, want)
+    # inserts: one pass over new nodes into a graph of the others
+    base = np.full((n, R), -1, np.int32)
+    oracle.vamana_insert(oracle.L2, X, base, order[:120], entry, W, 1.2, R)
+    want = base.copy()
+    oracle.vamana_insert(oracle.L2, X, want, order[120:], entry, W, 1.2, R)
+    got = base.copy()
+    oracle.vamana_update(oracle.L2, X, got, order[120:], 120, entry, W, 1.2, R, 1, 1)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_batched_update_by_hand():
+    # points on a line: node 0 at 0 (entry), 1 at 10, 2 at 4, 3 at 6; the
+    # graph of {0, 1} with R = 1 is 0 -> 1, 1 -> 0.  Nodes 2 and 3 inserted in
+    # one batch (in_graph = 2 allows a batch of 2) both search the pre-batch
+    # graph: 2 finds (0, 1) and keeps 0; 3 finds (1, 0) and keeps 1.  Reverse
+    # edges: node 0 takes source 2, its row {1, 2} exceeds R and is pruned to
+    # the nearer, 2; node 1 likewise ends at 3.  Inserted one at a time, 3
+    # would search the graph already holding 2, never reach 1, and link to 2.
+    X = _line([0, 10, 4, 6])
+    graph = np.array([[1], [0], [-1], [-1]], np.int32)
+    batched = oracle.vamana_update(oracle.L2, X, graph.copy(), [2, 3], 2, 0, 2, 1.2, 1, 1, 2)
+    assert batched[:, 0].tolist() == [2, 3, 0, 1]
+    seq = oracle.vamana_update(oracle.L2, X, graph.copy(), [2, 3], 2, 0, 2, 1.2, 1, 1, 1)
+    assert seq[:, 0].tolist() == [2, 0, 3, 2]
+
+
+def test_batch_members_do_not_link_to_each_other_in_one_pass():
+    g = synth.rng(8907, 0)
+    n, R, W = 200, 8, 16
+    X = g.standard_normal((n, 4)).astype(np.float32)
+    graph = oracle.vamana_build(oracle.L2, X[:150], 0, W, 1.2, R)
+    full = np.full((n, R), -1, np.int32)
+    full[:150] = graph
+    oracle.vamana_update(oracle.L2, X, full, list(range(150, 200)), 150, 0, W, 1.2, R, 1, 50)
+    new = set(range(150, 200))
+    for i in range(150, 200):
+        row = [int(v) for v in full[i] if v >= 0]
+        assert row and not (set(row) & new) and len(row) <= R
+    for i in range(n):
+        row = [int(v) for v in full[i] if v >= 0]
+        assert len(row) == len(set(row)) and i not in row and len(row) <= R
+
+
+def test_decision_margins_by_hand():
+    # pruning 0 over candidates at 1 and 2 on a line (alpha 1): the ranking
+    # gap |1 - 4| = 3, and the rule test of 2 against x* = 1: |1 * 1 - 4| = 3;
+    # error bounds subtract from each margin
+    X = _line([0, 1, 2])
+    m = []
+    assert oracle.robust_prune(oracle.L2, X, 0, [1, 2], [], 1.0, 8, tol=lambda a, b, s: 0.0, margins=m) == [1]
+    assert m == [3.0, 3.0]
+    m = []
+    oracle.robust_prune(oracle.L2, X, 0, [1, 2], [], 1.0, 8, tol=lambda a, b, s: 0.25 * s, margins=m)
+    assert m == [3.0 - 1.25, 3.0 - 1.25]
+    # the walk on a line (d = 1 rows decode exactly): margins are the score
+    # gaps of its decisions, minus the bounds
+    Xl = _line([0, 1, 2, 3, 4])
+    graph = np.array([[1, -1], [0, 2], [1, 3], [2, 4], [3, -1]], np.int32)
+    scores = lambda q: (lambda slots: np.array([(q - float(Xl[s, 0])) ** 2 for s in slots]))
+    m = []
+    out, _, _ = oracle._walk(scores(3.4), oracle.L2, graph, [0], 2, 1, tol=lambda s: 0.0, margins=m)
+    assert out.tolist() == [3] and min(m) > 0
+    m = []
+    oracle._walk(scores(3.5), oracle.L2, graph, [0], 2, 1, tol=lambda s: 0.0, margins=m)
+    assert min(m) == 0.0      # 3 and 4 tie at 0.25: the walk has a decision at zero margin
+
+
+def test_first_pass_batches_never_outgrow_the_graph():
+    # line 0..3, entry 0, R = 2, W = 2, one pass, max_batch = 4.  Batches are
+    # [0], [1], [2, 3]: 0 finds only itself (empty row); 1 links to 0, which
+    # takes 1 back; 2 and 3 both find (1, 0) in the graph {0, 1} and keep 1
+    # (x* = 1 removes 0: 1.2 * 1 <= 4 and <= 9); node 1 then takes sources 2
+    # and 3 beside 0, three > R, pruned: order 0, 2 (both at 1), 3; x* = 0
+    # keeps 2 (1.2 * 4 > 1) and 3 (1.2 * 9 > 4); x* = 2 fills R: {0, 2}.
+    # All four in one batch would search an empty graph and all link to 0.
+    X = _line([0, 1, 2, 3])
+    g = np.full((4, 2), -1, np.int32)
+    oracle.vamana_update(oracle.L2, X, g, [0, 1, 2, 3], 0, 0, 2, 1.2, 2, 1, 4)
+    assert [[int(v) for v in r if v >= 0] for r in g] == [[1], [0, 2], [1], [1]]
