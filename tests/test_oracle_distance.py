@@ -154,3 +154,16 @@ def test_exhaustive_topk_and_recall():
         np.testing.assert_array_equal(np.sort(gt[i]), np.sort(np.argsort(dx, kind="stable")[:10]))
     assert oracle.recall(ts, gt) >= 0.9
     assert oracle.recall(gt, gt) == 1.0
+
+
+def test_recall_hand_value():
+    # Sec. 2.1: k-recall@k = |S n G| / k averaged over queries; order and
+    # padding do not count.  Query 0: {3, 2} of G = {3, 2, 9} found (2 of 3);
+    # query 1: {4} of {7, 8, 4} (1 of 3): (2 + 1) / 6 = 0.5
+    found = np.array([[1, 2, 3], [4, 5, -1]])
+    truth = np.array([[3, 2, 9], [7, 8, 4]])
+    assert oracle.recall(found, truth) == 0.5
+    assert oracle.recall(found[:, ::-1], truth) == 0.5
+    assert oracle.recall(truth[:, ::-1], truth) == 1.0
+    # an id returned twice counts once
+    assert oracle.recall(np.array([[3, 3, 2]]), np.array([[3, 2, 9]])) == 2.0 / 3.0

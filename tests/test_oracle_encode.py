@@ -189,6 +189,54 @@ def test_turbo_worked_example(golden_dir):
         np.testing.assert_array_equal(got, np.array(gold[grp]["dims"]) % 16)
 
 
+def test_turbo8_layout_from_the_lane_remark(golden_dir):
+    """App. B: with 8-bit codes the sixteen lanes of a 64-byte block hold four
+    dimensions each (tests/golden/turbo8_layout.json).  Rows spanning exactly
+    0 .. 255 (mean 0) have Delta = 1 and codes equal to their coordinates, so
+    the bytes of the block can be read against the placements directly."""
+    gold = _golden(golden_dir, "turbo8_layout.json")
+    d = 70                                          # a second block, partly filled
+    g = np.random.default_rng(8000)
+    x = g.integers(0, 256, d).astype(np.float32)
+    x[0], x[1] = 0, 255
+    fmt = oracle.Format(d, 8, 0, oracle.TURBO)
+    rows, _, _ = oracle.encode_rows(fmt, x[None], np.zeros((1, d), np.float32))
+    assert oracle.unpack(fmt, rows)[1][0] == 1.0
+    code = rows[0, 32:]
+    for p in gold["placements"]:
+        if p["dim"] < d:
+            assert code[4 * p["word"] + p["byte"]] == x[p["dim"]], p
+    words = code[:gold["block_bytes"]].view("<u4")
+    assert words.shape[0] == gold["words_per_block"]
+    for grp in gold["groups"]:
+        got = (words >> grp["shift"]) & 0xFF
+        np.testing.assert_array_equal(got, x[grp["first_dim"]:grp["first_dim"] + 16].astype(np.uint32))
+    # the second block holds dimensions 64 .. 69 in byte 0 of words 0 .. 5; the rest is zero
+    blk = code[64:128].reshape(16, 4)
+    np.testing.assert_array_equal(blk[:6, 0], x[64:70].astype(np.uint8))
+    assert blk[6:, 0].sum() == 0 and blk[:, 1:].sum() == 0 and code[128:].sum() == 0
+
+
+def test_eps1_hand_value():
+    """Eq. 4 on rows whose codes are exact: Delta = (u - l) / 15 = 1 for 4-bit
+    codes when the centred vector spans 0 .. 15.  Centred vector (0, 15,
+    7.25, 3.5): codes 0, 15, 7, 4 (round half up: 3.5 -> 4), reconstruction
+    (0, 15, 7, 4), squared error 0.25^2 + 0.5^2 = 0.3125.  Two such vectors,
+    one encoded against mean (1, 1, 1, 1) and one against (40, 40, 40, 40)
+    (their nearest means, Def. 1: squared distances 289.8 against over 4,000),
+    give the sum 0.625 of Eq. 4; a per-vector mean would give 0.3125."""
+    t = np.array([0.0, 15.0, 7.25, 3.5], np.float32)
+    means = np.array([[1, 1, 1, 1], [40, 40, 40, 40]], np.float32)
+    X = np.stack([t + 1.0, t + 40.0]).astype(np.float32)
+    fmt = oracle.Format(4, 4, 0, oracle.SEQUENTIAL)
+    rows, _, _ = oracle.encode_rows(fmt, X, means)
+    l, delta, _, mid, c1, _ = oracle.unpack(fmt, rows)
+    assert mid.tolist() == [0, 1] and (l == 0).all() and (delta == 1).all()
+    assert c1.tolist() == [[0, 15, 7, 4], [0, 15, 7, 4]]
+    assert oracle.eps1(fmt, X, rows, means) == 0.625
+    assert oracle.eps1(fmt, X[:1], rows[:1], means) == 0.3125
+
+
 @pytest.mark.parametrize("d", [1, 96, 130, 200, 768])
 def test_turbo_and_sequential_hold_the_same_codes(d):
     """The permutation changes where codes live, not their values (Sec. 3.1);

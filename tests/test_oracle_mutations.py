@@ -30,6 +30,8 @@ MUTATIONS = {
     "probe_ties_to_higher_mean": ("return ma < mb;", "return ma > mb;"),
     "probe_nan_first": ("if (isnan(sa) != isnan(sb)) return isnan(sb);", "if (isnan(sa) != isnan(sb)) return isnan(sa);"),
     "probe_distance_unsquared": ("float sq = e * e;", "float sq = fabsf(e);"),
+    "eps1_per_vector_mean": ("    free(xhat);\n    return total;\n}", "    free(xhat);\n    return total / (double)n;\n}"),
+    "eps1_absolute_error": ("            total += e * e;", "            total += fabs(e);"),
 }
 
 # mistakes in the graph functions of oracle/__init__.py (Alg. 1, Alg. 2, App. A)
@@ -55,6 +57,8 @@ PY_MUTATIONS = {
     "batched_second_pass_alpha_one": ("a = 1.0 if (passes == 2 and pass_ == 0) else alpha", "a = 1.0"),
     "delete_rows_kept": ("    out[deleted] = -1\n    return out", "    return out"),
     "delete_never_prunes": ("if len(cand) > R else cand", "if False else cand"),
+    "recall_counts_repeats": ("hits = sum(len(set(found[i].tolist()) & set(truth[i].tolist()))",
+                              "hits = sum(sum(int(v in set(truth[i].tolist())) for v in found[i].tolist())"),
 }
 
 
