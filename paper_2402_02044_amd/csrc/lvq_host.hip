@@ -159,7 +159,7 @@ void pin_after_capture(lvq_index *ix, hipStream_t s, bool reads_list)
 {
     if (!ix->capturing) return;
     Workspace &w = ix->ws[s];
-    for (DevBuf *b : {&w.qk, &w.qsum, &w.cm, &w.order, &w.queue, &w.part, &w.q16, &w.gthr, &w.members, &w.moffs,
+    for (DevBuf *b : {&w.qk, &w.qsum, &w.cm, &w.order, &w.queue, &w.part, &w.q16, &w.gthr, &w.mkeys, &w.members, &w.moffs,
                       &w.mcount, &w.mcursor, &w.probe, &w.qoffs, &w.qids})
         if (b->p) b->pinned = true;
     if (reads_list && ix->list_active >= 0) ix->lists[ix->list_active].captured = true;
@@ -435,7 +435,7 @@ int lvq_destroy(lvq_index *ix)
     (void)hipDeviceSynchronize();
     for (auto &kv : ix->ws) {
         Workspace &w = kv.second;
-        for (DevBuf *b : {&w.qk, &w.qsum, &w.cm, &w.order, &w.queue, &w.part, &w.q16, &w.gthr, &w.members, &w.moffs,
+        for (DevBuf *b : {&w.qk, &w.qsum, &w.cm, &w.order, &w.queue, &w.part, &w.q16, &w.gthr, &w.mkeys, &w.members, &w.moffs,
                           &w.mcount, &w.mcursor, &w.probe, &w.qoffs, &w.qids})
             dev_free(ix, *b);
     }
@@ -882,6 +882,39 @@ static int64_t scan_parts_mfma(const lvq_index *ix, int64_t qtiles, int32_t k, i
     return parts;
 }
 
+// Row parts and persistent grid of the wide MFMA scan (one workgroup per
+// compute unit, a multiple of 8 for the XCD-aware tile walk).  Time model:
+// each workgroup runs ceil(tiles per XCD / workgroups per XCD) tiles of
+// N = n_rows / parts rows, plus a per-tile cost in row equivalents: 10,240
+// for staging the queries and the final merge, and the appends of a part's
+// loose bound.  A 32 x 32 block of scores holds a key beating the running
+// k-th best of t rows with probability about min(1, 1024 k / t), so the
+// blocks that append add about 512 k (1 + ln(N / 1024 k)) rows' worth.
+// Parts keep at least 8 rounds of rows, and the merge (parts * k keys, + k)
+// fits one workgroup's LDS.
+static int64_t scan_parts_wide(const lvq_index *ix, int64_t qtiles, int32_t k, int64_t n_rows, int64_t *grid)
+{
+    const int64_t slots = std::max<int64_t>(8, ix->n_cu / 8 * 8);
+    const int64_t max_parts = std::max<int64_t>(
+        1, std::min<int64_t>(n_rows / 4096, (int64_t)(ix->lds_max / 8 - k) / k));
+    int64_t parts = 1;
+    double best = 0.0;
+    for (int64_t p = 1; p <= max_parts; ++p) {
+        const int64_t tiles = qtiles * p;
+        const int64_t g = std::min<int64_t>(slots, (tiles + 7) / 8 * 8);
+        const int64_t per_xcd = (tiles + 7) / 8;
+        const int64_t iters = (per_xcd + g / 8 - 1) / (g / 8);
+        const double rows = (double)((n_rows + p - 1) / p), warm = 1024.0 * k;
+        const double cost = (double)iters * (rows + 10240.0 + 0.5 * warm * (1.0 + std::log(std::max(1.0, rows / warm))));
+        if (p == 1 || cost < best) {
+            best = cost;
+            parts = p;
+        }
+    }
+    *grid = std::min<int64_t>(slots, (qtiles * parts + 7) / 8 * 8);
+    return parts;
+}
+
 int lvq::host_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level,
                    int32_t *ids_dev, float *dist_dev, hipStream_t s, uint32_t epoch)
 {
@@ -991,10 +1024,13 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     if (ix->cfg.metric != LVQ_IP) return LVQ_ERR_UNSUPPORTED;
     const int bits2 = level == LVQ_FULL ? f.bits2 : 0;
     if (bits2 != 0 && bits2 != 8) return LVQ_ERR_UNSUPPORTED;   // both levels need 8-bit residual codes
-    const int qb = mfma_query_block(f.bits1, bits2, f.kpos);
+    // first level with k <= 512: the wide kernel (queries in LDS); else the
+    // register-resident kernel
+    const int qbw = bits2 == 0 ? mfma_wide_query_block(f.bits1, f.kpos, k, ix->n_means, ix->lds_max) : 0;
+    const int qb = qbw ? qbw : mfma_query_block(f.bits1, bits2, f.kpos);
     if (!qb) return LVQ_ERR_UNSUPPORTED;
-    const int capq = mfma_capq(qb, ix->n_means, k, ix->lds_max);
-    if (!capq) return LVQ_ERR_UNSUPPORTED;
+    const int capq = qbw ? 0 : mfma_capq(qb, ix->n_means, k, ix->lds_max);
+    if (!qbw && !capq) return LVQ_ERR_UNSUPPORTED;
     int rc = order_after_updates(ix, s);
     if (rc) return rc;
     Workspace &w = workspace(ix, s);
@@ -1006,10 +1042,12 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     LVQ_HIP(launch_prep16(q_dev, nq, f.dim, f.kpos, f.bits1, qb, prec, P<int32_t>(ix->kdim), P<float>(ix->means),
                           ix->n_means, w.q16.p, P<float>(w.qsum), P<float>(w.cm), s));
     const int64_t n_rows = ix->list_len;
-    const int64_t parts = scan_parts_mfma(ix, qtiles, k, n_rows);
+    int64_t grid = 0;
+    const int64_t parts = qbw ? scan_parts_wide(ix, qtiles, k, n_rows, &grid) : scan_parts_mfma(ix, qtiles, k, n_rows);
     const int64_t rows_per_part = std::max<int64_t>(1, (n_rows + parts - 1) / parts);
     if ((rc = dev_alloc(ix, w.part, sizeof(uint64_t) * (size_t)nq * parts * k))) return rc;
     if ((rc = dev_alloc(ix, w.gthr, sizeof(uint32_t) * (size_t)nq))) return rc;
+    if (qbw && (rc = dev_alloc(ix, w.mkeys, sizeof(uint64_t) * (size_t)grid * tq * mfma_wide_cap(k)))) return rc;
     LVQ_HIP(launch_fill_u32(P<uint32_t>(w.gthr), 0xFFFFFFFFu, nq, s));
     ScanArgs a;
     a.rows = P<uint8_t>(ix->rows);
@@ -1036,11 +1074,17 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     a.gthr = P<uint32_t>(w.gthr);
     a.part_keys = P<uint64_t>(w.part);
     a.err = P<uint32_t>(ix->err);
-    ix->last_wg = (qtiles * parts + 7) / 8 * 8;
+    a.mkeys = qbw ? P<uint64_t>(w.mkeys) : nullptr;
+    a.mcap = qbw ? mfma_wide_cap(k) : 0;
+    a.mks = qbw ? mfma_wide_sorted(k) : 0;
+    ix->last_wg = qbw ? grid : (qtiles * parts + 7) / 8 * 8;
     ix->last_lists = 0;
     ix->last_parts = (int32_t)parts;
     if ((rc = timing_begin(ix, s))) return rc;
-    LVQ_HIP(launch_scan_mfma(a, f.bits1, bits2, prec, s));
+    if (qbw)
+        LVQ_HIP(launch_scan_mfma_wide(a, f.bits1, prec, grid, s));
+    else
+        LVQ_HIP(launch_scan_mfma(a, f.bits1, bits2, prec, s));
     if ((rc = timing_end(ix, s))) return rc;
     LVQ_HIP(launch_topk_merge(a.part_keys, nq, (int)parts, k, LVQ_IP, ids_dev, dist_dev, s));
     return LVQ_OK;
@@ -1310,7 +1354,7 @@ int lvq::host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_fi
     if (k_rerank > 0 && rerank_level != LVQ_PRIMARY && rerank_level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
     const Format &f = ix->f;
     const int64_t n_rows = ix->cfg.capacity;   // the part counts grow with the rows scanned
-    size_t qk = 0, part = 0, q16 = 0, gthr = 0, order = 0;
+    size_t qk = 0, part = 0, q16 = 0, gthr = 0, order = 0, mkeys = 0;
     const size_t qsum = sizeof(float) * (size_t)max_nq;
     const size_t cm = sizeof(float) * (size_t)max_nq * kMaxMeans;   // any mean count the index may reach
     if (prec == LVQ_FP32 || k_rerank > 0) qk = sizeof(float) * (size_t)max_nq * f.kpos;
@@ -1318,16 +1362,31 @@ int lvq::host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_fi
         for (int64_t nq = 1; nq <= max_nq; ++nq)
             part = std::max(part, sizeof(uint64_t) * (size_t)(nq * scan_parts_fp32(ix, nq, k_first, n_rows) * k_first));
     } else {
-        const int qb = mfma_query_block(f.bits1, scan_level == LVQ_FULL ? f.bits2 : 0, f.kpos);
+        const int bits2 = scan_level == LVQ_FULL ? f.bits2 : 0;
+        const int qbw = bits2 == 0 ? mfma_wide_query_block(f.bits1, f.kpos, k_first, kMaxMeans, ix->lds_max) : 0;
+        const int qb = qbw ? qbw : mfma_query_block(f.bits1, bits2, f.kpos);
         if (!qb) return LVQ_ERR_UNSUPPORTED;
-        const int64_t tq = 32 * qb;
-        q16 = (size_t)((max_nq + tq - 1) / tq) * tq * f.kpos * 2;
-        gthr = sizeof(uint32_t) * (size_t)max_nq;
-        for (int64_t nq = 1; nq <= max_nq; ++nq) {
-            const int64_t qtiles = (nq + tq - 1) / tq;
-            part = std::max(part,
-                            sizeof(uint64_t) * (size_t)(nq * scan_parts_mfma(ix, qtiles, k_first, n_rows) * k_first));
+        // the wide kernel when it takes any mean count the index may reach;
+        // else reserve for both kernels (the register-resident one serves
+        // what the wide one cannot)
+        const int qbw_any = bits2 == 0 ? mfma_wide_query_block(f.bits1, f.kpos, k_first, 1, ix->lds_max) : 0;
+        const int qbo = mfma_query_block(f.bits1, bits2, f.kpos);
+        for (int kind = 0; kind < 2; ++kind) {
+            const bool wide = kind == 0;
+            const int q = wide ? qbw_any : (qbw ? 0 : qbo);
+            if (!q) continue;
+            const int64_t tq = 32 * q;
+            q16 = std::max(q16, (size_t)((max_nq + tq - 1) / tq) * tq * f.kpos * 2);
+            for (int64_t nq = 1; nq <= max_nq; ++nq) {
+                const int64_t qtiles = (nq + tq - 1) / tq;
+                int64_t grid = 0;
+                const int64_t parts = wide ? scan_parts_wide(ix, qtiles, k_first, n_rows, &grid)
+                                           : scan_parts_mfma(ix, qtiles, k_first, n_rows);
+                part = std::max(part, sizeof(uint64_t) * (size_t)(nq * parts * k_first));
+                if (wide) mkeys = std::max(mkeys, sizeof(uint64_t) * (size_t)grid * tq * mfma_wide_cap(k_first));
+            }
         }
+        gthr = sizeof(uint32_t) * (size_t)max_nq;
     }
     if (k_rerank > 0) order = sizeof(int32_t) * (size_t)max_nq;
     Workspace &w = workspace(ix, s);
@@ -1338,6 +1397,7 @@ int lvq::host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_fi
     if (part && (rc = dev_alloc(ix, w.part, part))) return rc;
     if (q16 && (rc = dev_alloc(ix, w.q16, q16))) return rc;
     if (gthr && (rc = dev_alloc(ix, w.gthr, gthr))) return rc;
+    if (mkeys && (rc = dev_alloc(ix, w.mkeys, mkeys))) return rc;
     if (order && (rc = dev_alloc(ix, w.order, order))) return rc;
     if (k_rerank > 0 && (rc = dev_alloc(ix, w.queue, 64))) return rc;
     return LVQ_OK;

@@ -31,7 +31,7 @@ struct DistScratch {
 
 // Per-stream scratch of the query entry points.
 struct Workspace {
-    DevBuf qk, qsum, cm, order, queue, part, q16, gthr;
+    DevBuf qk, qsum, cm, order, queue, part, q16, gthr, mkeys;
     // soft inverted index: this stream's per-mean member lists (built at
     // store version members_version) and per-call routing / candidate lists
     DevBuf members, moffs, mcount, mcursor, probe, qoffs, qids;

@@ -472,7 +472,9 @@ def test_exhaustive_topk_mfma(L, d, b1, b2, layout, M, prec):
     levels = [(oracle.PRIMARY, L.LVQ_PRIMARY)] + ([(oracle.FULL, L.LVQ_FULL)] if b2 == 8 else [])
     for olev, glev in levels:
         ref, tol = pair_reference(fmt, oracle.IP, olev, Qr, rows, resid, means, offs, allids)
-        for k in (1, 10, 100):
+        # k = 300: the first level with one mean keeps 512 sorted keys per
+        # query (the queries-in-LDS kernel)
+        for k in (1, 10, 100) + ((300,) if olev == oracle.PRIMARY and M == 1 else ()):
             ti, td = ix.topk(Qh.cuda(), k, level=glev)
             assert ix.sync() == 0
             ti, td = ti.cpu().numpy(), td.cpu().numpy()
