@@ -674,7 +674,7 @@ def bench_c4(args):
                             "FP32 vector kernel on the same store", "n": n, "dim": d, "queries": nq, "k": k},
                {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
-                "kernel": "k_scan_mfma (bf16, fused top-100)", "kernel_ms": k_ms},
+                "kernel": "k_scan_mfma_wide (bf16, fused top-100)", "kernel_ms": k_ms},
                precision=acc, accuracy_sample="%d queries: recall@100 vs the exact float top-100; errors "
                                               "|gpu - binary64 oracle (float32 query)| / sum_j |q_j x_hat_j| "
                                               "(with the CPU baseline)" % ns)
