@@ -192,14 +192,16 @@ __global__ __launch_bounds__(256) void k_encode(EncodeArgs a)
             }
         }
     }
-    // means for the nearest-mean search, staged in LDS as [dim][mean] when
-    // they fit (conflict-free: the lanes of a group read consecutive means)
+    // means for the nearest-mean search, staged in LDS as [mean][dim] rows
+    // of the staging stride when they fit: the lanes of a group read four
+    // dimensions of their means with one 16-byte load, and the odd
+    // multiple-of-four stride keeps those loads free of bank conflicts
     const int M = a.n_means;
     float *mt = lds + (size_t)V * stride;
     if (a.means_lds) {
         for (int e = threadIdx.x; e < M * d; e += 256) {
-            const int j = e / M, m = e - j * M;
-            mt[e] = a.means_t[(int64_t)j * a.means_t_stride + m];
+            const int m = e / d, j = e - m * d;
+            mt[m * stride + j] = a.means[e];
         }
     }
     finite = group_and<G>(finite);
@@ -215,12 +217,33 @@ __global__ __launch_bounds__(256) void k_encode(EncodeArgs a)
             const bool two = m0 + G < M;
             const int m1 = two ? m0 + G : m0;
             float s0 = 0.0f, s1 = 0.0f;
-            if (a.means_lds) {
+            if (a.means_lds && vec4) {
+                const float4 *x4 = reinterpret_cast<const float4 *>(ts);
+                const float4 *a4 = reinterpret_cast<const float4 *>(mt + m0 * stride);
+                const float4 *b4 = reinterpret_cast<const float4 *>(mt + m1 * stride);
+                auto step = [](float x, float mu, float &acc) {
+                    float e = x - mu;
+                    e = e * e;
+                    acc = acc + e;
+                };
+#pragma unroll 4
+                for (int q = 0; q < (d >> 2); ++q) {
+                    const float4 xv = x4[q], av = a4[q], bv = b4[q];
+                    step(xv.x, av.x, s0);
+                    step(xv.x, bv.x, s1);
+                    step(xv.y, av.y, s0);
+                    step(xv.y, bv.y, s1);
+                    step(xv.z, av.z, s0);
+                    step(xv.z, bv.z, s1);
+                    step(xv.w, av.w, s0);
+                    step(xv.w, bv.w, s1);
+                }
+            } else if (a.means_lds) {
 #pragma unroll 8
                 for (int j = 0; j < d; ++j) {
                     const float x = ts[j];
-                    float e0 = x - mt[j * M + m0];
-                    float e1 = x - mt[j * M + m1];
+                    float e0 = x - mt[m0 * stride + j];
+                    float e1 = x - mt[m1 * stride + j];
                     e0 = e0 * e0;
                     e1 = e1 * e1;
                     s0 = s0 + e0;
@@ -439,7 +462,7 @@ hipError_t launch_encode(const EncodeArgs &a, hipStream_t s)
     while (G < 64 && units > 4 * G) G *= 2;
     const int V = 256 / G;
     size_t lds = (size_t)V * stage_stride(a.f.dim) * sizeof(float);
-    if (a.means_lds) lds += (size_t)a.n_means * a.f.dim * sizeof(float);
+    if (a.means_lds) lds += (size_t)a.n_means * stage_stride(a.f.dim) * sizeof(float);
     const int64_t blocks = (a.n + V - 1) / V;
     const int b1 = a.f.bits1, b2 = a.f.bits2;
     if (b1 == 4 && b2 == 0) return launch_encode_t<4, 0>(a, G, lds, blocks, s);

@@ -46,7 +46,7 @@ struct EncodeArgs {
     const float *means_t;    // dim rows of means_t_stride (transposed copy, coalesced assignment)
     int means_t_stride;
     int n_means;
-    int means_lds;           // stage the transposed means in LDS (small M x dim)
+    int means_lds;           // stage the means in LDS (small M x dim)
     const uint8_t *mean_active;  // n_means flags: 0 = retired (not chosen by the nearest-mean search)
     Format f;
     uint8_t *rows;           // output rows (row i at rows + slot(i) * row_bytes)
