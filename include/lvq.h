@@ -211,13 +211,16 @@ int lvq_num_tile_shapes(void);
 int lvq_tile_shape(int32_t shape, int32_t *lanes, int32_t *piece_bytes, int32_t *pieces, int32_t *pipe);
 
 /* Exhaustive top-k over every slot live at the call (Sec. 2.1 k-NN problem),
- * for nq queries q_dev (nq x dim) of precision prec at `level`: LVQ_FP32 runs
- * the FP32 vector path; LVQ_BF16 / LVQ_FP16 take queries already in that type
- * and run matrix-core (MFMA) products of queries and exactly converted integer
- * codes with FP32 accumulation (inner product; both levels need 8-bit
- * residual codes).  1 <= k <= 1024 (the per-query candidate buffers must fit
- * the LDS: LVQ_ERR_UNSUPPORTED otherwise).  Output ids_dev / dist_dev nq x k,
- * padded as for lvq_distances.                                             */
+ * for nq queries q_dev (nq x dim) of precision prec at `level`: LVQ_FP32
+ * takes float queries and FP32 products -- on the FP32 matrix cores
+ * (v_mfma_f32_32x32x2_f32, codes converted exactly) for the first-level inner
+ * product of an index with one mean and k <= 512, else on the vector ALUs;
+ * LVQ_BF16 / LVQ_FP16 take queries already in that type and run matrix-core
+ * (MFMA) products of queries and exactly converted integer codes with FP32
+ * accumulation (inner product; both levels need 8-bit residual codes).
+ * 1 <= k <= 1024 (the per-query candidate buffers must fit the LDS:
+ * LVQ_ERR_UNSUPPORTED otherwise).  Output ids_dev / dist_dev nq x k, padded
+ * as for lvq_distances.                                                    */
 int lvq_topk(lvq_index *index, const void *q_dev, int32_t prec, int64_t nq, int32_t k,
              int32_t level, int32_t *ids_dev, float *dist_dev, void *stream);
 

@@ -1,6 +1,7 @@
 // k_mfma_ops.h -- operand helpers of the matrix-core scans: 16-bit vector
-// types, exact conversion of integer codes to bf16 / fp16 MFMA fragments, and
-// the 32x32x16 MFMA itself.  A fragment of one MFMA step holds, per lane, 8
+// types, exact conversion of integer codes to bf16 / fp16 MFMA fragments or
+// to one FP32 value per lane, and the 32x32x16 and 32x32x2 MFMAs (FP32
+// accumulation).  A 16-bit fragment of one MFMA step holds, per lane, 8
 // consecutive kernel-order positions of one row (lane & 31) and K half
 // (lane >> 5); the same layout serves as the A or the B operand.
 #pragma once
@@ -79,6 +80,34 @@ __device__ __forceinline__ uint4 r_fragment(const uint4 (&v)[B1 == 4 ? 2 : 1], i
         r.w = pack2<FP16>(ub<1>(hi), ub<3>(hi));
         return r;
     }
+}
+
+// FP32 operands: one code (exact as a float) and one query value per lane.
+// The lane's 16 loaded bytes as words whose bytes are its codes in kernel
+// order, code t = byte t % 4 of word t / 4: 8-bit codes as loaded; 4-bit
+// codes split into the low fields (0,2,4,6) and the high fields (1,3,5,7) of
+// each word, the order of b_fragment.
+template <int B1>
+__device__ __forceinline__ void code_words(const uint4 &v, uint32_t (&w)[B1 == 8 ? 4 : 8])
+{
+    const uint32_t x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if constexpr (B1 == 8) {
+            w[i] = x[i];
+        } else {
+            w[2 * i] = opaque_and_m(x[i], 0x0F0F0F0Fu);
+            w[2 * i + 1] = opaque_and_m(x[i] >> 4, 0x0F0F0F0Fu);
+        }
+    }
+}
+
+// 32x32 FP32 scores += (32 rows x 2 codes) x (2 positions x 32 queries):
+// lane l gives row (l & 31)'s code and query (l & 31)'s value at K index
+// l >> 5.
+__device__ __forceinline__ f32x16 mfma_f32(float a, float b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
 template <bool FP16>

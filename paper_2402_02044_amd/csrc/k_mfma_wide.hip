@@ -1,18 +1,21 @@
 // k_mfma_wide.hip -- exhaustive inner-product top-k on the matrix cores with
 // the queries staged in LDS (first level; Sec. 3.2 similarity, Sec. 2.1 k-NN):
 //   <q, x_hat> = c_m + l sum(q) + Delta <q, c1>
-// (one mean: c_m = <q, mu> is one value per query) with bf16 / fp16 queries times codes converted exactly to the same type and
-// FP32 accumulation (v_mfma_f32_32x32x16).
+// (one mean: c_m = <q, mu> is one value per query) with bf16 / fp16 queries
+// times codes converted exactly to the same type (v_mfma_f32_32x32x16), or
+// FP32 queries times codes converted exactly to FP32 (v_mfma_f32_32x32x2),
+// both with FP32 accumulation.
 //
-// Tiling.  A workgroup of twelve waves (three per SIMD) copies the MFMA
+// Tiling.  A workgroup of eight waves (two per SIMD) copies the MFMA
 // fragments of TQ = 32*QB queries into LDS once per tile, so every code
-// fragment a wave converts feeds QB MFMAs, one per 32-query block.  The codes
-// are the A operand and the queries the B operand: lane l then owns query
-// (l & 31) of every block -- its sum(q), c_m and admission bound stay in
-// registers -- and rows 8*(i/4) + 4*(l >> 5) + (i % 4), i < 16, of each
-// 32-row block.  A wave scores one 32-row block per round; its 16-byte code
-// pieces stream through a ring of loads a few chunks ahead, which runs on
-// into the next round's rows.
+// fragment a wave converts (FP32: every code a lane converts) feeds QB MFMAs,
+// one per 32-query block.  The codes are the A operand and the queries the B
+// operand: lane l then owns query (l & 31) of every block -- its sum(q), c_m
+// and admission bound stay in registers -- and rows 8*(i/4) + 4*(l >> 5) +
+// (i % 4), i < 16, of each 32-row block.  A wave scores RB = 2 blocks of 32
+// rows per round, so each query fragment it reads from LDS feeds two MFMAs;
+// its 16-byte code pieces stream through a ring of loads a few chunks ahead,
+// which runs on into the next round's rows.
 //
 // Top-k.  Each query keeps, in the workgroup's region of device memory, its
 // KS best keys so far (sorted, KS = k rounded up to a power of two >= 64)
@@ -128,23 +131,27 @@ __device__ __forceinline__ int merge_region_ks(int ks, uint64_t *rq, int poff, i
     return merge_region<8>(rq, poff, pend, k, out, kth);
 }
 
-// LDS bytes of a workgroup: query fragments, per-wave row constants (l,
-// Delta, slot of its rows), per-query bounds and pending counts.
-__host__ __device__ constexpr size_t wide_lds_bytes(int qb, int kpos, int rb)
+// LDS bytes of a workgroup: query fragments (esize bytes per value),
+// per-wave row constants (l, Delta, slot of its rows), per-query bounds and
+// pending counts.
+__host__ __device__ constexpr size_t wide_lds_bytes(int qb, int kpos, int rb, int esize)
 {
-    return (size_t)32 * qb * kpos * 2 + (size_t)wide_waves(rb) * 32 * rb * 12 + (size_t)32 * qb * 8;
+    return (size_t)32 * qb * kpos * esize + (size_t)wide_waves(rb) * 32 * rb * 12 + (size_t)32 * qb * 8;
 }
 
-template <int B1, int KPOS, int QB, int RB, bool FP16>
+template <int B1, int KPOS, int QB, int RB, int PREC>
 __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanArgs a)
 {
+    constexpr bool F32 = PREC == LVQ_FP32, FP16 = PREC == LVQ_FP16;
     constexpr int WAVES = wide_waves(RB);
     constexpr int RW = 32 * RB;               // rows per wave and round
     constexpr int RROUND = WAVES * RW;        // rows per round
     constexpr int TQ = 32 * QB;
     constexpr int CHUNK_POS = B1 == 8 ? 32 : 64;
     constexpr int NCHUNK = KPOS / CHUNK_POS;
-    constexpr int STEPS = B1 == 8 ? 2 : 4;
+    // 16-byte query fragments per chunk and block: 8 positions each in 16
+    // bits, 4 in FP32 (one per lane and MFMA)
+    constexpr int STEPS = F32 ? CHUNK_POS / 8 : CHUNK_POS / 16;
     constexpr int RING = NCHUNK < 4 ? NCHUNK : 4;
     constexpr int NFRAG = QB * NCHUNK * STEPS * 64;   // 16-byte fragments per query tile
     static_assert(KPOS % CHUNK_POS == 0, "KPOS");
@@ -266,16 +273,42 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                     ring[c % RING][j] =
                         *reinterpret_cast<const uint4 *>(p + (c + RING < NCHUNK ? c + RING : c + RING - NCHUNK) * 32);
                 }
+                if constexpr (F32) {
+                    // code 4 s + e of the lane's piece is byte e of word s
+                    uint32_t cw[RB][STEPS];
 #pragma unroll
-                for (int s = 0; s < STEPS; ++s) {
-                    uint4 af[RB];
+                    for (int j = 0; j < RB; ++j) code_words<B1>(v[j], cw[j]);
 #pragma unroll
-                    for (int j = 0; j < RB; ++j) af[j] = b_fragment<B1, FP16>(v[j], s);
+                    for (int s = 0; s < STEPS; ++s) {
+                        float4 bq[QB];
 #pragma unroll
-                    for (int b = 0; b < QB; ++b) {
-                        const uint4 bq = qf[((b * NCHUNK + c) * STEPS + s) * 64 + lane];
+                        for (int b = 0; b < QB; ++b)
+                            bq[b] = reinterpret_cast<const float4 *>(qf)[((b * NCHUNK + c) * STEPS + s) * 64 + lane];
 #pragma unroll
-                        for (int j = 0; j < RB; ++j) acc[j][b] = mfma<FP16>(af[j], bq, acc[j][b]);
+                        for (int e = 0; e < 4; ++e) {
+                            float af[RB];
+#pragma unroll
+                            for (int j = 0; j < RB; ++j) af[j] = (float)((cw[j][s] >> (8 * e)) & 0xFFu);
+#pragma unroll
+                            for (int b = 0; b < QB; ++b) {
+                                const float bv = e == 0 ? bq[b].x : e == 1 ? bq[b].y : e == 2 ? bq[b].z : bq[b].w;
+#pragma unroll
+                                for (int j = 0; j < RB; ++j) acc[j][b] = mfma_f32(af[j], bv, acc[j][b]);
+                            }
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < STEPS; ++s) {
+                        uint4 af[RB];
+#pragma unroll
+                        for (int j = 0; j < RB; ++j) af[j] = b_fragment<B1, FP16>(v[j], s);
+#pragma unroll
+                        for (int b = 0; b < QB; ++b) {
+                            const uint4 bq = qf[((b * NCHUNK + c) * STEPS + s) * 64 + lane];
+#pragma unroll
+                            for (int j = 0; j < RB; ++j) acc[j][b] = mfma<FP16>(af[j], bq, acc[j][b]);
+                        }
                     }
                 }
             }
@@ -400,37 +433,86 @@ using WideKernel = void (*)(ScanArgs);
 
 // Instantiated position counts: 32-query blocks per workgroup (as many as
 // the query fragments' LDS allows, at most four) and row blocks per wave.
-template <int B1, bool FP16>
-WideKernel wide_lookup(int kpos, int *qb, int *rb)
+template <int B1, int PREC>
+WideKernel wide_lookup_16(int kpos, int *qb, int *rb)
 {
     switch (kpos) {
-    case 96: *qb = 4; *rb = 2; return B1 == 8 ? k_scan_mfma_wide<8, 96, 4, 2, FP16> : nullptr;
-    case 128: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 128, 4, 2, FP16>;
-    case 256: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 256, 4, 2, FP16>;
-    case 384: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 384, 4, 2, FP16>;
-    case 512: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 512, 4, 2, FP16>;
-    case 768: *qb = 2; *rb = 2; return k_scan_mfma_wide<B1, 768, 2, 2, FP16>;
-    case 1024: *qb = 2; *rb = 2; return k_scan_mfma_wide<B1, 1024, 2, 2, FP16>;
+    case 96: *qb = 4; *rb = 2; return B1 == 8 ? k_scan_mfma_wide<8, 96, 4, 2, PREC> : nullptr;
+    case 128: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 128, 4, 2, PREC>;
+    case 256: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 256, 4, 2, PREC>;
+    case 384: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 384, 4, 2, PREC>;
+    case 512: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 512, 4, 2, PREC>;
+    case 768: *qb = 2; *rb = 2; return k_scan_mfma_wide<B1, 768, 2, 2, PREC>;
+    case 1024: *qb = 2; *rb = 2; return k_scan_mfma_wide<B1, 1024, 2, 2, PREC>;
     default: return nullptr;
     }
 }
 
-WideKernel wide_kernel(int bits1, int kpos, int fp16, int *qb, int *rb)
+// FP32 query values take twice the LDS of 16-bit ones.
+template <int B1>
+WideKernel wide_lookup_32(int kpos, int *qb, int *rb)
 {
-    if (bits1 == 8) return fp16 ? wide_lookup<8, true>(kpos, qb, rb) : wide_lookup<8, false>(kpos, qb, rb);
-    if (bits1 == 4) return fp16 ? wide_lookup<4, true>(kpos, qb, rb) : wide_lookup<4, false>(kpos, qb, rb);
+    switch (kpos) {
+    case 96: *qb = 4; *rb = 2; return B1 == 8 ? k_scan_mfma_wide<8, 96, 4, 2, LVQ_FP32> : nullptr;
+    case 128: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 128, 4, 2, LVQ_FP32>;
+    case 256: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 256, 4, 2, LVQ_FP32>;
+    case 384: *qb = 2; *rb = 2; return k_scan_mfma_wide<B1, 384, 2, 2, LVQ_FP32>;
+    case 512: *qb = 2; *rb = 2; return k_scan_mfma_wide<B1, 512, 2, 2, LVQ_FP32>;
+    case 768: *qb = 1; *rb = 2; return k_scan_mfma_wide<B1, 768, 1, 2, LVQ_FP32>;
+    case 1024: *qb = 1; *rb = 2; return k_scan_mfma_wide<B1, 1024, 1, 2, LVQ_FP32>;
+    default: return nullptr;
+    }
+}
+
+template <int B1>
+WideKernel wide_lookup(int kpos, int prec, int *qb, int *rb)
+{
+    if (prec == LVQ_BF16) return wide_lookup_16<B1, LVQ_BF16>(kpos, qb, rb);
+    if (prec == LVQ_FP16) return wide_lookup_16<B1, LVQ_FP16>(kpos, qb, rb);
+    if (prec == LVQ_FP32) return wide_lookup_32<B1>(kpos, qb, rb);
     return nullptr;
+}
+
+WideKernel wide_kernel(int bits1, int kpos, int prec, int *qb, int *rb)
+{
+    if (bits1 == 8) return wide_lookup<8>(kpos, prec, qb, rb);
+    if (bits1 == 4) return wide_lookup<4>(kpos, prec, qb, rb);
+    return nullptr;
+}
+
+// FP32 query fragments from kernel-order queries (nq x kpos, zero at padding
+// positions): [tile][block][chunk][step][lane] float4s, element e of step s
+// being the value for MFMA 4 s + e, whose lane l holds position
+// CHUNK_POS c + (CHUNK_POS / 2)(l >> 5) + 4 s + e of query 32 block + (l & 31)
+// (zero past nq) -- the positions of the codes that code_words hands that lane.
+__global__ __launch_bounds__(256) void k_frag32(const float *qk, int64_t nq, int kpos, int chunk_pos, int qb,
+                                                float4 *frag)
+{
+    const int nchunk = kpos / chunk_pos, steps = chunk_pos / 8;
+    const int64_t per_tile = (int64_t)qb * nchunk * steps * 64;
+    const int64_t tile = blockIdx.x;
+    for (int64_t e = threadIdx.x; e < per_tile; e += 256) {
+        const int l = (int)(e % 64);
+        const int s = (int)((e / 64) % steps);
+        const int c = (int)((e / (64 * steps)) % nchunk);
+        const int b = (int)(e / (64 * steps * nchunk));
+        const int64_t gq = tile * 32 * qb + 32 * b + (l & 31);
+        const int p = c * chunk_pos + (l >> 5) * (chunk_pos / 2) + 4 * s;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (gq < nq) v = *reinterpret_cast<const float4 *>(qk + gq * kpos + p);
+        frag[tile * per_tile + e] = v;
+    }
 }
 
 }  // namespace
 
-int mfma_wide_query_block(int bits1, int kpos, int k, int n_means, size_t lds_max)
+int mfma_wide_query_block(int bits1, int kpos, int prec, int k, int n_means, size_t lds_max)
 {
     if ((bits1 != 4 && bits1 != 8) || kpos % (bits1 == 8 ? 32 : 64)) return 0;
     if (k < 1 || k > kWideMaxK || n_means != 1) return 0;
     int qb = 0, rb = 0;
-    if (!wide_kernel(bits1, kpos, 0, &qb, &rb)) return 0;
-    return wide_lds_bytes(qb, kpos, rb) <= lds_max ? qb : 0;
+    if (!wide_kernel(bits1, kpos, prec, &qb, &rb)) return 0;
+    return wide_lds_bytes(qb, kpos, rb, prec == LVQ_FP32 ? 4 : 2) <= lds_max ? qb : 0;
 }
 
 int mfma_wide_sorted(int k)
@@ -448,11 +530,23 @@ int mfma_wide_cap(int k)
 hipError_t launch_scan_mfma_wide(const ScanArgs &a, int bits1, int prec, int64_t grid, hipStream_t s)
 {
     int qb = 0, rb = 0;
-    WideKernel kern = wide_kernel(bits1, a.kpos, prec == LVQ_FP16 ? 1 : 0, &qb, &rb);
+    WideKernel kern = wide_kernel(bits1, a.kpos, prec, &qb, &rb);
     if (!kern || grid < 8 || grid % 8 || a.k < 1 || a.k > kWideMaxK || a.mks != mfma_wide_sorted(a.k) ||
         a.mcap != mfma_wide_cap(a.k) || a.n_means != 1)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * wide_waves(rb)), wide_lds_bytes(qb, a.kpos, rb), s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * wide_waves(rb)),
+                       wide_lds_bytes(qb, a.kpos, rb, prec == LVQ_FP32 ? 4 : 2), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_frag32(const float *qk, int64_t nq, int kpos, int bits1, int qb, void *frag, hipStream_t s)
+{
+    const int chunk_pos = bits1 == 8 ? 32 : 64;
+    if (qb < 1 || (bits1 != 4 && bits1 != 8) || kpos % chunk_pos) return hipErrorInvalidValue;
+    if (nq <= 0) return hipSuccess;
+    const int64_t tiles = (nq + 32 * qb - 1) / (32 * qb);
+    hipLaunchKernelGGL(k_frag32, dim3((unsigned)tiles), dim3(256), 0, s, qk, nq, kpos, chunk_pos, qb,
+                       reinterpret_cast<float4 *>(frag));
     return hipGetLastError();
 }
 

@@ -885,14 +885,16 @@ static int64_t scan_parts_mfma(const lvq_index *ix, int64_t qtiles, int32_t k, i
 // Row parts and persistent grid of the wide MFMA scan (one workgroup per
 // compute unit, a multiple of 8 for the XCD-aware tile walk).  Time model:
 // each workgroup runs ceil(tiles per XCD / workgroups per XCD) tiles of
-// N = n_rows / parts rows, plus a per-tile cost in row equivalents: 10,240
-// for staging the queries and the final merge, and the appends of a part's
-// loose bound.  A 32 x 32 block of scores holds a key beating the running
-// k-th best of t rows with probability about min(1, 1024 k / t), so the
-// blocks that append add about 512 k (1 + ln(N / 1024 k)) rows' worth.
-// Parts keep at least 8 rounds of rows, and the merge (parts * k keys, + k)
-// fits one workgroup's LDS.
-static int64_t scan_parts_wide(const lvq_index *ix, int64_t qtiles, int32_t k, int64_t n_rows, int64_t *grid)
+// N = n_rows / parts rows, plus a per-tile cost in 16-bit row equivalents:
+// 10,240 for staging the queries and the final merge, and the appends of a
+// part's loose bound.  A 32 x 32 block of scores holds a key beating the
+// running k-th best of t rows with probability about min(1, 1024 k / t), so
+// the blocks that append add about 512 k (1 + ln(N / 1024 k)) rows' worth.
+// An FP32 row costs about 8 16-bit ones (a sixteenth of the matrix-core
+// rate, half the queries per tile).  Parts keep at least 8 rounds of rows,
+// and the merge (parts * k keys, + k) fits one workgroup's LDS.
+static int64_t scan_parts_wide(const lvq_index *ix, int64_t qtiles, int32_t k, int64_t n_rows, int32_t prec,
+                               int64_t *grid)
 {
     const int64_t slots = std::max<int64_t>(8, ix->n_cu / 8 * 8);
     const int64_t max_parts = std::max<int64_t>(
@@ -905,7 +907,8 @@ static int64_t scan_parts_wide(const lvq_index *ix, int64_t qtiles, int32_t k, i
         const int64_t per_xcd = (tiles + 7) / 8;
         const int64_t iters = (per_xcd + g / 8 - 1) / (g / 8);
         const double rows = (double)((n_rows + p - 1) / p), warm = 1024.0 * k;
-        const double cost = (double)iters * (rows + 10240.0 + 0.5 * warm * (1.0 + std::log(std::max(1.0, rows / warm))));
+        const double row_cost = prec == LVQ_FP32 ? 8.0 : 1.0;
+        const double cost = (double)iters * (rows + (10240.0 + 0.5 * warm * (1.0 + std::log(std::max(1.0, rows / warm)))) / row_cost);
         if (p == 1 || cost < best) {
             best = cost;
             parts = p;
@@ -927,6 +930,9 @@ int lvq::host_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, i
     const Format &f = ix->f;
     if (prec != LVQ_FP32) return topk_mfma(ix, q_dev, prec, nq, k, level, ids_dev, dist_dev, s, epoch);
     const bool l2 = ix->cfg.metric == LVQ_L2;
+    // the first-level inner product with one mean runs on the FP32 matrix cores
+    if (!l2 && level == LVQ_PRIMARY && mfma_wide_query_block(f.bits1, f.kpos, LVQ_FP32, k, ix->n_means, ix->lds_max))
+        return topk_mfma(ix, q_dev, prec, nq, k, level, ids_dev, dist_dev, s, epoch);
     if (l2 && ix->n_means > 1) return LVQ_ERR_UNSUPPORTED;
     const bool masked = l2 && f.kpos != f.dim;
     const int variant = !l2 ? 0 : (masked ? 2 : 1);
@@ -1016,7 +1022,8 @@ int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t
 
 }  // extern "C"
 
-// Exhaustive top-k on the matrix cores: inner product, first level only.
+// Exhaustive top-k on the matrix cores: inner product; bf16 / fp16 queries
+// at either level, FP32 queries at the first level (wide kernel only).
 static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level,
                      int32_t *ids_dev, float *dist_dev, hipStream_t s, uint32_t epoch)
 {
@@ -1025,8 +1032,9 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     const int bits2 = level == LVQ_FULL ? f.bits2 : 0;
     if (bits2 != 0 && bits2 != 8) return LVQ_ERR_UNSUPPORTED;   // both levels need 8-bit residual codes
     // first level with k <= 512: the wide kernel (queries in LDS); else the
-    // register-resident kernel
-    const int qbw = bits2 == 0 ? mfma_wide_query_block(f.bits1, f.kpos, k, ix->n_means, ix->lds_max) : 0;
+    // register-resident kernel (16-bit queries only)
+    const int qbw = bits2 == 0 ? mfma_wide_query_block(f.bits1, f.kpos, prec, k, ix->n_means, ix->lds_max) : 0;
+    if (prec == LVQ_FP32 && !qbw) return LVQ_ERR_UNSUPPORTED;
     const int qb = qbw ? qbw : mfma_query_block(f.bits1, bits2, f.kpos);
     if (!qb) return LVQ_ERR_UNSUPPORTED;
     const int capq = qbw ? 0 : mfma_capq(qb, ix->n_means, k, ix->lds_max);
@@ -1036,14 +1044,22 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     Workspace &w = workspace(ix, s);
     const int tq = 32 * qb;
     const int64_t qtiles = (nq + tq - 1) / tq;
-    if ((rc = dev_alloc(ix, w.q16, (size_t)qtiles * tq * f.kpos * 2))) return rc;
-    if ((rc = dev_alloc(ix, w.qsum, sizeof(float) * (size_t)nq))) return rc;
-    if ((rc = dev_alloc(ix, w.cm, sizeof(float) * (size_t)nq * ix->n_means))) return rc;
-    LVQ_HIP(launch_prep16(q_dev, nq, f.dim, f.kpos, f.bits1, qb, prec, P<int32_t>(ix->kdim), P<float>(ix->means),
-                          ix->n_means, w.q16.p, P<float>(w.qsum), P<float>(w.cm), s));
+    if (prec == LVQ_FP32) {
+        // kernel-order FP32 queries, sum(q) and c_m, then their MFMA fragments
+        if ((rc = prep_queries(ix, w, (const float *)q_dev, nq, s))) return rc;
+        if ((rc = dev_alloc(ix, w.q16, (size_t)qtiles * tq * f.kpos * 4))) return rc;
+        LVQ_HIP(launch_frag32(P<float>(w.qk), nq, f.kpos, f.bits1, qb, w.q16.p, s));
+    } else {
+        if ((rc = dev_alloc(ix, w.q16, (size_t)qtiles * tq * f.kpos * 2))) return rc;
+        if ((rc = dev_alloc(ix, w.qsum, sizeof(float) * (size_t)nq))) return rc;
+        if ((rc = dev_alloc(ix, w.cm, sizeof(float) * (size_t)nq * ix->n_means))) return rc;
+        LVQ_HIP(launch_prep16(q_dev, nq, f.dim, f.kpos, f.bits1, qb, prec, P<int32_t>(ix->kdim), P<float>(ix->means),
+                              ix->n_means, w.q16.p, P<float>(w.qsum), P<float>(w.cm), s));
+    }
     const int64_t n_rows = ix->list_len;
     int64_t grid = 0;
-    const int64_t parts = qbw ? scan_parts_wide(ix, qtiles, k, n_rows, &grid) : scan_parts_mfma(ix, qtiles, k, n_rows);
+    const int64_t parts =
+        qbw ? scan_parts_wide(ix, qtiles, k, n_rows, prec, &grid) : scan_parts_mfma(ix, qtiles, k, n_rows);
     const int64_t rows_per_part = std::max<int64_t>(1, (n_rows + parts - 1) / parts);
     if ((rc = dev_alloc(ix, w.part, sizeof(uint64_t) * (size_t)nq * parts * k))) return rc;
     if ((rc = dev_alloc(ix, w.gthr, sizeof(uint32_t) * (size_t)nq))) return rc;
@@ -1361,15 +1377,31 @@ int lvq::host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_fi
     if (prec == LVQ_FP32) {
         for (int64_t nq = 1; nq <= max_nq; ++nq)
             part = std::max(part, sizeof(uint64_t) * (size_t)(nq * scan_parts_fp32(ix, nq, k_first, n_rows) * k_first));
+        // the FP32 matrix-core scan (first-level inner product while the
+        // index has one mean)
+        const int qbf = scan_level == LVQ_PRIMARY && ix->cfg.metric == LVQ_IP
+                            ? mfma_wide_query_block(f.bits1, f.kpos, LVQ_FP32, k_first, 1, ix->lds_max)
+                            : 0;
+        if (qbf) {
+            const int64_t tq = 32 * qbf;
+            q16 = (size_t)((max_nq + tq - 1) / tq) * tq * f.kpos * 4;
+            for (int64_t nq = 1; nq <= max_nq; ++nq) {
+                int64_t grid = 0;
+                const int64_t parts = scan_parts_wide(ix, (nq + tq - 1) / tq, k_first, n_rows, LVQ_FP32, &grid);
+                part = std::max(part, sizeof(uint64_t) * (size_t)(nq * parts * k_first));
+                mkeys = std::max(mkeys, sizeof(uint64_t) * (size_t)grid * tq * mfma_wide_cap(k_first));
+            }
+            gthr = sizeof(uint32_t) * (size_t)max_nq;
+        }
     } else {
         const int bits2 = scan_level == LVQ_FULL ? f.bits2 : 0;
-        const int qbw = bits2 == 0 ? mfma_wide_query_block(f.bits1, f.kpos, k_first, kMaxMeans, ix->lds_max) : 0;
+        const int qbw = bits2 == 0 ? mfma_wide_query_block(f.bits1, f.kpos, prec, k_first, kMaxMeans, ix->lds_max) : 0;
         const int qb = qbw ? qbw : mfma_query_block(f.bits1, bits2, f.kpos);
         if (!qb) return LVQ_ERR_UNSUPPORTED;
         // the wide kernel when it takes any mean count the index may reach;
         // else reserve for both kernels (the register-resident one serves
         // what the wide one cannot)
-        const int qbw_any = bits2 == 0 ? mfma_wide_query_block(f.bits1, f.kpos, k_first, 1, ix->lds_max) : 0;
+        const int qbw_any = bits2 == 0 ? mfma_wide_query_block(f.bits1, f.kpos, prec, k_first, 1, ix->lds_max) : 0;
         const int qbo = mfma_query_block(f.bits1, bits2, f.kpos);
         for (int kind = 0; kind < 2; ++kind) {
             const bool wide = kind == 0;
@@ -1380,7 +1412,7 @@ int lvq::host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_fi
             for (int64_t nq = 1; nq <= max_nq; ++nq) {
                 const int64_t qtiles = (nq + tq - 1) / tq;
                 int64_t grid = 0;
-                const int64_t parts = wide ? scan_parts_wide(ix, qtiles, k_first, n_rows, &grid)
+                const int64_t parts = wide ? scan_parts_wide(ix, qtiles, k_first, n_rows, prec, &grid)
                                            : scan_parts_mfma(ix, qtiles, k_first, n_rows);
                 part = std::max(part, sizeof(uint64_t) * (size_t)(nq * parts * k_first));
                 if (wide) mkeys = std::max(mkeys, sizeof(uint64_t) * (size_t)grid * tq * mfma_wide_cap(k_first));

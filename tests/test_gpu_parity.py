@@ -440,20 +440,22 @@ MFMA_CASES = [
 
 
 @pytest.mark.parametrize("d,b1,b2,layout,M", MFMA_CASES)
-@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp32"])
 def test_exhaustive_topk_mfma(L, d, b1, b2, layout, M, prec):
     """Matrix-core form: 16-bit queries x exactly converted codes, FP32
     accumulation, at the first level and (8-bit residual codes) at both
     levels.  The oracle runs on the same 16-bit query values (upcast exactly),
-    so the only difference left is FP32 accumulation order."""
-    g = synth.rng(3100 + d, M + (prec == "fp16"))
+    so the only difference left is FP32 accumulation order.  FP32 queries:
+    the first level with one mean runs on the FP32 matrix cores (codes
+    converted exactly, FP32 products), the rest on the vector path."""
+    g = synth.rng(3100 + d, M + {"bf16": 0, "fp16": 1, "fp32": 2}[prec])
     n, nq = 3000, 70
     cent = g.standard_normal((8, d)).astype(np.float32)
     X = (cent[g.integers(0, 8, n)] + 0.4 * g.standard_normal((n, d))).astype(np.float32)
     X /= np.linalg.norm(X, axis=1, keepdims=True)
     Q = (cent[g.integers(0, 8, nq)] + 0.4 * g.standard_normal((nq, d))).astype(np.float32)
     Q /= np.linalg.norm(Q, axis=1, keepdims=True)
-    tdt = torch.bfloat16 if prec == "bf16" else torch.float16
+    tdt = {"bf16": torch.bfloat16, "fp16": torch.float16, "fp32": torch.float32}[prec]
     Qh = torch.from_numpy(Q).to(tdt)
     Qr = Qh.float().numpy()
     means = X.astype(np.float64).mean(0, keepdims=True).astype(np.float32) if M == 1 \
@@ -481,7 +483,7 @@ def test_exhaustive_topk_mfma(L, d, b1, b2, layout, M, prec):
             for i in range(nq):
                 a, b = offs[i], offs[i + 1]
                 check_topk(oracle.IP, ti[i], td[i], allids[a:b], ref[a:b], tol[a:b], k, live)
-    if b2 == 4:   # both levels on the matrix cores need 8-bit residual codes
+    if b2 == 4 and prec != "fp32":   # both levels on the matrix cores need 8-bit residual codes
         with pytest.raises(L.LVQError) as e:
             ix.topk(Qh.cuda(), 10, level=L.LVQ_FULL)
         assert e.value.code == L.LVQ_ERR_UNSUPPORTED
