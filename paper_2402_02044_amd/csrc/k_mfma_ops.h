@@ -102,6 +102,30 @@ __device__ __forceinline__ void code_words(const uint4 &v, uint32_t (&w)[B1 == 8
     }
 }
 
+// The lane's residual bytes of a chunk (8-bit codes, one per first-level
+// position) as words in code_words' order: byte e of word s is the residual
+// code of code 4 s + e.  8-bit first level: the 16 bytes as loaded.  4-bit
+// first level: the 32 bytes hold, at bytes 8w .. 8w + 7, the codes of fields
+// 0..7 of first-level word w, regrouped as fields (0,2,4,6) and (1,3,5,7).
+template <int B1>
+__device__ __forceinline__ void resid_words(const uint4 (&v)[B1 == 8 ? 1 : 2], uint32_t (&w)[B1 == 8 ? 4 : 8])
+{
+    if constexpr (B1 == 8) {
+        w[0] = v[0].x;
+        w[1] = v[0].y;
+        w[2] = v[0].z;
+        w[3] = v[0].w;
+    } else {
+        const uint32_t x[8] = {v[0].x, v[0].y, v[0].z, v[0].w, v[1].x, v[1].y, v[1].z, v[1].w};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            // bytes (0,2) of the low word then (0,2) of the high word; then (1,3), (1,3)
+            w[2 * s] = __builtin_amdgcn_perm(x[2 * s + 1], x[2 * s], 0x06040200u);
+            w[2 * s + 1] = __builtin_amdgcn_perm(x[2 * s + 1], x[2 * s], 0x07050301u);
+        }
+    }
+}
+
 // 32x32 FP32 scores += (32 rows x 2 codes) x (2 positions x 32 queries):
 // lane l gives row (l & 31)'s code and query (l & 31)'s value at K index
 // l >> 5.

@@ -930,8 +930,10 @@ int lvq::host_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, i
     const Format &f = ix->f;
     if (prec != LVQ_FP32) return topk_mfma(ix, q_dev, prec, nq, k, level, ids_dev, dist_dev, s, epoch);
     const bool l2 = ix->cfg.metric == LVQ_L2;
-    // the first-level inner product with one mean runs on the FP32 matrix cores
-    if (!l2 && level == LVQ_PRIMARY && mfma_wide_query_block(f.bits1, f.kpos, LVQ_FP32, k, ix->n_means, ix->lds_max))
+    // the inner product runs on the FP32 matrix cores when the format, k and
+    // the means' c_m table allow
+    if (!l2 && mfma_wide_query_block(f.bits1, level == LVQ_FULL ? f.bits2 : 0, f.kpos, LVQ_FP32, k, ix->n_means,
+                                     ix->lds_max))
         return topk_mfma(ix, q_dev, prec, nq, k, level, ids_dev, dist_dev, s, epoch);
     if (l2 && ix->n_means > 1) return LVQ_ERR_UNSUPPORTED;
     const bool masked = l2 && f.kpos != f.dim;
@@ -1023,7 +1025,7 @@ int lvq_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t
 }  // extern "C"
 
 // Exhaustive top-k on the matrix cores: inner product; bf16 / fp16 queries
-// at either level, FP32 queries at the first level (wide kernel only).
+// at either level, FP32 queries on the wide kernel only.
 static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, int32_t k, int32_t level,
                      int32_t *ids_dev, float *dist_dev, hipStream_t s, uint32_t epoch)
 {
@@ -1031,9 +1033,9 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     if (ix->cfg.metric != LVQ_IP) return LVQ_ERR_UNSUPPORTED;
     const int bits2 = level == LVQ_FULL ? f.bits2 : 0;
     if (bits2 != 0 && bits2 != 8) return LVQ_ERR_UNSUPPORTED;   // both levels need 8-bit residual codes
-    // first level with k <= 512: the wide kernel (queries in LDS); else the
+    // the wide kernel (queries in LDS) when it takes the case; else the
     // register-resident kernel (16-bit queries only)
-    const int qbw = bits2 == 0 ? mfma_wide_query_block(f.bits1, f.kpos, prec, k, ix->n_means, ix->lds_max) : 0;
+    const int qbw = mfma_wide_query_block(f.bits1, bits2, f.kpos, prec, k, ix->n_means, ix->lds_max);
     if (prec == LVQ_FP32 && !qbw) return LVQ_ERR_UNSUPPORTED;
     const int qb = qbw ? qbw : mfma_query_block(f.bits1, bits2, f.kpos);
     if (!qb) return LVQ_ERR_UNSUPPORTED;
@@ -1098,7 +1100,7 @@ static int topk_mfma(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq,
     ix->last_parts = (int32_t)parts;
     if ((rc = timing_begin(ix, s))) return rc;
     if (qbw)
-        LVQ_HIP(launch_scan_mfma_wide(a, f.bits1, prec, grid, s));
+        LVQ_HIP(launch_scan_mfma_wide(a, f.bits1, bits2, prec, grid, ix->lds_max, s));
     else
         LVQ_HIP(launch_scan_mfma(a, f.bits1, bits2, prec, s));
     if ((rc = timing_end(ix, s))) return rc;
@@ -1377,10 +1379,12 @@ int lvq::host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_fi
     if (prec == LVQ_FP32) {
         for (int64_t nq = 1; nq <= max_nq; ++nq)
             part = std::max(part, sizeof(uint64_t) * (size_t)(nq * scan_parts_fp32(ix, nq, k_first, n_rows) * k_first));
-        // the FP32 matrix-core scan (first-level inner product while the
-        // index has one mean)
-        const int qbf = scan_level == LVQ_PRIMARY && ix->cfg.metric == LVQ_IP
-                            ? mfma_wide_query_block(f.bits1, f.kpos, LVQ_FP32, k_first, 1, ix->lds_max)
+        // the FP32 matrix-core scan (inner product; its query block does not
+        // depend on the mean count, which only decides whether the c_m table
+        // fits)
+        const int qbf = ix->cfg.metric == LVQ_IP
+                            ? mfma_wide_query_block(f.bits1, scan_level == LVQ_FULL ? f.bits2 : 0, f.kpos, LVQ_FP32,
+                                                    k_first, 1, ix->lds_max)
                             : 0;
         if (qbf) {
             const int64_t tq = 32 * qbf;
@@ -1395,13 +1399,13 @@ int lvq::host_reserve(lvq_index *ix, hipStream_t s, int64_t max_nq, int32_t k_fi
         }
     } else {
         const int bits2 = scan_level == LVQ_FULL ? f.bits2 : 0;
-        const int qbw = bits2 == 0 ? mfma_wide_query_block(f.bits1, f.kpos, prec, k_first, kMaxMeans, ix->lds_max) : 0;
+        const int qbw = mfma_wide_query_block(f.bits1, bits2, f.kpos, prec, k_first, kMaxMeans, ix->lds_max);
         const int qb = qbw ? qbw : mfma_query_block(f.bits1, bits2, f.kpos);
         if (!qb) return LVQ_ERR_UNSUPPORTED;
         // the wide kernel when it takes any mean count the index may reach;
         // else reserve for both kernels (the register-resident one serves
         // what the wide one cannot)
-        const int qbw_any = bits2 == 0 ? mfma_wide_query_block(f.bits1, f.kpos, prec, k_first, 1, ix->lds_max) : 0;
+        const int qbw_any = mfma_wide_query_block(f.bits1, bits2, f.kpos, prec, k_first, 1, ix->lds_max);
         const int qbo = mfma_query_block(f.bits1, bits2, f.kpos);
         for (int kind = 0; kind < 2; ++kind) {
             const bool wide = kind == 0;

@@ -275,20 +275,23 @@ MfmaKernelPtr mfma_kernel_full(int bits1, int kpos, int fp16, int *qb);
 int mfma_query_block(int bits1, int bits2, int kpos);
 size_t mfma_lds_bytes(int qb, int n_means, int k, int capq);
 int mfma_capq(int qb, int n_means, int k, size_t lds_max);
-// The wide matrix-core scan (first level, queries staged in LDS, k <= 512;
-// prec LVQ_BF16 / LVQ_FP16, or LVQ_FP32 on the FP32 MFMA): 32-query blocks
-// per workgroup (0 when the format, precision, k or the LDS bytes rule it
-// out), the sorted keys kept per query (k rounded up to a power of two, at
-// least 64) and the key-region capacity per query, and the launch of a
-// persistent grid (a multiple of 8 workgroups, each owning 32*qb*cap keys of
-// a.mkeys; a.mks and a.mcap as these functions give them).  The FP32 form
-// reads a.q16 as the fragments launch_frag32 writes from kernel-order
-// queries (nq x kpos FP32, as prep_queries leaves them): 32*qb*kpos*4 bytes
-// per tile of 32*qb queries.
-int mfma_wide_query_block(int bits1, int kpos, int prec, int k, int n_means, size_t lds_max);
+// The wide matrix-core scan (queries staged in LDS, inner product, k <=
+// 512): prec LVQ_BF16 / LVQ_FP16 at the first level with one mean, or
+// LVQ_FP32 on the FP32 MFMA at the first level (bits2 0) or both levels
+// (bits2 8) with any mean count whose c_m table fits the LDS.  The 32-query
+// blocks per workgroup (0 when the format, precision, k, means or the LDS
+// bytes rule it out), the sorted keys kept per query (k rounded up to a
+// power of two, at least 64) and the key-region capacity per query, and the
+// launch of a persistent grid (a multiple of 8 workgroups, each owning
+// 32*qb*cap keys of a.mkeys; a.mks and a.mcap as these functions give them).
+// The FP32 forms read a.q16 as the fragments launch_frag32 writes from
+// kernel-order queries (nq x kpos FP32, as prep_queries leaves them):
+// 32*qb*kpos*4 bytes per tile of 32*qb queries; and a.cm as nq x n_means.
+int mfma_wide_query_block(int bits1, int bits2, int kpos, int prec, int k, int n_means, size_t lds_max);
 int mfma_wide_sorted(int k);
 int mfma_wide_cap(int k);
-hipError_t launch_scan_mfma_wide(const ScanArgs &a, int bits1, int prec, int64_t grid, hipStream_t s);
+hipError_t launch_scan_mfma_wide(const ScanArgs &a, int bits1, int bits2, int prec, int64_t grid, size_t lds_max,
+                                 hipStream_t s);
 hipError_t launch_frag32(const float *qk, int64_t nq, int kpos, int bits1, int qb, void *frag, hipStream_t s);
 hipError_t launch_prep16(const void *q, int64_t nq, int dim, int kpos, int bits1, int qb, int prec,
                          const int32_t *kdim, const float *means, int n_means, void *frag, float *qsum, float *cm,

@@ -436,6 +436,7 @@ MFMA_CASES = [
     (256, 8, 8, oracle.SEQUENTIAL, 3),
     (512, 4, 8, oracle.TURBO, 1),
     (128, 4, 4, oracle.TURBO, 1),
+    (384, 4, 0, oracle.TURBO, 1),   # six chunks of 64 positions: a three-chunk ring
 ]
 
 
