@@ -13,7 +13,8 @@ LIB = os.path.join(HERE, "liblvq.so")
 
 SOURCES = ["lvq_host.hip", "k_encode.hip", "k_misc.hip", "k_cand4.hip", "k_cand8.hip",
            "k_scan4.hip", "k_scan8.hip", "k_mfma.hip", "k_mfma_full.hip", "k_mfma_wide.hip", "k_mfma_wide32.hip",
-           "k_mfma_wide32r.hip", "lvq_serve.hip", "k_probe.hip", "k_graph.hip",
+           "k_mfma_wide32r.hip", "k_mfma_wide16r.hip",
+           "lvq_serve.hip", "k_probe.hip", "k_graph.hip",
            "lvq_noalloc.hip"]
 # binary32 encoding must round every operation on its own
 EXTRA = {"k_encode.hip": ["-ffp-contract=off"], "k_probe.hip": ["-ffp-contract=off"]}

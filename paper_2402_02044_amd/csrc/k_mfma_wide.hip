@@ -1,6 +1,6 @@
 // k_mfma_wide.hip -- the queries-in-LDS matrix-core scan (k_mfma_wide_impl.h):
-// bf16 / fp16 instantiations, the FP32 query fragments, and the host-side
-// helpers and launch of every form.
+// bf16 / fp16 first-level instantiations, the FP32 query fragments, and the
+// host-side helpers and launch of every form.
 #include "k_mfma_wide_impl.h"
 
 namespace lvq {
@@ -23,7 +23,7 @@ WideKernel wide_lookup_16(int kpos, int *qb, int *rb)
     }
 }
 
-// prec LVQ_BF16 / LVQ_FP16 (first level) or LVQ_FP32 (bits2 0 or 8).
+// prec LVQ_BF16 / LVQ_FP16 or LVQ_FP32; bits2 0 (first level) or 8.
 WideKernel wide_kernel(int bits1, int bits2, int kpos, int prec, int *qb, int *rb)
 {
     if (bits1 != 4 && bits1 != 8) return nullptr;
@@ -32,16 +32,20 @@ WideKernel wide_kernel(int bits1, int bits2, int kpos, int prec, int *qb, int *r
         if (bits2 == 8) return wide_kernel_f32r(bits1, kpos, qb, rb);
         return nullptr;
     }
+    if (bits2 == 8) return wide_kernel_16r(bits1, kpos, prec, qb, rb);
     if (bits2 != 0) return nullptr;
     if (prec == LVQ_BF16) return bits1 == 8 ? wide_lookup_16<8, LVQ_BF16>(kpos, qb, rb) : wide_lookup_16<4, LVQ_BF16>(kpos, qb, rb);
     if (prec == LVQ_FP16) return bits1 == 8 ? wide_lookup_16<8, LVQ_FP16>(kpos, qb, rb) : wide_lookup_16<4, LVQ_FP16>(kpos, qb, rb);
     return nullptr;
 }
 
-// LDS bytes of a launch: FP32 forms carry the c_m table of every mean.
-size_t wide_lds(int qb, int kpos, int rb, int prec, int n_means)
+// LDS bytes of a launch: FP32 and both-level forms carry the c_m table of
+// every mean (and each row's mean id); 16-bit both-level forms each row's
+// Delta2.
+size_t wide_lds(int qb, int kpos, int rb, int prec, int bits2, int n_means)
 {
-    return prec == LVQ_FP32 ? wide_lds_bytes(qb, kpos, rb, 4, n_means) : wide_lds_bytes(qb, kpos, rb, 2, 0);
+    const bool mm = prec == LVQ_FP32 || bits2 != 0, ch2 = prec != LVQ_FP32 && bits2 != 0;
+    return wide_lds_bytes(qb, kpos, rb, prec == LVQ_FP32 ? 4 : 2, mm ? n_means : 0, 12 + (mm ? 4 : 0) + (ch2 ? 4 : 0));
 }
 
 // FP32 query fragments from kernel-order queries (nq x kpos, zero at padding
@@ -73,10 +77,10 @@ __global__ __launch_bounds__(256) void k_frag32(const float *qk, int64_t nq, int
 int mfma_wide_query_block(int bits1, int bits2, int kpos, int prec, int k, int n_means, size_t lds_max)
 {
     if ((bits1 != 4 && bits1 != 8) || kpos % (bits1 == 8 ? 32 : 64)) return 0;
-    if (k < 1 || k > kWideMaxK || n_means < 1 || (prec != LVQ_FP32 && n_means != 1)) return 0;
+    if (k < 1 || k > kWideMaxK || n_means < 1 || (prec != LVQ_FP32 && bits2 == 0 && n_means != 1)) return 0;
     int qb = 0, rb = 0;
     if (!wide_kernel(bits1, bits2, kpos, prec, &qb, &rb)) return 0;
-    return wide_lds(qb, kpos, rb, prec, n_means) <= lds_max ? qb : 0;
+    return wide_lds(qb, kpos, rb, prec, bits2, n_means) <= lds_max ? qb : 0;
 }
 
 int mfma_wide_sorted(int k)
@@ -97,9 +101,9 @@ hipError_t launch_scan_mfma_wide(const ScanArgs &a, int bits1, int bits2, int pr
     int qb = 0, rb = 0;
     WideKernel kern = wide_kernel(bits1, bits2, a.kpos, prec, &qb, &rb);
     if (!kern || grid < 8 || grid % 8 || a.k < 1 || a.k > kWideMaxK || a.mks != mfma_wide_sorted(a.k) ||
-        a.mcap != mfma_wide_cap(a.k) || a.n_means < 1 || (prec != LVQ_FP32 && a.n_means != 1))
+        a.mcap != mfma_wide_cap(a.k) || a.n_means < 1 || (prec != LVQ_FP32 && bits2 == 0 && a.n_means != 1))
         return hipErrorInvalidValue;
-    const size_t lds = wide_lds(qb, a.kpos, rb, prec, a.n_means);
+    const size_t lds = wide_lds(qb, a.kpos, rb, prec, bits2, a.n_means);
     if (lds > lds_max) return hipErrorInvalidValue;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * wide_waves(rb)), lds, s, a);
     return hipGetLastError();

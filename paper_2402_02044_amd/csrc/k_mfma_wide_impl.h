@@ -152,22 +152,24 @@ __device__ __forceinline__ int merge_region_ks(int ks, uint64_t *rq, int poff, i
 }
 
 // LDS bytes of a workgroup: query fragments (esize bytes per value),
-// per-wave row constants (l, Delta, slot of its rows; with a c_m table also
-// their mean ids), per-query bounds and pending counts, and the c_m table
-// ([mean][query], n_tab means; 0 for none).
-__host__ __device__ constexpr size_t wide_lds_bytes(int qb, int kpos, int rb, int esize, int n_tab)
+// per-wave row constants (row_bytes per row: l, Delta, slot; with a c_m table
+// also the mean id; with a residual chain also Delta2), per-query bounds and
+// pending counts, and the c_m table ([mean][query], n_tab means; 0 for none).
+__host__ __device__ constexpr size_t wide_lds_bytes(int qb, int kpos, int rb, int esize, int n_tab, int row_bytes)
 {
-    return (size_t)32 * qb * kpos * esize + (size_t)wide_waves(rb) * 32 * rb * (n_tab ? 16 : 12) +
-           (size_t)32 * qb * 8 + (size_t)32 * qb * n_tab * 4;
+    return (size_t)32 * qb * kpos * esize + (size_t)wide_waves(rb) * 32 * rb * row_bytes + (size_t)32 * qb * 8 +
+           (size_t)32 * qb * n_tab * 4;
 }
 
 template <int B1, int B2, int KPOS, int QB, int RB, int PREC>
 __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanArgs a)
 {
     constexpr bool F32 = PREC == LVQ_FP32, FP16 = PREC == LVQ_FP16;
-    constexpr bool MM = F32;      // several means: c_m of (row mean, query) from the LDS table
-    constexpr bool DEC = B2 != 0; // A values Delta c1 + Delta2 c2 decoded per lane
-    static_assert(!DEC || (F32 && B2 == 8), "both levels: FP32 queries, 8-bit residual codes");
+    constexpr bool RES = B2 != 0;         // both levels: residual codes read with the codes
+    constexpr bool DEC = RES && F32;      // FP32: A values Delta c1 + Delta2 c2 decoded per lane
+    constexpr bool CH2 = RES && !F32;     // 16-bit: a second accumulator chain for the residual codes
+    constexpr bool MM = F32 || RES;       // several means: c_m of (row mean, query) from the LDS table
+    static_assert(!RES || B2 == 8, "both levels: 8-bit residual codes");
     constexpr int WAVES = wide_waves(RB);
     constexpr int RW = 32 * RB;               // rows per wave and round
     constexpr int RROUND = WAVES * RW;        // rows per round
@@ -177,10 +179,10 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
     // 16-byte query fragments per chunk and block: 8 positions each in 16
     // bits, 4 in FP32 (one per lane and MFMA)
     constexpr int STEPS = F32 ? CHUNK_POS / 8 : CHUNK_POS / 16;
-    constexpr int RING = wide_ring(NCHUNK, DEC);
+    constexpr int RING = wide_ring(NCHUNK, RES);
     // residual 16-byte pieces per lane and chunk (one 8-bit code per
     // first-level position)
-    constexpr int RP = DEC ? CHUNK_POS / 32 : 1;
+    constexpr int RP = RES ? CHUNK_POS / 32 : 1;
     constexpr int NFRAG = QB * NCHUNK * STEPS * 64;   // 16-byte fragments per query tile
     static_assert(KPOS % CHUNK_POS == 0, "KPOS");
     static_assert(NCHUNK % RING == 0, "every round starts at ring slot 0");
@@ -192,7 +194,8 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
     float *rd = rl + WAVES * RW;                                    // [wave][RW] Delta (1 when decoded)
     int32_t *rs = reinterpret_cast<int32_t *>(rd + WAVES * RW);     // [wave][RW] slot
     int32_t *rm = rs + WAVES * RW;                                  // [wave][RW] mean id (c_m table)
-    float *thr_f = reinterpret_cast<float *>(rm + (MM ? WAVES * RW : 0));   // TQ admission bounds
+    float *rd2 = reinterpret_cast<float *>(rm + (MM ? WAVES * RW : 0));     // [wave][RW] Delta2 (two chains)
+    float *thr_f = rd2 + (CH2 ? WAVES * RW : 0);                    // TQ admission bounds
     int *cnt = reinterpret_cast<int *>(thr_f + TQ);                 // TQ pending keys
     float *cmt = reinterpret_cast<float *>(cnt + TQ);               // [mean][TQ] c_m
 
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
     const int k = a.k, cap = a.mcap, ks = a.mks;
     const bool one_mean = a.n_means == 1;
     uint64_t *region = a.mkeys + (size_t)blockIdx.x * TQ * cap;
-    float *wl = rl + wave * RW, *wd = rd + wave * RW;
+    float *wl = rl + wave * RW, *wd = rd + wave * RW, *wd2 = rd2 + wave * RW;
     int32_t *ws = rs + wave * RW, *wm = rm + wave * RW;
 
     const int64_t qtiles = (a.nq + TQ - 1) / TQ;
@@ -274,18 +277,20 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
             const uint8_t *p = codes(sc[j]);
 #pragma unroll
             for (int c = 0; c < RING; ++c) ring[c][j] = *reinterpret_cast<const uint4 *>(p + c * 32);
-            if constexpr (DEC) {
+            if constexpr (RES) {
                 const uint8_t *r = resid(sc[j]);
 #pragma unroll
                 for (int c = 0; c < RING; ++c)
 #pragma unroll
                     for (int w = 0; w < RP; ++w)
                         rring[c][j][w] = *reinterpret_cast<const uint4 *>(r + c * 32 * RP + 16 * w);
+            }
+            if constexpr (DEC) {
                 hd[j] = *reinterpret_cast<const float4 *>(header(sc[j]));
                 ep[j] = *reinterpret_cast<const uint2 *>(header(sc[j]) + 16);
             }
         }
-        f32x16 acc[RB][QB];
+        f32x16 acc[RB][QB], acc2[CH2 ? RB : 1][CH2 ? QB : 1];
         for (int64_t base = r0; base < r1; base += RROUND) {
             const bool last = base + RROUND >= r1;
             int32_t sa[RB];
@@ -296,7 +301,10 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
 #pragma unroll
                 for (int b = 0; b < QB; ++b)
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) acc[j][b][i] = 0.0f;
+                    for (int i = 0; i < 16; ++i) {
+                        acc[j][b][i] = 0.0f;
+                        if constexpr (CH2) acc2[j][b][i] = 0.0f;
+                    }
             // decoding scales of the lane's own rows
             float s1[RB], s2[RB];
 #pragma unroll
@@ -333,7 +341,7 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                     const bool cur = c + RING < NCHUNK;
                     const int cn = cur ? c + RING : c + RING - NCHUNK;
                     ring[c % RING][j] = *reinterpret_cast<const uint4 *>(codes(cur ? sc[j] : sn[j]) + cn * 32);
-                    if constexpr (DEC) {
+                    if constexpr (RES) {
                         const uint8_t *r = resid(cur ? sc[j] : sn[j]) + cn * 32 * RP;
 #pragma unroll
                         for (int w = 0; w < RP; ++w) {
@@ -381,14 +389,20 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                 } else {
 #pragma unroll
                     for (int s = 0; s < STEPS; ++s) {
-                        uint4 af[RB];
+                        uint4 af[RB], af2[RB];
 #pragma unroll
-                        for (int j = 0; j < RB; ++j) af[j] = b_fragment<B1, FP16>(v[j], s);
+                        for (int j = 0; j < RB; ++j) {
+                            af[j] = b_fragment<B1, FP16>(v[j], s);
+                            if constexpr (CH2) af2[j] = r_fragment<B1, FP16>(rv[j], s);
+                        }
 #pragma unroll
                         for (int b = 0; b < QB; ++b) {
                             const uint4 bq = qf[((b * NCHUNK + c) * STEPS + s) * 64 + lane];
 #pragma unroll
-                            for (int j = 0; j < RB; ++j) acc[j][b] = mfma<FP16>(af[j], bq, acc[j][b]);
+                            for (int j = 0; j < RB; ++j) {
+                                acc[j][b] = mfma<FP16>(af[j], bq, acc[j][b]);
+                                if constexpr (CH2) acc2[j][b] = mfma<FP16>(af2[j], bq, acc2[j][b]);
+                            }
                         }
                     }
                 }
@@ -412,8 +426,9 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                 const uint32_t f = __float_as_uint(H.w);
                 const bool live = base + wrow + 32 * j < r1 && ((f >> 8) & 1u) && E.x <= a.epoch && a.epoch < E.y;
                 if (half == 0) {
-                    wl[32 * j + col] = live ? (DEC ? H.x - 0.5f * H.y : H.x) : __builtin_nanf("");
+                    wl[32 * j + col] = live ? (RES ? H.x - 0.5f * H.y : H.x) : __builtin_nanf("");
                     ws[32 * j + col] = sc[j];
+                    if constexpr (CH2) wd2[32 * j + col] = H.z;
                 } else {
                     wd[32 * j + col] = DEC ? 1.0f : H.y;
                     if constexpr (MM) {
@@ -441,8 +456,10 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                         if constexpr (TAB) return cmt[m * TQ + 32 * b + col];
                         else return cq[b];
                     };
-                    auto score = [&](int b, int i, float l, float dlt, int m) {
-                        return fmaf(dlt, acc[j][b][i], fmaf(l, qs[b], cmv(b, m)));
+                    auto score = [&](int b, int i, float l, float dlt, float d2, int m) {
+                        const float t = fmaf(dlt, acc[j][b][i], fmaf(l, qs[b], cmv(b, m)));
+                        if constexpr (CH2) return fmaf(d2, acc2[j][b][i], t);
+                        else return t;
                     };
                     float mx[QB];
 #pragma unroll
@@ -453,13 +470,16 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                         const float4 D = *reinterpret_cast<const float4 *>(wd + 32 * j + 8 * g + 4 * half);
                         int4 M4 = make_int4(0, 0, 0, 0);
                         if constexpr (TAB) M4 = *reinterpret_cast<const int4 *>(wm + 32 * j + 8 * g + 4 * half);
+                        float4 D2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                        if constexpr (CH2) D2 = *reinterpret_cast<const float4 *>(wd2 + 32 * j + 8 * g + 4 * half);
                         const float lr[4] = {L.x, L.y, L.z, L.w}, dr[4] = {D.x, D.y, D.z, D.w};
+                        const float d2r[4] = {D2.x, D2.y, D2.z, D2.w};
                         const int mr[4] = {M4.x, M4.y, M4.z, M4.w};
 #pragma unroll
                         for (int b = 0; b < QB; ++b)
 #pragma unroll
                             for (int r4 = 0; r4 < 4; ++r4) {
-                                const float sv = score(b, 4 * g + r4, lr[r4], dr[r4], mr[r4]);
+                                const float sv = score(b, 4 * g + r4, lr[r4], dr[r4], d2r[r4], mr[r4]);
                                 mx[b] = sv > mx[b] ? sv : mx[b];
                             }
                     }
@@ -472,7 +492,7 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
 #pragma unroll 4
                         for (int i = 0; i < 16; ++i) {
                             const int m = 32 * j + 8 * (i >> 2) + 4 * half + (i & 3);
-                            np += score(b, i, wl[m], wd[m], TAB ? wm[m] : 0) >= tau[b] ? 1 : 0;
+                            np += score(b, i, wl[m], wd[m], CH2 ? wd2[m] : 0.0f, TAB ? wm[m] : 0) >= tau[b] ? 1 : 0;
                         }
                         const int qi = 32 * b + col;
                         int pos = np ? atomicAdd(&cnt[qi], np) : 0;
@@ -480,7 +500,7 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
 #pragma unroll 4
                         for (int i = 0; i < 16; ++i) {
                             const int m = 32 * j + 8 * (i >> 2) + 4 * half + (i & 3);
-                            const float sv = score(b, i, wl[m], wd[m], TAB ? wm[m] : 0);
+                            const float sv = score(b, i, wl[m], wd[m], CH2 ? wd2[m] : 0.0f, TAB ? wm[m] : 0);
                             if (sv >= tau[b]) {
                                 if (pos < kWidePending) dst[pos] = make_key(sv, ws[m], LVQ_IP);
                                 ++pos;
@@ -545,11 +565,13 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
 
 using WideKernel = void (*)(ScanArgs);
 
-// FP32 instantiations, by first-level bits and position count (nullptr when
-// not instantiated; *qb = 32-query blocks per workgroup, *rb = row blocks per
-// wave): first level (k_mfma_wide32.hip), both levels with 8-bit residual
-// codes (k_mfma_wide32r.hip).
+// Instantiations in their own units, by first-level bits and position count
+// (nullptr when not instantiated; *qb = 32-query blocks per workgroup, *rb =
+// row blocks per wave): FP32 first level (k_mfma_wide32.hip), FP32 both
+// levels with 8-bit residual codes (k_mfma_wide32r.hip), bf16 / fp16 both
+// levels (k_mfma_wide16r.hip, prec LVQ_BF16 or LVQ_FP16).
 WideKernel wide_kernel_f32(int bits1, int kpos, int *qb, int *rb);
 WideKernel wide_kernel_f32r(int bits1, int kpos, int *qb, int *rb);
+WideKernel wide_kernel_16r(int bits1, int kpos, int prec, int *qb, int *rb);
 
 }  // namespace lvq
