@@ -617,19 +617,21 @@ def bench_c4(args):
     assert ix.sync() == 0
     qf = torch.from_numpy(Q).to(dev)
     res = {}
-    forms = [f for f in (("bf16", torch.bfloat16), ("fp16", torch.float16), ("fp32", torch.float32))
+    # fp32: FP32 on the matrix cores; fp32_plain: the plain FP32 vector kernel
+    forms = [f for f in (("bf16", torch.bfloat16), ("fp16", torch.float16), ("fp32", torch.float32),
+                         ("fp32_plain", torch.float32))
              if f[0] in args.forms.split(",")]
     for name, tdt in forms:
         q = qf.to(tdt)
         ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
         dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
-        prec = {"bf16": L.LVQ_BF16, "fp16": L.LVQ_FP16, "fp32": L.LVQ_FP32}[name]
+        prec = {"bf16": L.LVQ_BF16, "fp16": L.LVQ_FP16, "fp32": L.LVQ_FP32, "fp32_plain": L.LVQ_FP32_VALU}[name]
         s = int(torch.cuda.current_stream().cuda_stream)
 
         def step():
             L.lvq_topk(ix.handle, q.data_ptr(), prec, nq, k, L.LVQ_PRIMARY, ids.data_ptr(), dist.data_ptr(), s)
 
-        steps = args.steps if name != "fp32" else max(1, args.steps // 4)
+        steps = {"fp32": max(1, args.steps // 4), "fp32_plain": max(1, args.steps // 15)}.get(name, args.steps)
         ms, k_ms = timed(step, steps, 1, ix)
         assert ix.sync() == 0
         res[name] = (ms, k_ms, ids.cpu().numpy(), dist.cpu().numpy())
@@ -641,7 +643,7 @@ def bench_c4(args):
     acc = {}
     for name, (ms, k_ms, ids, dist) in res.items():
         tf = 2.0 * d * n * nq / (k_ms / 1000.0) / 1e12
-        peak = FP32_PEAK_TFLOPS if name == "fp32" else MFMA_BF16_PEAK_TFLOPS
+        peak = FP32_PEAK_TFLOPS if name.startswith("fp32") else MFMA_BF16_PEAK_TFLOPS
         acc[name] = {"recall_at_100": recall_at_k(ids[:ns], gt), "ms_per_step": ms, "kernel_ms": k_ms,
                      "distances_per_s": n * nq / (ms / 1000.0), "kernel_tflops": tf,
                      "frac_of_dense_peak": tf / peak, "peak_tflops": peak}
@@ -673,11 +675,12 @@ def bench_c4(args):
     ms, k_ms = res[main_form][0], res[main_form][1]
     flops = 2.0 * d * n * nq
     achieved = flops / (k_ms / 1000.0) / 1e12
-    peak = FP32_PEAK_TFLOPS if main_form == "fp32" else MFMA_BF16_PEAK_TFLOPS
+    peak = FP32_PEAK_TFLOPS if main_form.startswith("fp32") else MFMA_BF16_PEAK_TFLOPS
     out = line(n * nq / (ms / 1000.0), "distances/s", args.steps, 1, ms, main_form,
                {"workload": "exhaustive inner-product top-100 over n=5,000,000 d=512 LVQ-8 codes (anisotropic "
-                            "unit vectors), 10,000 queries in bf16 on MFMA with FP32 accumulation; fp16 and "
-                            "FP32 queries (FP32 MFMA) on the same store", "n": n, "dim": d, "queries": nq, "k": k},
+                            "unit vectors), 10,000 queries in bf16 on MFMA with FP32 accumulation; fp16, "
+                            "FP32 queries on the FP32 MFMA, and the plain FP32 vector kernel on the same store",
+                "n": n, "dim": d, "queries": nq, "k": k},
                {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None,
                 "kernel": "k_scan_mfma_wide (%s, fused top-100)" % main_form, "kernel_ms": k_ms},
@@ -1714,7 +1717,8 @@ def main():
     ap.add_argument("--sat-batches", type=int, default=60, help="c5: batches of each saturation burst")
     ap.add_argument("--lat-batches", type=int, default=120, help="c5: batches of each latency phase")
     ap.add_argument("--level", default="full", choices=["full", "primary"])
-    ap.add_argument("--forms", default="bf16,fp16,fp32", help="c4: query precisions to run (comma list)")
+    ap.add_argument("--forms", default="bf16,fp16,fp32,fp32_plain",
+                    help="c4: query precisions to run (comma list; fp32_plain = the FP32 vector kernel)")
     ap.add_argument("--align", type=int, default=32)
     ap.add_argument("--n", type=int, default=0, help="override the store size (testing)")
     ap.add_argument("--nq", type=int, default=0, help="override the query count (testing)")

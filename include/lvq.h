@@ -58,7 +58,9 @@ typedef struct lvq_index lvq_index;            /* opaque, owned by the library *
 typedef enum { LVQ_L2 = 0, LVQ_IP = 1 } lvq_metric;
 typedef enum { LVQ_SEQUENTIAL = 0, LVQ_TURBO = 1 } lvq_layout;
 typedef enum { LVQ_PRIMARY = 1, LVQ_FULL = 2 } lvq_level;
-typedef enum { LVQ_FP32 = 0, LVQ_BF16 = 1, LVQ_FP16 = 2 } lvq_precision;
+/* LVQ_FP32_VALU: FP32 on the vector ALUs only (the plain kernel), for
+ * lvq_topk; it computes what LVQ_FP32 computes, in another order. */
+typedef enum { LVQ_FP32 = 0, LVQ_BF16 = 1, LVQ_FP16 = 2, LVQ_FP32_VALU = 3 } lvq_precision;
 
 enum {
     LVQ_OK = 0,
@@ -220,7 +222,8 @@ int lvq_tile_shape(int32_t shape, int32_t *lanes, int32_t *piece_bytes, int32_t 
  * accumulation (inner product; both levels need 8-bit residual codes).
  * 1 <= k <= 1024 (the per-query candidate buffers must fit the LDS:
  * LVQ_ERR_UNSUPPORTED otherwise).  Output ids_dev / dist_dev nq x k, padded
- * as for lvq_distances.                                                    */
+ * as for lvq_distances.  LVQ_FP32_VALU takes float queries on the vector
+ * path whatever the format (the plain FP32 kernel, for comparisons).        */
 int lvq_topk(lvq_index *index, const void *q_dev, int32_t prec, int64_t nq, int32_t k,
              int32_t level, int32_t *ids_dev, float *dist_dev, void *stream);
 

@@ -24,7 +24,7 @@ TILE_CACHE = os.path.join(HERE, "tile_cache.json")
 LVQ_L2, LVQ_IP = 0, 1
 LVQ_SEQUENTIAL, LVQ_TURBO = 0, 1
 LVQ_PRIMARY, LVQ_FULL = 1, 2
-LVQ_FP32, LVQ_BF16, LVQ_FP16 = 0, 1, 2
+LVQ_FP32, LVQ_BF16, LVQ_FP16, LVQ_FP32_VALU = 0, 1, 2, 3
 
 LVQ_OK = 0
 LVQ_ERR_INVALID_ARG = -1
@@ -492,9 +492,15 @@ class Index:
                       _ptr(ti), _ptr(td), _stream(stream))
         return dist, ti, td
 
-    def topk(self, q, k, level=LVQ_PRIMARY, stream=None):
+    def topk(self, q, k, level=LVQ_PRIMARY, stream=None, plain=False):
+        """Exhaustive top-k; the query dtype picks the precision (plain: FP32
+        on the vector ALUs only)."""
         import torch
         prec = {torch.float32: LVQ_FP32, torch.bfloat16: LVQ_BF16, torch.float16: LVQ_FP16}[q.dtype]
+        if plain:
+            if prec != LVQ_FP32:
+                raise ValueError("plain takes float32 queries")
+            prec = LVQ_FP32_VALU
         nq = q.shape[0]
         ids = torch.empty((nq, k), dtype=torch.int32, device=q.device)
         dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)

@@ -923,18 +923,22 @@ int lvq::host_topk(lvq_index *ix, const void *q_dev, int32_t prec, int64_t nq, i
 {
     if (nq < 0 || nq > INT32_MAX || k < 1 || k > kMaxTopK) return LVQ_ERR_INVALID_ARG;
     if (level != LVQ_PRIMARY && level != LVQ_FULL) return LVQ_ERR_INVALID_ARG;
-    if (prec != LVQ_FP32 && prec != LVQ_BF16 && prec != LVQ_FP16) return LVQ_ERR_INVALID_ARG;
+    if (prec != LVQ_FP32 && prec != LVQ_BF16 && prec != LVQ_FP16 && prec != LVQ_FP32_VALU)
+        return LVQ_ERR_INVALID_ARG;
     if (nq == 0) return LVQ_OK;
     if (!q_dev || !ids_dev || !dist_dev) return LVQ_ERR_INVALID_ARG;
     if (level == LVQ_FULL && ix->f.bits2 == 0) return LVQ_ERR_INVALID_ARG;
     const Format &f = ix->f;
-    if (prec != LVQ_FP32) return topk_mfma(ix, q_dev, prec, nq, k, level, ids_dev, dist_dev, s, epoch);
+    if (prec == LVQ_BF16 || prec == LVQ_FP16)
+        return topk_mfma(ix, q_dev, prec, nq, k, level, ids_dev, dist_dev, s, epoch);
     const bool l2 = ix->cfg.metric == LVQ_L2;
     // the inner product runs on the FP32 matrix cores when the format, k and
     // the means' c_m table allow
-    if (!l2 && mfma_wide_query_block(f.bits1, level == LVQ_FULL ? f.bits2 : 0, f.kpos, LVQ_FP32, k, ix->n_means,
-                                     ix->lds_max))
-        return topk_mfma(ix, q_dev, prec, nq, k, level, ids_dev, dist_dev, s, epoch);
+    // (LVQ_FP32_VALU: the vector path whatever the format)
+    if (prec == LVQ_FP32 && !l2 &&
+        mfma_wide_query_block(f.bits1, level == LVQ_FULL ? f.bits2 : 0, f.kpos, LVQ_FP32, k, ix->n_means,
+                              ix->lds_max))
+        return topk_mfma(ix, q_dev, LVQ_FP32, nq, k, level, ids_dev, dist_dev, s, epoch);
     if (l2 && ix->n_means > 1) return LVQ_ERR_UNSUPPORTED;
     const bool masked = l2 && f.kpos != f.dim;
     const int variant = !l2 ? 0 : (masked ? 2 : 1);

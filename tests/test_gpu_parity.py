@@ -329,15 +329,17 @@ def test_exhaustive_topk(L, d, b1, b2, layout, metric, M):
     live[dead] = False
     offs = np.arange(nq + 1, dtype=np.int64) * n
     allids = np.tile(np.arange(n, dtype=np.int32), nq)
-    for level in ([oracle.PRIMARY, oracle.FULL] if b2 else [oracle.PRIMARY]):
-        ref, tol = pair_reference(fmt, metric, level, Q, rows, resid, means, offs, allids)
-        for k in (1, 10, 100):
-            ti, td = ix.topk(torch.from_numpy(Q).cuda(), k, level=level)
-            assert ix.sync() == 0
-            ti, td = ti.cpu().numpy(), td.cpu().numpy()
-            for i in range(nq):
-                a, b = offs[i], offs[i + 1]
-                check_topk(metric, ti[i], td[i], allids[a:b], ref[a:b], tol[a:b], k, live)
+    # inner product: the FP32 matrix cores and the plain vector kernel
+    for plain in ((False, True) if metric == oracle.IP else (False,)):
+        for level in ([oracle.PRIMARY, oracle.FULL] if b2 else [oracle.PRIMARY]):
+            ref, tol = pair_reference(fmt, metric, level, Q, rows, resid, means, offs, allids)
+            for k in (1, 10, 100):
+                ti, td = ix.topk(torch.from_numpy(Q).cuda(), k, level=level, plain=plain)
+                assert ix.sync() == 0
+                ti, td = ti.cpu().numpy(), td.cpu().numpy()
+                for i in range(nq):
+                    a, b = offs[i], offs[i + 1]
+                    check_topk(metric, ti[i], td[i], allids[a:b], ref[a:b], tol[a:b], k, live)
     ix.close()
 
 
