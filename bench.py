@@ -1694,7 +1694,7 @@ def bench_c5(args):
                 "n0": n0, "dim": 768, "rounds": rounds, "inserts_per_round": ins, "slots": SLOTS,
                 "max_batch": MAXB, "k": K, "k_first": KF},
                {"bound": "mfma", "achieved": None, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
-                "traffic": None, "kernel": "k_scan_mfma (two-level exhaustive scan of every batch)"},
+                "traffic": None, "kernel": "k_scan_mfma_wide (two-level exhaustive scan of every batch)"},
                serving=serving, rounds_record=rec)
     flops = 2.0 * 2 * 768 * rows_scanned * bf["qps_saturation"] / 1e12
     out["roofline"]["achieved"] = flops
