@@ -768,7 +768,7 @@ def bench_means(args):
                             "both-level top-10 of 200 queries of the round's distribution" % ins,
                 "n": n0, "dim": 768, "rounds": rounds, "online_threshold": thr},
                {"bound": "mfma", "achieved": None, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
-                "traffic": None, "kernel": "k_scan_mfma (both levels); value: scan rate during the rounds"},
+                "traffic": None, "kernel": "k_scan_mfma_wide (both levels); value: scan rate during the rounds"},
                policies=res)
     return out
 
