@@ -8,9 +8,8 @@
 namespace lvq {
 namespace {
 
-// Two 32-query blocks per workgroup; one 32-row block per wave and twelve
-// waves, so that both chains' accumulators fit the registers of three waves
-// per SIMD.
+// Two 32-query blocks per workgroup and one 32-row block per wave, so that
+// both chains' accumulators fit a wave's registers.
 template <int B1, int PREC>
 WideKernel lookup_16r(int kpos, int *qb, int *rb)
 {

@@ -47,12 +47,14 @@
 namespace lvq {
 namespace {
 
-// Waves per workgroup by row blocks per wave: three per SIMD with one
-// 32-row block (each query fragment read from LDS feeds one MFMA), two per
-// SIMD with two (it feeds two, at twice the accumulator registers).
-__host__ __device__ constexpr int wide_waves(int rb)
+// Waves per workgroup: two per SIMD, with 256 registers each, whether a
+// wave scores two 32-row blocks per round (each query fragment read from LDS
+// feeds two MFMAs) or one (the both-level 16-bit forms, whose second chain
+// takes the registers of the second block).  Three waves per SIMD with one
+// block each spilled about 80 registers and served 13% fewer queries.
+__host__ __device__ constexpr int wide_waves(int)
 {
-    return rb == 2 ? 8 : 12;
+    return 8;
 }
 // Chunks of codes in flight: a divisor of the chunk count, so that the ring
 // slot of chunk c is c % RING in every round.  Up to four; two when each

@@ -477,9 +477,12 @@ def test_exhaustive_topk_mfma(L, d, b1, b2, layout, M, prec):
     levels = [(oracle.PRIMARY, L.LVQ_PRIMARY)] + ([(oracle.FULL, L.LVQ_FULL)] if b2 == 8 else [])
     for olev, glev in levels:
         ref, tol = pair_reference(fmt, oracle.IP, olev, Qr, rows, resid, means, offs, allids)
-        # k = 300: the first level with one mean keeps 512 sorted keys per
-        # query (the queries-in-LDS kernel)
-        for k in (1, 10, 100) + ((300,) if olev == oracle.PRIMARY and M == 1 else ()):
+        # k = 300 and 512: 512 sorted keys per query in the queries-in-LDS
+        # kernel, which takes the first level and both levels with 8-bit
+        # residual codes, any of these mean counts
+        wide = (olev == oracle.FULL and b2 == 8) or (olev == oracle.PRIMARY and (M == 1 or prec == "fp32"))
+        big = (300,) + ((512,) if M == 1 and olev == oracle.PRIMARY and prec == "bf16" else ())
+        for k in (1, 10, 100) + (big if wide else ()):
             ti, td = ix.topk(Qh.cuda(), k, level=glev)
             assert ix.sync() == 0
             ti, td = ti.cpu().numpy(), td.cpu().numpy()
