@@ -7,16 +7,18 @@ namespace lvq {
 namespace {
 
 // Instantiated position counts: 32-query blocks per workgroup (as many as
-// the query fragments' LDS allows, at most four) and row blocks per wave.
+// the query fragments' LDS allows, at most four) and row blocks per wave
+// (one with four query blocks: two spilled 32 registers and ran 4% slower at
+// C4).
 template <int B1, int PREC>
 WideKernel wide_lookup_16(int kpos, int *qb, int *rb)
 {
     switch (kpos) {
-    case 96: *qb = 4; *rb = 2; return B1 == 8 ? k_scan_mfma_wide<8, 0, 96, 4, 2, PREC> : nullptr;
-    case 128: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 0, 128, 4, 2, PREC>;
-    case 256: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 0, 256, 4, 2, PREC>;
-    case 384: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 0, 384, 4, 2, PREC>;
-    case 512: *qb = 4; *rb = 2; return k_scan_mfma_wide<B1, 0, 512, 4, 2, PREC>;
+    case 96: *qb = 4; *rb = 1; return B1 == 8 ? k_scan_mfma_wide<8, 0, 96, 4, 1, PREC> : nullptr;
+    case 128: *qb = 4; *rb = 1; return k_scan_mfma_wide<B1, 0, 128, 4, 1, PREC>;
+    case 256: *qb = 4; *rb = 1; return k_scan_mfma_wide<B1, 0, 256, 4, 1, PREC>;
+    case 384: *qb = 4; *rb = 1; return k_scan_mfma_wide<B1, 0, 384, 4, 1, PREC>;
+    case 512: *qb = 4; *rb = 1; return k_scan_mfma_wide<B1, 0, 512, 4, 1, PREC>;
     case 768: *qb = 2; *rb = 2; return k_scan_mfma_wide<B1, 0, 768, 2, 2, PREC>;
     case 1024: *qb = 2; *rb = 2; return k_scan_mfma_wide<B1, 0, 1024, 2, 2, PREC>;
     default: return nullptr;

@@ -18,10 +18,11 @@
 // one per 32-query block.  The codes are the A operand and the queries the B
 // operand: lane l then owns query (l & 31) of every block -- its sum(q), c_m
 // (one mean) and admission bound stay in registers -- and rows 8*(i/4) + 4*(l >> 5) +
-// (i % 4), i < 16, of each 32-row block.  A wave scores RB = 2 blocks of 32
-// rows per round, so each query fragment it reads from LDS feeds two MFMAs;
-// its 16-byte code pieces stream through a ring of loads a few chunks ahead,
-// which runs on into the next round's rows.
+// (i % 4), i < 16, of each 32-row block.  A wave scores RB = 1 or 2 blocks
+// of 32 rows per round (two: each query fragment it reads from LDS feeds two
+// MFMAs; one where the accumulators of four query blocks or of two chains
+// take the registers); its 16-byte code pieces stream through a ring of
+// loads a few chunks ahead, which runs on into the next round's rows.
 //
 // Top-k.  Each query keeps, in the workgroup's region of device memory, its
 // KS best keys so far (sorted, KS = k rounded up to a power of two >= 64)
