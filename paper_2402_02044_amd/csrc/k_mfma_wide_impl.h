@@ -3,14 +3,16 @@
 //   <q, x_hat> = c_m + l' sum(q) + <q, y>,
 //   y = Delta c1 (first level, l' = l) or Delta c1 + Delta2 c2 (both levels,
 //   l' = l - Delta / 2).
-// 16-bit forms (first level, one mean): bf16 / fp16 queries times codes
-// converted exactly to the same type (v_mfma_f32_32x32x16), Delta applied to
-// the FP32 accumulator, c_m one value per query.  FP32 forms: FP32 queries
-// times one FP32 value per lane (v_mfma_f32_32x32x2): the exactly converted
-// first-level code (Delta applied to the accumulator) or, at both levels, y
-// decoded per lane as the vector path decodes it (Delta c1 rounded, then
-// fused with Delta2 c2); c_m of the row's mean comes from an LDS table
-// [mean][query], so any number of means whose table fits.
+// 16-bit forms: bf16 / fp16 queries times codes converted exactly to the
+// same type (v_mfma_f32_32x32x16), Delta applied to the FP32 accumulator; at
+// both levels a second accumulator chain takes the residual codes, scaled by
+// Delta2.  FP32 forms: FP32 queries times one FP32 value per lane
+// (v_mfma_f32_32x32x2): the exactly converted first-level code (Delta applied
+// to the accumulator) or, at both levels, y decoded per lane as the vector
+// path decodes it (Delta c1 rounded, then fused with Delta2 c2).  c_m is one
+// value per query with one mean; at both levels and in FP32 the row's mean
+// picks it from an LDS table [mean][query], so any number of means whose
+// table fits.
 //
 // Tiling.  A workgroup of eight waves (two per SIMD) copies the MFMA
 // fragments of TQ = 32*QB queries into LDS once per tile, so every code
@@ -37,8 +39,9 @@
 // barrier, which precedes its appends.  Workgroups are persistent, one per
 // compute unit, and walk the part-major (part, query tile) sequence
 // XCD-aware: the workgroups of one XCD take consecutive tiles, which read
-// the same rows through its L2.  The decoded form also reads each row's
-// residual codes through the ring and its header a round ahead.
+// the same rows through its L2.  The both-level forms also read each row's
+// residual codes through the ring (the decoded FP32 form its header a round
+// ahead).
 #pragma once
 
 #include <type_traits>
@@ -50,9 +53,10 @@ namespace {
 
 // Waves per workgroup: two per SIMD, with 256 registers each, whether a
 // wave scores two 32-row blocks per round (each query fragment read from LDS
-// feeds two MFMAs) or one (the both-level 16-bit forms, whose second chain
-// takes the registers of the second block).  Three waves per SIMD with one
-// block each spilled about 80 registers and served 13% fewer queries.
+// feeds two MFMAs) or one (where four query blocks, or a second accumulator
+// chain, take the registers of the second block).  Three waves per SIMD with
+// one block each spilled about 80 registers in the both-level forms and
+// served 13% fewer queries.
 __host__ __device__ constexpr int wide_waves(int)
 {
     return 8;
