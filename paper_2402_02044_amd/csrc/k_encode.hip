@@ -105,30 +105,32 @@ __device__ __forceinline__ void pack_unit(const float *ts, const Format &f, int 
         const int ds = turbo ? 16 : 1;            // dimension step between fields
 #pragma unroll
         for (int k = 0; k < PER1; ++k) {
+            // Branch-free: every field runs the same sequence, and fields
+            // with no dimension, or a vector with no step, keep code 0.  With
+            // no step inv (inv2) is 0, so the values stay in [0, top] (a NaN
+            // fails the comparisons and becomes 0).
             const int dim = base + ds * k;
-            if (base < 0 || dim >= f.dim || p0 + k >= f.npos) continue;
-            const float t = ts[dim];
-            unsigned c1 = 0u, c2 = 0u;
-            if (st.step1) {
-                float a = t - st.l;
-                float b = a * st.inv;
-                float c = b + 0.5f;
-                float v = floorf(c);
-                v = v > 0.0f ? v : 0.0f;
-                v = v > (float)st.top1 ? (float)st.top1 : v;
-                c1 = (unsigned)v;
-                if (B2 != 0 && st.step2) {
-                    float y = st.delta * v;
-                    y = y + st.l;
-                    const float r = t - y;
-                    float a2 = r - (-st.half);
-                    float b2 = a2 * st.inv2;
-                    float c2f = b2 + 0.5f;
-                    float v2 = floorf(c2f);
-                    v2 = v2 > 0.0f ? v2 : 0.0f;
-                    v2 = v2 > (float)st.top2 ? (float)st.top2 : v2;
-                    c2 = (unsigned)v2;
-                }
+            const bool valid = base >= 0 && dim < f.dim && p0 + k < f.npos;
+            const float t = ts[valid ? dim : 0];
+            float a = t - st.l;
+            float b = a * st.inv;
+            float c = b + 0.5f;
+            float v = floorf(c);
+            v = v > 0.0f ? v : 0.0f;
+            v = v > (float)st.top1 ? (float)st.top1 : v;
+            const unsigned c1 = valid && st.step1 ? (unsigned)v : 0u;
+            unsigned c2 = 0u;
+            if constexpr (B2 != 0) {
+                float y = st.delta * v;
+                y = y + st.l;
+                const float r = t - y;
+                float a2 = r - (-st.half);
+                float b2 = a2 * st.inv2;
+                float c2f = b2 + 0.5f;
+                float v2 = floorf(c2f);
+                v2 = v2 > 0.0f ? v2 : 0.0f;
+                v2 = v2 > (float)st.top2 ? (float)st.top2 : v2;
+                c2 = valid && st.step1 && st.step2 ? (unsigned)v2 : 0u;
             }
             const int q = h * PER1 + k;            // field index within the unit
             pw[q / PER1] |= c1 << (B1 * (q % PER1));
