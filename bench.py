@@ -12,7 +12,9 @@ Other workloads (each prints its own line): c1 (LVQ-8 encode + exhaustive L2
 top-10, n = 10^4, d = 96), c3 (multi-means LVQ-8, L2, n = 10^7, d = 96, uneven
 lists in one persistent launch replayed from a HIP graph), c4 (exhaustive
 inner-product top-100 over n = 5 * 10^6, d = 512 LVQ-8 on the matrix cores with
-bf16, fp16 and FP32 queries).
+bf16, fp16 and FP32 queries), c5scan (the serving store's exhaustive
+both-level top-10 alone: 10^6 LVQ-4x8 rows of d = 768 with 16 means, a batch
+of 2,048 queries in each precision).
 
 Prints one JSON line per workload.  Progress goes to stderr.
 """
@@ -692,6 +694,69 @@ def bench_c4(args):
     out["encode"] = encode_roofline(warm_encode_ms(ix, X, dev), n, d, ix.row_bytes, ix.resid_bytes, enc_ms)
     if cpu:
         out["cpu_baseline"] = cpu
+    ix.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# The both-level exhaustive scan at the serving store's shape, alone: 10^6
+# LVQ-4x8 Turbo rows of d = 768 with 16 means, a batch of queries in each
+# precision, top-10 (the kernel the C5 server runs per batch)
+# ---------------------------------------------------------------------------
+
+def bench_c5scan(args):
+    import torch
+
+    import paper_2402_02044_amd as L
+    import synth
+    n, nq, d, k = args.n or 1_000_000, args.nq or 2048, 768, 10
+    dev = torch.device("cuda:0")
+    log("generating %d x %d C5 vectors, 16 means" % (n, d))
+    X = synth.vectors("C5", synth.S_BASE, 0, n)
+    means = host_kmeans(X[synth.sample_indices(5, n, 100_000)], 16, 25, 5)
+    ix = L.Index(d, 4, 8, L.LVQ_IP, L.LVQ_TURBO, capacity=n, means=means)
+    to_gpu_rows(ix, X, dev)
+    assert ix.sync() == 0
+    Q = synth.c5_points(synth.S_QUERY, 1, nq, part=1)
+    qf = torch.from_numpy(Q).to(dev)
+    forms = [f for f in (("bf16", torch.bfloat16), ("fp16", torch.float16), ("fp32", torch.float32),
+                         ("fp32_plain", torch.float32)) if f[0] in args.forms.split(",")]
+    # flops the matrix cores execute per (query, row): the 16-bit forms take
+    # <q, c1> and <q, c2> (two chains, 4d), the FP32 form <q, y> on decoded y
+    # (2d); the plain vector kernel 2d FMAs on decoded y
+    per_pair = {"bf16": 4 * d, "fp16": 4 * d, "fp32": 2 * d, "fp32_plain": 2 * d}
+    res = {}
+    for name, tdt in forms:
+        q = qf.to(tdt)
+        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        prec = {"bf16": L.LVQ_BF16, "fp16": L.LVQ_FP16, "fp32": L.LVQ_FP32, "fp32_plain": L.LVQ_FP32_VALU}[name]
+        s = int(torch.cuda.current_stream().cuda_stream)
+
+        def step():
+            L.lvq_topk(ix.handle, q.data_ptr(), prec, nq, k, L.LVQ_FULL, ids.data_ptr(), dist.data_ptr(), s)
+
+        steps = args.steps if name != "fp32_plain" else max(1, args.steps // 4)
+        ms, k_ms = timed(step, steps, 1, ix)
+        assert ix.sync() == 0
+        tf = per_pair[name] * float(n) * nq / (k_ms / 1000.0) / 1e12
+        peak = MFMA_BF16_PEAK_TFLOPS if name in ("bf16", "fp16") else FP32_PEAK_TFLOPS
+        res[name] = {"ms_per_step": ms, "kernel_ms": k_ms, "queries_per_s": nq / (ms / 1000.0),
+                     "kernel_tflops": tf, "frac_of_peak": tf / peak, "peak_tflops": peak,
+                     "flops_per_pair": per_pair[name]}
+        log("%s: step %.2f ms, kernel %.2f ms, %.1f TFLOP/s (%.3f of %.1f)" % (name, ms, k_ms, tf, tf / peak, peak))
+    main_form = "bf16" if "bf16" in res else next(iter(res))
+    r = res[main_form]
+    out = line(r["queries_per_s"], "queries/s", args.steps, 1, r["ms_per_step"], main_form,
+               {"workload": "exhaustive both-level inner-product top-%d of %d queries over n=%d d=%d LVQ-4x8 Turbo "
+                            "rows with 16 means (the serving store), bf16 on MFMA; fp16, FP32 on the FP32 MFMA and "
+                            "the plain FP32 vector kernel on the same store" % (k, nq, n, d),
+                "n": n, "dim": d, "queries": nq, "k": k},
+               {"bound": "mfma", "achieved": r["kernel_tflops"], "peak": r["peak_tflops"], "unit": "TFLOP/s",
+                "frac": r["frac_of_peak"], "traffic": None,
+                "kernel": "k_scan_mfma_wide (%s, both levels, fused top-%d)" % (main_form, k),
+                "kernel_ms": r["kernel_ms"]},
+               forms=res)
     ix.close()
     return out
 
@@ -1714,7 +1779,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "layouts", "probe", "means", "graph", "graph_stream"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "c5scan", "layouts", "probe",
+                                                         "means", "graph", "graph_stream"])
     ap.add_argument("--rounds", type=int, default=30, help="c5: update rounds")
     ap.add_argument("--sat-batches", type=int, default=60, help="c5: batches of each saturation burst")
     ap.add_argument("--lat-batches", type=int, default=120, help="c5: batches of each latency phase")
@@ -1754,7 +1820,7 @@ def main():
         print(json.dumps({"copy_bytes_read_per_launch": n * 4, "copy_bytes_written_per_launch": n * 4,
                           "launches": 5}), flush=True)
         return
-    fn = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
+    fn = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c5scan": bench_c5scan,
           "layouts": bench_layouts, "probe": bench_probe, "means": bench_means,
           "graph": bench_graph, "graph_stream": bench_graph_stream}[args.workload]
     out = fn(args)
