@@ -481,7 +481,8 @@ def test_exhaustive_topk_mfma(L, d, b1, b2, layout, M, prec):
         # kernel, which takes the first level and both levels with 8-bit
         # residual codes, any of these mean counts
         wide = (olev == oracle.FULL and b2 == 8) or (olev == oracle.PRIMARY and (M == 1 or prec == "fp32"))
-        big = (300,) + ((512,) if M == 1 and olev == oracle.PRIMARY and prec == "bf16" else ())
+        big = (300,) + ((512,) if (M == 1 and olev == oracle.PRIMARY and prec == "bf16") or
+                        (M > 1 and olev == oracle.FULL and prec == "fp32") else ())
         for k in (1, 10, 100) + (big if wide else ()):
             ti, td = ix.topk(Qh.cuda(), k, level=glev)
             assert ix.sync() == 0
@@ -493,6 +494,49 @@ def test_exhaustive_topk_mfma(L, d, b1, b2, layout, M, prec):
         with pytest.raises(L.LVQError) as e:
             ix.topk(Qh.cuda(), 10, level=L.LVQ_FULL)
         assert e.value.code == L.LVQ_ERR_UNSUPPORTED
+    ix.close()
+
+
+@pytest.mark.parametrize("b2", [0, 8])
+def test_exhaustive_topk_many_means(L, b2):
+    """Two hundred means: the queries-in-LDS kernel's c_m table at the size
+    a large M-LVQ store reaches (FP32 at either level, bf16 at both levels),
+    the rows' mean ids spread over all of them, nq past one query tile."""
+    d, n, nq, M = 96, 4000, 150, 200
+    g = synth.rng(3400 + b2, M)
+    cent = g.standard_normal((M, d)).astype(np.float32)
+    X = (cent[g.integers(0, M, n)] + 0.3 * g.standard_normal((n, d))).astype(np.float32)
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    Q = (cent[g.integers(0, M, nq)] + 0.3 * g.standard_normal((nq, d))).astype(np.float32)
+    Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    means = X[g.choice(n, M, replace=False)]
+    fmt = oracle.Format(d, 8, b2, oracle.SEQUENTIAL)
+    rows, resid, _ = oracle.encode_rows(fmt, X, means)
+    assert len(np.unique(rows[:, 12])) > M // 2   # the rows use many of the means
+    ix = L.Index(d, 8, b2, L.LVQ_IP, L.LVQ_SEQUENTIAL, capacity=n, means=means)
+    ix.insert(torch.from_numpy(X).cuda())
+    dead = np.sort(g.choice(n, 300, replace=False)).astype(np.int32)
+    ix.delete(torch.from_numpy(dead).cuda())
+    assert ix.sync() == 0
+    live = np.ones(n, bool)
+    live[dead] = False
+    offs = np.arange(nq + 1, dtype=np.int64) * n
+    allids = np.tile(np.arange(n, dtype=np.int32), nq)
+    levels = [(oracle.PRIMARY, L.LVQ_PRIMARY)] + ([(oracle.FULL, L.LVQ_FULL)] if b2 else [])
+    for prec, tdt in (("fp32", torch.float32), ("bf16", torch.bfloat16)):
+        Qh = torch.from_numpy(Q).to(tdt)
+        Qr = Qh.float().numpy()
+        for olev, glev in levels:
+            if prec == "bf16" and olev == oracle.PRIMARY:
+                continue   # the register-resident kernel; its per-query buffers cap the mean count
+            ref, tol = pair_reference(fmt, oracle.IP, olev, Qr, rows, resid, means, offs, allids)
+            for k in (10, 100):
+                ti, td = ix.topk(Qh.cuda(), k, level=glev)
+                assert ix.sync() == 0
+                ti, td = ti.cpu().numpy(), td.cpu().numpy()
+                for i in range(nq):
+                    a, b = offs[i], offs[i + 1]
+                    check_topk(oracle.IP, ti[i], td[i], allids[a:b], ref[a:b], tol[a:b], k, live)
     ix.close()
 
 
