@@ -30,7 +30,8 @@
 // KS best keys so far (sorted, KS = k rounded up to a power of two >= 64)
 // followed by the keys pending a merge.  The epilogue tests a lane's 16
 // scores against its query's bound; a lane with passing scores reserves room
-// with one LDS atomic and writes its keys.  After the round's appends (a
+// with one LDS atomic and writes its keys (the both-level 16-bit forms take
+// one atomic per passing key, in a single sweep).  After the round's appends (a
 // barrier), queries with 64 or more pending keys are merged by their owner
 // wave: 64 keys at a time are sorted in registers and folded into the sorted
 // list by one bitonic merge, and the bound becomes the k-th key, shared with
@@ -468,6 +469,44 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                         if constexpr (CH2) return fmaf(d2, acc2[j][b][i], t);
                         else return t;
                     };
+                    if constexpr (CH2) {
+                        // One sweep: each score that reaches its bound is
+                        // appended at once (one LDS atomic per key).  A score
+                        // here costs three products and three LDS values
+                        // (l', Delta, Delta2; c_m by mean), so scoring the
+                        // passing blocks twice, as below, costs more than
+                        // the per-key atomics.
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            const float4 L = *reinterpret_cast<const float4 *>(wl + 32 * j + 8 * g + 4 * half);
+                            const float4 D = *reinterpret_cast<const float4 *>(wd + 32 * j + 8 * g + 4 * half);
+                            int4 M4 = make_int4(0, 0, 0, 0);
+                            if constexpr (TAB) M4 = *reinterpret_cast<const int4 *>(wm + 32 * j + 8 * g + 4 * half);
+                            const float4 D2 = *reinterpret_cast<const float4 *>(wd2 + 32 * j + 8 * g + 4 * half);
+                            const float lr[4] = {L.x, L.y, L.z, L.w}, dr[4] = {D.x, D.y, D.z, D.w};
+                            const float d2r[4] = {D2.x, D2.y, D2.z, D2.w};
+                            const int mr[4] = {M4.x, M4.y, M4.z, M4.w};
+#pragma unroll
+                            for (int b = 0; b < QB; ++b)
+#pragma unroll
+                                for (int r4 = 0; r4 < 4; ++r4) {
+                                    const float sv = score(b, 4 * g + r4, lr[r4], dr[r4], d2r[r4], mr[r4]);
+                                    if (sv >= tau[b]) {
+                                        const int qi = 32 * b + col;
+                                        const int pos = atomicAdd(&cnt[qi], 1);
+                                        if (pos < kWidePending)
+                                            region[(size_t)qi * cap + ks + pos] =
+                                                make_key(sv, ws[32 * j + 8 * g + 4 * half + r4], LVQ_IP);
+                                    }
+                                }
+                        }
+                        continue;
+                    }
+                    // One product chain: a first sweep takes each lane's
+                    // largest score per query block; only blocks where some
+                    // lane reaches its bound are scored again to count and
+                    // append (one LDS atomic per lane).  Testing every score
+                    // with its own branch measured slower here.
                     float mx[QB];
 #pragma unroll
                     for (int b = 0; b < QB; ++b) mx[b] = -__builtin_inff();
