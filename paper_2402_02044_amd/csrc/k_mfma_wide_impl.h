@@ -29,9 +29,8 @@
 // Top-k.  Each query keeps, in the workgroup's region of device memory, its
 // KS best keys so far (sorted, KS = k rounded up to a power of two >= 64)
 // followed by the keys pending a merge.  The epilogue tests a lane's 16
-// scores against its query's bound; a lane with passing scores reserves room
-// with one LDS atomic and writes its keys (the both-level 16-bit forms take
-// one atomic per passing key, in a single sweep).  After the round's appends (a
+// scores against its query's bound; each passing score takes a pending slot
+// with one LDS atomic and writes its key.  After the round's appends (a
 // barrier), queries with 64 or more pending keys are merged by their owner
 // wave: 64 keys at a time are sorted in registers and folded into the sorted
 // list by one bitonic merge, and the bound becomes the k-th key, shared with
@@ -449,13 +448,12 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
             __builtin_amdgcn_wave_barrier();
             // Lane rows 32*j + 8*g + 4*half + r4, r4 < 4: the score of (row,
             // query 32*b + col) is c_m + l' sum(q) + Delta <q, c1> (decoded:
-            // + <q, y>).  A query block whose lanes' largest scores all stay
-            // below their bounds is done; else each lane counts its scores
-            // that reach the bound (a NaN score, from a row not scored,
-            // never does), reserves room with one LDS atomic and writes
-            // their keys.
-            // With several means (FP32 forms) c_m comes from the LDS table by
-            // the row's mean id, else from the lane's registers.
+            // + <q, y>; two chains: + Delta2 <q, c2>).  A score that reaches
+            // its query's bound (a NaN score, from a row not scored, never
+            // does) takes the next pending slot of that query by an LDS
+            // atomic and writes its key there.  With several means c_m comes
+            // from the LDS table by the row's mean id, else from the lane's
+            // registers.
             auto epilogue = [&](auto tab) {
                 constexpr bool TAB = decltype(tab)::value;
 #pragma unroll
@@ -471,11 +469,11 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                     };
                     if constexpr (CH2) {
                         // One sweep: each score that reaches its bound is
-                        // appended at once (one LDS atomic per key).  A score
-                        // here costs three products and three LDS values
-                        // (l', Delta, Delta2; c_m by mean), so scoring the
-                        // passing blocks twice, as below, costs more than
-                        // the per-key atomics.
+                        // appended at once.  A score here costs three
+                        // products and three LDS values (l', Delta, Delta2;
+                        // c_m by mean), so a first sweep for the largest
+                        // score per block, as below, costs more than it
+                        // saves.
 #pragma unroll
                         for (int g = 0; g < 4; ++g) {
                             const float4 L = *reinterpret_cast<const float4 *>(wl + 32 * j + 8 * g + 4 * half);
@@ -504,9 +502,9 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                     }
                     // One product chain: a first sweep takes each lane's
                     // largest score per query block; only blocks where some
-                    // lane reaches its bound are scored again to count and
-                    // append (one LDS atomic per lane).  Testing every score
-                    // with its own branch measured slower here.
+                    // lane reaches its bound are scored again, appending
+                    // each passing key.  A branch per score in the first
+                    // sweep measured slower here.
                     float mx[QB];
 #pragma unroll
                     for (int b = 0; b < QB; ++b) mx[b] = -__builtin_inff();
@@ -532,24 +530,15 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
 #pragma unroll
                     for (int b = 0; b < QB; ++b) {
                         if (!__ballot(mx[b] >= tau[b])) continue;
-                        // one score per iteration (a uniform index into the
-                        // accumulators)
-                        int np = 0;
-#pragma unroll 4
-                        for (int i = 0; i < 16; ++i) {
-                            const int m = 32 * j + 8 * (i >> 2) + 4 * half + (i & 3);
-                            np += score(b, i, wl[m], wd[m], CH2 ? wd2[m] : 0.0f, TAB ? wm[m] : 0) >= tau[b] ? 1 : 0;
-                        }
                         const int qi = 32 * b + col;
-                        int pos = np ? atomicAdd(&cnt[qi], np) : 0;
                         uint64_t *dst = region + (size_t)qi * cap + ks;
 #pragma unroll 4
                         for (int i = 0; i < 16; ++i) {
                             const int m = 32 * j + 8 * (i >> 2) + 4 * half + (i & 3);
                             const float sv = score(b, i, wl[m], wd[m], CH2 ? wd2[m] : 0.0f, TAB ? wm[m] : 0);
                             if (sv >= tau[b]) {
+                                const int pos = atomicAdd(&cnt[qi], 1);
                                 if (pos < kWidePending) dst[pos] = make_key(sv, ws[m], LVQ_IP);
-                                ++pos;
                             }
                         }
                     }
