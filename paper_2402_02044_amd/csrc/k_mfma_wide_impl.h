@@ -524,7 +524,7 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
 #pragma unroll
                             for (int r4 = 0; r4 < 4; ++r4) {
                                 const float sv = score(b, 4 * g + r4, lr[r4], dr[r4], d2r[r4], mr[r4]);
-                                mx[b] = sv > mx[b] ? sv : mx[b];
+                                mx[b] = fmaxf(mx[b], sv);   // a NaN score leaves mx[b]
                             }
                     }
 #pragma unroll
