@@ -532,13 +532,34 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                         if (!__ballot(mx[b] >= tau[b])) continue;
                         const int qi = 32 * b + col;
                         uint64_t *dst = region + (size_t)qi * cap + ks;
+                        if constexpr (RES) {
 #pragma unroll 4
-                        for (int i = 0; i < 16; ++i) {
-                            const int m = 32 * j + 8 * (i >> 2) + 4 * half + (i & 3);
-                            const float sv = score(b, i, wl[m], wd[m], CH2 ? wd2[m] : 0.0f, TAB ? wm[m] : 0);
-                            if (sv >= tau[b]) {
-                                const int pos = atomicAdd(&cnt[qi], 1);
-                                if (pos < kWidePending) dst[pos] = make_key(sv, ws[m], LVQ_IP);
+                            for (int i = 0; i < 16; ++i) {
+                                const int m = 32 * j + 8 * (i >> 2) + 4 * half + (i & 3);
+                                const float sv = score(b, i, wl[m], wd[m], 0.0f, TAB ? wm[m] : 0);
+                                if (sv >= tau[b]) {
+                                    const int pos = atomicAdd(&cnt[qi], 1);
+                                    if (pos < kWidePending) dst[pos] = make_key(sv, ws[m], LVQ_IP);
+                                }
+                            }
+                            continue;
+                        }
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            const int m0 = 32 * j + 8 * g + 4 * half;
+                            const float4 L = *reinterpret_cast<const float4 *>(wl + m0);
+                            const float4 D = *reinterpret_cast<const float4 *>(wd + m0);
+                            int4 M4 = make_int4(0, 0, 0, 0);
+                            if constexpr (TAB) M4 = *reinterpret_cast<const int4 *>(wm + m0);
+                            const float lr[4] = {L.x, L.y, L.z, L.w}, dr[4] = {D.x, D.y, D.z, D.w};
+                            const int mr[4] = {M4.x, M4.y, M4.z, M4.w};
+#pragma unroll
+                            for (int r4 = 0; r4 < 4; ++r4) {
+                                const float sv = score(b, 4 * g + r4, lr[r4], dr[r4], 0.0f, mr[r4]);
+                                if (sv >= tau[b]) {
+                                    const int pos = atomicAdd(&cnt[qi], 1);
+                                    if (pos < kWidePending) dst[pos] = make_key(sv, ws[m0 + r4], LVQ_IP);
+                                }
                             }
                         }
                     }
