@@ -328,6 +328,9 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
             uint32_t gb[QB];
 #pragma unroll
             for (int c = 0; c < NCHUNK; ++c) {
+                // Chunks are scheduling regions: the compiler otherwise sinks
+                // each ring load to its use and waits on it there.
+                __builtin_amdgcn_sched_barrier(0);
                 if (c == NCHUNK / 2) {
 #pragma unroll
                     for (int j = 0; j < RB; ++j) {
