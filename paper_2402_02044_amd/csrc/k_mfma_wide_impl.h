@@ -334,9 +334,10 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                 if (c == NCHUNK / 2) {
 #pragma unroll
                     for (int j = 0; j < RB; ++j) {
-                        const uint8_t *h = header(DEC ? sn[j] : sc[j]);
-                        hn[j] = *reinterpret_cast<const float4 *>(h);
-                        en[j] = *reinterpret_cast<const uint2 *>(h + 16);
+                        const uint32_t *h = reinterpret_cast<const uint32_t *>(header(DEC ? sn[j] : sc[j]));
+                        hn[j] = make_float4(__uint_as_float(h[0]), __uint_as_float(h[1]), __uint_as_float(h[2]),
+                                            __uint_as_float(h[3]));
+                        en[j] = make_uint2(h[4], h[5]);
                     }
 #pragma unroll
                     for (int b = 0; b < QB; ++b) {
