@@ -398,6 +398,13 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                         }
                     }
                 } else {
+                    // the chunk's query fragments are read first, so that
+                    // their LDS latency overlaps the conversions and products
+                    uint4 bqs[STEPS][QB];
+#pragma unroll
+                    for (int s = 0; s < STEPS; ++s)
+#pragma unroll
+                        for (int b = 0; b < QB; ++b) bqs[s][b] = qf[((b * NCHUNK + c) * STEPS + s) * 64 + lane];
 #pragma unroll
                     for (int s = 0; s < STEPS; ++s) {
                         uint4 af[RB], af2[RB];
@@ -408,13 +415,19 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                         }
 #pragma unroll
                         for (int b = 0; b < QB; ++b) {
-                            const uint4 bq = qf[((b * NCHUNK + c) * STEPS + s) * 64 + lane];
+                            const uint4 bq = bqs[s][b];
 #pragma unroll
                             for (int j = 0; j < RB; ++j) {
                                 acc[j][b] = mfma<FP16>(af[j], bq, acc[j][b]);
                                 if constexpr (CH2) acc2[j][b] = mfma<FP16>(af2[j], bq, acc2[j][b]);
                             }
                         }
+                    }
+                    // LDS reads of the chunk ahead of its products (up to
+                    // 768 positions; longer rows spill with it)
+                    if constexpr (KPOS <= 768) {
+                        __builtin_amdgcn_sched_group_barrier(0x100, STEPS * QB, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x008, STEPS * QB * RB * (CH2 ? 2 : 1), 0);
                     }
                 }
             }
