@@ -434,10 +434,14 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
 
             // the previous round's merges are done: their bounds are in thr_f
             __syncthreads();
+            // (branch-free, so that the LDS reads of all blocks go out together)
+            float tf[QB];
+#pragma unroll
+            for (int b = 0; b < QB; ++b) tf[b] = thr_f[32 * b + col];
 #pragma unroll
             for (int b = 0; b < QB; ++b) {
-                tau[b] = fmaxf(tau[b], thr_f[32 * b + col]);
-                if (gb[b] != 0xFFFFFFFFu) tau[b] = fmaxf(tau[b], key_score((uint64_t)gb[b] << 32, LVQ_IP));
+                const float other = key_score((uint64_t)gb[b] << 32, LVQ_IP);
+                tau[b] = fmaxf(tau[b], fmaxf(tf[b], gb[b] != 0xFFFFFFFFu ? other : -__builtin_inff()));
             }
             // Row constants of the round to the wave's LDS area: half 0
             // writes l' (NaN for rows not scored: dead, outside the snapshot,
@@ -597,9 +601,16 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
             // that reads or resets their counts here; they end before the
             // next round's first barrier.  After the last round the merged
             // list's first k keys are the tile's result.
-            for (int qw = 0; qw < TQ; qw += 64) {
-                const int qi_l = qw + lane;
-                uint64_t m = __ballot(qi_l < nqt && qi_l % WAVES == wave && (last || cnt[qi_l] >= kWideMerge));
+            // (the counts are read before any merge: a wave's merges reset
+            // only its own queries' counts)
+            constexpr int NQW = (TQ + 63) / 64;
+            int cv[NQW];
+#pragma unroll
+            for (int t = 0; t < NQW; ++t) cv[t] = 64 * t + lane < nqt ? cnt[64 * t + lane] : 0;
+#pragma unroll
+            for (int t = 0; t < NQW; ++t) {
+                const int qw = 64 * t, qi_l = qw + lane;
+                uint64_t m = __ballot(qi_l < nqt && qi_l % WAVES == wave && (last || cv[t] >= kWideMerge));
                 while (m) {
                     const int qi = qw + __builtin_ctzll(m);
                     m &= m - 1;
