@@ -62,7 +62,8 @@ __host__ __device__ constexpr int wide_waves(int)
     return 8;
 }
 // Chunks of codes in flight: a divisor of the chunk count, so that the ring
-// slot of chunk c is c % RING in every round.  Up to four; two when each
+// slot of chunk c is c % RING in every round.  Up to four (eight in the
+// 16-bit first-level forms with one row block per wave); two when each
 // chunk also brings residual codes (the registers of a deeper ring would
 // spill).
 __host__ __device__ constexpr int wide_ring(int nchunk, bool resid)
@@ -186,7 +187,9 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
     // 16-byte query fragments per chunk and block: 8 positions each in 16
     // bits, 4 in FP32 (one per lane and MFMA)
     constexpr int STEPS = F32 ? CHUNK_POS / 8 : CHUNK_POS / 16;
-    constexpr int RING = wide_ring(NCHUNK, RES);
+    // eight chunks in flight where the registers allow it (16-bit first
+    // level, one row block per wave): a row missing in L2 then waits less
+    constexpr int RING = (!RES && !F32 && RB == 1 && NCHUNK % 8 == 0) ? 8 : wide_ring(NCHUNK, RES);
     // residual 16-byte pieces per lane and chunk (one 8-bit code per
     // first-level position)
     constexpr int RP = RES ? CHUNK_POS / 32 : 1;
