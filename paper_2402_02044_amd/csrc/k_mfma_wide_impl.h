@@ -532,10 +532,18 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                     float mx[QB];
 #pragma unroll
                     for (int b = 0; b < QB; ++b) mx[b] = -__builtin_inff();
+                    // one-mean first level: the rows' l' and Delta stay in
+                    // registers for the passing blocks' second scoring
+                    constexpr bool KEEP = !RES && !F32;
+                    float4 Lk[KEEP ? 4 : 1], Dk[KEEP ? 4 : 1];
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
                         const float4 L = *reinterpret_cast<const float4 *>(wl + 32 * j + 8 * g + 4 * half);
                         const float4 D = *reinterpret_cast<const float4 *>(wd + 32 * j + 8 * g + 4 * half);
+                        if constexpr (KEEP) {
+                            Lk[g] = L;
+                            Dk[g] = D;
+                        }
                         int4 M4 = make_int4(0, 0, 0, 0);
                         if constexpr (TAB) M4 = *reinterpret_cast<const int4 *>(wm + 32 * j + 8 * g + 4 * half);
                         float4 D2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -571,8 +579,14 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
 #pragma unroll
                         for (int g = 0; g < 4; ++g) {
                             const int m0 = 32 * j + 8 * g + 4 * half;
-                            const float4 L = *reinterpret_cast<const float4 *>(wl + m0);
-                            const float4 D = *reinterpret_cast<const float4 *>(wd + m0);
+                            float4 L, D;
+                            if constexpr (KEEP) {
+                                L = Lk[g];
+                                D = Dk[g];
+                            } else {
+                                L = *reinterpret_cast<const float4 *>(wl + m0);
+                                D = *reinterpret_cast<const float4 *>(wd + m0);
+                            }
                             int4 M4 = make_int4(0, 0, 0, 0);
                             if constexpr (TAB) M4 = *reinterpret_cast<const int4 *>(wm + m0);
                             const float lr[4] = {L.x, L.y, L.z, L.w}, dr[4] = {D.x, D.y, D.z, D.w};
