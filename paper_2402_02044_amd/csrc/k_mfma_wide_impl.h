@@ -532,9 +532,10 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                     float mx[QB];
 #pragma unroll
                     for (int b = 0; b < QB; ++b) mx[b] = -__builtin_inff();
-                    // one-mean first level: the rows' l' and Delta stay in
-                    // registers for the passing blocks' second scoring
-                    constexpr bool KEEP = !RES && !F32;
+                    // the rows' l' and Delta stay in registers for the
+                    // passing blocks' second scoring (not in the decoded
+                    // forms with two query blocks, where they would spill)
+                    constexpr bool KEEP = !(DEC && QB > 1);
                     float4 Lk[KEEP ? 4 : 1], Dk[KEEP ? 4 : 1];
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
@@ -564,7 +565,7 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                         if (!__ballot(mx[b] >= tau[b])) continue;
                         const int qi = 32 * b + col;
                         uint64_t *dst = region + (size_t)qi * cap + ks;
-                        if constexpr (RES) {
+                        if constexpr (!KEEP) {
 #pragma unroll 4
                             for (int i = 0; i < 16; ++i) {
                                 const int m = 32 * j + 8 * (i >> 2) + 4 * half + (i & 3);
