@@ -514,11 +514,13 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                                 for (int r4 = 0; r4 < 4; ++r4) {
                                     const float sv = score(b, 4 * g + r4, lr[r4], dr[r4], d2r[r4], mr[r4]);
                                     if (sv >= tau[b]) {
+                                        // the slot read and the atomic share one LDS wait;
+                                        // the position is clamped (the pending room holds
+                                        // a round's keys, so it never is)
+                                        const int32_t slot = ws[32 * j + 8 * g + 4 * half + r4];
                                         const int qi = 32 * b + col;
-                                        const int pos = atomicAdd(&cnt[qi], 1);
-                                        if (pos < kWidePending)
-                                            region[(size_t)qi * cap + ks + pos] =
-                                                make_key(sv, ws[32 * j + 8 * g + 4 * half + r4], LVQ_IP);
+                                        const int pos = min(atomicAdd(&cnt[qi], 1), kWidePending - 1);
+                                        region[(size_t)qi * cap + ks + pos] = make_key(sv, slot, LVQ_IP);
                                     }
                                 }
                         }
@@ -571,8 +573,9 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                                 const int m = 32 * j + 8 * (i >> 2) + 4 * half + (i & 3);
                                 const float sv = score(b, i, wl[m], wd[m], 0.0f, TAB ? wm[m] : 0);
                                 if (sv >= tau[b]) {
-                                    const int pos = atomicAdd(&cnt[qi], 1);
-                                    if (pos < kWidePending) dst[pos] = make_key(sv, ws[m], LVQ_IP);
+                                    const int32_t slot = ws[m];
+                                    const int pos = min(atomicAdd(&cnt[qi], 1), kWidePending - 1);
+                                    dst[pos] = make_key(sv, slot, LVQ_IP);
                                 }
                             }
                             continue;
@@ -596,8 +599,9 @@ __global__ __launch_bounds__(64 * wide_waves(RB), 1) void k_scan_mfma_wide(ScanA
                             for (int r4 = 0; r4 < 4; ++r4) {
                                 const float sv = score(b, 4 * g + r4, lr[r4], dr[r4], 0.0f, mr[r4]);
                                 if (sv >= tau[b]) {
-                                    const int pos = atomicAdd(&cnt[qi], 1);
-                                    if (pos < kWidePending) dst[pos] = make_key(sv, ws[m0 + r4], LVQ_IP);
+                                    const int32_t slot = ws[m0 + r4];
+                                    const int pos = min(atomicAdd(&cnt[qi], 1), kWidePending - 1);
+                                    dst[pos] = make_key(sv, slot, LVQ_IP);
                                 }
                             }
                         }
